@@ -1,0 +1,415 @@
+"""Pins of the FP64 oracle's particle-in-cell pieces against what the paper and
+the mathematics fix (closed forms, invariants, brute force).  CPU only."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle as O
+
+# --------------------------------------------------------------- shapes (II.D)
+
+
+def paper_s2(xi):
+    """Eq. 17: the triangle shape S_2."""
+    return max(0.0, 1.0 - abs(xi))
+
+
+def tophat(xi):
+    return 1.0 if abs(xi) <= 0.5 else 0.0
+
+
+@pytest.mark.parametrize("order,S", [(1, tophat), (2, paper_s2)])
+def test_weights_are_cell_integrals_of_the_shape(order, S):
+    """W_n(i - i_c) = integral over the cell of node i of S_n(xi' - x_p) (Sec. II.D)."""
+    rng = np.random.default_rng(1)
+    for xi in rng.uniform(-3, 3, 40):
+        i0, w = O.shape(order, xi)
+        for k in range(-3, 4):
+            node = i0 + k
+            ref = integrate.quad(lambda s: S(s - xi), node - 0.5, node + 0.5,
+                                 points=[xi - 1, xi - 0.5, xi, xi + 0.5, xi + 1], epsabs=1e-13)[0]
+            got = w[k] if 0 <= k < len(w) else 0.0
+            assert abs(got - ref) < 1e-10, (order, xi, k, got, ref)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_weights_partition_of_unity_and_linear_reproduction(order):
+    rng = np.random.default_rng(2)
+    for xi in rng.uniform(-50, 50, 500):
+        i0, w = O.shape(order, xi)
+        nodes = i0 + np.arange(len(w))
+        assert abs(w.sum() - 1.0) < 1e-14
+        assert abs((w * nodes).sum() - xi) < 1e-12
+        assert np.all(w >= 0)
+
+
+def test_quadratic_nearest_node_ties():
+    """At delta = -1/2 the outer weight vanishes, so either nearest-node choice
+    gives the same field (the reading of the nearest node at ties)."""
+    i0, w = O.shape(2, 3.5)
+    assert i0 == 3 and list(w) == [0.5, 0.5, 0.0]
+
+
+# ------------------------------------------------------------- gather (Eq. 19)
+
+def grid2(order=2, n=(16, 12), d=(0.3, 0.2), dt=0.1):
+    return O.Grid(2, n, d, dt, order)
+
+
+def grid3(order=2, n=(10, 8, 6), d=(0.3, 0.25, 0.2), dt=0.08):
+    return O.Grid(3, n, d, dt, order)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("order", [1, 2])
+def test_gather_uniform_field_exact(dim, order):
+    g = grid2(order) if dim == 2 else grid3(order)
+    vals = np.arange(1, 7) * 0.37
+    F = [np.full(g.shape, v) for v in vals]
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        x = rng.uniform(0, 1, 3) * np.array(list(g.n) + [1] * (3 - dim)) * np.array(
+            list(g.d) + [1] * (3 - dim))
+        assert np.allclose(O.gather(g, F, x), vals, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("order", [1, 2])
+def test_gather_linear_field_on_staggered_nodes(dim, order):
+    """A field linear in x, sampled at each component's own staggered location,
+    is reproduced exactly at the particle (linear reproduction + stagger)."""
+    g = grid2(order, n=(40, 40)) if dim == 2 else grid3(order, n=(30, 30, 30))
+    stag = [(0.5, 0, 0), (0, 0.5, 0), (0, 0, 0.5), (0, 0.5, 0.5), (0.5, 0, 0.5), (0.5, 0.5, 0)]
+    coef = np.array([[0.3, -0.2, 0.1], [0.05, 0.4, -0.3], [-0.1, 0.2, 0.6],
+                     [0.7, 0.1, -0.2], [-0.4, 0.3, 0.2], [0.2, -0.5, 0.1]])
+    shape = g.shape
+    k, j, i = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    F = []
+    for c in range(6):
+        pos = [(i + stag[c][0]) * g.d[0], (j + stag[c][1]) * g.d[1]]
+        if dim == 3:
+            pos.append((k + stag[c][2]) * g.d[2])
+        F.append(1.0 + sum(coef[c][a] * pos[a] for a in range(dim)))
+    rng = np.random.default_rng(4)
+    for _ in range(30):
+        # stay away from the periodic seam where the linear field jumps
+        x = np.array([rng.uniform(5, g.n[a] - 5) * g.d[a] for a in range(dim)] + [0.0] * (3 - dim))
+        ref = [1.0 + sum(coef[c][a] * x[a] for a in range(dim)) for c in range(6)]
+        assert np.allclose(O.gather(g, F, x), ref, rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------ Boris (II.C)
+
+def test_boris_pure_electric_field_is_exact():
+    """With B = 0, Eqs. 13-16 reduce to u^{n+1} = u^n + q_m dt E exactly."""
+    u = np.array([0.3, -0.2, 0.9])
+    E = np.array([0.01, 0.02, -0.03])
+    out = O.boris(-1.0, 0.1, E, np.zeros(3), u)
+    assert np.allclose(out, u - 0.1 * E, atol=1e-15)
+
+
+def test_boris_rotation_angle_and_energy():
+    """Uniform B, E = 0: |u| is conserved to round-off and u rotates by
+    2 atan(Omega dt / 2) per step with Omega = |q_m| B / gamma."""
+    qm, dt, B = -1.0, 0.7, np.array([0.0, 0.0, 2.5])
+    u = np.array([3.0, 0.0, 0.5])
+    gam = math.sqrt(1 + u @ u)
+    om = abs(qm) * B[2] / gam
+    theta = 2 * math.atan(om * dt / 2)
+    v = u.copy()
+    for n in range(1, 400):
+        v = O.boris(qm, dt, np.zeros(3), B, v)
+        assert abs(np.linalg.norm(v) - np.linalg.norm(u)) < 1e-13
+        ang = math.atan2(v[1], v[0])
+        # electrons (q_m < 0) gyrate counter-clockwise about +z
+        ref = math.remainder(n * theta, 2 * math.pi)
+        assert abs(math.remainder(ang - ref, 2 * math.pi)) < 1e-11 * n
+        assert v[2] == pytest.approx(u[2], abs=1e-14)
+
+
+def test_push_gyration_radius_exact():
+    """Whole particle step in a uniform B_z (E = 0): full-step positions lie on
+    the circle of radius r_L = |u_perp| / |q_m B| and half-step positions on
+    r_L sqrt(1 + (Omega dt / 2)^2) (Boris with the Eq. 12 position update)."""
+    g = O.Grid(2, (32, 32), (1.0, 1.0), 0.5, 2)
+    st = O.State.zeros(g)
+    st.B[2][...] = 0.8
+    u0 = np.array([1.5, 0.0, 0.0])
+    sp = O.Species(q=-1.0, m=1.0, x=[np.array([16.0]), np.array([14.0])],
+                   u=[np.array([u0[0]]), np.array([u0[1]]), np.array([u0[2]])], w0=0.0)
+    gam = math.sqrt(1 + u0 @ u0)
+    rl = np.linalg.norm(u0[:2]) / 0.8
+    om = 0.8 / gam
+    rh = rl * math.sqrt(1 + (om * g.dt / 2) ** 2)
+    full, half = [], []
+    F = st.E + st.B
+    for _ in range(300):
+        u = np.array([c[0] for c in sp.u])
+        x = np.array([sp.x[0][0], sp.x[1][0]])
+        half.append(x + 0.5 * g.dt * u[:2] / math.sqrt(1 + u @ u))
+        O.push(g, sp, F, st.J)
+        full.append([sp.x[0][0], sp.x[1][0]])
+    full, half = np.array(full), np.array(half)
+    # centre: electrons with u along +x in B_z>0 turn towards +y ... fit it
+    A = np.c_[2 * full, np.ones(len(full))]
+    sol = np.linalg.lstsq(A, (full ** 2).sum(1), rcond=None)[0]
+    c = sol[:2]
+    assert np.allclose(np.linalg.norm(full - c, axis=1), rl, rtol=0, atol=1e-11)
+    assert np.allclose(np.linalg.norm(half - c, axis=1), rh, rtol=0, atol=1e-11)
+
+
+# ----------------------------------------------------------- Esirkepov (II.E)
+
+def random_move(g, rng):
+    dim = g.dim
+    L = np.array([g.n[a] * g.d[a] for a in range(dim)])
+    xh = np.zeros(3)
+    xe = np.zeros(3)
+    xh[:dim] = rng.uniform(0, 1, dim) * L
+    step = rng.uniform(-0.99, 0.99, dim) * np.array(g.d[:dim])
+    xe[:dim] = xh[:dim] + step
+    return xh, xe
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("order", [1, 2])
+def test_esirkepov_discrete_continuity(dim, order):
+    """Eq. 5 on the grid: (rho(x_e) - rho(x_h)) / dt + div J = 0 to round-off
+    for every single move shorter than one cell per axis."""
+    g = grid2(order) if dim == 2 else grid3(order)
+    rng = np.random.default_rng(5 + dim + order)
+    for _ in range(60):
+        xh, xe = random_move(g, rng)
+        qw = rng.uniform(-2, 2)
+        J = [np.zeros(g.shape) for _ in range(3)]
+        O.deposit(g, qw, xh, xe, 0.3, J)
+        r0 = O.rho(g, qw, [np.array([xh[a]]) for a in range(dim)], None, 1.0)
+        r1 = O.rho(g, qw, [np.array([xe[a]]) for a in range(dim)], None, 1.0)
+        res = (r1 - r0) / g.dt + O.div(g, J)
+        scale = abs(qw) / g.dt / min(g.d[:dim])
+        assert np.abs(res).max() < 1e-13 * scale
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("order", [1, 2])
+def test_esirkepov_total_current(dim, order):
+    """The summed current equals q w v (the charge times the mean velocity of
+    the straight move); in 2D3V the summed J_z equals q w v_z."""
+    g = grid2(order) if dim == 2 else grid3(order)
+    rng = np.random.default_rng(11)
+    for _ in range(30):
+        xh, xe = random_move(g, rng)
+        qw = rng.uniform(-2, 2)
+        vz = rng.uniform(-0.9, 0.9)
+        J = [np.zeros(g.shape) for _ in range(3)]
+        O.deposit(g, qw, xh, xe, vz, J)
+        for a in range(dim):
+            assert J[a].sum() == pytest.approx(qw * (xe[a] - xh[a]) / g.dt, abs=1e-12)
+        if dim == 2:
+            assert J[2].sum() == pytest.approx(qw * vz, abs=1e-12)
+
+
+def test_esirkepov_reduces_to_exact_1d_flux():
+    """A move along x only, inside one cell, with CIC: the current is the
+    charge flux through the single face crossed, J_x = q w dx / dt times the
+    transverse weights (the area-weighting special case)."""
+    g = O.Grid(2, (8, 8), (1.0, 1.0), 1.0, 1)
+    J = [np.zeros(g.shape) for _ in range(3)]
+    xh = np.array([3.2, 5.25, 0])
+    xe = np.array([3.6, 5.25, 0])
+    O.deposit(g, 1.0, xh, xe, 0.0, J)
+    # CIC in y at 5.25: nodes 5, 6 with weights 0.75, 0.25; only face i=3 (x=3.5)
+    ref = np.zeros(g.shape)
+    ref[0, 5, 3] = 0.4 * 0.75
+    ref[0, 6, 3] = 0.4 * 0.25
+    assert np.allclose(J[0], ref, atol=1e-15)
+    assert np.abs(J[1]).max() < 1e-15
+
+
+# ----------------------------------------------------------------- Yee (II.B)
+
+def yee_standing_wave(g, kvec, nsteps):
+    st = O.State.zeros(g)
+    k, j, i = np.meshgrid(*[np.arange(s) for s in g.shape], indexing="ij")
+    # E_z on integer (i, j) nodes in 2D
+    phase = kvec[0] * i * g.d[0] + kvec[1] * j * g.d[1]
+    mode = np.cos(phase)
+    st.E[2][...] = mode
+    amps = []
+    for _ in range(nsteps):
+        O.step(st)
+        amps.append((st.E[2] * mode).sum() / (mode * mode).sum())
+    return np.array(amps)
+
+
+def test_yee_vacuum_dispersion():
+    """(sin(w dt/2)/dt)^2 = sum_d (sin(k_d d_d/2)/d_d)^2 for the leapfrog Yee
+    scheme (Eqs. 9-10) on a single Fourier mode."""
+    g = O.Grid(2, (32, 24), (0.4, 0.3), 0.2, 2)
+    kvec = (2 * np.pi * 3 / (32 * 0.4), 2 * np.pi * 2 / (24 * 0.3))
+    a = np.r_[1.0, yee_standing_wave(g, kvec, 60)]
+    s = sum((np.sin(kvec[q] * g.d[q] / 2) / g.d[q]) ** 2 for q in range(2))
+    cos_wdt = 1 - 2 * (g.dt ** 2) * s  # cos(w dt) = 1 - 2 sin^2(w dt / 2)
+    est = (a[2:] + a[:-2]) / (2 * a[1:-1])
+    mask = np.abs(a[1:-1]) > 0.2
+    assert np.allclose(est[mask], cos_wdt, rtol=0, atol=1e-10)
+
+
+def test_yee_unstable_above_courant():
+    """Above the Courant limit the checkerboard mode grows (and below it does not)."""
+    dx = 0.5
+    courant = 1 / math.sqrt(2 / dx ** 2)
+    for fac, grows in [(0.99, False), (1.02, True)]:
+        g = O.Grid(2, (16, 16), (dx, dx), fac * courant, 1)
+        a = yee_standing_wave(g, (np.pi / dx, np.pi / dx), 400)
+        assert (np.abs(a).max() > 10) == grows
+
+
+def test_yee_divergence_invariants():
+    """div(curl E) = 0 on the Yee grid, so div B stays zero (Eq. 2) and div E
+    changes only by -dt div J (Eqs. 1, 5)."""
+    g = grid3(n=(8, 6, 5))
+    rng = np.random.default_rng(7)
+    E = [rng.standard_normal(g.shape) for _ in range(3)]
+    c = O.curl_e(g, E)
+    # div B at cell centres (forward differences on the face-centred B stagger)
+    divb = sum((np.roll(c[a], -1, axis=2 - a) - c[a]) / g.d[a] for a in range(3))
+    assert np.abs(divb).max() < 1e-11
+    assert np.abs(c[0]).max() > 1.0
+    st = O.State(g, E, [np.zeros(g.shape) for _ in range(3)],
+                 [rng.standard_normal(g.shape) for _ in range(3)])
+    d0 = O.div(g, st.E)
+    O.half_e(g, st.E, st.B, st.J)
+    assert np.allclose(O.div(g, st.E) - d0, -0.5 * g.dt * O.div(g, st.J), atol=1e-10)
+
+
+# ---------------------------------------------------- whole step invariants
+
+def plasma_state(g, ppc_axis, rng, uth=0.05, w=None):
+    dim = g.dim
+    n = list(g.n)[:dim]
+    grids = np.meshgrid(*[np.arange(n[a] * ppc_axis[a]) for a in range(dim)], indexing="ij")
+    xs = [((grids[a].ravel() + rng.uniform(0, 1, grids[a].size)) / ppc_axis[a]) * g.d[a]
+          for a in range(dim)]
+    N = xs[0].size
+    u = [rng.normal(0, uth, N) for _ in range(3)]
+    ppc = int(np.prod(ppc_axis[:dim]))
+    return O.Species(q=-1.0, m=1.0, x=xs, u=u, w=None, w0=1.0 / ppc if w is None else w)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gauss_residual_constant(dim):
+    """With the charge-conserving deposit, div E - rho at half steps keeps its
+    initial value to round-off (the divergence equations hold automatically,
+    Sec. II.B)."""
+    if dim == 2:
+        g = O.Grid(2, (16, 12), (0.2, 0.25), 0.12, 2)
+        ppc = (2, 2)
+    else:
+        g = O.Grid(3, (8, 6, 6), (0.2, 0.25, 0.3), 0.1, 2)
+        ppc = (1, 2, 1)
+    rng = np.random.default_rng(8)
+    st = O.State.zeros(g)
+    sp = plasma_state(g, ppc, rng, uth=0.2)
+    st.species.append(sp)
+    res = []
+    for _ in range(25):
+        # the Gauss residual at the half step, after the first half E update
+        O.half_e(g, st.E, st.B, st.J)
+        xh = []
+        u = sp.u
+        gam = np.sqrt(1 + u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+        for a in range(dim):
+            xh.append(sp.x[a] + 0.5 * g.dt * u[a] / gam)
+        res.append(O.div(g, st.E) - O.rho(g, sp.q, xh, None, sp.w0))
+        O.half_b(g, st.E, st.B)
+        for a in range(3):
+            st.J[a][...] = 0
+        O.push(g, sp, st.E + st.B, st.J)
+        O.half_b(g, st.E, st.B)
+        O.half_e(g, st.E, st.B, st.J)
+    for r in res[1:]:
+        assert np.abs(r - res[0]).max() < 1e-11
+
+
+def test_langmuir_frequency():
+    """Cold Langmuir oscillation: the leapfrog plasma frequency
+    (2/dt) asin(w_p dt / 2) (w_p = 1 in plasma units), measured within 1%."""
+    n = (64, 4)
+    d = (0.05, 0.05)
+    dt = 0.95 / math.sqrt(sum(1 / v ** 2 for v in d))
+    g = O.Grid(2, n, d, dt, 1)
+    ppc = (4, 4)
+    # quiet start lattice, velocity perturbation u_x = 0.001 sin(k x)
+    gx, gy = np.meshgrid(np.arange(n[0] * ppc[0]), np.arange(n[1] * ppc[1]), indexing="ij")
+    x = (gx.ravel() + 0.5) / ppc[0] * d[0]
+    y = (gy.ravel() + 0.5) / ppc[1] * d[1]
+    L = n[0] * d[0]
+    k = 2 * np.pi / L
+    ux = 0.001 * np.sin(k * x)
+    sp = O.Species(q=-1.0, m=1.0, x=[x, y], u=[ux, np.zeros_like(x), np.zeros_like(x)],
+                   w0=1.0 / 16)
+    st = O.State.zeros(g)
+    st.species.append(sp)
+    nsteps = 400
+    xs = (np.arange(n[0]) + 0.5) * d[0]  # E_x stagger
+    sig = []
+    for _ in range(nsteps):
+        O.step(st)
+        ex = st.E[0][0, 0, :]
+        sig.append((ex * np.sin(k * xs)).sum())
+    sig = np.array(sig)
+    t = dt * (np.arange(nsteps) + 1)
+    ws = np.linspace(0.9, 1.1, 4001)
+    resid = [np.linalg.lstsq(np.c_[np.sin(w * t), np.cos(w * t)], sig, rcond=None)[1].sum()
+             for w in ws]
+    best = ws[int(np.argmin(resid))]
+    expect = 2 / dt * math.asin(dt / 2)
+    assert abs(best / expect - 1) < 0.01
+
+
+# ------------------------------------------------------------------ sort
+
+def brute_force_order(n, tile, cells):
+    dim = len(cells)
+    seen = {}
+    keys = []
+    for p in range(len(cells[0])):
+        c = tuple(int(cells[a][p]) for a in range(dim))
+        r = seen.get(c, 0)
+        seen[c] = r + 1
+        nt = [n[a] // tile[a] for a in range(dim)]
+        t = 0
+        loc = 0
+        for a in reversed(range(dim)):
+            t = t * nt[a] + c[a] // tile[a]
+            loc = loc * tile[a] + c[a] % tile[a]
+        keys.append((t, r, loc, p))
+    keys.sort()
+    return [k[3] for k in keys], [k[0] for k in keys]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sort_matches_brute_force(dim):
+    rng = np.random.default_rng(9)
+    n = (16, 8) if dim == 2 else (8, 8, 4)
+    tile = (4, 4) if dim == 2 else (4, 2, 2)
+    g = O.Grid(dim, n, (1.0,) * dim, 0.1, 2)
+    N = 700
+    # clustered cells: duplicates, empty tiles
+    cells = [rng.integers(0, n[a] // 2, N).astype(np.int32) for a in range(dim)]
+    perm, start = O.sort(g, tile, cells)
+    ref, tiles = brute_force_order(n, tile, cells)
+    assert list(perm) == ref
+    assert sorted(perm) == list(range(N))
+    ntiles = int(np.prod([n[a] // tile[a] for a in range(dim)]))
+    counts = np.bincount(tiles, minlength=ntiles)
+    assert list(start) == [0] + list(np.cumsum(counts))
+
+
+def test_sort_empty_input():
+    g = O.Grid(2, (8, 8), (1.0, 1.0), 0.1, 2)
+    perm, start = O.sort(g, (4, 4), [np.zeros(0, np.int32), np.zeros(0, np.int32)])
+    assert len(perm) == 0 and list(start) == [0] * 5

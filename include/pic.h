@@ -1,0 +1,192 @@
+/*
+ * pic.h -- C ABI of libpic, the MI355X (gfx950) hot path of a fully
+ * relativistic electromagnetic particle-in-cell step.
+ *
+ * Method: Song, Wang & Li, "YUNIC: A Multi-Dimensional Particle-In-Cell Code
+ * for Laser-Plasma Interaction", arXiv:2104.00642:
+ *   - field solver: Yee staggered grid, leapfrog FDTD (Sec. II.B, Eqs. 9-10),
+ *     applied as two half updates per step so that fields and particles exist
+ *     at the same times (Sec. II.F);
+ *   - particle pusher: Boris (Sec. II.C, Eqs. 11-16);
+ *   - field interpolation with cell-integrated shape weights (Sec. II.D,
+ *     Eqs. 17-19), the same shape for gather and deposit (Sec. II.E);
+ *   - Esirkepov charge-conserving current deposit (Sec. II.E, Eqs. 20-22);
+ *   - Monte-Carlo nonlinear Compton / Breit-Wheeler (Sec. IV, Eqs. 23-24).
+ *
+ * UNITS.  Every argument is in the normalized units of Sec. II.A (Eq. 8):
+ * time in 1/w_r, length in c/w_r, E and B in m_e c w_r / e, momentum
+ * u = p/m in units of c, charge in e, mass in m_e, density and macro-particle
+ * weight in n_r = m_e w_r^2 / (4 pi e^2), current in c e n_r.  Then
+ * dE/dt = curl B - J and div E = rho.
+ *
+ * GRID AND FIELD LAYOUT (device memory, caller-owned).  One plane per field
+ * component, n[0]*n[1]*n[2] elements, element (i,j,k) at i + n0*(j + n1*k),
+ * no guard cells, periodic in every axis.  Yee stagger (array index i of a
+ * component staggered along an axis sits at (i + 1/2) * d):
+ *   E_x, J_x: (1/2,0,0)  E_y, J_y: (0,1/2,0)  E_z, J_z: (0,0,1/2)
+ *   B_x: (0,1/2,1/2)     B_y: (1/2,0,1/2)     B_z: (1/2,1/2,0)
+ * In 2D3V (dim 2) n[2] = 1, the z offsets are dropped and d/dz = 0.
+ * Field element type: float (PIC_FP32_MIXED) or double (PIC_FP64_PLAIN).
+ *
+ * PARTICLES (device memory, caller-owned, structure of arrays).
+ *   PIC_FP32_MIXED: int32 packed cell index  cell = ix | iy << bx | iz << (bx+by)
+ *     with bx = ceil(log2 n[0]), by = ceil(log2 n[1]) (pic_get_layout), float
+ *     in-cell offsets off[a] in [0,1) (position x_a = (i_a + off_a) d_a), float
+ *     momenta u[3], optional float weight w.
+ *   PIC_FP64_PLAIN: double absolute positions x[a] in [0, n[a] d[a]), double
+ *     momenta u[3], optional double weight w.
+ * Positions and momenta are at the same full step n (Sec. II.F).
+ *
+ * STREAMS.  `stream` is a hipStream_t passed as void* (NULL = default
+ * stream).  Calls only enqueue work; they return before it finishes.  Arrays
+ * must stay alive until the stream is synchronized.
+ *
+ * ERRORS.  Argument and configuration errors are found before anything is
+ * enqueued and returned as a pic_status with a message in pic_last_error().
+ * HIP launch failures give PIC_E_HIP.  Data-dependent conditions seen by the
+ * kernels set bits of a device status word read (and cleared) by pic_check().
+ * Nothing aborts and no C++ exception crosses the ABI.  A context is not
+ * thread-safe; several contexts may coexist.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_E_ARG = 1,          /* null or inconsistent argument                */
+    PIC_E_CFL = 2,          /* dt above the Courant limit                   */
+    PIC_E_UNSUPPORTED = 3,  /* order / dim / bc / precision not built       */
+    PIC_E_NOMEM = 4,        /* device allocation of context scratch failed  */
+    PIC_E_HIP = 5,          /* a HIP runtime call or launch failed          */
+    PIC_E_CAPACITY = 6,     /* pic_check: particle creation hit capacity    */
+    PIC_E_STATE = 7         /* pic_check: bad particle data was seen        */
+} pic_status;
+
+enum { PIC_FP32_MIXED = 0, PIC_FP64_PLAIN = 1 };
+enum { PIC_BC_PERIODIC = 0 };
+
+/* Status-word bits reported by pic_check. */
+enum {
+    PIC_F_NONFINITE = 1u,   /* NaN/Inf momentum or offset on input           */
+    PIC_F_OFFSET = 2u,      /* FP32 offset outside [0,1) or cell out of grid */
+    PIC_F_STRAGGLER = 4u,   /* particle outside its tile window (handled by
+                               the global-memory path; sort more often)      */
+    PIC_F_CAPACITY = 8u     /* QED creation beyond capacity (events dropped) */
+};
+
+typedef struct {
+    int32_t dim;            /* 2 = 2D3V, 3 = 3D3V                                     */
+    int32_t order;          /* 1 = linear (CIC) weights, 2 = quadratic (Sec. II.D)     */
+    int32_t precision;      /* PIC_FP32_MIXED or PIC_FP64_PLAIN                       */
+    int32_t drift;          /* FP32 path: cells a particle may leave its tile between
+                               sorts and still use the LDS window (0..4; default 2)  */
+    int64_t n[3];           /* cells per axis; n[2] = 1 when dim = 2                  */
+    double d[3];            /* cell sizes (c/w_r)                                     */
+    double dt;              /* step (1/w_r); PIC_E_CFL unless dt*sqrt(sum 1/d^2) <= 1  */
+    int32_t bc[3];          /* PIC_BC_PERIODIC (fields and particles)                 */
+    int32_t tile[3];        /* FP32 path tile in cells (must divide n); 0 = default   */
+    uint64_t seed;          /* key of the counter-based generator (QED)               */
+    double hbar_omega_mc2;  /* hbar w_r / (m_e c^2) for chi (2.4263e-6 at 1 um);
+                               0 disables the chi output of the push                  */
+} pic_config;
+
+typedef struct {
+    double q;               /* charge (e)                                   */
+    double m;               /* mass (m_e)                                   */
+    double w0;              /* weight used when the particle w is NULL (n_r) */
+} pic_species;
+
+typedef struct {
+    int64_t n;              /* live particles                                          */
+    int32_t *cell;          /* FP32: packed cell                                       */
+    float *off[3];          /* FP32: in-cell offsets                                   */
+    double *x[3];           /* FP64: absolute positions                                */
+    void *u[3];             /* float* (FP32) or double* (FP64)                         */
+    void *w;                /* nullable; float* or double*                             */
+    float *chi;             /* nullable; chi at step n+1/2 written by the push (FP32)  */
+    int64_t *tile_start;    /* FP32 path: ntiles+1 offsets of the tile-sorted order,
+                               written by pic_sort and read by the push               */
+} pic_particles;
+
+typedef struct {
+    void *E[3];
+    void *B[3];
+    void *J[3];
+} pic_fields;
+
+/* Create a context for one grid and step (validates the configuration and
+ * allocates the context's scratch).  Errors: PIC_E_ARG, PIC_E_CFL,
+ * PIC_E_UNSUPPORTED, PIC_E_NOMEM, PIC_E_HIP; *out is NULL on error and
+ * pic_last_error(NULL) holds the message. */
+pic_status pic_init(const pic_config *cfg, void **out);
+void pic_destroy(void *ctx);
+const char *pic_last_error(const void *ctx);
+
+/* Packed-cell layout and tiling chosen by pic_init: bits[3] per-axis field
+ * widths of the packed cell, tile[3] tile size in cells, *ntiles number of
+ * tiles (tile_start needs ntiles+1 entries). */
+pic_status pic_get_layout(const void *ctx, int32_t bits[3], int32_t tile[3], int64_t *ntiles);
+
+/*
+ * Gather + Boris push + move + Esirkepov deposit for every particle of one
+ * species (Secs. II.C-E), in the order of Sec. II.F:
+ *   gamma = sqrt(1+|u|^2); x_h = x^n + dt u^n/(2 gamma)            (time n+1/2)
+ *   E, B gathered at x_h with each component's staggered weights  (Eq. 19)
+ *   Boris with gamma^{n+1/2} from u^-                              (Eqs. 13-16)
+ *   v = u^{n+1}/gamma^{n+1}; x^{n+1} = x_h + dt v/2; deposit of the straight
+ *   move x_h -> x_h + dt v (Eq. 12) into J                        (Eqs. 20-22)
+ * fields->E, fields->B hold E^{n+1/2}, B^{n+1/2} (read only); fields->J is
+ * ACCUMULATED into (the caller zeroes it once per step before the first
+ * species).  Particles are updated in place and wrapped periodically.
+ * FP32 path: particles must be in the order of the last pic_sort (tile_start
+ * valid); particles that left their tile by more than `drift` cells are
+ * still pushed correctly through global memory and flagged PIC_F_STRAGGLER.
+ * diag (nullable, device double[4]) receives += {sum w m (gamma^{n+1}-1) dV,
+ * sum q w dV, -, -} computed in FP64 in a fixed order.  When chi is non-NULL
+ * and hbar_omega_mc2 > 0 it receives chi_e of Sec. IV at the fields of x_h
+ * and u^{n+1/2} = (u^n + u^{n+1})/2.
+ */
+pic_status pic_gather_push_deposit(void *ctx, const pic_species *sp, const pic_particles *p,
+                                   const pic_fields *fields, double *diag, void *stream);
+
+/*
+ * Half field update (Sec. II.B Eqs. 9-10 split as in Sec. II.F):
+ *   half = 1:  E += (dt/2)(curl B - J);  B -= (dt/2) curl E
+ *   half = 2:  B -= (dt/2) curl E;       E += (dt/2)(curl B - J)
+ * A step is half 1 (J = J^n), the particle push (J^{n+1}), half 2.
+ * diag (nullable, device double[4]) receives diag[2] += 1/2 sum(E^2+B^2) dV
+ * of the fields after the update (FP64, fixed order) when half = 2.
+ */
+pic_status pic_yee_step(void *ctx, int32_t half, const pic_fields *fields, double *diag,
+                        void *stream);
+
+/*
+ * Tile binning (FP32 path).  Writes src's particles into dst in the order
+ * (tile, rank of the particle among those of its cell in src order, cell
+ * within the tile), and dst->tile_start[0..ntiles] (first index of each tile).
+ * Tiles are tile[0] x tile[1] (x tile[2]) blocks of cells numbered
+ * x-fastest; cells within a tile likewise.  dst arrays must hold src->n
+ * elements and may not alias src.  Every non-NULL src array (cell, off, u,
+ * w, chi) is permuted into the matching dst array.  Bit-exact and
+ * deterministic.
+ */
+pic_status pic_sort(void *ctx, const pic_particles *src, const pic_particles *dst, void *stream);
+
+/* Synchronize `stream`, return the device status word in *flags (nullable)
+ * and the number of straggler particles since the last check in
+ * *stragglers (nullable), then clear both.  Returns PIC_E_CAPACITY if
+ * PIC_F_CAPACITY is set, else PIC_E_STATE if NONFINITE or OFFSET is set,
+ * else PIC_OK. */
+pic_status pic_check(void *ctx, void *stream, uint32_t *flags, uint64_t *stragglers);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

@@ -1,0 +1,286 @@
+"""ctypes binding of libpic (include/pic.h): argument marshalling only.
+
+Every function here has the name of the C entry point it wraps and takes
+torch tensors (device memory) for the arrays; it converts them to raw
+pointers, passes the current HIP stream, and raises ``PicError`` on a
+non-OK status.  All computation happens in the HIP kernels of the library.
+Loading fails loudly when ``libpic.so`` is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpic.so")
+
+PIC_OK, PIC_E_ARG, PIC_E_CFL, PIC_E_UNSUPPORTED, PIC_E_NOMEM, PIC_E_HIP, PIC_E_CAPACITY, PIC_E_STATE = range(8)
+STATUS_NAMES = ["PIC_OK", "PIC_E_ARG", "PIC_E_CFL", "PIC_E_UNSUPPORTED", "PIC_E_NOMEM", "PIC_E_HIP",
+                "PIC_E_CAPACITY", "PIC_E_STATE"]
+PIC_FP32_MIXED, PIC_FP64_PLAIN = 0, 1
+PIC_BC_PERIODIC = 0
+PIC_F_NONFINITE, PIC_F_OFFSET, PIC_F_STRAGGLER, PIC_F_CAPACITY = 1, 2, 4, 8
+
+EXPORTED = ["pic_init", "pic_destroy", "pic_last_error", "pic_get_layout", "pic_gather_push_deposit",
+            "pic_yee_step", "pic_sort", "pic_check"]
+
+
+class PicError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {msg}")
+
+
+class pic_config(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("order", C.c_int32), ("precision", C.c_int32),
+                ("drift", C.c_int32), ("n", C.c_int64 * 3), ("d", C.c_double * 3),
+                ("dt", C.c_double), ("bc", C.c_int32 * 3), ("tile", C.c_int32 * 3),
+                ("seed", C.c_uint64), ("hbar_omega_mc2", C.c_double)]
+
+
+class pic_species(C.Structure):
+    _fields_ = [("q", C.c_double), ("m", C.c_double), ("w0", C.c_double)]
+
+
+class pic_particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("cell", C.c_void_p), ("off", C.c_void_p * 3),
+                ("x", C.c_void_p * 3), ("u", C.c_void_p * 3), ("w", C.c_void_p),
+                ("chi", C.c_void_p), ("tile_start", C.c_void_p)]
+
+
+class pic_fields(C.Structure):
+    _fields_ = [("E", C.c_void_p * 3), ("B", C.c_void_p * 3), ("J", C.c_void_p * 3)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2104_00642_amd.build` "
+                               "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        L.pic_init.argtypes = [C.POINTER(pic_config), C.POINTER(C.c_void_p)]
+        L.pic_init.restype = C.c_int
+        L.pic_destroy.argtypes = [C.c_void_p]
+        L.pic_destroy.restype = None
+        L.pic_last_error.argtypes = [C.c_void_p]
+        L.pic_last_error.restype = C.c_char_p
+        L.pic_get_layout.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int64)]
+        L.pic_get_layout.restype = C.c_int
+        L.pic_gather_push_deposit.argtypes = [C.c_void_p, C.POINTER(pic_species), C.POINTER(pic_particles),
+                                              C.POINTER(pic_fields), C.c_void_p, C.c_void_p]
+        L.pic_gather_push_deposit.restype = C.c_int
+        L.pic_yee_step.argtypes = [C.c_void_p, C.c_int32, C.POINTER(pic_fields), C.c_void_p, C.c_void_p]
+        L.pic_yee_step.restype = C.c_int
+        L.pic_sort.argtypes = [C.c_void_p, C.POINTER(pic_particles), C.POINTER(pic_particles), C.c_void_p]
+        L.pic_sort.restype = C.c_int
+        L.pic_check.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)]
+        L.pic_check.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_contiguous(), "arrays must be contiguous"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return None
+    return C.c_void_p(int(stream))
+
+
+# ----------------------------------------------------------------- containers
+
+@dataclass
+class Config:
+    """Mirror of pic_config (units of Eq. 8 of the paper)."""
+    dim: int
+    n: tuple
+    d: tuple
+    dt: float
+    order: int = 2
+    precision: int = PIC_FP32_MIXED
+    drift: int = 2
+    tile: tuple = (0, 0, 0)
+    seed: int = 0
+    hbar_omega_mc2: float = 0.0
+
+    def c(self) -> pic_config:
+        cfg = pic_config()
+        cfg.dim, cfg.order, cfg.precision, cfg.drift = self.dim, self.order, self.precision, self.drift
+        n = list(self.n) + [1] * (3 - len(self.n))
+        d = list(self.d) + [1.0] * (3 - len(self.d))
+        t = list(self.tile) + [0] * (3 - len(self.tile))
+        for a in range(3):
+            cfg.n[a], cfg.d[a], cfg.tile[a], cfg.bc[a] = int(n[a]), float(d[a]), int(t[a]), PIC_BC_PERIODIC
+        cfg.dt = float(self.dt)
+        cfg.seed = int(self.seed)
+        cfg.hbar_omega_mc2 = float(self.hbar_omega_mc2)
+        return cfg
+
+    @property
+    def ncell(self):
+        n = list(self.n) + [1] * (3 - len(self.n))
+        return n[0] * n[1] * n[2]
+
+    @property
+    def plane_shape(self):
+        n = list(self.n) + [1] * (3 - len(self.n))
+        return (n[2], n[1], n[0])
+
+
+@dataclass
+class Species:
+    q: float
+    m: float
+    w0: float = 1.0
+
+    def c(self) -> pic_species:
+        return pic_species(self.q, self.m, self.w0)
+
+
+@dataclass
+class Particles:
+    """Structure of arrays of one species (torch tensors on the device).
+    FP32 path: cell (int32 packed), off[dim] (float32), u[3] (float32), w, chi,
+    tile_start (int64, ntiles+1).  FP64 path: x[dim] (float64), u[3], w, chi."""
+    n: int
+    u: list
+    cell: Optional[torch.Tensor] = None
+    off: list = field(default_factory=list)
+    x: list = field(default_factory=list)
+    w: Optional[torch.Tensor] = None
+    chi: Optional[torch.Tensor] = None
+    tile_start: Optional[torch.Tensor] = None
+
+    def c(self) -> pic_particles:
+        p = pic_particles()
+        p.n = int(self.n)
+        p.cell = _ptr(self.cell)
+        for a, t in enumerate(self.off):
+            p.off[a] = _ptr(t)
+        for a, t in enumerate(self.x):
+            p.x[a] = _ptr(t)
+        for a, t in enumerate(self.u):
+            p.u[a] = _ptr(t)
+        p.w = _ptr(self.w)
+        p.chi = _ptr(self.chi)
+        p.tile_start = _ptr(self.tile_start)
+        return p
+
+    def empty_like(self) -> "Particles":
+        e = lambda t: None if t is None else torch.empty_like(t)  # noqa: E731
+        return Particles(self.n, [e(t) for t in self.u], e(self.cell), [e(t) for t in self.off],
+                         [e(t) for t in self.x], e(self.w), e(self.chi), e(self.tile_start))
+
+
+@dataclass
+class Fields:
+    E: list
+    B: list
+    J: list
+
+    def c(self) -> pic_fields:
+        f = pic_fields()
+        for a in range(3):
+            f.E[a], f.B[a], f.J[a] = _ptr(self.E[a]), _ptr(self.B[a]), _ptr(self.J[a])
+        return f
+
+    @staticmethod
+    def zeros(cfg: Config, device, dtype):
+        z = lambda: [torch.zeros(cfg.plane_shape, device=device, dtype=dtype) for _ in range(3)]  # noqa: E731
+        return Fields(z(), z(), z())
+
+
+# -------------------------------------------------------------- entry points
+
+class Context:
+    def __init__(self, handle: int, cfg: Config):
+        self.handle = handle
+        self.cfg = cfg
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                lib().pic_destroy(C.c_void_p(self.handle))
+            except Exception:
+                pass
+            self.handle = None
+
+
+def _check(status: int, ctx_handle):
+    if status != PIC_OK:
+        msg = lib().pic_last_error(ctx_handle)
+        raise PicError(status, msg.decode() if msg else "")
+
+
+def pic_init(cfg: Config) -> Context:
+    h = C.c_void_p()
+    c = cfg.c()
+    st = lib().pic_init(C.byref(c), C.byref(h))
+    _check(st, None)
+    return Context(h.value, cfg)
+
+
+def pic_destroy(ctx: Context):
+    if ctx.handle:
+        lib().pic_destroy(C.c_void_p(ctx.handle))
+        ctx.handle = None
+
+
+def pic_last_error(ctx: Optional[Context]) -> str:
+    r = lib().pic_last_error(C.c_void_p(ctx.handle) if ctx else None)
+    return r.decode() if r else ""
+
+
+def pic_get_layout(ctx: Context):
+    bits = (C.c_int32 * 3)()
+    tile = (C.c_int32 * 3)()
+    nt = C.c_int64()
+    _check(lib().pic_get_layout(C.c_void_p(ctx.handle), bits, tile, C.byref(nt)), C.c_void_p(ctx.handle))
+    return list(bits), list(tile), nt.value
+
+
+def pic_gather_push_deposit(ctx: Context, sp: Species, p: Particles, f: Fields,
+                            diag: Optional[torch.Tensor] = None, stream=None):
+    sc, pc, fc = sp.c(), p.c(), f.c()
+    st = lib().pic_gather_push_deposit(C.c_void_p(ctx.handle), C.byref(sc), C.byref(pc), C.byref(fc),
+                                       _ptr(diag), _stream(stream))
+    _check(st, C.c_void_p(ctx.handle))
+
+
+def pic_yee_step(ctx: Context, half: int, f: Fields, diag: Optional[torch.Tensor] = None, stream=None):
+    fc = f.c()
+    st = lib().pic_yee_step(C.c_void_p(ctx.handle), int(half), C.byref(fc), _ptr(diag), _stream(stream))
+    _check(st, C.c_void_p(ctx.handle))
+
+
+def pic_sort(ctx: Context, src: Particles, dst: Particles, stream=None):
+    s, d = src.c(), dst.c()
+    st = lib().pic_sort(C.c_void_p(ctx.handle), C.byref(s), C.byref(d), _stream(stream))
+    _check(st, C.c_void_p(ctx.handle))
+
+
+def pic_check(ctx: Context, stream=None):
+    """Returns (status, flags, stragglers) without raising on data conditions."""
+    fl = C.c_uint32()
+    ns = C.c_uint64()
+    st = lib().pic_check(C.c_void_p(ctx.handle), _stream(stream), C.byref(fl), C.byref(ns))
+    if st not in (PIC_OK, PIC_E_STATE, PIC_E_CAPACITY):
+        _check(st, C.c_void_p(ctx.handle))
+    return st, fl.value, ns.value

@@ -1,0 +1,318 @@
+// abi.hip -- the extern "C" entry points of libpic: argument validation,
+// context lifetime, scratch management, launch dispatch.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "pic_internal.h"
+
+namespace pic {
+
+static thread_local std::string g_init_error;
+
+pic_status fail(Ctx *c, pic_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    else g_init_error = msg;
+    return s;
+}
+
+static pic_status hip_fail(Ctx *c, hipError_t e, const char *what) {
+    return fail(c, PIC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+pic_status ensure_partials(Ctx *c, size_t n) {
+    if (n <= c->partials_cap) return PIC_OK;
+    // work already queued may still read the old buffer
+    if (c->partials) {
+        hipDeviceSynchronize();
+        hipFree(c->partials);
+        c->partials = nullptr;
+        c->partials_cap = 0;
+    }
+    size_t cap = n + n / 4 + 64;
+    if (hipMalloc(&c->partials, cap * sizeof(double)) != hipSuccess) {
+        c->partials = nullptr;
+        return fail(c, PIC_E_NOMEM, "cannot allocate reduction partials");
+    }
+    c->partials_cap = cap;
+    return PIC_OK;
+}
+
+pic_status ensure_sort_scratch(Ctx *c, int64_t n) {
+    const int64_t items = 256 * 16;
+    const int64_t nblocks = (n + items - 1) / items;
+    const size_t hist_need = (size_t)(256 * nblocks + (256 * nblocks + items - 1) / items + 16);
+    if ((size_t)n <= c->sort_cap && hist_need <= c->hist_cap) return PIC_OK;
+    hipDeviceSynchronize();
+    for (int b = 0; b < 2; ++b) {
+        hipFree(c->keys[b]);
+        hipFree(c->vals[b]);
+        c->keys[b] = c->vals[b] = nullptr;
+    }
+    hipFree(c->hist);
+    hipFree(c->final_perm);
+    c->hist = c->final_perm = nullptr;
+    c->sort_cap = c->hist_cap = 0;
+    size_t cap = (size_t)n + (size_t)n / 8 + 1024;
+    size_t hcap = hist_need + hist_need / 8 + 1024;
+    bool ok = true;
+    for (int b = 0; b < 2; ++b) {
+        ok &= hipMalloc(&c->keys[b], cap * 4) == hipSuccess;
+        ok &= hipMalloc(&c->vals[b], cap * 4) == hipSuccess;
+    }
+    ok &= hipMalloc(&c->hist, hcap * 4) == hipSuccess;
+    ok &= hipMalloc(&c->final_perm, cap * 4) == hipSuccess;
+    if (!ok) return fail(c, PIC_E_NOMEM, "cannot allocate sort scratch");
+    c->sort_cap = cap;
+    c->hist_cap = hcap;
+    return PIC_OK;
+}
+
+hipError_t set_tiled_lds_limit(size_t bytes);
+
+}  // namespace pic
+
+using namespace pic;
+
+static int ceil_log2(int64_t v) {
+    int b = 0;
+    while ((1ll << b) < v) ++b;
+    return b;
+}
+
+static bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
+    if (!out) return fail(nullptr, PIC_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(nullptr, PIC_E_ARG, "config is NULL");
+    if (cfg->dim != 2 && cfg->dim != 3)
+        return fail(nullptr, PIC_E_UNSUPPORTED, "dim must be 2 (2D3V) or 3 (3D3V)");
+    if (cfg->order != 1 && cfg->order != 2)
+        return fail(nullptr, PIC_E_UNSUPPORTED, "order must be 1 (CIC) or 2 (quadratic)");
+    if (cfg->precision != PIC_FP32_MIXED && cfg->precision != PIC_FP64_PLAIN)
+        return fail(nullptr, PIC_E_UNSUPPORTED, "precision must be PIC_FP32_MIXED or PIC_FP64_PLAIN");
+    const int dim = cfg->dim;
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (a < dim) {
+            if (cfg->n[a] < 8 || cfg->n[a] > (1 << 20))
+                return fail(nullptr, PIC_E_ARG, "cells per axis must be in [8, 2^20]");
+            if (!finite_pos(cfg->d[a])) return fail(nullptr, PIC_E_ARG, "cell sizes must be > 0");
+            s += 1.0 / (cfg->d[a] * cfg->d[a]);
+            if (cfg->bc[a] != PIC_BC_PERIODIC)
+                return fail(nullptr, PIC_E_UNSUPPORTED, "only periodic boundaries are built");
+        } else if (cfg->n[a] != 1) {
+            return fail(nullptr, PIC_E_ARG, "n[2] must be 1 in 2D");
+        }
+    }
+    if (!finite_pos(cfg->dt)) return fail(nullptr, PIC_E_ARG, "dt must be > 0");
+    if (cfg->dt * sqrt(s) > 1.0 + 1e-12)
+        return fail(nullptr, PIC_E_CFL, "dt exceeds the Courant limit 1/sqrt(sum 1/d^2)");
+    // the deposit stencils assume a move shorter than one cell per axis with margin
+    for (int a = 0; a < dim; ++a)
+        if (cfg->dt / cfg->d[a] > 0.999)
+            return fail(nullptr, PIC_E_CFL, "dt / d above 0.999 on one axis (extreme cell aspect ratio)");
+    if (!(cfg->hbar_omega_mc2 >= 0.0) || !isfinite(cfg->hbar_omega_mc2))
+        return fail(nullptr, PIC_E_ARG, "hbar_omega_mc2 must be >= 0");
+    if (cfg->drift < 0 || cfg->drift > 4) return fail(nullptr, PIC_E_ARG, "drift must be in [0, 4]");
+
+    Ctx *c = new (std::nothrow) Ctx();
+    if (!c) return fail(nullptr, PIC_E_NOMEM, "cannot allocate context");
+    c->cfg = *cfg;
+    c->dim = dim;
+    c->drift = cfg->drift;
+    int64_t ncell = cfg->n[0] * cfg->n[1] * cfg->n[2];
+    int total_bits = 0;
+    for (int a = 0; a < 3; ++a) {
+        c->bits[a] = a < dim ? ceil_log2(cfg->n[a]) : 0;
+        total_bits += c->bits[a];
+    }
+    if (cfg->precision == PIC_FP32_MIXED && total_bits > 31) {
+        delete c;
+        return fail(nullptr, PIC_E_UNSUPPORTED, "packed cell index needs more than 31 bits");
+    }
+    if (ncell > (int64_t)1 << 31) {
+        delete c;
+        return fail(nullptr, PIC_E_UNSUPPORTED, "more than 2^31 cells");
+    }
+    c->ntiles = 1;
+    for (int a = 0; a < 3; ++a) {
+        int t = cfg->tile[a];
+        if (a >= dim) t = 1;
+        else if (t == 0) t = dim == 2 ? 16 : 8;
+        if (t < 1 || cfg->n[a] % t != 0) {
+            delete c;
+            return fail(nullptr, PIC_E_ARG, "tile size must divide the cell count on every axis");
+        }
+        c->tile[a] = t;
+        c->ntile_axis[a] = (int)(cfg->n[a] / t);
+        c->ntiles *= c->ntile_axis[a];
+        c->win[a] = a < dim ? t + 2 * c->drift + 5 : 1;
+        if (a < dim && c->win[a] > cfg->n[a] && cfg->precision == PIC_FP32_MIXED) {
+            delete c;
+            return fail(nullptr, PIC_E_UNSUPPORTED, "grid smaller than one tile window (tile + 2 drift + 5)");
+        }
+    }
+    if (c->tile[0] * c->tile[1] * c->tile[2] > 4096) {
+        delete c;
+        return fail(nullptr, PIC_E_UNSUPPORTED, "more than 4096 cells per tile");
+    }
+    c->lds_bytes = (size_t)9 * c->win[0] * c->win[1] * c->win[2] * sizeof(float);
+    if (cfg->precision == PIC_FP32_MIXED && c->lds_bytes + 8 * 1024 > 160 * 1024) {
+        delete c;
+        return fail(nullptr, PIC_E_UNSUPPORTED, "tile window does not fit in 160 KB of LDS");
+    }
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipMalloc(&c->status, 16);
+    if (e == hipSuccess) e = hipMemset(c->status, 0, 16);
+    if (e == hipSuccess && cfg->precision == PIC_FP32_MIXED && c->lds_bytes > 64 * 1024)
+        e = set_tiled_lds_limit(c->lds_bytes);
+    if (e != hipSuccess) {
+        pic_status st = hip_fail(nullptr, e, "pic_init");
+        if (c->status) hipFree(c->status);
+        delete c;
+        return st;
+    }
+    if (ensure_partials(c, 2 * (size_t)c->ntiles + 1024) != PIC_OK) {
+        g_init_error = c->err;
+        hipFree(c->status);
+        delete c;
+        return PIC_E_NOMEM;
+    }
+    *out = c;
+    return PIC_OK;
+}
+
+extern "C" void pic_destroy(void *ctx) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    hipFree(c->status);
+    hipFree(c->partials);
+    for (int b = 0; b < 2; ++b) {
+        hipFree(c->keys[b]);
+        hipFree(c->vals[b]);
+    }
+    hipFree(c->hist);
+    hipFree(c->final_perm);
+    delete c;
+}
+
+extern "C" const char *pic_last_error(const void *ctx) {
+    const Ctx *c = (const Ctx *)ctx;
+    return c ? c->err.c_str() : g_init_error.c_str();
+}
+
+extern "C" pic_status pic_get_layout(const void *ctx, int32_t bits[3], int32_t tile[3], int64_t *ntiles) {
+    const Ctx *c = (const Ctx *)ctx;
+    if (!c) return PIC_E_ARG;
+    for (int a = 0; a < 3; ++a) {
+        if (bits) bits[a] = c->bits[a];
+        if (tile) tile[a] = c->tile[a];
+    }
+    if (ntiles) *ntiles = c->ntiles;
+    return PIC_OK;
+}
+
+static pic_status check_fields(Ctx *c, const pic_fields *f) {
+    if (!f) return fail(c, PIC_E_ARG, "fields is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!f->E[a] || !f->B[a] || !f->J[a]) return fail(c, PIC_E_ARG, "a field plane is NULL");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_gather_push_deposit(void *ctx, const pic_species *sp, const pic_particles *p,
+                                              const pic_fields *fields, double *diag, void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (!sp || !p) return fail(c, PIC_E_ARG, "species or particles is NULL");
+    if (!(sp->m > 0.0) || !isfinite(sp->q) || !isfinite(sp->w0))
+        return fail(c, PIC_E_ARG, "species mass must be > 0 and charge/weight finite");
+    if (p->n < 0) return fail(c, PIC_E_ARG, "negative particle count");
+    pic_status st = check_fields(c, fields);
+    if (st != PIC_OK) return st;
+    for (int a = 0; a < 3; ++a)
+        if (!p->u[a]) return fail(c, PIC_E_ARG, "momentum array is NULL");
+    if (c->cfg.precision == PIC_FP32_MIXED) {
+        if (!p->cell || !p->tile_start) return fail(c, PIC_E_ARG, "cell or tile_start is NULL");
+        for (int a = 0; a < c->dim; ++a)
+            if (!p->off[a]) return fail(c, PIC_E_ARG, "offset array is NULL");
+        if (p->n >= ((int64_t)1 << 31)) return fail(c, PIC_E_UNSUPPORTED, "more than 2^31 particles");
+    } else {
+        for (int a = 0; a < c->dim; ++a)
+            if (!p->x[a]) return fail(c, PIC_E_ARG, "position array is NULL");
+    }
+    if (p->n == 0) return PIC_OK;
+    hipSetDevice(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = c->cfg.precision == PIC_FP32_MIXED ? launch_gpd_tiled(c, sp, p, fields, diag, s)
+                                                      : launch_gpd_plain(c, sp, p, fields, diag, s);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_gather_push_deposit");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_yee_step(void *ctx, int32_t half, const pic_fields *fields, double *diag,
+                                   void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (half != 1 && half != 2) return fail(c, PIC_E_ARG, "half must be 1 or 2");
+    pic_status st = check_fields(c, fields);
+    if (st != PIC_OK) return st;
+    hipSetDevice(c->device);
+    hipError_t e = launch_yee(c, half, fields, diag, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_yee_step");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_sort(void *ctx, const pic_particles *src, const pic_particles *dst,
+                               void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (c->cfg.precision != PIC_FP32_MIXED)
+        return fail(c, PIC_E_UNSUPPORTED, "pic_sort works on the FP32 particle layout");
+    if (!src || !dst) return fail(c, PIC_E_ARG, "src or dst is NULL");
+    if (src->n < 0 || src->n >= ((int64_t)1 << 31)) return fail(c, PIC_E_ARG, "bad particle count");
+    if (!dst->tile_start) return fail(c, PIC_E_ARG, "dst->tile_start is NULL");
+    if (src->n > 0) {
+        if (!src->cell || !dst->cell) return fail(c, PIC_E_ARG, "cell array is NULL");
+        if (src->cell == dst->cell) return fail(c, PIC_E_ARG, "src and dst alias");
+        for (int a = 0; a < c->dim; ++a)
+            if (!src->off[a] || !dst->off[a]) return fail(c, PIC_E_ARG, "offset array is NULL");
+        for (int a = 0; a < 3; ++a)
+            if (!src->u[a] || !dst->u[a]) return fail(c, PIC_E_ARG, "momentum array is NULL");
+        if ((src->w != nullptr) != (dst->w != nullptr) && src->w)
+            return fail(c, PIC_E_ARG, "src has weights but dst has none");
+        if (src->chi && !dst->chi) return fail(c, PIC_E_ARG, "src has chi but dst has none");
+    }
+    hipSetDevice(c->device);
+    if (src->n > 0) {
+        pic_status st = ensure_sort_scratch(c, src->n);
+        if (st != PIC_OK) return st;
+    }
+    hipError_t e = launch_sort(c, src, dst, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_sort");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_check(void *ctx, void *stream, uint32_t *flags, uint64_t *stragglers) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    hipSetDevice(c->device);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_check: stream synchronize");
+    uint32_t h[4] = {0, 0, 0, 0};
+    e = hipMemcpy(h, c->status, 16, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemset(c->status, 0, 16);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_check: status word");
+    if (flags) *flags = h[0];
+    if (stragglers) *stragglers = (uint64_t)h[2] | ((uint64_t)h[3] << 32);
+    if (h[0] & PIC_F_CAPACITY) return fail(c, PIC_E_CAPACITY, "particle creation hit capacity");
+    if (h[0] & (PIC_F_NONFINITE | PIC_F_OFFSET))
+        return fail(c, PIC_E_STATE, "non-finite momentum or offset outside [0,1) seen");
+    return PIC_OK;
+}

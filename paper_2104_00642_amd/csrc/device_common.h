@@ -1,0 +1,94 @@
+// device_common.h -- device-side building blocks shared by the HIP kernels:
+// shape weights (Sec. II.D, Eqs. 17-18), Boris rotation (Sec. II.C,
+// Eqs. 13-16) and the Esirkepov stencil weights (Sec. II.E, Eqs. 20-22),
+// templated on the real type so the FP32 and FP64 paths use one definition.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+// Component staggers in half cells: E_x, E_y, E_z, B_x, B_y, B_z (Yee cell,
+// Sec. II.B).  sx/sy/sz[c] is 1 when component c sits half a cell up that axis.
+__host__ __device__ constexpr int stag(int comp, int axis) {
+    // rows: Ex Ey Ez Bx By Bz ; columns x y z
+    return (comp == 0 && axis == 0) || (comp == 1 && axis == 1) || (comp == 2 && axis == 2) ||
+                   (comp == 3 && axis != 0) || (comp == 4 && axis != 1) ||
+                   (comp == 5 && axis != 2)
+               ? 1
+               : 0;
+}
+
+// Cell-integrated shape weights of order ORDER at position xi (cell units,
+// stagger already subtracted): first node *i0 and ORDER+1 weights.
+//   ORDER 1: integral of the unit top-hat -> (1-d, d) on floor(xi), floor(xi)+1
+//   ORDER 2: integral of the triangle S_2 (Eq. 17) -> quadratic spline on the
+//            nearest node and its two neighbours.
+template <int ORDER, typename R>
+__device__ __forceinline__ void shape_weights(R xi, int &i0, R *w) {
+    if constexpr (ORDER == 1) {
+        R f = floor(xi);
+        R d = xi - f;
+        i0 = (int)f;
+        w[0] = R(1) - d;
+        w[1] = d;
+    } else {
+        R ic = floor(xi + R(0.5));
+        R d = xi - ic;
+        i0 = (int)ic - 1;
+        R a = R(0.5) - d, b = R(0.5) + d;
+        w[0] = R(0.5) * a * a;
+        w[1] = R(0.75) - d * d;
+        w[2] = R(0.5) * b * b;
+    }
+}
+
+// Boris push (Eqs. 13-16): u += q_m dt E/2; rotate about B with
+// t = q_m dt B / (2 gamma(u^-)); u += q_m dt E/2.  `h` = q_m dt / 2.
+template <typename R>
+__device__ __forceinline__ void boris(R h, const R *E, const R *B, R *u) {
+    R um0 = u[0] + h * E[0], um1 = u[1] + h * E[1], um2 = u[2] + h * E[2];
+    R ig = R(1) / sqrt(R(1) + um0 * um0 + um1 * um1 + um2 * um2);
+    R t0 = h * B[0] * ig, t1 = h * B[1] * ig, t2 = h * B[2] * ig;
+    R f = R(2) / (R(1) + t0 * t0 + t1 * t1 + t2 * t2);
+    R s0 = f * t0, s1 = f * t1, s2 = f * t2;
+    R p0 = um0 + (um1 * t2 - um2 * t1);
+    R p1 = um1 + (um2 * t0 - um0 * t2);
+    R p2 = um2 + (um0 * t1 - um1 * t0);
+    u[0] = um0 + (p1 * s2 - p2 * s1) + h * E[0];
+    u[1] = um1 + (p2 * s0 - p0 * s2) + h * E[1];
+    u[2] = um2 + (p0 * s1 - p1 * s0) + h * E[2];
+}
+
+// Esirkepov stencil along one axis: S0 (weights at the start of the move),
+// DS = S1 - S0, on ORDER+2 nodes from *base = min of the two supports.
+// xh, xe are start/end positions in cell units relative to any integer origin
+// (integer nodes, no stagger); |xe - xh| < 1.
+template <int ORDER, typename R>
+__device__ __forceinline__ void esirkepov_axis(R xh, R xe, int &base, R *S0, R *DS) {
+    constexpr int L = ORDER + 2;
+    R wh[ORDER + 1], we[ORDER + 1];
+    int ih, ie;
+    shape_weights<ORDER>(xh, ih, wh);
+    shape_weights<ORDER>(xe, ie, we);
+    base = ih < ie ? ih : ie;
+    const int oh = ih - base, oe = ie - base;  // 0 or 1
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        R a = R(0), b = R(0);
+#pragma unroll
+        for (int m = 0; m <= ORDER; ++m) {
+            a = (k == m + oh) ? wh[m] : a;
+            b = (k == m + oe) ? we[m] : b;
+        }
+        S0[k] = a;
+        DS[k] = b - a;
+    }
+}
+
+__device__ __forceinline__ int wrap_index(int i, int n) {
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+}  // namespace pic

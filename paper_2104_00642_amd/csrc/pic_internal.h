@@ -1,0 +1,54 @@
+// pic_internal.h -- context structure and launcher declarations of libpic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/pic.h"
+
+namespace pic {
+
+struct Ctx {
+    pic_config cfg;
+    int dim = 2;
+    int bits[3] = {0, 0, 0};     // packed-cell field widths
+    int tile[3] = {1, 1, 1};     // tile size (cells)
+    int ntile_axis[3] = {1, 1, 1};
+    int64_t ntiles = 1;
+    int win[3] = {1, 1, 1};      // LDS window (cells) of the FP32 push
+    int drift = 2;
+    size_t lds_bytes = 0;
+    int device = 0;
+    // device status: [0] flags, [2..3] straggler count (uint64 at byte 8)
+    uint32_t *status = nullptr;
+    // FP64 block partials of the diagnostics reductions
+    double *partials = nullptr;
+    size_t partials_cap = 0;     // in doubles
+    // sort scratch (grown on demand)
+    uint32_t *keys[2] = {nullptr, nullptr};
+    uint32_t *vals[2] = {nullptr, nullptr};
+    uint32_t *hist = nullptr;
+    uint32_t *final_perm = nullptr;
+    size_t sort_cap = 0;         // elements
+    size_t hist_cap = 0;         // entries
+    std::string err;
+};
+
+// error helpers
+pic_status fail(Ctx *c, pic_status s, const std::string &msg);
+pic_status ensure_partials(Ctx *c, size_t n);
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_gpd_plain(Ctx *c, const pic_species *sp, const pic_particles *p,
+                            const pic_fields *f, double *diag, hipStream_t s);
+hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *p,
+                            const pic_fields *f, double *diag, hipStream_t s);
+hipError_t launch_yee(Ctx *c, int half, const pic_fields *f, double *diag, hipStream_t s);
+hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *dst,
+                       hipStream_t s);
+hipError_t launch_finalize(const double *partials, int64_t nblocks, int nval, double *diag,
+                           int diag_offset, double scale, hipStream_t s);
+
+}  // namespace pic

@@ -1,0 +1,347 @@
+// sort.hip -- tile binning of the FP32 particles (pic_sort).
+//
+// Order produced: (tile, rank of the particle among those of its cell in the
+// source order, cell within the tile).  Steps:
+//   1. key = tile * cells_per_tile + cell_in_tile, value = source index;
+//   2. stable LSD radix sort of (key, value), 8-bit digits: per-block digit
+//      histograms, one device-wide exclusive scan, stable scatter (ranks
+//      inside a wavefront from 8 ballots, across wavefronts from an LDS
+//      prefix), so equal keys keep source order;
+//   3. tile_start from the key boundaries;
+//   4. per tile (one workgroup): cell counts, then layer r = 0,1,... of the
+//      r-th particles of each populated cell, cells ascending;
+//   5. gather every particle array into the destination.
+// All integer work: the permutation is deterministic and bit-exact.
+#include "device_common.h"
+#include "pic_internal.h"
+
+namespace pic {
+
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ROUNDS = 16;
+constexpr int SORT_ITEMS = SORT_THREADS * SORT_ROUNDS;  // keys per block
+
+struct SortGeom {
+    int dim;
+    int bx, by;
+    int tile[3];
+    int ntile_axis[3];
+    int ct;  // cells per tile
+};
+
+__global__ void __launch_bounds__(256) sort_keys_kernel(const int32_t *cell, int64_t n, SortGeom g,
+                                                        uint32_t *keys, uint32_t *vals) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t c = cell[p];
+    const int mx = (1 << g.bx) - 1, my = (1 << g.by) - 1;
+    const int ix = c & mx, iy = (c >> g.bx) & my, iz = g.dim == 3 ? (c >> (g.bx + g.by)) : 0;
+    const int tx = ix / g.tile[0], ty = iy / g.tile[1], tz = iz / g.tile[2];
+    const int lx = ix - tx * g.tile[0], ly = iy - ty * g.tile[1], lz = iz - tz * g.tile[2];
+    const uint32_t tile = (uint32_t)(tx + g.ntile_axis[0] * (ty + g.ntile_axis[1] * tz));
+    const uint32_t local = (uint32_t)(lx + g.tile[0] * (ly + g.tile[1] * lz));
+    keys[p] = tile * (uint32_t)g.ct + local;
+    vals[p] = (uint32_t)p;
+}
+
+__global__ void __launch_bounds__(SORT_THREADS) radix_hist_kernel(const uint32_t *keys, int64_t n,
+                                                                  int shift, uint32_t *hist,
+                                                                  int64_t nblocks) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t start = (int64_t)blockIdx.x * SORT_ITEMS;
+    for (int r = 0; r < SORT_ROUNDS; ++r) {
+        const int64_t i = start + r * SORT_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// ---- device-wide exclusive scan of uint32 (chunks of SORT_ITEMS) --------
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp, uint32_t &total) {
+    // tmp: 256 entries
+    const int t = threadIdx.x;
+    tmp[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        uint32_t add = t >= off ? tmp[t - off] : 0u;
+        __syncthreads();
+        tmp[t] += add;
+        __syncthreads();
+    }
+    total = tmp[255];
+    uint32_t incl = tmp[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(256) scan_sums_kernel(const uint32_t *a, int64_t n, uint32_t *sums) {
+    __shared__ uint32_t tmp[256];
+    const int64_t start = (int64_t)blockIdx.x * SORT_ITEMS;
+    uint32_t s = 0;
+    for (int r = 0; r < SORT_ROUNDS; ++r) {
+        const int64_t i = start + (int64_t)threadIdx.x * SORT_ROUNDS + r;
+        if (i < n) s += a[i];
+    }
+    uint32_t total;
+    block_exclusive_scan(s, tmp, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of `m` chunk sums in place
+__global__ void __launch_bounds__(256) scan_top_kernel(uint32_t *sums, int64_t m) {
+    __shared__ uint32_t tmp[256];
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < m; base += 256) {
+        const int64_t i = base + threadIdx.x;
+        uint32_t v = i < m ? sums[i] : 0u;
+        uint32_t total;
+        uint32_t ex = block_exclusive_scan(v, tmp, total);
+        if (i < m) sums[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ void __launch_bounds__(256) scan_apply_kernel(uint32_t *a, int64_t n, const uint32_t *sums) {
+    __shared__ uint32_t tmp[256];
+    const int64_t start = (int64_t)blockIdx.x * SORT_ITEMS;
+    uint32_t v[SORT_ROUNDS];
+    uint32_t s = 0;
+    for (int r = 0; r < SORT_ROUNDS; ++r) {
+        const int64_t i = start + (int64_t)threadIdx.x * SORT_ROUNDS + r;
+        v[r] = i < n ? a[i] : 0u;
+        s += v[r];
+    }
+    uint32_t total;
+    uint32_t ex = block_exclusive_scan(s, tmp, total) + sums[blockIdx.x];
+    for (int r = 0; r < SORT_ROUNDS; ++r) {
+        const int64_t i = start + (int64_t)threadIdx.x * SORT_ROUNDS + r;
+        if (i < n) a[i] = ex;
+        ex += v[r];
+    }
+}
+
+static hipError_t exclusive_scan(Ctx *c, uint32_t *a, int64_t n, uint32_t *sums, hipStream_t s) {
+    const int64_t nb = (n + SORT_ITEMS - 1) / SORT_ITEMS;
+    scan_sums_kernel<<<(unsigned)nb, 256, 0, s>>>(a, n, sums);
+    scan_top_kernel<<<1, 256, 0, s>>>(sums, nb);
+    scan_apply_kernel<<<(unsigned)nb, 256, 0, s>>>(a, n, sums);
+    (void)c;
+    return hipGetLastError();
+}
+
+// ---- stable scatter ------------------------------------------------------
+
+__global__ void __launch_bounds__(SORT_THREADS) radix_scatter_kernel(
+    const uint32_t *kin, const uint32_t *vin, int64_t n, int shift, const uint32_t *offs,
+    int64_t nblocks, uint32_t *kout, uint32_t *vout) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[SORT_THREADS / 64][256];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    base[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int64_t start = (int64_t)blockIdx.x * SORT_ITEMS;
+    for (int r = 0; r < SORT_ROUNDS; ++r) {
+        const int64_t i = start + r * SORT_THREADS + t;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+#pragma unroll
+        for (int w = 0; w < SORT_THREADS / 64; ++w) wcnt[w][t] = 0;
+        __syncthreads();
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+        const uint32_t cnt = (uint32_t)__popcll(peers);
+        if (valid && rank == 0) wcnt[wave][d] = cnt;
+        __syncthreads();
+        {
+            uint32_t run = base[t];
+#pragma unroll
+            for (int w = 0; w < SORT_THREADS / 64; ++w) {
+                const uint32_t c = wcnt[w][t];
+                wcnt[w][t] = run;
+                run += c;
+            }
+            base[t] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = wcnt[wave][d] + rank;
+            kout[pos] = key;
+            vout[pos] = vin[i];
+        }
+        __syncthreads();
+    }
+}
+
+// ---- tile boundaries -----------------------------------------------------
+
+__global__ void __launch_bounds__(256) tile_bounds_kernel(const uint32_t *keys, int64_t n, int ct,
+                                                          int64_t ntiles, int64_t *tile_start) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    const int64_t tprev = i == 0 ? -1 : (int64_t)(keys[i - 1] / (uint32_t)ct);
+    const int64_t tcur = i == n ? ntiles : (int64_t)(keys[i] / (uint32_t)ct);
+    for (int64_t t = tprev + 1; t <= tcur; ++t) tile_start[t] = i;
+}
+
+// ---- per-tile layer interleave ------------------------------------------
+
+__global__ void __launch_bounds__(256) interleave_kernel(const uint32_t *keys, const uint32_t *vals,
+                                                         const int64_t *tile_start, int ct,
+                                                         uint32_t *perm) {
+    extern __shared__ uint32_t sm[];
+    uint32_t *cnt = sm;         // ct
+    uint32_t *cst = sm + ct;    // ct: start of each cell's run in the tile
+    __shared__ uint32_t tmp[256];
+    __shared__ uint32_t maxc;
+    const int t = blockIdx.x;
+    const int64_t ts = tile_start[t], te = tile_start[t + 1];
+    if (ts == te) return;
+    for (int l = threadIdx.x; l < ct; l += blockDim.x) cnt[l] = 0;
+    if (threadIdx.x == 0) maxc = 0;
+    __syncthreads();
+    for (int64_t i = ts + threadIdx.x; i < te; i += blockDim.x) atomicAdd(&cnt[keys[i] % (uint32_t)ct], 1u);
+    __syncthreads();
+    // exclusive scan of counts (cells per thread: ct / 256, consecutive)
+    const int per = (ct + 255) / 256;
+    uint32_t loc = 0, mx = 0;
+    for (int q = 0; q < per; ++q) {
+        const int l = threadIdx.x * per + q;
+        if (l < ct) {
+            loc += cnt[l];
+            mx = max(mx, cnt[l]);
+        }
+    }
+    atomicMax(&maxc, mx);
+    uint32_t total;
+    uint32_t ex = block_exclusive_scan(loc, tmp, total);
+    for (int q = 0; q < per; ++q) {
+        const int l = threadIdx.x * per + q;
+        if (l < ct) {
+            cst[l] = ex;
+            ex += cnt[l];
+        }
+    }
+    __syncthreads();
+    // layers
+    uint32_t layer_base = 0;
+    const uint32_t layers = maxc;
+    for (uint32_t r = 0; r < layers; ++r) {
+        uint32_t f = 0;
+        for (int q = 0; q < per; ++q) {
+            const int l = threadIdx.x * per + q;
+            f += (l < ct && cnt[l] > r) ? 1u : 0u;
+        }
+        uint32_t lt;
+        uint32_t pos = block_exclusive_scan(f, tmp, lt);
+        for (int q = 0; q < per; ++q) {
+            const int l = threadIdx.x * per + q;
+            if (l < ct && cnt[l] > r) {
+                perm[ts + layer_base + pos] = vals[ts + cst[l] + r];
+                ++pos;
+            }
+        }
+        layer_base += lt;
+    }
+}
+
+// ---- permute ---------------------------------------------------------------
+
+struct PermArgs {
+    int64_t n;
+    const uint32_t *perm;
+    const int32_t *cell_in;
+    int32_t *cell_out;
+    const float *fin[8];
+    float *fout[8];
+    int nf;
+};
+
+__global__ void __launch_bounds__(256) permute_kernel(PermArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const uint32_t src = a.perm[i];
+    a.cell_out[i] = a.cell_in[src];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (q < a.nf) a.fout[q][i] = a.fin[q][src];
+}
+
+pic_status ensure_sort_scratch(Ctx *c, int64_t n);
+
+hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *dst, hipStream_t s) {
+    const int64_t n = src->n;
+    SortGeom g{};
+    g.dim = c->dim;
+    g.bx = c->bits[0];
+    g.by = c->bits[1];
+    for (int d = 0; d < 3; ++d) {
+        g.tile[d] = c->tile[d];
+        g.ntile_axis[d] = c->ntile_axis[d];
+    }
+    g.ct = c->tile[0] * c->tile[1] * c->tile[2];
+    if (n > 0) {
+        sort_keys_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src->cell, n, g, c->keys[0],
+                                                                     c->vals[0]);
+        int64_t ncell = c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2];
+        int bits = 0;
+        while ((1ll << bits) < ncell) ++bits;
+        const int passes = (bits + 7) / 8;
+        const int64_t nblocks = (n + SORT_ITEMS - 1) / SORT_ITEMS;
+        int cur = 0;
+        for (int pass = 0; pass < passes; ++pass) {
+            const int shift = 8 * pass;
+            radix_hist_kernel<<<(unsigned)nblocks, SORT_THREADS, 0, s>>>(c->keys[cur], n, shift,
+                                                                         c->hist, nblocks);
+            hipError_t e = exclusive_scan(c, c->hist, 256 * nblocks, c->hist + 256 * nblocks, s);
+            if (e != hipSuccess) return e;
+            radix_scatter_kernel<<<(unsigned)nblocks, SORT_THREADS, 0, s>>>(
+                c->keys[cur], c->vals[cur], n, shift, c->hist, nblocks, c->keys[cur ^ 1],
+                c->vals[cur ^ 1]);
+            cur ^= 1;
+        }
+        tile_bounds_kernel<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(c->keys[cur], n, g.ct,
+                                                                           c->ntiles, dst->tile_start);
+        interleave_kernel<<<(unsigned)c->ntiles, 256, 2 * g.ct * sizeof(uint32_t), s>>>(
+            c->keys[cur], c->vals[cur], dst->tile_start, g.ct, c->final_perm);
+        PermArgs pa{};
+        pa.n = n;
+        pa.perm = c->final_perm;
+        pa.cell_in = src->cell;
+        pa.cell_out = dst->cell;
+        int nf = 0;
+        for (int d = 0; d < c->dim; ++d) {
+            pa.fin[nf] = src->off[d];
+            pa.fout[nf++] = dst->off[d];
+        }
+        for (int d = 0; d < 3; ++d) {
+            pa.fin[nf] = (const float *)src->u[d];
+            pa.fout[nf++] = (float *)dst->u[d];
+        }
+        if (src->w) {
+            pa.fin[nf] = (const float *)src->w;
+            pa.fout[nf++] = (float *)dst->w;
+        }
+        if (src->chi) {
+            pa.fin[nf] = src->chi;
+            pa.fout[nf++] = dst->chi;
+        }
+        pa.nf = nf;
+        permute_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(pa);
+    } else {
+        tile_bounds_kernel<<<1, 256, 0, s>>>(c->keys[0], 0, g.ct, c->ntiles, dst->tile_start);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pic

@@ -1,0 +1,108 @@
+"""Step driver: the sequence of library calls that makes one PIC step.
+
+    pic_yee_step(half=1)                  E^n, B^n, J^n   -> E^{n+1/2}, B^{n+1/2}
+    J = 0
+    pic_gather_push_deposit(species ...)  particles n -> n+1, J^{n+1}
+    pic_yee_step(half=2)                  -> E^{n+1}, B^{n+1}
+    pic_sort every `sort_every` steps (FP32 layout)
+
+Orchestration only (Sec. II.F of the paper gives the order); every step runs
+in the library's kernels.
+"""
+from __future__ import annotations
+
+from typing import List, Optional
+
+import torch
+
+from . import _lib as L
+from .workloads import RawParticles, Workload, fields_for, to_fp32, to_fp64
+
+
+class Simulation:
+    def __init__(self, cfg: L.Config, species: List[L.Species], particles: List[L.Particles],
+                 fields: L.Fields, sort_every: int = 8, device="cuda"):
+        self.cfg = cfg
+        self.ctx = L.pic_init(cfg)
+        self.species = species
+        self.particles = particles
+        self.fields = fields
+        self.sort_every = max(1, int(sort_every))
+        self.device = device
+        self.fp32 = cfg.precision == L.PIC_FP32_MIXED
+        self.bits, self.tile, self.ntiles = L.pic_get_layout(self.ctx)
+        self.spare: List[Optional[L.Particles]] = []
+        if self.fp32:
+            for p in particles:
+                if p.tile_start is None:
+                    p.tile_start = torch.zeros(self.ntiles + 1, dtype=torch.int64, device=device)
+                self.spare.append(p.empty_like())
+        self.diag = torch.zeros(4, dtype=torch.float64, device=device)
+        self.step_index = 0
+        self.sorted_at = -1
+
+    @staticmethod
+    def from_workload(wl: Workload, precision=L.PIC_FP32_MIXED, device="cuda", sort_every=8,
+                      from_fp32=False, with_chi=False, drift=2, tile=None):
+        cfg = L.Config(**{**wl.cfg.__dict__})
+        cfg.precision = precision
+        cfg.drift = drift
+        if tile is not None:
+            cfg.tile = tile
+        ctx_probe = L.pic_init(cfg)
+        bits, _, _ = L.pic_get_layout(ctx_probe)
+        L.pic_destroy(ctx_probe)
+        dtype = torch.float32 if precision == L.PIC_FP32_MIXED else torch.float64
+        fields = fields_for(cfg, wl, device, dtype)
+        sps, parts = [], []
+        for q, m, raw in wl.species:
+            raw = RawParticles([c.to(device) for c in raw.cell], [o.to(device) for o in raw.off],
+                               [v.to(device) for v in raw.u], raw.w.to(device))
+            sps.append(L.Species(q, m, 1.0))
+            if precision == L.PIC_FP32_MIXED:
+                parts.append(to_fp32(raw, bits, with_chi=with_chi))
+            else:
+                parts.append(to_fp64(raw, cfg, from_fp32=from_fp32, with_chi=with_chi))
+        return Simulation(cfg, sps, parts, fields, sort_every=sort_every, device=device)
+
+    def sort(self):
+        for k, p in enumerate(self.particles):
+            dst = self.spare[k]
+            L.pic_sort(self.ctx, p, dst)
+            self.particles[k], self.spare[k] = dst, p
+        self.sorted_at = self.step_index
+
+    def step(self, with_diag: bool = False):
+        if self.fp32 and (self.sorted_at < 0 or self.step_index - self.sorted_at >= self.sort_every):
+            self.sort()
+        diag = self.diag if with_diag else None
+        L.pic_yee_step(self.ctx, 1, self.fields)
+        for j in self.fields.J:
+            j.zero_()
+        for sp, p in zip(self.species, self.particles):
+            L.pic_gather_push_deposit(self.ctx, sp, p, self.fields, diag)
+        L.pic_yee_step(self.ctx, 2, self.fields, diag)
+        self.step_index += 1
+
+    def check(self):
+        return L.pic_check(self.ctx)
+
+    def energy(self):
+        """Run-time diagnostics accumulated since the last reset: kinetic,
+        charge, field energy (FP64, from the last step with_diag)."""
+        return self.diag.cpu().tolist()
+
+    def positions64(self, k=0):
+        """Absolute FP64 positions of species k (for comparisons)."""
+        p = self.particles[k]
+        if not self.fp32:
+            return [x.clone() for x in p.x]
+        out = []
+        mask = [(1 << b) - 1 for b in self.bits]
+        cell = p.cell.to(torch.int64)
+        shift = 0
+        for a in range(self.cfg.dim):
+            c = (cell >> shift) & mask[a]
+            shift += self.bits[a]
+            out.append((c.to(torch.float64) + p.off[a].to(torch.float64)) * self.cfg.d[a])
+        return out

@@ -1,0 +1,256 @@
+"""Seeded synthetic inputs shaped like the paper's cases.
+
+Input generation only: cell occupancy, random in-cell positions, momenta,
+weights and initial fields.  Nothing here performs a step of the method; the
+same arrays feed the HIP library and the oracle.  All randomness comes from a
+``torch.Generator`` seeded explicitly, on the device the arrays are made on.
+
+Units are those of Eq. 8 of the paper.  With the laser frequency as the
+reference (w_r = w_L) the wavelength is 2 pi and the critical density is 1;
+with w_r = w_p the plasma density is 1.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Callable, Optional
+
+import torch
+
+from ._lib import PIC_FP32_MIXED, PIC_FP64_PLAIN, Config, Fields, Particles
+
+LAMBDA = 2.0 * math.pi  # laser wavelength in c / w_L
+
+
+def courant_dt(d, frac=0.95):
+    """frac times the Courant limit 1/sqrt(sum 1/d^2)."""
+    return frac / math.sqrt(sum(1.0 / v ** 2 for v in d))
+
+
+@dataclass
+class RawParticles:
+    """Particles as generated: integer cells (int64), FP64 in-cell offsets in
+    [0,1), FP64 momenta and weights."""
+    cell: list          # per axis, int64
+    off: list           # per axis, float64
+    u: list             # 3 x float64
+    w: torch.Tensor     # float64
+
+    @property
+    def n(self):
+        return self.u[0].numel()
+
+    def subset(self, idx):
+        return RawParticles([c[idx] for c in self.cell], [o[idx] for o in self.off],
+                            [v[idx] for v in self.u], self.w[idx])
+
+
+def plasma(cfg: Config, ppc: int, density: Callable, gen: torch.Generator, device,
+           uth: float = 0.0, ux_fn: Optional[Callable] = None) -> RawParticles:
+    """`ppc` particles in every cell whose density (a function of the cell's
+    x index, vectorised) is positive, uniform random positions in the cell,
+    Gaussian momenta of spread `uth` per component plus ux_fn(x) along x,
+    weight density/ppc (density in n_r)."""
+    dim = cfg.dim
+    n = list(cfg.n) + [1] * (3 - len(cfg.n))
+    ix = torch.arange(n[0], device=device)
+    dens_x = density(ix.to(torch.float64))
+    occupied = torch.nonzero(dens_x > 0).flatten()
+    nx_occ = occupied.numel()
+    ncell = nx_occ * n[1] * n[2]
+    N = ncell * ppc
+    # cells enumerated x-fastest over the occupied x range
+    lin = torch.arange(N, device=device, dtype=torch.int64) // ppc
+    cx = occupied[lin % nx_occ]
+    rest = lin // nx_occ
+    cy = rest % n[1]
+    cz = rest // n[1]
+    cells = [cx, cy, cz][:dim]
+    off = [torch.rand(N, generator=gen, device=device, dtype=torch.float64) for _ in range(dim)]
+    u = [torch.randn(N, generator=gen, device=device, dtype=torch.float64) * uth for _ in range(3)]
+    if ux_fn is not None:
+        u[0] = u[0] + ux_fn((cx.to(torch.float64) + off[0]) * cfg.d[0])
+    w = dens_x[cx] / ppc
+    return RawParticles(cells, off, u, w)
+
+
+def concat(parts):
+    return RawParticles([torch.cat([p.cell[a] for p in parts]) for a in range(len(parts[0].cell))],
+                        [torch.cat([p.off[a] for p in parts]) for a in range(len(parts[0].off))],
+                        [torch.cat([p.u[a] for p in parts]) for a in range(3)],
+                        torch.cat([p.w for p in parts]))
+
+
+def packed_cells(cells, bits):
+    c = cells[0].to(torch.int64)
+    if len(cells) > 1:
+        c = c | (cells[1].to(torch.int64) << bits[0])
+    if len(cells) > 2:
+        c = c | (cells[2].to(torch.int64) << (bits[0] + bits[1]))
+    return c.to(torch.int32)
+
+
+def to_fp32(raw: RawParticles, bits, with_w=True, with_chi=False) -> Particles:
+    """FP32 layout: packed int32 cell, float32 offsets (an offset that rounds
+    up to 1.0 is clamped to the largest float below 1), float32 u and w."""
+    off = []
+    one_minus = torch.tensor(1.0, dtype=torch.float32).nextafter(torch.tensor(0.0)).item()
+    for o in raw.off:
+        o32 = o.to(torch.float32)
+        off.append(torch.clamp(o32, max=one_minus).contiguous())
+    return Particles(
+        n=raw.n, u=[v.to(torch.float32).contiguous() for v in raw.u],
+        cell=packed_cells(raw.cell, bits).contiguous(), off=off,
+        w=raw.w.to(torch.float32).contiguous() if with_w else None,
+        chi=torch.zeros(raw.n, dtype=torch.float32, device=raw.w.device) if with_chi else None)
+
+
+def to_fp64(raw: RawParticles, cfg: Config, from_fp32: bool = False, with_w=True,
+            with_chi=False) -> Particles:
+    """FP64 layout: absolute x = (cell + offset) d.  With from_fp32 the offsets
+    and momenta are first rounded as in to_fp32, so both paths start from the
+    same physical state."""
+    xs, us = [], []
+    one_minus = torch.tensor(1.0, dtype=torch.float32).nextafter(torch.tensor(0.0)).item()
+    for a in range(cfg.dim):
+        o = raw.off[a]
+        if from_fp32:
+            o = torch.clamp(o.to(torch.float32), max=one_minus).to(torch.float64)
+        xs.append(((raw.cell[a].to(torch.float64) + o) * cfg.d[a]).contiguous())
+    for v in raw.u:
+        us.append((v.to(torch.float32).to(torch.float64) if from_fp32 else v).contiguous())
+    w = raw.w
+    if from_fp32:
+        w = w.to(torch.float32).to(torch.float64)
+    return Particles(n=raw.n, u=us, x=xs, w=w.contiguous() if with_w else None,
+                     chi=torch.zeros(raw.n, dtype=torch.float32, device=w.device) if with_chi else None)
+
+
+# --------------------------------------------------------------- the configs
+
+@dataclass
+class Workload:
+    name: str
+    cfg: Config
+    species: list          # (q, m, RawParticles)
+    E0: Optional[list] = None   # initial E planes (float64) or None = zero
+    B0: Optional[list] = None
+    steps: int = 0
+
+
+def langmuir_2d(seed=643, n=(64, 64), ppc=16, device="cpu", order=1, precision=PIC_FP64_PLAIN) -> Workload:
+    """2D3V periodic box, dx = dy = 0.05 c/w_p, 16 electrons per cell at
+    uniform random positions, Maxwellian thermal spread 0.01 c per component
+    plus a 0.001 c sinusoidal drift (Langmuir mode k = 2 pi / L_x), immobile
+    neutralizing ions (not represented), linear (CIC) weights, dt = 0.95 of the
+    Courant limit, 200 steps, FP64."""
+    d = (0.05, 0.05)
+    cfg = Config(dim=2, n=n, d=d, dt=courant_dt(d), order=order, precision=precision, seed=seed)
+    gen = torch.Generator(device=device).manual_seed(seed)
+    L = n[0] * d[0]
+    raw = plasma(cfg, ppc, lambda x: torch.ones_like(x), gen, device, uth=0.01,
+                 ux_fn=lambda x: 0.001 * torch.sin(2 * math.pi * x / L))
+    return Workload("langmuir_2d_64x64_cic", cfg, [(-1.0, 1.0, raw)], steps=200)
+
+
+def laser_fields(cfg: Config, device, a0: float, waist: float, x_start: float, n_cycles: int,
+                 circular: bool = False):
+    """A laser pulse already inside the box, moving along +x: transverse E and
+    the matching B (E_y = B_z, E_z = -B_y), Gaussian transverse profile of
+    waist `waist`, sin^2 field envelope over `n_cycles` periods starting at
+    x_start.  Linear polarisation along y with amplitude a0; circular with
+    a0 on each transverse component.  Sampled at each component's Yee
+    location.  Returns (E, B) as float64 planes."""
+    dim = cfg.dim
+    n = list(cfg.n) + [1] * (3 - len(cfg.n))
+    shape = (n[2], n[1], n[0])
+    k_i = torch.arange(n[2], device=device, dtype=torch.float64).view(-1, 1, 1)
+    j_i = torch.arange(n[1], device=device, dtype=torch.float64).view(1, -1, 1)
+    i_i = torch.arange(n[0], device=device, dtype=torch.float64).view(1, 1, -1)
+    length = n_cycles * LAMBDA
+    yc = n[1] * cfg.d[1] / 2
+    zc = n[2] * cfg.d[2] / 2 if dim == 3 else 0.0
+
+    def profile(sx, sy, sz, phase_shift):
+        x = (i_i + sx) * cfg.d[0]
+        y = (j_i + sy) * cfg.d[1]
+        r2 = (y - yc) ** 2
+        if dim == 3:
+            z = (k_i + sz) * cfg.d[2]
+            r2 = r2 + (z - zc) ** 2
+        xi = (x - x_start) / length
+        env = torch.where((xi >= 0) & (xi <= 1), torch.sin(math.pi * xi) ** 2, torch.zeros_like(xi))
+        return (a0 * env * torch.exp(-r2 / waist ** 2) * torch.sin(x + phase_shift)).expand(shape)
+
+    zero = lambda: torch.zeros(shape, device=device, dtype=torch.float64)  # noqa: E731
+    E = [zero(), profile(0, 0.5, 0, 0.0).contiguous(), zero()]
+    B = [zero(), zero(), profile(0.5, 0.5, 0, 0.0).contiguous()]
+    if circular:
+        E[2] = profile(0, 0, 0.5, math.pi / 2).contiguous()
+        B[1] = (-profile(0.5, 0, 0.5, math.pi / 2)).contiguous()
+    return E, B
+
+
+def laser_plasma_2d(seed=644, scale=1, device="cuda", ppc=32, order=2) -> Workload:
+    """2D3V laser-plasma case: 4096 x 2048 cells at 20 cells per laser
+    wavelength, linearly polarized Gaussian pulse a0 = 2 (waist 5 lambda,
+    10-cycle sin^2 envelope) moving into an underdense electron plasma of
+    density 0.01 n_c behind a 2-lambda linear ramp, 32 particles per cell,
+    quadratic weights, dt = 0.95 of the Courant limit.  The box is periodic;
+    the pulse starts in the vacuum gap [1, 11] lambda and the ramp spans
+    [12, 14] lambda.  `scale` divides both cell counts (same cell size)."""
+    n = (4096 // scale, 2048 // scale)
+    d = (LAMBDA / 20, LAMBDA / 20)
+    cfg = Config(dim=2, n=n, d=d, dt=courant_dt(d), order=order, seed=seed)
+    gen = torch.Generator(device=device).manual_seed(seed)
+    x0, x1 = 12 * LAMBDA, 14 * LAMBDA
+    if scale > 1:  # keep a plasma region on small boxes
+        x0, x1 = 0.3 * n[0] * d[0], 0.4 * n[0] * d[0]
+
+    def density(ix):
+        x = (ix + 0.5) * d[0]
+        return 0.01 * torch.clamp((x - x0) / (x1 - x0), 0.0, 1.0)
+
+    raw = plasma(cfg, ppc, density, gen, device)
+    xs = 1 * LAMBDA if scale == 1 else 0.02 * n[0] * d[0]
+    ncyc = 10 if scale == 1 else max(2, int(0.25 * n[0] * d[0] / LAMBDA))
+    E, B = laser_fields(cfg, device, a0=2.0, waist=5 * LAMBDA if scale == 1 else 0.2 * n[1] * d[1],
+                        x_start=xs, n_cycles=ncyc)
+    return Workload(f"laser_plasma_2d_{n[0]}x{n[1]}_ppc{ppc}_quadratic", cfg, [(-1.0, 1.0, raw)], E, B,
+                    steps=1000)
+
+
+def laser_plasma_3d(seed=645, scale=1, device="cuda", ppc=8, order=2, tile=(8, 8, 8)) -> Workload:
+    """3D3V laser-plasma case: 512 x 256 x 256 cells at 20 cells per
+    wavelength, electrons and protons (mass 1836) with 8 particles per cell
+    each at 0.05 n_c behind a 2-lambda ramp, circularly polarized pulse
+    a0 = 5 (waist 3 lambda, 10-cycle sin^2), quadratic weights.  Periodic box;
+    the pulse starts at x = 0 and overlaps the ramp.  `scale` divides the cell
+    counts."""
+    n = (512 // scale, 256 // scale, 256 // scale)
+    d = (LAMBDA / 20,) * 3
+    cfg = Config(dim=3, n=n, d=d, dt=courant_dt(d), order=order, seed=seed, tile=tile)
+    gen = torch.Generator(device=device).manual_seed(seed)
+    x0, x1 = 2 * LAMBDA, 4 * LAMBDA
+    if scale > 1:
+        x0, x1 = 0.1 * n[0] * d[0], 0.2 * n[0] * d[0]
+
+    def density(ix):
+        x = (ix + 0.5) * d[0]
+        return 0.05 * torch.clamp((x - x0) / (x1 - x0), 0.0, 1.0)
+
+    el = plasma(cfg, ppc, density, gen, device)
+    ion = plasma(cfg, ppc, density, gen, device)
+    E, B = laser_fields(cfg, device, a0=5.0, waist=3 * LAMBDA if scale == 1 else 0.2 * n[1] * d[1],
+                        x_start=0.0, n_cycles=10 if scale == 1 else 2, circular=True)
+    return Workload(f"laser_plasma_3d_{n[0]}x{n[1]}x{n[2]}_ppc{ppc}x2_quadratic", cfg,
+                    [(-1.0, 1.0, el), (1.0, 1836.0, ion)], E, B, steps=500)
+
+
+def fields_for(cfg: Config, wl: Workload, device, dtype) -> Fields:
+    f = Fields.zeros(cfg, device, dtype)
+    if wl.E0 is not None:
+        for a in range(3):
+            f.E[a].copy_(wl.E0[a].to(device=device, dtype=dtype))
+            f.B[a].copy_(wl.B0[a].to(device=device, dtype=dtype))
+    return f

@@ -17,3 +17,13 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def piclib():
+    """The built HIP library (built here only if nothing is built yet)."""
+    from paper_2104_00642_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2104_00642_amd import build
+        build.build()
+    return _lib.lib()

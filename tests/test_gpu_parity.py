@@ -1,0 +1,288 @@
+"""Parity of the HIP library with the FP64 oracle on seeded inputs small enough
+for the oracle, spanning several tiles with ragged tails.  Calls go through
+the C ABI (ctypes)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2104_00642_amd import _lib as L
+from paper_2104_00642_amd.workloads import courant_dt, to_fp32, to_fp64
+
+from _helpers import (DEV, np64, oracle_grid, oracle_species, periodic_dx, random_fields, random_raw,
+                      rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(2, 1), (2, 2), (3, 1), (3, 2)]
+
+
+def make_cfg(dim, order, precision, drift=2):
+    if dim == 2:
+        n, d, tile = (48, 40), (0.3, 0.25), (16, 8)
+    else:
+        n, d, tile = (24, 20, 18), (0.3, 0.25, 0.2), (8, 4, 6)
+    return L.Config(dim=dim, n=n, d=d, dt=courant_dt(d, 0.9), order=order, precision=precision,
+                    tile=tile, drift=drift, hbar_omega_mc2=2.4263e-6)
+
+
+def run_oracle_push(cfg, raw, E, B, q, m, from_fp32):
+    g = oracle_grid(cfg)
+    sp = oracle_species(cfg, raw, q, m, from_fp32)
+    F = [a.numpy().copy() for a in E] + [a.numpy().copy() for a in B]
+    J = [np.zeros(cfg.plane_shape) for _ in range(3)]
+    diag = np.zeros(2)
+    O.push(g, sp, F, J, diag)
+    return sp, J, diag
+
+
+def lengths(cfg):
+    return [cfg.n[a] * cfg.d[a] for a in range(cfg.dim)]
+
+
+@pytest.mark.parametrize("dim,order", CASES)
+def test_plain_fp64_push_matches_oracle(dim, order):
+    print(f"plain fp64 dim={dim} order={order}", flush=True)
+    cfg = make_cfg(dim, order, L.PIC_FP64_PLAIN)
+    raw = random_raw(cfg, 3001, seed=10 * dim + order)
+    E, B = random_fields(cfg, seed=dim + order)
+    q, m = -1.0, 1.0
+    sp_o, J_o, diag_o = run_oracle_push(cfg, raw, E, B, q, m, from_fp32=False)
+
+    ctx = L.pic_init(cfg)
+    p = to_fp64(raw, cfg)
+    p = L.Particles(p.n, [t.to(DEV) for t in p.u], x=[t.to(DEV) for t in p.x], w=p.w.to(DEV),
+                    chi=torch.zeros(p.n, device=DEV))
+    f = L.Fields([t.to(DEV) for t in E], [t.to(DEV) for t in B],
+                 [torch.zeros(cfg.plane_shape, dtype=torch.float64, device=DEV) for _ in range(3)])
+    diag = torch.zeros(4, dtype=torch.float64, device=DEV)
+    L.pic_gather_push_deposit(ctx, L.Species(q, m, 1.0), p, f, diag)
+    st, flags, _ = L.pic_check(ctx)
+    assert st == L.PIC_OK and flags == 0
+    for a in range(3):
+        assert np.allclose(np64(p.u[a]), sp_o.u[a], rtol=1e-12, atol=1e-12)
+    for a, Lx in enumerate(lengths(cfg)):
+        assert np.abs(periodic_dx(np64(p.x[a]), sp_o.x[a], Lx)).max() < 1e-12 * Lx
+    for a in range(3):
+        assert rel_l2(np64(f.J[a]), J_o[a]) < 1e-12
+    assert np64(diag)[:2] == pytest.approx(diag_o, rel=1e-12)
+
+
+def sorted_fp32_state(cfg, raw, E, B):
+    """Sort the FP32 particles on the GPU; return (ctx, particles, fields, perm_oracle)."""
+    ctx = L.pic_init(cfg)
+    bits, tile, ntiles = L.pic_get_layout(ctx)
+    p = to_fp32(raw, bits, with_chi=True)
+    p = L.Particles(p.n, [t.to(DEV) for t in p.u], cell=p.cell.to(DEV), off=[t.to(DEV) for t in p.off],
+                    w=p.w.to(DEV), chi=p.chi.to(DEV),
+                    tile_start=torch.zeros(ntiles + 1, dtype=torch.int64, device=DEV))
+    dst = p.empty_like()
+    L.pic_sort(ctx, p, dst)
+    perm, start = O.sort(oracle_grid(cfg), tile[: cfg.dim], [c.numpy() for c in raw.cell])
+    f = L.Fields([t.to(DEV, torch.float32) for t in E], [t.to(DEV, torch.float32) for t in B],
+                 [torch.zeros(cfg.plane_shape, dtype=torch.float32, device=DEV) for _ in range(3)])
+    return ctx, dst, f, perm, start, bits
+
+
+@pytest.mark.parametrize("dim,order", CASES)
+def test_sort_then_fp32_push_matches_oracle(dim, order):
+    print(f"tiled fp32 dim={dim} order={order}", flush=True)
+    cfg = make_cfg(dim, order, L.PIC_FP32_MIXED)
+    raw = random_raw(cfg, 5003, seed=20 * dim + order)
+    E, B = random_fields(cfg, seed=3 * dim + order)
+    # the FP32 path starts from the FP32-rounded fields
+    E = [e.to(torch.float32).to(torch.float64) for e in E]
+    B = [b.to(torch.float32).to(torch.float64) for b in B]
+    ctx, p, f, perm, start, bits = sorted_fp32_state(cfg, raw, E, B)
+    torch.cuda.synchronize()
+    # sort parity: bit-exact tile offsets and cell order
+    assert np.array_equal(p.tile_start.cpu().numpy(), start)
+    ref_cell = to_fp32(raw, bits).cell.numpy()[perm]
+    assert np.array_equal(p.cell.cpu().numpy(), ref_cell)
+
+    q, m = -1.0, 1.0
+    raw_sorted = raw.subset(torch.from_numpy(perm))
+    sp_o, J_o, diag_o = run_oracle_push(cfg, raw_sorted, E, B, q, m, from_fp32=True)
+    diag = torch.zeros(4, dtype=torch.float64, device=DEV)
+    L.pic_gather_push_deposit(ctx, L.Species(q, m, 1.0), p, f, diag)
+    st, flags, nstray = L.pic_check(ctx)
+    assert st == L.PIC_OK and flags == 0 and nstray == 0
+
+    # positions in cell units, momenta, current
+    mask = [(1 << b) - 1 for b in bits]
+    cell = p.cell.cpu().to(torch.int64)
+    shift = 0
+    for a, Lx in enumerate(lengths(cfg)):
+        c = ((cell >> shift) & mask[a]).numpy()
+        shift += bits[a]
+        x = (c + np64(p.off[a])) * cfg.d[a]
+        assert np.abs(periodic_dx(x, sp_o.x[a], Lx)).max() / cfg.d[a] < 2e-6
+        offs = np64(p.off[a])
+        assert offs.min() >= 0.0 and offs.max() < 1.0
+    for a in range(3):
+        ug = np64(p.u[a])
+        assert np.max(np.abs(ug - sp_o.u[a]) / (1.0 + np.abs(sp_o.u[a]))) < 2e-6
+    for a in range(3):
+        assert rel_l2(np64(f.J[a]), J_o[a]) < 1e-5, a
+    assert np64(diag)[:2] == pytest.approx(diag_o, rel=1e-5)
+
+
+@pytest.mark.parametrize("dim,order", [(2, 2), (3, 2)])
+def test_stragglers_take_the_global_path(dim, order):
+    """Particles far outside their tile window (no sort since they moved) are
+    still pushed exactly like the oracle and are counted."""
+    print(f"stragglers dim={dim}", flush=True)
+    cfg = make_cfg(dim, order, L.PIC_FP32_MIXED, drift=0)
+    raw = random_raw(cfg, 2001, seed=77 + dim)
+    E, B = random_fields(cfg, seed=9)
+    E = [e.to(torch.float32).to(torch.float64) for e in E]
+    B = [b.to(torch.float32).to(torch.float64) for b in B]
+    ctx, p, f, perm, start, bits = sorted_fp32_state(cfg, raw, E, B)
+    # move every third particle by +5 cells in x after the sort
+    raw_sorted = raw.subset(torch.from_numpy(perm))
+    idx = torch.arange(raw.n)[::3]
+    raw_sorted.cell[0][idx] = (raw_sorted.cell[0][idx] + 5) % cfg.n[0]
+    moved = to_fp32(raw_sorted, bits)
+    p.cell.copy_(moved.cell.to(DEV))
+    sp_o, J_o, _ = run_oracle_push(cfg, raw_sorted, E, B, -1.0, 1.0, from_fp32=True)
+    L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), p, f)
+    st, flags, nstray = L.pic_check(ctx)
+    assert flags & L.PIC_F_STRAGGLER and nstray > 0 and st == L.PIC_OK
+    for a in range(3):
+        ug = np64(p.u[a])
+        assert np.max(np.abs(ug - sp_o.u[a]) / (1.0 + np.abs(sp_o.u[a]))) < 2e-6
+        assert rel_l2(np64(f.J[a]), J_o[a]) < 1e-5
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
+def test_yee_half_steps_match_oracle(dim, precision):
+    print(f"yee dim={dim} prec={precision}", flush=True)
+    cfg = make_cfg(dim, 2, precision)
+    g = oracle_grid(cfg)
+    E, B = random_fields(cfg, seed=5)
+    gen = torch.Generator().manual_seed(6)
+    J = [torch.randn(cfg.plane_shape, generator=gen, dtype=torch.float64) * 0.3 for _ in range(3)]
+    dt = torch.float64 if precision == L.PIC_FP64_PLAIN else torch.float32
+    E = [e.to(dt).to(torch.float64) for e in E]
+    B = [b.to(dt).to(torch.float64) for b in B]
+    J = [j.to(dt).to(torch.float64) for j in J]
+    ctx = L.pic_init(cfg)
+    f = L.Fields([e.to(DEV, dt) for e in E], [b.to(DEV, dt) for b in B], [j.to(DEV, dt) for j in J])
+    Eo = [e.numpy().copy() for e in E]
+    Bo = [b.numpy().copy() for b in B]
+    Jo = [j.numpy().copy() for j in J]
+    diag = torch.zeros(4, dtype=torch.float64, device=DEV)
+    U = 0.0
+    for half in (1, 2, 1, 2):
+        L.pic_yee_step(ctx, half, f, diag if half == 2 else None)
+        if half == 1:
+            O.half_e(g, Eo, Bo, Jo)
+            O.half_b(g, Eo, Bo)
+        else:
+            O.half_b(g, Eo, Bo)
+            O.half_e(g, Eo, Bo, Jo)
+            U += O.field_energy(g, Eo, Bo)
+    tol = 1e-13 if precision == L.PIC_FP64_PLAIN else 2e-6
+    for a in range(3):
+        assert rel_l2(np64(f.E[a]), Eo[a]) < tol
+        assert rel_l2(np64(f.B[a]), Bo[a]) < tol
+    # diag[2] accumulates the field energy after each second half
+    assert np64(diag)[2] == pytest.approx(U, rel=max(tol, 1e-12) * 10)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_field_energy_diagnostic(dim):
+    cfg = make_cfg(dim, 2, L.PIC_FP64_PLAIN)
+    g = oracle_grid(cfg)
+    E, B = random_fields(cfg, seed=12)
+    Z = [torch.zeros(cfg.plane_shape, dtype=torch.float64) for _ in range(3)]
+    ctx = L.pic_init(cfg)
+    f = L.Fields([e.to(DEV) for e in E], [b.to(DEV) for b in B], [z.to(DEV) for z in Z])
+    Eo = [e.numpy().copy() for e in E]
+    Bo = [b.numpy().copy() for b in B]
+    diag = torch.zeros(4, dtype=torch.float64, device=DEV)
+    L.pic_yee_step(ctx, 2, f, diag)
+    O.half_b(g, Eo, Bo)
+    O.half_e(g, Eo, Bo, [z.numpy() for z in Z])
+    assert np64(diag)[2] == pytest.approx(O.field_energy(g, Eo, Bo), rel=1e-12)
+
+
+@pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097, 30011])
+def test_sort_bit_exact(n):
+    print(f"sort n={n}", flush=True)
+    cfg = make_cfg(2, 2, L.PIC_FP32_MIXED)
+    gen = torch.Generator().manual_seed(n + 3)
+    # clustered cells: duplicates and empty tiles
+    cells = [torch.randint(0, cfg.n[0] // 3, (n,), generator=gen),
+             torch.randint(0, cfg.n[1], (n,), generator=gen)]
+    raw = random_raw(cfg, n, seed=n, cells=cells)
+    ctx = L.pic_init(cfg)
+    bits, tile, ntiles = L.pic_get_layout(ctx)
+    p = to_fp32(raw, bits, with_chi=True)
+    p.chi = torch.arange(n, dtype=torch.float32)  # carries the source index through the sort
+    p = L.Particles(n, [t.to(DEV) for t in p.u], cell=p.cell.to(DEV), off=[t.to(DEV) for t in p.off],
+                    w=p.w.to(DEV), chi=p.chi.to(DEV),
+                    tile_start=torch.zeros(ntiles + 1, dtype=torch.int64, device=DEV))
+    dst = p.empty_like()
+    dst.tile_start.fill_(-7)
+    L.pic_sort(ctx, p, dst)
+    torch.cuda.synchronize()
+    perm, start = O.sort(oracle_grid(cfg), tile[:2], [c.numpy() for c in cells])
+    assert np.array_equal(dst.tile_start.cpu().numpy(), start)
+    assert np.array_equal(dst.chi.cpu().numpy().astype(np.int64), perm)
+    for a in range(2):
+        assert np.array_equal(dst.off[a].cpu().numpy(), p.off[a].cpu().numpy()[perm])
+    for a in range(3):
+        assert np.array_equal(dst.u[a].cpu().numpy(), p.u[a].cpu().numpy()[perm])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sort_3d_and_2d_many_particles(dim):
+    cfg = make_cfg(dim, 2, L.PIC_FP32_MIXED)
+    n = 200003
+    raw = random_raw(cfg, n, seed=99 + dim)
+    ctx = L.pic_init(cfg)
+    bits, tile, ntiles = L.pic_get_layout(ctx)
+    p = to_fp32(raw, bits)
+    p = L.Particles(n, [t.to(DEV) for t in p.u], cell=p.cell.to(DEV), off=[t.to(DEV) for t in p.off],
+                    w=p.w.to(DEV), tile_start=torch.zeros(ntiles + 1, dtype=torch.int64, device=DEV))
+    dst = p.empty_like()
+    L.pic_sort(ctx, p, dst)
+    torch.cuda.synchronize()
+    perm, start = O.sort(oracle_grid(cfg), tile[:dim], [c.numpy() for c in raw.cell])
+    assert np.array_equal(dst.tile_start.cpu().numpy(), start)
+    assert np.array_equal(dst.cell.cpu().numpy(), p.cell.cpu().numpy()[perm])
+    assert np.array_equal(dst.w.cpu().numpy(), p.w.cpu().numpy()[perm])
+
+
+@pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
+def test_multistep_run_matches_oracle(precision):
+    """20 whole steps (Yee halves, push, deposit, sorts) of a warm plasma in
+    FP64 and FP32 against the oracle's FP64 steps."""
+    print(f"multistep prec={precision}", flush=True)
+    from paper_2104_00642_amd.sim import Simulation
+    from paper_2104_00642_amd.workloads import Workload
+    cfg = make_cfg(2, 2, precision)
+    raw = random_raw(cfg, 4000, seed=5, uth=0.3)
+    E, B = random_fields(cfg, seed=8, amp=0.05)
+    wl = Workload("warm", cfg, [(-1.0, 1.0, raw)], E, B)
+    sim = Simulation.from_workload(wl, precision=precision, device=DEV, sort_every=4,
+                                   from_fp32=False)
+    st = O.State(oracle_grid(cfg), [e.numpy().copy() for e in E], [b.numpy().copy() for b in B],
+                 [np.zeros(cfg.plane_shape) for _ in range(3)])
+    if precision == L.PIC_FP32_MIXED:
+        st.E = [e.astype(np.float32).astype(np.float64) for e in st.E]
+        st.B = [b.astype(np.float32).astype(np.float64) for b in st.B]
+    st.species.append(oracle_species(cfg, raw, -1.0, 1.0, from_fp32=precision == L.PIC_FP32_MIXED))
+    for _ in range(20):
+        sim.step()
+        O.step(st)
+    torch.cuda.synchronize()
+    tol = 1e-10 if precision == L.PIC_FP64_PLAIN else 3e-4
+    for a in range(3):
+        assert rel_l2(np64(sim.fields.E[a]), st.E[a]) < tol
+        assert rel_l2(np64(sim.fields.B[a]), st.B[a]) < tol
+    assert sim.check()[0] == L.PIC_OK

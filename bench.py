@@ -1,0 +1,265 @@
+"""Throughput of the gather + push + deposit hot path on one MI355X.
+
+Workload: the 2D3V laser-plasma case (4096 x 2048 cells, 20 cells per laser
+wavelength, a0 = 2 linearly polarized pulse, n = 0.01 n_c electrons at 1 keV
+behind a 2-lambda ramp, 32 particles per cell, quadratic weights), synthetic
+and seeded.  A step is one whole pass of the path: Yee half step, J reset,
+gather-push-deposit of every particle, Yee half step, and the tile sort every
+`--sort-every` steps (FP32 path).  Both the FP32 mixed-precision path and the
+plain FP64 path run; `value` is the FP32 path's particle-steps/s over the
+timed steps (inputs resident in HBM), the FP64 path is reported beside it.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--sort-every", type=int, default=8)
+    ap.add_argument("--scale", type=int, default=1, help="divide the grid (tests only)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--tile", type=str, default="16,16")
+    ap.add_argument("--drift", type=int, default=2)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_bytes_per_particle(dim, real_bytes, ppc, with_w=True):
+    """Bytes the method must move per particle-step: the particle state read
+    and written once, each field cell read once (6 components) and each
+    current cell written once (3), spread over the particles of the cell."""
+    if real_bytes == 4:
+        s_read = 4 + 4 * dim + 12 + (4 if with_w else 0)
+        s_write = 4 + 4 * dim + 12
+    else:
+        s_read = 8 * dim + 24 + (8 if with_w else 0)
+        s_write = 8 * dim + 24
+    return s_read + s_write + 9 * real_bytes / ppc
+
+
+def run_path(args, wl, precision, torch, L, Simulation):
+    sim = Simulation.from_workload(wl, precision=precision, device="cuda",
+                                   sort_every=args.sort_every,
+                                   tile=tuple(int(v) for v in args.tile.split(",")), drift=args.drift)
+    n = sum(p.n for p in sim.particles)
+    for _ in range(args.warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    st, flags, stray = sim.check()
+    # timed region: whole steps; HIP events bracket each push launch on the
+    # library's stream (torch's current stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        sim.step(events=ev[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gpd_ms = [a.elapsed_time(b) for a, b in ev]
+    st, flags, stray = sim.check()
+    # one sort and one pair of Yee half steps on their own, for the breakdown
+    extra = {}
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if sim.fp32:
+        a.record()
+        sim.sort()
+        b.record()
+        torch.cuda.synchronize()
+        extra["sort_ms"] = a.elapsed_time(b)
+    a.record()
+    L.pic_yee_step(sim.ctx, 1, sim.fields)
+    L.pic_yee_step(sim.ctx, 2, sim.fields)
+    b.record()
+    torch.cuda.synchronize()
+    extra["yee_ms"] = a.elapsed_time(b)
+    extra["stragglers_per_step"] = stray / max(args.steps, 1)
+    return sim, n, (t1 - t0), gpd_ms, (st, flags, stray), extra
+
+
+def sampled_error(sim, torch, L, O, nsample=2000, seed=7):
+    """One more step on the GPU; the oracle pushes a random sample of the same
+    particles with the same half-step fields; returns max errors, and the
+    total-current consistency sum(J_x) vs sum q w v_x."""
+    import numpy as np
+    cfg = sim.cfg
+    g = O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order)
+    L.pic_yee_step(sim.ctx, 1, sim.fields)
+    for j in sim.fields.J:
+        j.zero_()
+    torch.cuda.synchronize()
+    F = [t.detach().to("cpu", torch.float64).numpy().copy() for t in list(sim.fields.E) + list(sim.fields.B)]
+    p = sim.particles[0]
+    gen = torch.Generator().manual_seed(seed)
+    idx = torch.randint(0, p.n, (nsample,), generator=gen)
+    idx_d = idx.to("cuda")
+    x0 = [t[idx_d].to("cpu", torch.float64).numpy() for t in sim.positions64(0)]
+    u0 = [t[idx_d].to("cpu", torch.float64).numpy() for t in p.u]
+    w0 = p.w[idx_d].to("cpu", torch.float64).numpy() if p.w is not None else None
+    sp = sim.species[0]
+    L.pic_gather_push_deposit(sim.ctx, sp, p, sim.fields)
+    torch.cuda.synchronize()
+    x1 = [t[idx_d].to("cpu", torch.float64).numpy() for t in sim.positions64(0)]
+    u1 = [t[idx_d].to("cpu", torch.float64).numpy() for t in p.u]
+    osp = O.Species(sp.q, sp.m, [a.copy() for a in x0], [a.copy() for a in u0],
+                    w0.copy() if w0 is not None else None, sp.w0)
+    Jd = [np.zeros(F[0].shape) for _ in range(3)]
+    O.push(g, osp, F, Jd)
+    du = max(float(np.max(np.abs(u1[a] - osp.u[a]) / (1 + np.abs(osp.u[a])))) for a in range(3))
+    dx = 0.0
+    for a in range(cfg.dim):
+        Lx = cfg.n[a] * cfg.d[a]
+        d = x1[a] - osp.x[a]
+        d = d - Lx * np.round(d / Lx)
+        dx = max(dx, float(np.max(np.abs(d))) / cfg.d[a])
+    # total current consistency over all particles (FP64 on the host)
+    jsum = [float(t.double().sum().item()) for t in sim.fields.J]
+    ux = p.u[0].double()
+    gam = torch.sqrt(1 + p.u[0].double() ** 2 + p.u[1].double() ** 2 + p.u[2].double() ** 2)
+    w = p.w.double() if p.w is not None else sp.w0
+    qwv = float((sp.q * w * ux / gam).sum().item())
+    qwv_abs = float((sp.q * w * ux / gam).abs().sum().item())
+    return {"sample": nsample, "u_max_rel": du, "x_max_cells": dx,
+            "sumJx_vs_sum_qwvx_rel": abs(jsum[0] - qwv) / max(qwv_abs, 1e-300)}
+
+
+def cpu_baseline(wl, O, target_s, log):
+    """The oracle's particle step (gather, Boris, move, deposit), single
+    threaded, on a random sample of the workload's particles with its
+    initial fields."""
+    import numpy as np
+    import torch
+    from paper_2104_00642_amd.workloads import to_fp64
+    cfg = wl.cfg
+    g = O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order)
+    F = [t.to("cpu", torch.float64).numpy().copy() for t in list(wl.E0) + list(wl.B0)]
+    q, m, raw = wl.species[0]
+    gen = torch.Generator().manual_seed(11)
+
+    def sample(k):
+        idx = torch.randint(0, raw.n, (k,), generator=gen).to(raw.w.device)
+        sub = raw.subset(idx)
+        p = to_fp64(sub, cfg)
+        return O.Species(q, m, [x.cpu().numpy().copy() for x in p.x], [u.cpu().numpy().copy() for u in p.u],
+                         p.w.cpu().numpy().copy())
+
+    J = [np.zeros(F[0].shape) for _ in range(3)]
+    sp = sample(20000)
+    t0 = time.perf_counter()
+    O.push(g, sp, F, J)
+    probe = time.perf_counter() - t0
+    k = int(min(2e7, max(2e4, 20000 * target_s / max(probe, 1e-6))))
+    sp = sample(k)
+    t0 = time.perf_counter()
+    O.push(g, sp, F, J)
+    el = time.perf_counter() - t0
+    log(f"cpu baseline: {k} particle-steps in {el:.2f}s")
+    return {"value": k / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} random particles of the workload, one oracle gather+push+deposit step each "
+                      f"(FP64, single thread), initial fields"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU domain decomposition is designed, not built)"}))
+        sys.exit(2)
+    import torch
+
+    import oracle as O
+    from paper_2104_00642_amd import _lib as L
+    from paper_2104_00642_amd.sim import Simulation
+    from paper_2104_00642_amd.workloads import laser_plasma_2d
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    log("generating workload")
+    wl = laser_plasma_2d(scale=args.scale, device="cuda")
+    ppc = 32
+    out = {}
+    for prec in ([L.PIC_FP32_MIXED] if args.no_fp64 else [L.PIC_FP32_MIXED, L.PIC_FP64_PLAIN]):
+        name = "fp32" if prec == L.PIC_FP32_MIXED else "fp64"
+        log(f"running {name} path")
+        sim, n, secs, gpd_ms, status, extra = run_path(args, wl, prec, torch, L, Simulation)
+        err = sampled_error(sim, torch, L, O)
+        rb = 4 if prec == L.PIC_FP32_MIXED else 8
+        bpp = alg_bytes_per_particle(2, rb, ppc)
+        gpd_avg = sum(gpd_ms) / len(gpd_ms)
+        achieved = n * bpp / (gpd_avg * 1e-3) / 1e9
+        out[name] = dict(n=n, secs=secs, gpd_ms=gpd_avg, gpd_ms_min=min(gpd_ms), err=err, status=status,
+                         bytes_per_particle=bpp, achieved_gbs=achieved, tile=sim.tile, ntiles=sim.ntiles,
+                         **extra)
+        log(name, json.dumps(out[name]))
+        del sim
+        torch.cuda.empty_cache()
+
+    r = out["fp32"]
+    value = r["n"] * args.steps / r["secs"]
+    line = {
+        "metric": "particle-steps/s (gather+push+deposit), FP32 vs FP64 plain, at stated error",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["secs"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded)",
+        "config": {"workload": "laser_plasma_2d_4096x2048_ppc32_quadratic" if args.scale == 1
+                   else f"laser_plasma_2d_scale{args.scale}",
+                   "particles": r["n"], "cells": [4096 // args.scale, 2048 // args.scale],
+                   "shape": "quadratic", "tile": r["tile"][:2], "sort_every": args.sort_every,
+                   "drift": args.drift, "parallelism": "single GPU"},
+        "gpd_only_particle_steps_per_s": r["n"] / (r["gpd_ms"] * 1e-3),
+        "gpd_ms_avg": r["gpd_ms"],
+        "breakdown_ms": {"gpd": r["gpd_ms"], "sort_once": r.get("sort_ms"), "yee_step": r.get("yee_ms"),
+                         "stragglers_per_step": r.get("stragglers_per_step")},
+        "roofline": {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "gpd_tiled_kernel<2,2>",
+                     "alg_bytes_per_particle": r["bytes_per_particle"]},
+        "error_vs_oracle": r["err"],
+    }
+    if "fp64" in out:
+        f = out["fp64"]
+        line["fp64_plain"] = {"value": f["n"] * args.steps / f["secs"],
+                              "ms_per_step": f["secs"] / args.steps * 1e3,
+                              "gpd_ms_avg": f["gpd_ms"],
+                              "roofline_frac": f["achieved_gbs"] / HBM_PEAK_GBS,
+                              "achieved_gbs": f["achieved_gbs"],
+                              "alg_bytes_per_particle": f["bytes_per_particle"],
+                              "error_vs_oracle": f["err"]}
+        line["speedup_fp32_vs_fp64_plain"] = value / line["fp64_plain"]["value"]
+    if not args.no_cpu:
+        log("cpu baseline")
+        line["cpu_baseline"] = cpu_baseline(wl, O, args.cpu_seconds, log)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,7 +143,7 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
     for (int a = 0; a < 3; ++a) {
         int t = cfg->tile[a];
         if (a >= dim) t = 1;
-        else if (t == 0) t = dim == 2 ? 16 : 8;
+        else if (t == 0) t = dim == 2 ? 16 : (a == 2 ? 4 : 8);
         if (t < 1 || cfg->n[a] % t != 0) {
             delete c;
             return fail(nullptr, PIC_E_ARG, "tile size must divide the cell count on every axis");
@@ -161,7 +161,8 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
         delete c;
         return fail(nullptr, PIC_E_UNSUPPORTED, "more than 4096 cells per tile");
     }
-    c->lds_bytes = (size_t)9 * c->win[0] * c->win[1] * c->win[2] * sizeof(float);
+    // fields: 6 float planes; current: 3 int64 planes (fixed point)
+    c->lds_bytes = (size_t)c->win[0] * c->win[1] * c->win[2] * (6 * sizeof(float) + 3 * sizeof(int64_t));
     if (cfg->precision == PIC_FP32_MIXED && c->lds_bytes + 8 * 1024 > 160 * 1024) {
         delete c;
         return fail(nullptr, PIC_E_UNSUPPORTED, "tile window does not fit in 160 KB of LDS");

@@ -8,9 +8,15 @@
 //      consecutive particles in distinct cells so that the LDS traffic of a
 //      wavefront spreads over distinct addresses): gather from LDS (Eq. 19),
 //      Boris (Eqs. 13-16), move (Eq. 12), Esirkepov current (Eqs. 20-22)
-//      accumulated with LDS float atomics,
+//      accumulated in an int64 fixed-point J window with LDS integer atomics,
 //   3. adds its J window to global J with one pass of coalesced global float
 //      atomics (neighbouring windows overlap in their guard cells).
+// The current window is integer because LDS float atomics (ds_add_f32) run an
+// order of magnitude slower than integer ones on gfx950.  Every contribution
+// is an FP32 value bounded by B = |q| w_max max(1, d/dt) (the running sums of
+// the Esirkepov weights stay within [-1, 1]); scaled by the power of two
+// S = 2^30 / B it converts exactly to an int32, and the int64 sums are exact
+// and independent of the order of the atomics.  The flush divides by S.
 // Particles are an int32 packed cell plus FP32 in-cell offsets, so every
 // weight is computed from a number in (-1.5, 2.5) and keeps full FP32
 // resolution regardless of the grid size.  A particle that has wandered more
@@ -49,21 +55,27 @@ struct TiledArgs {
     float qm_h;         // q/m dt/2
     float jfac[3];      // q d / dt
     float q;
+    float jmax;         // max(1, d/dt) over the axes
     double mdV, qdV;
     double *partials;
     uint32_t *status;
     unsigned long long *stragglers;
 };
 
-// Accessor of the LDS window: coordinates local to the window origin.
+// Accessor of the LDS window: coordinates local to the window origin.  Fields
+// are the first 6*wn floats of the dynamic LDS, the fixed-point current the
+// following 3*wn int64 words.
 struct LdsAcc {
     int wx, wxy, wn;
+    float scale;  // S of the fixed-point current
     __device__ __forceinline__ int idx(int i, int j, int k) const { return i + wx * j + wxy * k; }
     __device__ __forceinline__ float f(int c, int i, int j, int k) const {
         return pic_smem[c * wn + idx(i, j, k)];
     }
     __device__ __forceinline__ void add(int c, int i, int j, int k, float v) const {
-        atomicAdd(&pic_smem[(6 + c) * wn + idx(i, j, k)], v);
+        unsigned long long *jw = (unsigned long long *)(pic_smem + 6 * wn);
+        const long long q = (long long)(int)rintf(v * scale);
+        atomicAdd(&jw[c * wn + idx(i, j, k)], (unsigned long long)q);
     }
 };
 
@@ -247,6 +259,7 @@ __global__ void __launch_bounds__(256) gpd_tiled_kernel(TiledArgs a) {
     const int64_t pbeg = a.tile_start[t], pend = a.tile_start[t + 1];
     __shared__ double red_k[256], red_q[256];
     __shared__ unsigned int nstray;
+    __shared__ float wmax_s[256];
     if (pbeg >= pend) {
         if (threadIdx.x == 0) {
             a.partials[2 * t] = 0.0;
@@ -259,10 +272,11 @@ __global__ void __launch_bounds__(256) gpd_tiled_kernel(TiledArgs a) {
     const int tz = DIM == 3 ? t / (a.ntile_axis[0] * a.ntile_axis[1]) : 0;
     const int g = a.drift + 2;
     int org[3] = {tx * a.tile[0] - g, ty * a.tile[1] - g, DIM == 3 ? tz * a.tile[2] - g : 0};
-    LdsAcc lds{a.win[0], a.win[0] * a.win[1], a.win[0] * a.win[1] * a.win[2]};
+    LdsAcc lds{a.win[0], a.win[0] * a.win[1], a.win[0] * a.win[1] * a.win[2], 0.0f};
     const int wn = lds.wn;
+    unsigned long long *jwin = (unsigned long long *)(pic_smem + 6 * wn);
 
-    // 1. stage E/B window, zero the J window
+    // 1. stage E/B window, zero the J window, bound the weights of the tile
     for (int e = threadIdx.x; e < 6 * wn; e += blockDim.x) {
         const int c = e / wn;
         const int r = e - c * wn;
@@ -275,23 +289,60 @@ __global__ void __launch_bounds__(256) gpd_tiled_kernel(TiledArgs a) {
         const int gk = DIM == 3 ? wrap_index(org[2] + k, a.ng[2]) : 0;
         pic_smem[e] = a.F[c][(int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk)];
     }
-    for (int e = threadIdx.x; e < 3 * wn; e += blockDim.x) pic_smem[6 * wn + e] = 0.0f;
+    for (int e = threadIdx.x; e < 3 * wn; e += blockDim.x) jwin[e] = 0ull;
+    float wm = fabsf(a.w0);
+    if (a.w) {
+        wm = 0.0f;
+        for (int64_t p = pbeg + threadIdx.x; p < pend; p += blockDim.x) wm = fmaxf(wm, fabsf(a.w[p]));
+    }
+    wmax_s[threadIdx.x] = wm;
     if (threadIdx.x == 0) nstray = 0;
     __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) wmax_s[threadIdx.x] = fmaxf(wmax_s[threadIdx.x], wmax_s[threadIdx.x + h]);
+        __syncthreads();
+    }
+    {
+        // S = 2^(30 - ceil(log2 B)), B = |q| w_max max(1, d/dt): |contribution| * S <= 2^30
+        const float B = fabsf(a.q) * wmax_s[0] * a.jmax;
+        int ex = 0;
+        frexpf(B > 0.0f ? B : 1.0f, &ex);  // B < 2^ex
+        lds.scale = ldexpf(1.0f, 30 - ex);
+    }
 
-    // 2. particles of the tile
+    // 2. particles of the tile, next particle prefetched while one is pushed
     const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
     const int hi[3] = {a.win[0] - 4, a.win[1] - 4, a.win[2] - 4};
     double kin = 0.0, chg = 0.0;
     GlobAcc glob{{a.F[0], a.F[1], a.F[2], a.F[3], a.F[4], a.F[5]},
                  {a.J[0], a.J[1], a.J[2]},
                  {a.ng[0], a.ng[1], a.ng[2]}};
-    for (int64_t p = pbeg + threadIdx.x; p < pend; p += blockDim.x) {
-        const int32_t cell = a.cell[p];
+    int64_t p = pbeg + threadIdx.x;
+    int32_t n_cell = 0;
+    float n_f[3] = {0.0f, 0.0f, 0.0f}, n_u[3] = {0.0f, 0.0f, 0.0f}, n_w = a.w0;
+    if (p < pend) {
+        n_cell = a.cell[p];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) n_f[d] = a.off[d][p];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) n_u[d] = a.u[d][p];
+        if (a.w) n_w = a.w[p];
+    }
+    for (; p < pend; p += blockDim.x) {
+        const int32_t cell = n_cell;
+        float f[3] = {n_f[0], n_f[1], n_f[2]};
+        float u[3] = {n_u[0], n_u[1], n_u[2]};
+        const float w = n_w;
+        const int64_t pn = p + blockDim.x;
+        if (pn < pend) {
+            n_cell = a.cell[pn];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) n_f[d] = a.off[d][pn];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) n_u[d] = a.u[d][pn];
+            if (a.w) n_w = a.w[pn];
+        }
         int cc[3] = {cell & mx, (cell >> a.bx) & my, DIM == 3 ? (cell >> (a.bx + a.by)) : 0};
-        float f[3] = {a.off[0][p], a.off[1][p], DIM == 3 ? a.off[2][p] : 0.0f};
-        float u[3] = {a.u[0][p], a.u[1][p], a.u[2][p]};
-        const float w = a.w ? a.w[p] : a.w0;
         bool bad = false;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) bad |= !(f[d] >= 0.0f && f[d] < 1.0f) || cc[d] >= a.ng[d];
@@ -348,9 +399,11 @@ __global__ void __launch_bounds__(256) gpd_tiled_kernel(TiledArgs a) {
     __syncthreads();
 
     // 3. flush the J window into global J (periodic wrap), skip exact zeros
+    const double inv_scale = 1.0 / (double)lds.scale;
     for (int e = threadIdx.x; e < 3 * wn; e += blockDim.x) {
-        const float v = pic_smem[6 * wn + e];
-        if (v != 0.0f) {
+        const long long q = (long long)jwin[e];
+        if (q != 0) {
+            const float v = (float)((double)q * inv_scale);
             const int c = e / wn;
             const int r = e - c * wn;
             const int k = r / lds.wxy;
@@ -415,6 +468,9 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
     a.drift = c->drift;
     a.qm_h = (float)(0.5 * sp->q / sp->m * cfg.dt);
     a.q = (float)sp->q;
+    double jm = 1.0;
+    for (int d = 0; d < c->dim; ++d) jm = fmax(jm, cfg.d[d] / cfg.dt);
+    a.jmax = (float)jm;
     const double dV = cfg.d[0] * cfg.d[1] * (c->dim == 3 ? cfg.d[2] : 1.0);
     a.mdV = sp->m * dV;
     a.qdV = sp->q * dV;

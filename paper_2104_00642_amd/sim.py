@@ -72,15 +72,21 @@ class Simulation:
             self.particles[k], self.spare[k] = dst, p
         self.sorted_at = self.step_index
 
-    def step(self, with_diag: bool = False):
+    def step(self, with_diag: bool = False, events=None):
+        """One step; `events` = (start, end) torch events recorded on the
+        current stream around the gather-push-deposit launches."""
         if self.fp32 and (self.sorted_at < 0 or self.step_index - self.sorted_at >= self.sort_every):
             self.sort()
         diag = self.diag if with_diag else None
         L.pic_yee_step(self.ctx, 1, self.fields)
         for j in self.fields.J:
             j.zero_()
+        if events is not None:
+            events[0].record()
         for sp, p in zip(self.species, self.particles):
             L.pic_gather_push_deposit(self.ctx, sp, p, self.fields, diag)
+        if events is not None:
+            events[1].record()
         L.pic_yee_step(self.ctx, 2, self.fields, diag)
         self.step_index += 1
 

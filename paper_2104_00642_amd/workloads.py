@@ -191,14 +191,19 @@ def laser_fields(cfg: Config, device, a0: float, waist: float, x_start: float, n
     return E, B
 
 
-def laser_plasma_2d(seed=644, scale=1, device="cuda", ppc=32, order=2) -> Workload:
+ME_KEV = 510.99895  # electron rest energy
+
+
+def laser_plasma_2d(seed=644, scale=1, device="cuda", ppc=32, order=2, t_kev=1.0) -> Workload:
     """2D3V laser-plasma case: 4096 x 2048 cells at 20 cells per laser
     wavelength, linearly polarized Gaussian pulse a0 = 2 (waist 5 lambda,
     10-cycle sin^2 envelope) moving into an underdense electron plasma of
     density 0.01 n_c behind a 2-lambda linear ramp, 32 particles per cell,
     quadratic weights, dt = 0.95 of the Courant limit.  The box is periodic;
     the pulse starts in the vacuum gap [1, 11] lambda and the ramp spans
-    [12, 14] lambda.  `scale` divides both cell counts (same cell size)."""
+    [12, 14] lambda.  Electrons start with a Maxwellian spread of temperature
+    t_kev (1 keV as in the paper's 2D benchmark), so every particle carries
+    current from the first step.  `scale` divides both cell counts."""
     n = (4096 // scale, 2048 // scale)
     d = (LAMBDA / 20, LAMBDA / 20)
     cfg = Config(dim=2, n=n, d=d, dt=courant_dt(d), order=order, seed=seed)
@@ -211,7 +216,7 @@ def laser_plasma_2d(seed=644, scale=1, device="cuda", ppc=32, order=2) -> Worklo
         x = (ix + 0.5) * d[0]
         return 0.01 * torch.clamp((x - x0) / (x1 - x0), 0.0, 1.0)
 
-    raw = plasma(cfg, ppc, density, gen, device)
+    raw = plasma(cfg, ppc, density, gen, device, uth=math.sqrt(t_kev / ME_KEV))
     xs = 1 * LAMBDA if scale == 1 else 0.02 * n[0] * d[0]
     ncyc = 10 if scale == 1 else max(2, int(0.25 * n[0] * d[0] / LAMBDA))
     E, B = laser_fields(cfg, device, a0=2.0, waist=5 * LAMBDA if scale == 1 else 0.2 * n[1] * d[1],
@@ -220,13 +225,14 @@ def laser_plasma_2d(seed=644, scale=1, device="cuda", ppc=32, order=2) -> Worklo
                     steps=1000)
 
 
-def laser_plasma_3d(seed=645, scale=1, device="cuda", ppc=8, order=2, tile=(8, 8, 8)) -> Workload:
+def laser_plasma_3d(seed=645, scale=1, device="cuda", ppc=8, order=2, tile=(8, 8, 4),
+                    t_kev=1.0) -> Workload:
     """3D3V laser-plasma case: 512 x 256 x 256 cells at 20 cells per
     wavelength, electrons and protons (mass 1836) with 8 particles per cell
     each at 0.05 n_c behind a 2-lambda ramp, circularly polarized pulse
-    a0 = 5 (waist 3 lambda, 10-cycle sin^2), quadratic weights.  Periodic box;
-    the pulse starts at x = 0 and overlaps the ramp.  `scale` divides the cell
-    counts."""
+    a0 = 5 (waist 3 lambda, 10-cycle sin^2), quadratic weights, electrons and
+    ions at t_kev.  Periodic box; the pulse starts at x = 0 and overlaps the
+    ramp.  `scale` divides the cell counts."""
     n = (512 // scale, 256 // scale, 256 // scale)
     d = (LAMBDA / 20,) * 3
     cfg = Config(dim=3, n=n, d=d, dt=courant_dt(d), order=order, seed=seed, tile=tile)
@@ -239,8 +245,8 @@ def laser_plasma_3d(seed=645, scale=1, device="cuda", ppc=8, order=2, tile=(8, 8
         x = (ix + 0.5) * d[0]
         return 0.05 * torch.clamp((x - x0) / (x1 - x0), 0.0, 1.0)
 
-    el = plasma(cfg, ppc, density, gen, device)
-    ion = plasma(cfg, ppc, density, gen, device)
+    el = plasma(cfg, ppc, density, gen, device, uth=math.sqrt(t_kev / ME_KEV))
+    ion = plasma(cfg, ppc, density, gen, device, uth=math.sqrt(t_kev / ME_KEV / 1836.0))
     E, B = laser_fields(cfg, device, a0=5.0, waist=3 * LAMBDA if scale == 1 else 0.2 * n[1] * d[1],
                         x_start=0.0, n_cycles=10 if scale == 1 else 2, circular=True)
     return Workload(f"laser_plasma_3d_{n[0]}x{n[1]}x{n[2]}_ppc{ppc}x2_quadratic", cfg,

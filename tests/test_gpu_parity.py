@@ -23,7 +23,9 @@ def make_cfg(dim, order, precision, drift=2):
     if dim == 2:
         n, d, tile = (48, 40), (0.3, 0.25), (16, 8)
     else:
+        # the int64 current window of a 3D tile limits the drift allowance
         n, d, tile = (24, 20, 18), (0.3, 0.25, 0.2), (8, 4, 6)
+        drift = min(drift, 1)
     return L.Config(dim=dim, n=n, d=d, dt=courant_dt(d, 0.9), order=order, precision=precision,
                     tile=tile, drift=drift, hbar_omega_mc2=2.4263e-6)
 

@@ -31,13 +31,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--sort-every", type=int, default=8)
+    ap.add_argument("--sort-every", type=int, default=16)
     ap.add_argument("--scale", type=int, default=1, help="divide the grid (tests only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tile", type=str, default="16,16")
     ap.add_argument("--drift", type=int, default=2)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the run, copy a 1 GiB float32 buffer (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -255,6 +257,14 @@ def main():
                               "alg_bytes_per_particle": f["bytes_per_particle"],
                               "error_vs_oracle": f["err"]}
         line["speedup_fp32_vs_fp64_plain"] = value / line["fp64_plain"]["value"]
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = 1 << 30
+        del a, b
     if not args.no_cpu:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(wl, O, args.cpu_seconds, log)

@@ -72,6 +72,7 @@ pic_status ensure_sort_scratch(Ctx *c, int64_t n) {
 }
 
 hipError_t set_tiled_lds_limit(size_t bytes);
+hipError_t set_sort_lds_limit(size_t bytes);
 
 }  // namespace pic
 
@@ -172,6 +173,9 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
     if (e == hipSuccess) e = hipMemset(c->status, 0, 16);
     if (e == hipSuccess && cfg->precision == PIC_FP32_MIXED && c->lds_bytes > 64 * 1024)
         e = set_tiled_lds_limit(c->lds_bytes);
+    const size_t sort_lds = (size_t)7 * c->tile[0] * c->tile[1] * c->tile[2] * sizeof(uint32_t);
+    if (e == hipSuccess && cfg->precision == PIC_FP32_MIXED && sort_lds > 64 * 1024)
+        e = set_sort_lds_limit(sort_lds);
     if (e != hipSuccess) {
         pic_status st = hip_fail(nullptr, e, "pic_init");
         if (c->status) hipFree(c->status);

@@ -44,14 +44,21 @@ __device__ __forceinline__ void shape_weights(R xi, int &i0, R *w) {
     }
 }
 
+// 1/sqrt(x) and 1/x: the FP32 path uses the hardware approximations (v_rsq_f32,
+// v_rcp_f32, about 1 ulp), the FP64 path the correctly rounded operations.
+__device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_r(double x) { return 1.0 / x; }
+
 // Boris push (Eqs. 13-16): u += q_m dt E/2; rotate about B with
 // t = q_m dt B / (2 gamma(u^-)); u += q_m dt E/2.  `h` = q_m dt / 2.
 template <typename R>
 __device__ __forceinline__ void boris(R h, const R *E, const R *B, R *u) {
     R um0 = u[0] + h * E[0], um1 = u[1] + h * E[1], um2 = u[2] + h * E[2];
-    R ig = R(1) / sqrt(R(1) + um0 * um0 + um1 * um1 + um2 * um2);
+    R ig = rsqrt_r(R(1) + um0 * um0 + um1 * um1 + um2 * um2);
     R t0 = h * B[0] * ig, t1 = h * B[1] * ig, t2 = h * B[2] * ig;
-    R f = R(2) / (R(1) + t0 * t0 + t1 * t1 + t2 * t2);
+    R f = R(2) * rcp_r(R(1) + t0 * t0 + t1 * t1 + t2 * t2);
     R s0 = f * t0, s1 = f * t1, s2 = f * t2;
     R p0 = um0 + (um1 * t2 - um2 * t1);
     R p1 = um1 + (um2 * t0 - um0 * t2);
@@ -84,6 +91,28 @@ __device__ __forceinline__ void esirkepov_axis(R xh, R xe, int &base, R *S0, R *
         }
         S0[k] = a;
         DS[k] = b - a;
+    }
+}
+
+// Same stencil when the start-point weights wh (first node ih) are already
+// known from the gather: only the end point is evaluated, and each node takes
+// one select since the two supports are offset by 0 or 1 from `base`.
+template <int ORDER, typename R>
+__device__ __forceinline__ void esirkepov_axis_from(int ih, const R *wh, R xe, int &base, R *S0,
+                                                    R *DS) {
+    constexpr int L = ORDER + 2;
+    R we[ORDER + 1];
+    int ie;
+    shape_weights<ORDER>(xe, ie, we);
+    base = ih < ie ? ih : ie;
+    const bool sh = ih > base, se = ie > base;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        const R h0 = k <= ORDER ? wh[k] : R(0), h1 = k >= 1 ? wh[k - 1] : R(0);
+        const R e0 = k <= ORDER ? we[k] : R(0), e1 = k >= 1 ? we[k - 1] : R(0);
+        const R a = sh ? h1 : h0;
+        S0[k] = a;
+        DS[k] = (se ? e1 : e0) - a;
     }
 }
 

@@ -72,10 +72,10 @@ struct LdsAcc {
     __device__ __forceinline__ float f(int c, int i, int j, int k) const {
         return pic_smem[c * wn + idx(i, j, k)];
     }
+    // v is already in fixed-point units (the prefactors carry S), |v| <= 2^30
     __device__ __forceinline__ void add(int c, int i, int j, int k, float v) const {
         unsigned long long *jw = (unsigned long long *)(pic_smem + 6 * wn);
-        const long long q = (long long)(int)rintf(v * scale);
-        atomicAdd(&jw[c * wn + idx(i, j, k)], (unsigned long long)q);
+        atomicAdd(&jw[c * wn + idx(i, j, k)], (unsigned long long)(long long)(int)v);
     }
 };
 
@@ -84,6 +84,7 @@ struct GlobAcc {
     const float *F[6];
     float *J[3];
     int ng[3];
+    float scale;  // 1: values arrive in physical units
     __device__ __forceinline__ int64_t idx(int i, int j, int k) const {
         i = wrap_index(i, ng[0]);
         j = wrap_index(j, ng[1]);
@@ -104,7 +105,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
                                          float *u, float w, int *dc, float *EB) {
     constexpr int NW = ORDER + 1;
     constexpr int L = ORDER + 2;
-    const float ig0 = 1.0f / sqrtf(1.0f + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const float ig0 = rsqrt_r(1.0f + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     float dh[3];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) dh[d] = f[d] + a.hdt_d[d] * u[d] * ig0;
@@ -150,7 +151,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
     }
 
     boris<float>(a.qm_h, EB, EB + 3, u);
-    const float ig1 = 1.0f / sqrtf(1.0f + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const float ig1 = rsqrt_r(1.0f + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     const float v[3] = {u[0] * ig1, u[1] * ig1, u[2] * ig1};
 
     // Esirkepov (Eqs. 20-22) for the move dh -> dh + dt v / d
@@ -158,9 +159,10 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
     float S0[3][L], DS[3][L];
 #pragma unroll
     for (int d = 0; d < DIM; ++d)
-        esirkepov_axis<ORDER>(dh[d], dh[d] + a.dt_d[d] * v[d], base[d], S0[d], DS[d]);
+        esirkepov_axis_from<ORDER>(i0[0][d], wt[0][d], dh[d] + a.dt_d[d] * v[d], base[d], S0[d], DS[d]);
     const int b0 = o[0] + base[0], b1 = o[1] + base[1];
-    const float jx = a.jfac[0] * w, jy = a.jfac[1] * w;
+    const float ws = w * acc.scale;  // fixed-point units in the LDS window
+    const float jx = a.jfac[0] * ws, jy = a.jfac[1] * ws;
     if constexpr (DIM == 2) {
 #pragma unroll
         for (int jj = 0; jj < L; ++jj) {
@@ -182,7 +184,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
                 acc.add(1, b0 + ii, b1 + jj, 0, run);
             }
         }
-        const float qv = a.q * w * v[2];
+        const float qv = a.q * ws * v[2];
 #pragma unroll
         for (int jj = 0; jj < L; ++jj) {
             const float a0 = qv * (S0[1][jj] + 0.5f * DS[1][jj]);
@@ -192,7 +194,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
         }
     } else {
         const int b2 = o[2] + base[2];
-        const float jz = a.jfac[2] * w;
+        const float jz = a.jfac[2] * ws;
         // W_x = DS_x (S0y S0z + DSy S0z/2 + S0y DSz/2 + DSy DSz/3), etc.
 #pragma unroll
         for (int kk = 0; kk < L; ++kk)
@@ -316,7 +318,7 @@ __global__ void __launch_bounds__(256) gpd_tiled_kernel(TiledArgs a) {
     double kin = 0.0, chg = 0.0;
     GlobAcc glob{{a.F[0], a.F[1], a.F[2], a.F[3], a.F[4], a.F[5]},
                  {a.J[0], a.J[1], a.J[2]},
-                 {a.ng[0], a.ng[1], a.ng[2]}};
+                 {a.ng[0], a.ng[1], a.ng[2]}, 1.0f};
     int64_t p = pbeg + threadIdx.x;
     int32_t n_cell = 0;
     float n_f[3] = {0.0f, 0.0f, 0.0f}, n_u[3] = {0.0f, 0.0f, 0.0f}, n_w = a.w0;

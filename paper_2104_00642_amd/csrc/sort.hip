@@ -2,15 +2,17 @@
 //
 // Order produced: (tile, rank of the particle among those of its cell in the
 // source order, cell within the tile).  Steps:
-//   1. key = tile * cells_per_tile + cell_in_tile, value = source index;
-//   2. stable LSD radix sort of (key, value), 8-bit digits: per-block digit
-//      histograms, one device-wide exclusive scan, stable scatter (ranks
-//      inside a wavefront from 8 ballots, across wavefronts from an LDS
-//      prefix), so equal keys keep source order;
+//   1. key = tile id of the particle's cell;
+//   2. stable LSD radix sort of the tile keys (8-bit digits: per-block digit
+//      histograms, one device-wide exclusive scan, stable scatter with ranks
+//      inside a wavefront from 8 ballots and across wavefronts from an LDS
+//      prefix).  Input that is already tile-ordered (every sort after the
+//      first) keeps long runs, so the scatter stays coalesced;
 //   3. tile_start from the key boundaries;
-//   4. per tile (one workgroup): cell counts, then layer r = 0,1,... of the
-//      r-th particles of each populated cell, cells ascending;
-//   5. gather every particle array into the destination.
+//   4. one workgroup per tile: counts per cell, stable rank of each particle
+//      within its cell (same ballot ranking, in source order), then layer r of
+//      the r-th particles of every populated cell, cells ascending, gathering
+//      every particle array straight into the destination.
 // All integer work: the permutation is deterministic and bit-exact.
 #include "device_common.h"
 #include "pic_internal.h"
@@ -29,19 +31,21 @@ struct SortGeom {
     int ct;  // cells per tile
 };
 
+__device__ __forceinline__ void decode_cell(int32_t c, const SortGeom &g, int &ix, int &iy, int &iz) {
+    const int mx = (1 << g.bx) - 1, my = (1 << g.by) - 1;
+    ix = c & mx;
+    iy = (c >> g.bx) & my;
+    iz = g.dim == 3 ? (c >> (g.bx + g.by)) : 0;
+}
+
 __global__ void __launch_bounds__(256) sort_keys_kernel(const int32_t *cell, int64_t n, SortGeom g,
-                                                        uint32_t *keys, uint32_t *vals) {
+                                                        uint32_t *keys) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const int32_t c = cell[p];
-    const int mx = (1 << g.bx) - 1, my = (1 << g.by) - 1;
-    const int ix = c & mx, iy = (c >> g.bx) & my, iz = g.dim == 3 ? (c >> (g.bx + g.by)) : 0;
+    int ix, iy, iz;
+    decode_cell(cell[p], g, ix, iy, iz);
     const int tx = ix / g.tile[0], ty = iy / g.tile[1], tz = iz / g.tile[2];
-    const int lx = ix - tx * g.tile[0], ly = iy - ty * g.tile[1], lz = iz - tz * g.tile[2];
-    const uint32_t tile = (uint32_t)(tx + g.ntile_axis[0] * (ty + g.ntile_axis[1] * tz));
-    const uint32_t local = (uint32_t)(lx + g.tile[0] * (ly + g.tile[1] * lz));
-    keys[p] = tile * (uint32_t)g.ct + local;
-    vals[p] = (uint32_t)p;
+    keys[p] = (uint32_t)(tx + g.ntile_axis[0] * (ty + g.ntile_axis[1] * tz));
 }
 
 __global__ void __launch_bounds__(SORT_THREADS) radix_hist_kernel(const uint32_t *keys, int64_t n,
@@ -177,7 +181,7 @@ __global__ void __launch_bounds__(SORT_THREADS) radix_scatter_kernel(
         if (valid) {
             const uint32_t pos = wcnt[wave][d] + rank;
             kout[pos] = key;
-            vout[pos] = vin[i];
+            vout[pos] = vin ? vin[i] : (uint32_t)i;
         }
         __syncthreads();
     }
@@ -185,34 +189,58 @@ __global__ void __launch_bounds__(SORT_THREADS) radix_scatter_kernel(
 
 // ---- tile boundaries -----------------------------------------------------
 
-__global__ void __launch_bounds__(256) tile_bounds_kernel(const uint32_t *keys, int64_t n, int ct,
+__global__ void __launch_bounds__(256) tile_bounds_kernel(const uint32_t *keys, int64_t n,
                                                           int64_t ntiles, int64_t *tile_start) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > n) return;
-    const int64_t tprev = i == 0 ? -1 : (int64_t)(keys[i - 1] / (uint32_t)ct);
-    const int64_t tcur = i == n ? ntiles : (int64_t)(keys[i] / (uint32_t)ct);
+    const int64_t tprev = i == 0 ? -1 : (int64_t)keys[i - 1];
+    const int64_t tcur = i == n ? ntiles : (int64_t)keys[i];
     for (int64_t t = tprev + 1; t <= tcur; ++t) tile_start[t] = i;
 }
 
-// ---- per-tile layer interleave ------------------------------------------
+// ---- per tile: stable in-cell ranks, layer order, gather into dst --------
 
-__global__ void __launch_bounds__(256) interleave_kernel(const uint32_t *keys, const uint32_t *vals,
-                                                         const int64_t *tile_start, int ct,
-                                                         uint32_t *perm) {
+struct PermArgs {
+    const int32_t *cell_in;
+    int32_t *cell_out;
+    const float *fin[8];
+    float *fout[8];
+    int nf;
+};
+
+__global__ void __launch_bounds__(256) tile_order_kernel(const uint32_t *vals, const int64_t *tile_start,
+                                                         SortGeom g, int lbits, uint32_t *lcell,
+                                                         uint32_t *slot_src, uint32_t *inv, PermArgs pa) {
     extern __shared__ uint32_t sm[];
-    uint32_t *cnt = sm;         // ct
-    uint32_t *cst = sm + ct;    // ct: start of each cell's run in the tile
-    __shared__ uint32_t tmp[256];
+    const int ct = g.ct;
+    uint32_t *cnt = sm;            // ct: particles per cell
+    uint32_t *cst = sm + ct;       // ct: first slot of each cell in cell order
+    uint32_t *run = sm + 2 * ct;   // ct: particles of the cell ranked so far
+    uint32_t *wcnt = sm + 3 * ct;  // 4 x ct: per-wave counts of one round
+    __shared__ uint32_t tmp_s[256];
     __shared__ uint32_t maxc;
     const int t = blockIdx.x;
     const int64_t ts = tile_start[t], te = tile_start[t + 1];
     if (ts == te) return;
-    for (int l = threadIdx.x; l < ct; l += blockDim.x) cnt[l] = 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int l = threadIdx.x; l < ct; l += blockDim.x) {
+        cnt[l] = 0;
+        run[l] = 0;
+    }
     if (threadIdx.x == 0) maxc = 0;
     __syncthreads();
-    for (int64_t i = ts + threadIdx.x; i < te; i += blockDim.x) atomicAdd(&cnt[keys[i] % (uint32_t)ct], 1u);
+    // 1. cell within the tile of every particle (gathered once), counts
+    for (int64_t i = ts + threadIdx.x; i < te; i += blockDim.x) {
+        int ix, iy, iz;
+        decode_cell(pa.cell_in[vals[i]], g, ix, iy, iz);
+        const uint32_t l =
+            (uint32_t)((ix % g.tile[0]) + g.tile[0] * ((iy % g.tile[1]) + g.tile[1] * (iz % g.tile[2])));
+        lcell[i] = l;
+        atomicAdd(&cnt[l], 1u);
+    }
     __syncthreads();
-    // exclusive scan of counts (cells per thread: ct / 256, consecutive)
+    // 2. exclusive scan of the counts (consecutive cells per thread)
     const int per = (ct + 255) / 256;
     uint32_t loc = 0, mx = 0;
     for (int q = 0; q < per; ++q) {
@@ -224,7 +252,7 @@ __global__ void __launch_bounds__(256) interleave_kernel(const uint32_t *keys, c
     }
     atomicMax(&maxc, mx);
     uint32_t total;
-    uint32_t ex = block_exclusive_scan(loc, tmp, total);
+    uint32_t ex = block_exclusive_scan(loc, tmp_s, total);
     for (int q = 0; q < per; ++q) {
         const int l = threadIdx.x * per + q;
         if (l < ct) {
@@ -233,7 +261,39 @@ __global__ void __launch_bounds__(256) interleave_kernel(const uint32_t *keys, c
         }
     }
     __syncthreads();
-    // layers
+    // 3. stable rank within the cell, in source order -> slot in cell order
+    for (int64_t base = ts; base < te; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < te;
+        const uint32_t l = valid ? lcell[i] : 0u;
+        for (int e = threadIdx.x; e < 4 * ct; e += blockDim.x) wcnt[e] = 0;
+        __syncthreads();
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < lbits; ++b) {
+            const uint64_t m = __ballot((l >> b) & 1u);
+            peers &= ((l >> b) & 1u) ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+        if (valid && rank == 0) wcnt[wave * ct + l] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        for (int q = 0; q < per; ++q) {
+            const int ll = threadIdx.x * per + q;
+            if (ll < ct) {
+                uint32_t r = run[ll];
+                for (int w = 0; w < 4; ++w) {
+                    const uint32_t c = wcnt[w * ct + ll];
+                    wcnt[w * ct + ll] = r;
+                    r += c;
+                }
+                run[ll] = r;
+            }
+        }
+        __syncthreads();
+        if (valid) slot_src[ts + cst[l] + wcnt[wave * ct + l] + rank] = vals[i];
+        __syncthreads();
+    }
+    // 4. layers: the r-th particle of every cell holding more than r, cells
+    //    ascending; record which cell-order slot lands at each position
     uint32_t layer_base = 0;
     const uint32_t layers = maxc;
     for (uint32_t r = 0; r < layers; ++r) {
@@ -243,38 +303,35 @@ __global__ void __launch_bounds__(256) interleave_kernel(const uint32_t *keys, c
             f += (l < ct && cnt[l] > r) ? 1u : 0u;
         }
         uint32_t lt;
-        uint32_t pos = block_exclusive_scan(f, tmp, lt);
+        uint32_t pos = block_exclusive_scan(f, tmp_s, lt);
         for (int q = 0; q < per; ++q) {
             const int l = threadIdx.x * per + q;
-            if (l < ct && cnt[l] > r) {
-                perm[ts + layer_base + pos] = vals[ts + cst[l] + r];
-                ++pos;
-            }
+            if (l < ct && cnt[l] > r) inv[ts + layer_base + pos++] = cst[l] + r;
         }
         layer_base += lt;
     }
-}
-
-// ---- permute ---------------------------------------------------------------
-
-struct PermArgs {
-    int64_t n;
-    const uint32_t *perm;
-    const int32_t *cell_in;
-    int32_t *cell_out;
-    const float *fin[8];
-    float *fout[8];
-    int nf;
-};
-
-__global__ void __launch_bounds__(256) permute_kernel(PermArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    const uint32_t src = a.perm[i];
-    a.cell_out[i] = a.cell_in[src];
+    __syncthreads();
+    // 5. gather every particle array into its final position (independent
+    //    iterations, four in flight per thread)
+    const int64_t n_t = te - ts;
+    for (int64_t j0 = threadIdx.x; j0 < n_t; j0 += 4 * (int64_t)blockDim.x) {
+        uint32_t src[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-        if (q < a.nf) a.fout[q][i] = a.fin[q][src];
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = j0 + u * (int64_t)blockDim.x;
+            src[u] = j < n_t ? slot_src[ts + inv[ts + j]] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = j0 + u * (int64_t)blockDim.x;
+            if (j < n_t) {
+                pa.cell_out[ts + j] = pa.cell_in[src[u]];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (k < pa.nf) pa.fout[k][ts + j] = pa.fin[k][src[u]];
+            }
+        }
+    }
 }
 
 pic_status ensure_sort_scratch(Ctx *c, int64_t n);
@@ -290,58 +347,65 @@ hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *ds
         g.ntile_axis[d] = c->ntile_axis[d];
     }
     g.ct = c->tile[0] * c->tile[1] * c->tile[2];
-    if (n > 0) {
-        sort_keys_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src->cell, n, g, c->keys[0],
-                                                                     c->vals[0]);
-        int64_t ncell = c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2];
-        int bits = 0;
-        while ((1ll << bits) < ncell) ++bits;
-        const int passes = (bits + 7) / 8;
-        const int64_t nblocks = (n + SORT_ITEMS - 1) / SORT_ITEMS;
-        int cur = 0;
-        for (int pass = 0; pass < passes; ++pass) {
-            const int shift = 8 * pass;
-            radix_hist_kernel<<<(unsigned)nblocks, SORT_THREADS, 0, s>>>(c->keys[cur], n, shift,
-                                                                         c->hist, nblocks);
-            hipError_t e = exclusive_scan(c, c->hist, 256 * nblocks, c->hist + 256 * nblocks, s);
-            if (e != hipSuccess) return e;
-            radix_scatter_kernel<<<(unsigned)nblocks, SORT_THREADS, 0, s>>>(
-                c->keys[cur], c->vals[cur], n, shift, c->hist, nblocks, c->keys[cur ^ 1],
-                c->vals[cur ^ 1]);
-            cur ^= 1;
-        }
-        tile_bounds_kernel<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(c->keys[cur], n, g.ct,
-                                                                           c->ntiles, dst->tile_start);
-        interleave_kernel<<<(unsigned)c->ntiles, 256, 2 * g.ct * sizeof(uint32_t), s>>>(
-            c->keys[cur], c->vals[cur], dst->tile_start, g.ct, c->final_perm);
-        PermArgs pa{};
-        pa.n = n;
-        pa.perm = c->final_perm;
-        pa.cell_in = src->cell;
-        pa.cell_out = dst->cell;
-        int nf = 0;
-        for (int d = 0; d < c->dim; ++d) {
-            pa.fin[nf] = src->off[d];
-            pa.fout[nf++] = dst->off[d];
-        }
-        for (int d = 0; d < 3; ++d) {
-            pa.fin[nf] = (const float *)src->u[d];
-            pa.fout[nf++] = (float *)dst->u[d];
-        }
-        if (src->w) {
-            pa.fin[nf] = (const float *)src->w;
-            pa.fout[nf++] = (float *)dst->w;
-        }
-        if (src->chi) {
-            pa.fin[nf] = src->chi;
-            pa.fout[nf++] = dst->chi;
-        }
-        pa.nf = nf;
-        permute_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(pa);
-    } else {
-        tile_bounds_kernel<<<1, 256, 0, s>>>(c->keys[0], 0, g.ct, c->ntiles, dst->tile_start);
+    if (n == 0) {
+        tile_bounds_kernel<<<1, 256, 0, s>>>(c->keys[0], 0, c->ntiles, dst->tile_start);
+        return hipGetLastError();
     }
+    sort_keys_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src->cell, n, g, c->keys[0]);
+    int bits = 0;
+    while ((1ll << bits) < c->ntiles) ++bits;
+    const int passes = bits == 0 ? 1 : (bits + 7) / 8;
+    const int64_t nblocks = (n + SORT_ITEMS - 1) / SORT_ITEMS;
+    int cur = 0;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = 8 * pass;
+        radix_hist_kernel<<<(unsigned)nblocks, SORT_THREADS, 0, s>>>(c->keys[cur], n, shift, c->hist,
+                                                                     nblocks);
+        hipError_t e = exclusive_scan(c, c->hist, 256 * nblocks, c->hist + 256 * nblocks, s);
+        if (e != hipSuccess) return e;
+        radix_scatter_kernel<<<(unsigned)nblocks, SORT_THREADS, 0, s>>>(
+            c->keys[cur], pass == 0 ? nullptr : c->vals[cur], n, shift, c->hist, nblocks,
+            c->keys[cur ^ 1], c->vals[cur ^ 1]);
+        cur ^= 1;
+    }
+    tile_bounds_kernel<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(c->keys[cur], n, c->ntiles,
+                                                                       dst->tile_start);
+    PermArgs pa{};
+    pa.cell_in = src->cell;
+    pa.cell_out = dst->cell;
+    int nf = 0;
+    for (int d = 0; d < c->dim; ++d) {
+        pa.fin[nf] = src->off[d];
+        pa.fout[nf++] = dst->off[d];
+    }
+    for (int d = 0; d < 3; ++d) {
+        pa.fin[nf] = (const float *)src->u[d];
+        pa.fout[nf++] = (float *)dst->u[d];
+    }
+    if (src->w) {
+        pa.fin[nf] = (const float *)src->w;
+        pa.fout[nf++] = (float *)dst->w;
+    }
+    if (src->chi) {
+        pa.fin[nf] = src->chi;
+        pa.fout[nf++] = dst->chi;
+    }
+    pa.nf = nf;
+    int lbits = 0;
+    while ((1 << lbits) < g.ct) ++lbits;
+    const size_t lds = (size_t)7 * g.ct * sizeof(uint32_t);
+    // scratch: keys[cur^1] (cells within the tile), final_perm (source of
+    // each cell-order slot), keys[cur] (slot of each final position; the
+    // sorted keys are no longer needed once tile_start is written)
+    tile_order_kernel<<<(unsigned)c->ntiles, 256, lds, s>>>(c->vals[cur], dst->tile_start, g, lbits,
+                                                            c->keys[cur ^ 1], c->final_perm,
+                                                            c->keys[cur], pa);
     return hipGetLastError();
+}
+
+hipError_t set_sort_lds_limit(size_t bytes) {
+    return hipFuncSetAttribute((const void *)tile_order_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 }  // namespace pic

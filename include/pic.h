@@ -112,6 +112,14 @@ typedef struct {
     float *chi;             /* nullable; chi at step n+1/2 written by the push (FP32)  */
     int64_t *tile_start;    /* FP32 path: ntiles+1 offsets of the tile-sorted order,
                                written by pic_sort and read by the push               */
+    /* QED (pic_qed_step; NULL/0 otherwise) */
+    double *tau;            /* optical depth accumulated since the last event         */
+    float *tau_thr;         /* threshold -ln r of the next event                      */
+    uint64_t *id;           /* unique identifiers (random streams, child identifiers) */
+    int64_t capacity;       /* length of every array: particles created beyond it are
+                               dropped and flagged PIC_F_CAPACITY                     */
+    int64_t *n_dev;         /* device count: n plus the particles pic_qed_step created;
+                               the caller reads it back and passes it as n next time  */
 } pic_particles;
 
 typedef struct {
@@ -177,6 +185,89 @@ pic_status pic_yee_step(void *ctx, int32_t half, const pic_fields *fields, doubl
  * deterministic.
  */
 pic_status pic_sort(void *ctx, const pic_particles *src, const pic_particles *dst, void *stream);
+
+/*
+ * Monte-Carlo QED step (Sec. IV), Method I in optical-depth form, on the
+ * FP32 particle layout.  Rates per unit time (1/w_r):
+ *   W_rad  = alpha/(sqrt3 pi) (m c^2/hbar w_r) F_rad(chi_e) / gamma     (Eq. 23)
+ *   W_pair = alpha/(sqrt3 pi) (m c^2/hbar w_r) F_pair(chi_g) / eps_gamma (Eq. 24)
+ * Each particle carries tau (FP64) and tau_thr; tau += W dt.  When tau >=
+ * tau_thr an event happens: the energy fraction comes from the inverse
+ * cumulative spectrum at a uniform r, tau <- 0, tau_thr <- -ln r'.  With
+ * (r, r') = Philox4x32-10(counter (id_lo, id_hi, step, 0), key seed) mapped to
+ * (0,1) by 52 bits each.
+ *   Leptons (chi from the last push): photon of energy u gamma along u,
+ *     recoil u <- u (1 - eps_gamma/|u|) (clamped at 0); the photon is appended
+ *     to `photons` when eps_gamma >= photon_min_energy.
+ *   Photons (momentum k = eps_gamma k^, chi_gamma computed here at the fields
+ *     of `fields` after moving dt at c): above 2 m c^2 an event appends a
+ *     positron with x eps_gamma and an electron with (1-x) eps_gamma along k
+ *     and sets the photon weight to 0.
+ * Created particles: identifier Philox(counter (parent_lo, parent_hi, step,
+ * 0x80000000 | tag), key seed) (tag 1 photon, 2 positron, 3 electron), tau 0,
+ * tau_thr from the counter (id_lo, id_hi, step, 1); parent position and
+ * weight.  F and the inverse spectra come from tables the library computes
+ * with its own quadrature at pic_init (PIC_QED_TABLE), or from the trained
+ * network (PIC_QED_MLP; chi outside the trained range uses the tables).
+ * Requires hbar_omega_mc2 > 0.
+ */
+enum { PIC_QED_TABLE = 0, PIC_QED_MLP = 1 };
+typedef struct {
+    const pic_particles *electrons;   /* nullable */
+    const pic_particles *positrons;   /* nullable */
+    const pic_particles *photons;     /* nullable */
+    const pic_fields *fields;         /* E, B at the end of the step (FP32)        */
+    int32_t mode;                     /* PIC_QED_TABLE or PIC_QED_MLP               */
+    uint32_t step;                    /* step index: counter of the random streams  */
+    double photon_min_energy;         /* m c^2 units                                */
+    const void *mlp;                  /* PIC_QED_MLP: device network (layout below) */
+} pic_qed_args;
+pic_status pic_qed_step(void *ctx, const pic_qed_args *args, void *stream);
+
+/*
+ * Surrogate network of the QED module: 4 -> 64 -> 64 -> 2 perceptron,
+ * h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 W3 + b3, BF16 weights,
+ * FP32 biases, FP32 accumulation (BF16 matrix cores).  Device layout
+ * (PIC_MLP_BYTES): W1 bf16[4][64] @0, W2 bf16[64][64] @512, W3 bf16[64][2]
+ * @8704, b1 f32[64] @8960, b2 f32[64] @9216, b3 f32[2] @9472 (row-major,
+ * input index first).  Inputs x = ((log10 chi - c)/h, 2 rho(r) - 1, [emission],
+ * [pairs]) where log10 chi spans [c-h, c+h] = [-4, 3] (emission) or
+ * [-1.7, 3] (pairs) and rho(r) = 1 - sqrt(1-r) (emission) or
+ * acos(1-2r)/pi (pairs); outputs y0 = ln(F_rad/chi) or ln F_pair + 8/(3 chi),
+ * y1 = u^(1/3) (photon energy fraction) or x (positron fraction).
+ * Training state (PIC_MLP_STATE_FLOATS floats, FP32): parameters, Adam first
+ * and second moments and the gradient (PIC_MLP_NPARAM each, order W1, b1, W2,
+ * b2, W3, b3), then the Adam step count.
+ */
+#define PIC_MLP_NPARAM 4610
+#define PIC_MLP_BYTES 9480
+#define PIC_MLP_OFF_W1 0
+#define PIC_MLP_OFF_W2 512
+#define PIC_MLP_OFF_W3 8704
+#define PIC_MLP_OFF_B1 8960
+#define PIC_MLP_OFF_B2 9216
+#define PIC_MLP_OFF_B3 9472
+#define PIC_MLP_STATE_FLOATS (4 * PIC_MLP_NPARAM + 1)
+
+/* y[n][2] = network(x[n][4]) (device arrays). */
+pic_status pic_mlp_forward(void *ctx, const void *mlp, const float *x, int64_t n, float *y, void *stream);
+/* grad[PIC_MLP_NPARAM] += d/dparams of sum (y - t)^2 / (2n) with the
+ * network's (BF16) weights; *loss (nullable) += that loss. */
+pic_status pic_mlp_grad(void *ctx, const void *mlp, const float *x, const float *t, int64_t n, float *grad,
+                        float *loss, void *stream);
+/* `iters` Adam steps (learning rate lr) on consecutive batches of `batch`
+ * rows of (x, t), starting from the state's parameters; the BF16 network is
+ * written to mlp after every step; *loss (nullable) receives the last
+ * batch's loss. */
+pic_status pic_mlp_train(void *ctx, float *state, void *mlp, const float *x, const float *t, int64_t n,
+                         int32_t batch, int32_t iters, float lr, float *loss, void *stream);
+/* n training rows from the library's tables (row i: process i & 1, log10 chi
+ * and r uniform from Philox(counter (i_lo, i_hi, 0, 7), key seed)). */
+pic_status pic_qed_training_data(void *ctx, int64_t n, uint64_t seed, float *x, float *t, void *stream);
+/* Table queries: what = 0 F(chi) (r unused), 1 inverse spectrum at (chi, r);
+ * proc 0 photon emission, 1 pair creation. */
+pic_status pic_qed_table_lookup(void *ctx, int32_t proc, int32_t what, const float *chi, const float *r,
+                                int64_t n, float *out, void *stream);
 
 /* Synchronize `stream`, return the device status word in *flags (nullable)
  * and the number of straggler particles since the last check in

@@ -1,0 +1,153 @@
+"""FP64 reference of one Monte-Carlo QED step (test infrastructure only).
+
+Sec. IV of the paper, Method I written in optical-depth form: a particle
+accumulates tau += W dt with W the total rate of Eq. 23 (photon emission) or
+Eq. 24 (pair creation); when tau reaches its threshold tau_thr = -ln r' the
+event happens, the energy fraction is the inverse of the cumulative spectrum
+at a uniform r, tau restarts from 0 and a fresh threshold is drawn.  The
+uniforms of particle `id` at `step` are Philox4x32-10 at counter
+(id_lo, id_hi, step, 0) with key = seed; created particles get the identifier
+Philox(parent_lo, parent_hi, step, 0x80000000 | tag) (tag 1 photon,
+2 positron, 3 electron) and their first threshold from counter
+(id_lo, id_hi, step, 1).  Recoil is collinear: u <- u (1 - eps_gamma/|u|),
+clamped at 0.  Plain Python loops: meant for small particle counts.
+"""
+from __future__ import annotations
+
+import math
+
+from . import compton_inverse, fpair, frad, pair_inverse, philox4x32_10, qed_uniforms
+
+ALPHA = 1.0 / 137.035999084
+A_CONST = ALPHA / (math.sqrt(3.0) * math.pi)
+
+
+def child_id(seed: int, parent: int, step: int, tag: int) -> int:
+    out = philox4x32_10([parent & 0xFFFFFFFF, (parent >> 32) & 0xFFFFFFFF, step & 0xFFFFFFFF,
+                         0x80000000 | tag], [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF])
+    return (out[1] << 32) | out[0]
+
+
+def first_threshold(seed: int, pid: int, step: int) -> float:
+    a, _ = qed_uniforms(seed, pid, step, 1)
+    return -math.log(a)
+
+
+class Rates:
+    """F_rad / F_pair and their inverse spectra from the oracle quadrature,
+    memoised per chi (tests reuse a few chi values).  With nodes > 0 the
+    inverse spectrum is the monotone linear interpolation of the exact
+    cumulative integral at `nodes` points (in s = u^(1/3) for emission, in x
+    for pairs) instead of a bisection over full quadratures: statistical tests
+    draw thousands of events."""
+
+    def __init__(self, nodes: int = 0):
+        self._fr, self._fp = {}, {}
+        self.nodes = nodes
+        self._cum = {}
+
+    def frad(self, chi):
+        if chi not in self._fr:
+            self._fr[chi] = frad(chi) if chi > 0 else 0.0
+        return self._fr[chi]
+
+    def fpair(self, chi):
+        if chi not in self._fp:
+            self._fp[chi] = fpair(chi) if chi > 0 else 0.0
+        return self._fp[chi]
+
+    def _table(self, proc, chi):
+        key = (proc, chi)
+        if key not in self._cum:
+            from . import compton_cum, pair_cum
+            xs = [i / self.nodes for i in range(self.nodes + 1)]
+            if proc == 0:
+                cum = [compton_cum(chi, s ** 3) for s in xs]
+            else:
+                cum = [pair_cum(chi, x) for x in xs]
+            self._cum[key] = (xs, cum)
+        return self._cum[key]
+
+    def inverse(self, proc, chi, r):
+        if self.nodes <= 0:
+            return compton_inverse(chi, r) if proc == 0 else pair_inverse(chi, r)
+        xs, cum = self._table(proc, chi)
+        target = r * cum[-1]
+        lo, hi = 0, len(xs) - 1
+        while hi - lo > 1:
+            mid = (lo + hi) // 2
+            if cum[mid] < target:
+                lo = mid
+            else:
+                hi = mid
+        f = (target - cum[lo]) / (cum[hi] - cum[lo]) if cum[hi] > cum[lo] else 0.0
+        v = xs[lo] + f * (xs[hi] - xs[lo])
+        return v ** 3 if proc == 0 else v
+
+
+def lepton_step(leptons: dict, seed: int, step: int, dt: float, hbar_w: float, emin: float,
+                rates: Rates, photons_out: list | None):
+    """leptons: dict of lists u (3 x n), chi, tau, tau_thr, id, w, pos (opaque
+    position token copied to created photons).  Updated in place; created
+    photons are appended to photons_out as dicts."""
+    R = 1.0 / hbar_w
+    n = len(leptons["chi"])
+    for p in range(n):
+        w = leptons["w"][p]
+        if w == 0.0:
+            continue
+        u = [leptons["u"][a][p] for a in range(3)]
+        chi = leptons["chi"][p]
+        pu2 = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+        gam = math.sqrt(1.0 + pu2)
+        W = A_CONST * R * rates.frad(chi) / gam
+        tau = leptons["tau"][p] + W * dt
+        if tau >= leptons["tau_thr"][p] and chi > 0.0:
+            pid = leptons["id"][p]
+            ru, rt = qed_uniforms(seed, pid, step, 0)
+            uf = rates.inverse(0, chi, ru)
+            eps = uf * gam
+            pm = math.sqrt(pu2)
+            if pm > 0:
+                k = [eps * c / pm for c in u]
+                if photons_out is not None and eps >= emin:
+                    cid = child_id(seed, pid, step, 1)
+                    photons_out.append(dict(k=k, w=w, pos=leptons["pos"][p], id=cid,
+                                            tau_thr=first_threshold(seed, cid, step)))
+                f = max(0.0, 1.0 - eps / pm)
+                for a in range(3):
+                    leptons["u"][a][p] = u[a] * f
+            tau = 0.0
+            leptons["tau_thr"][p] = -math.log(rt)
+        leptons["tau"][p] = tau
+
+
+def photon_decay(photons: dict, seed: int, step: int, dt: float, hbar_w: float, rates: Rates,
+                 positrons_out: list, electrons_out: list):
+    """photons: dict of lists k (3 x n), chi (chi_gamma, already at the photon),
+    tau, tau_thr, id, w, pos.  Pair creation above 2 m c^2."""
+    R = 1.0 / hbar_w
+    n = len(photons["chi"])
+    for p in range(n):
+        w = photons["w"][p]
+        if w == 0.0:
+            continue
+        k = [photons["k"][a][p] for a in range(3)]
+        eps = math.sqrt(sum(c * c for c in k))
+        chi = photons["chi"][p]
+        W = A_CONST * R * rates.fpair(chi) / eps
+        tau = photons["tau"][p] + W * dt
+        if tau >= photons["tau_thr"][p] and eps > 2.0 and chi > 0.0:
+            pid = photons["id"][p]
+            rx, _ = qed_uniforms(seed, pid, step, 0)
+            x = rates.inverse(1, chi, rx)
+            ep, em = x * eps, (1.0 - x) * eps
+            npl = math.sqrt(max(ep * ep - 1.0, 0.0)) / eps
+            nmi = math.sqrt(max(em * em - 1.0, 0.0)) / eps
+            for out, nn, tag in ((positrons_out, npl, 2), (electrons_out, nmi, 3)):
+                cid = child_id(seed, pid, step, tag)
+                out.append(dict(u=[nn * c for c in k], w=w, pos=photons["pos"][p], id=cid,
+                                tau_thr=first_threshold(seed, cid, step)))
+            photons["w"][p] = 0.0
+            tau = 0.0
+        photons["tau"][p] = tau

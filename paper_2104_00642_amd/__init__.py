@@ -5,6 +5,8 @@ of ``include/pic.h``); ``_lib`` marshals arguments, ``sim`` sequences the calls
 of one step, ``workloads`` makes seeded synthetic inputs.
 """
 from ._lib import (PIC_BC_PERIODIC, PIC_F_CAPACITY, PIC_F_NONFINITE, PIC_F_OFFSET,  # noqa: F401
-                   PIC_F_STRAGGLER, PIC_FP32_MIXED, PIC_FP64_PLAIN, Config, Context, Fields,
-                   Particles, PicError, Species, pic_check, pic_destroy, pic_gather_push_deposit,
-                   pic_get_layout, pic_init, pic_last_error, pic_sort, pic_yee_step)
+                   PIC_F_STRAGGLER, PIC_FP32_MIXED, PIC_FP64_PLAIN, PIC_QED_MLP, PIC_QED_TABLE, Config,
+                   Context, Fields, Particles, PicError, Species, pic_check, pic_destroy,
+                   pic_gather_push_deposit, pic_get_layout, pic_init, pic_last_error, pic_mlp_forward,
+                   pic_mlp_grad, pic_mlp_train, pic_qed_step, pic_qed_table_lookup,
+                   pic_qed_training_data, pic_sort, pic_yee_step)

@@ -25,8 +25,14 @@ PIC_FP32_MIXED, PIC_FP64_PLAIN = 0, 1
 PIC_BC_PERIODIC = 0
 PIC_F_NONFINITE, PIC_F_OFFSET, PIC_F_STRAGGLER, PIC_F_CAPACITY = 1, 2, 4, 8
 
+PIC_QED_TABLE, PIC_QED_MLP = 0, 1
+PIC_MLP_NPARAM = 4610
+PIC_MLP_BYTES = 9480
+PIC_MLP_STATE_FLOATS = 4 * PIC_MLP_NPARAM + 1
+
 EXPORTED = ["pic_init", "pic_destroy", "pic_last_error", "pic_get_layout", "pic_gather_push_deposit",
-            "pic_yee_step", "pic_sort", "pic_check"]
+            "pic_yee_step", "pic_sort", "pic_check", "pic_qed_step", "pic_mlp_forward", "pic_mlp_grad",
+            "pic_mlp_train", "pic_qed_training_data", "pic_qed_table_lookup"]
 
 
 class PicError(RuntimeError):
@@ -50,11 +56,20 @@ class pic_species(C.Structure):
 class pic_particles(C.Structure):
     _fields_ = [("n", C.c_int64), ("cell", C.c_void_p), ("off", C.c_void_p * 3),
                 ("x", C.c_void_p * 3), ("u", C.c_void_p * 3), ("w", C.c_void_p),
-                ("chi", C.c_void_p), ("tile_start", C.c_void_p)]
+                ("chi", C.c_void_p), ("tile_start", C.c_void_p),
+                ("tau", C.c_void_p), ("tau_thr", C.c_void_p), ("id", C.c_void_p),
+                ("capacity", C.c_int64), ("n_dev", C.c_void_p)]
 
 
 class pic_fields(C.Structure):
     _fields_ = [("E", C.c_void_p * 3), ("B", C.c_void_p * 3), ("J", C.c_void_p * 3)]
+
+
+class pic_qed_args(C.Structure):
+    _fields_ = [("electrons", C.POINTER(pic_particles)), ("positrons", C.POINTER(pic_particles)),
+                ("photons", C.POINTER(pic_particles)), ("fields", C.POINTER(pic_fields)),
+                ("mode", C.c_int32), ("step", C.c_uint32), ("photon_min_energy", C.c_double),
+                ("mlp", C.c_void_p)]
 
 
 _lib = None
@@ -85,6 +100,22 @@ def lib():
         L.pic_sort.restype = C.c_int
         L.pic_check.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)]
         L.pic_check.restype = C.c_int
+        L.pic_qed_step.argtypes = [C.c_void_p, C.POINTER(pic_qed_args), C.c_void_p]
+        L.pic_qed_step.restype = C.c_int
+        L.pic_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+        L.pic_mlp_forward.restype = C.c_int
+        L.pic_mlp_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]
+        L.pic_mlp_grad.restype = C.c_int
+        L.pic_mlp_train.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                    C.c_int32, C.c_int32, C.c_float, C.c_void_p, C.c_void_p]
+        L.pic_mlp_train.restype = C.c_int
+        L.pic_qed_training_data.argtypes = [C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p, C.c_void_p,
+                                            C.c_void_p]
+        L.pic_qed_training_data.restype = C.c_int
+        L.pic_qed_table_lookup.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                           C.c_int64, C.c_void_p, C.c_void_p]
+        L.pic_qed_table_lookup.restype = C.c_int
         _lib = L
     return _lib
 
@@ -167,6 +198,11 @@ class Particles:
     w: Optional[torch.Tensor] = None
     chi: Optional[torch.Tensor] = None
     tile_start: Optional[torch.Tensor] = None
+    tau: Optional[torch.Tensor] = None       # float64
+    tau_thr: Optional[torch.Tensor] = None   # float32
+    id: Optional[torch.Tensor] = None        # int64 (bits of the uint64 identifiers)
+    capacity: int = 0
+    n_dev: Optional[torch.Tensor] = None     # int64[1]
 
     def c(self) -> pic_particles:
         p = pic_particles()
@@ -181,12 +217,18 @@ class Particles:
         p.w = _ptr(self.w)
         p.chi = _ptr(self.chi)
         p.tile_start = _ptr(self.tile_start)
+        p.tau = _ptr(self.tau)
+        p.tau_thr = _ptr(self.tau_thr)
+        p.id = _ptr(self.id)
+        p.capacity = int(self.capacity if self.capacity else self.n)
+        p.n_dev = _ptr(self.n_dev)
         return p
 
     def empty_like(self) -> "Particles":
         e = lambda t: None if t is None else torch.empty_like(t)  # noqa: E731
         return Particles(self.n, [e(t) for t in self.u], e(self.cell), [e(t) for t in self.off],
-                         [e(t) for t in self.x], e(self.w), e(self.chi), e(self.tile_start))
+                         [e(t) for t in self.x], e(self.w), e(self.chi), e(self.tile_start),
+                         e(self.tau), e(self.tau_thr), e(self.id), self.capacity, e(self.n_dev))
 
 
 @dataclass
@@ -284,3 +326,47 @@ def pic_check(ctx: Context, stream=None):
     if st not in (PIC_OK, PIC_E_STATE, PIC_E_CAPACITY):
         _check(st, C.c_void_p(ctx.handle))
     return st, fl.value, ns.value
+
+
+def pic_qed_step(ctx: Context, fields: Fields, electrons: Optional[Particles] = None,
+                 positrons: Optional[Particles] = None, photons: Optional[Particles] = None,
+                 mode: int = PIC_QED_TABLE, step: int = 0, photon_min_energy: float = 2.0,
+                 mlp: Optional[torch.Tensor] = None, stream=None):
+    keep = []
+
+    def ref(p):
+        if p is None:
+            return None
+        c = p.c()
+        keep.append(c)
+        return C.pointer(c)
+    fc = fields.c()
+    a = pic_qed_args(ref(electrons), ref(positrons), ref(photons), C.pointer(fc), int(mode), int(step) & 0xFFFFFFFF,
+                     float(photon_min_energy), _ptr(mlp))
+    _check(lib().pic_qed_step(C.c_void_p(ctx.handle), C.byref(a), _stream(stream)), C.c_void_p(ctx.handle))
+
+
+def pic_mlp_forward(ctx: Context, mlp: torch.Tensor, x: torch.Tensor, y: torch.Tensor, stream=None):
+    _check(lib().pic_mlp_forward(C.c_void_p(ctx.handle), _ptr(mlp), _ptr(x), x.shape[0], _ptr(y),
+                                 _stream(stream)), C.c_void_p(ctx.handle))
+
+
+def pic_mlp_grad(ctx: Context, mlp, x, t, grad, loss=None, stream=None):
+    _check(lib().pic_mlp_grad(C.c_void_p(ctx.handle), _ptr(mlp), _ptr(x), _ptr(t), x.shape[0], _ptr(grad),
+                              _ptr(loss), _stream(stream)), C.c_void_p(ctx.handle))
+
+
+def pic_mlp_train(ctx: Context, state, mlp, x, t, batch: int, iters: int, lr: float, loss=None, stream=None):
+    _check(lib().pic_mlp_train(C.c_void_p(ctx.handle), _ptr(state), _ptr(mlp), _ptr(x), _ptr(t), x.shape[0],
+                               int(batch), int(iters), float(lr), _ptr(loss), _stream(stream)),
+           C.c_void_p(ctx.handle))
+
+
+def pic_qed_training_data(ctx: Context, n: int, seed: int, x, t, stream=None):
+    _check(lib().pic_qed_training_data(C.c_void_p(ctx.handle), int(n), int(seed), _ptr(x), _ptr(t),
+                                       _stream(stream)), C.c_void_p(ctx.handle))
+
+
+def pic_qed_table_lookup(ctx: Context, proc: int, what: int, chi, r, out, stream=None):
+    _check(lib().pic_qed_table_lookup(C.c_void_p(ctx.handle), int(proc), int(what), _ptr(chi), _ptr(r),
+                                      chi.shape[0], _ptr(out), _stream(stream)), C.c_void_p(ctx.handle))

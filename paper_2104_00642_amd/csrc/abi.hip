@@ -86,6 +86,8 @@ static int ceil_log2(int64_t v) {
 
 static bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
+extern "C" void pic_destroy(void *ctx);
+
 extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
     if (!out) return fail(nullptr, PIC_E_ARG, "out is NULL");
     *out = nullptr;
@@ -188,6 +190,14 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
         delete c;
         return PIC_E_NOMEM;
     }
+    if (cfg->hbar_omega_mc2 > 0.0) {
+        e = build_qed_tables(&c->qed, nullptr);
+        if (e != hipSuccess) {
+            pic_status st = hip_fail(nullptr, e, "pic_init: QED tables");
+            pic_destroy(c);
+            return st;
+        }
+    }
     *out = c;
     return PIC_OK;
 }
@@ -205,6 +215,8 @@ extern "C" void pic_destroy(void *ctx) {
     }
     hipFree(c->hist);
     hipFree(c->final_perm);
+    hipFree(c->qed.dev);
+    hipFree(c->mlp_scratch);
     delete c;
 }
 
@@ -293,6 +305,8 @@ extern "C" pic_status pic_sort(void *ctx, const pic_particles *src, const pic_pa
         if ((src->w != nullptr) != (dst->w != nullptr) && src->w)
             return fail(c, PIC_E_ARG, "src has weights but dst has none");
         if (src->chi && !dst->chi) return fail(c, PIC_E_ARG, "src has chi but dst has none");
+        if ((src->tau && !dst->tau) || (src->tau_thr && !dst->tau_thr) || (src->id && !dst->id))
+            return fail(c, PIC_E_ARG, "src has QED arrays that dst lacks");
     }
     hipSetDevice(c->device);
     if (src->n > 0) {
@@ -319,5 +333,116 @@ extern "C" pic_status pic_check(void *ctx, void *stream, uint32_t *flags, uint64
     if (h[0] & PIC_F_CAPACITY) return fail(c, PIC_E_CAPACITY, "particle creation hit capacity");
     if (h[0] & (PIC_F_NONFINITE | PIC_F_OFFSET))
         return fail(c, PIC_E_STATE, "non-finite momentum or offset outside [0,1) seen");
+    return PIC_OK;
+}
+
+static pic_status check_qed_species(Ctx *c, const pic_particles *p, const char *name) {
+    if (!p) return PIC_OK;
+    if (p->n < 0 || p->n > p->capacity)
+        return fail(c, PIC_E_ARG, std::string(name) + ": need 0 <= n <= capacity");
+    if (p->n == 0 && p->capacity == 0) return PIC_OK;
+    if (!p->cell || !p->u[0] || !p->u[1] || !p->u[2] || !p->tau || !p->tau_thr || !p->id || !p->n_dev)
+        return fail(c, PIC_E_ARG, std::string(name) + ": cell, u, tau, tau_thr, id and n_dev are required");
+    for (int a = 0; a < c->dim; ++a)
+        if (!p->off[a]) return fail(c, PIC_E_ARG, std::string(name) + ": offset array is NULL");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_qed_step(void *ctx, const pic_qed_args *qa, void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (!qa) return fail(c, PIC_E_ARG, "args is NULL");
+    if (c->cfg.precision != PIC_FP32_MIXED)
+        return fail(c, PIC_E_UNSUPPORTED, "pic_qed_step works on the FP32 particle layout");
+    if (!(c->cfg.hbar_omega_mc2 > 0.0) || !c->qed.dev)
+        return fail(c, PIC_E_ARG, "QED needs hbar_omega_mc2 > 0 at pic_init");
+    if (qa->mode != PIC_QED_TABLE && qa->mode != PIC_QED_MLP) return fail(c, PIC_E_ARG, "bad mode");
+    if (qa->mode == PIC_QED_MLP && !qa->mlp) return fail(c, PIC_E_ARG, "PIC_QED_MLP needs a network");
+    pic_status st = check_fields(c, qa->fields);
+    if (st != PIC_OK) return st;
+    const pic_particles *sp[3] = {qa->electrons, qa->positrons, qa->photons};
+    const char *names[3] = {"electrons", "positrons", "photons"};
+    int64_t nmax = 0;
+    for (int k = 0; k < 3; ++k) {
+        st = check_qed_species(c, sp[k], names[k]);
+        if (st != PIC_OK) return st;
+        if (sp[k] && k < 2 && sp[k]->n > 0 && !sp[k]->chi)
+            return fail(c, PIC_E_ARG, "leptons need the chi array written by the push");
+        if (sp[k] && sp[k]->n > nmax) nmax = sp[k]->n;
+    }
+    hipSetDevice(c->device);
+    if (qa->mode == PIC_QED_MLP && (size_t)(2 * nmax) > c->mlp_scratch_cap) {
+        hipDeviceSynchronize();
+        hipFree(c->mlp_scratch);
+        c->mlp_scratch = nullptr;
+        c->mlp_scratch_cap = 0;
+        const size_t cap = (size_t)(2 * nmax) + (size_t)nmax / 2 + 1024;
+        if (hipMalloc(&c->mlp_scratch, cap * sizeof(float)) != hipSuccess)
+            return fail(c, PIC_E_NOMEM, "cannot allocate network outputs");
+        c->mlp_scratch_cap = cap;
+    }
+    hipError_t e = launch_qed(c, qa, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_qed_step");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_mlp_forward(void *ctx, const void *mlp, const float *x, int64_t n, float *y,
+                                      void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (!mlp || (n > 0 && (!x || !y)) || n < 0) return fail(c, PIC_E_ARG, "null or bad argument");
+    hipSetDevice(c->device);
+    hipError_t e = launch_mlp_forward(mlp, x, n, y, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_mlp_forward");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_mlp_grad(void *ctx, const void *mlp, const float *x, const float *t, int64_t n,
+                                   float *grad, float *loss, void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (!mlp || !x || !t || !grad || n <= 0) return fail(c, PIC_E_ARG, "null or bad argument");
+    hipSetDevice(c->device);
+    hipError_t e = launch_mlp_grad(mlp, x, t, n, grad, loss, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_mlp_grad");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_mlp_train(void *ctx, float *state, void *mlp, const float *x, const float *t,
+                                    int64_t n, int32_t batch, int32_t iters, float lr, float *loss,
+                                    void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (!state || !mlp || !x || !t || n <= 0 || batch <= 0 || iters < 0 || !(lr > 0.0f))
+        return fail(c, PIC_E_ARG, "null or bad argument");
+    hipSetDevice(c->device);
+    hipError_t e = launch_mlp_train(state, mlp, x, t, n, batch, iters, lr, loss, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_mlp_train");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_qed_training_data(void *ctx, int64_t n, uint64_t seed, float *x, float *t,
+                                            void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (!c->qed.dev) return fail(c, PIC_E_ARG, "QED needs hbar_omega_mc2 > 0 at pic_init");
+    if (n < 0 || (n > 0 && (!x || !t))) return fail(c, PIC_E_ARG, "null or bad argument");
+    hipSetDevice(c->device);
+    hipError_t e = launch_mlp_data(c, n, seed, x, t, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_qed_training_data");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_qed_table_lookup(void *ctx, int32_t proc, int32_t what, const float *chi,
+                                           const float *r, int64_t n, float *out, void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (!c->qed.dev) return fail(c, PIC_E_ARG, "QED needs hbar_omega_mc2 > 0 at pic_init");
+    if ((proc != 0 && proc != 1) || (what != 0 && what != 1) || n < 0 ||
+        (n > 0 && (!chi || !out || (what == 1 && !r))))
+        return fail(c, PIC_E_ARG, "null or bad argument");
+    hipSetDevice(c->device);
+    hipError_t e = launch_qed_lookup(c, proc, what, chi, r, n, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_qed_table_lookup");
     return PIC_OK;
 }

@@ -439,6 +439,71 @@ __global__ void __launch_bounds__(256) gpd_tiled_kernel(TiledArgs a) {
     }
 }
 
+// Particles after the last tile (created since the last sort, e.g. by the QED
+// step) take the global-memory path; a fixed grid strides over them.
+constexpr int TAIL_BLOCKS = 256;
+
+template <int DIM, int ORDER>
+__global__ void __launch_bounds__(256) gpd_tail_kernel(TiledArgs a, int64_t n) {
+    const int64_t first = a.tile_start[a.ntiles];
+    __shared__ double red_k[256], red_q[256];
+    double kin = 0.0, chg = 0.0;
+    GlobAcc glob{{a.F[0], a.F[1], a.F[2], a.F[3], a.F[4], a.F[5]},
+                 {a.J[0], a.J[1], a.J[2]},
+                 {a.ng[0], a.ng[1], a.ng[2]}, 1.0f};
+    const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
+    for (int64_t p = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t cell = a.cell[p];
+        int cc[3] = {cell & mx, (cell >> a.bx) & my, DIM == 3 ? (cell >> (a.bx + a.by)) : 0};
+        float f[3] = {a.off[0][p], a.off[1][p], DIM == 3 ? a.off[2][p] : 0.0f};
+        float u[3] = {a.u[0][p], a.u[1][p], a.u[2][p]};
+        const float w = a.w ? a.w[p] : a.w0;
+        const float u_old[3] = {u[0], u[1], u[2]};
+        float EB[6];
+        int dc[3] = {0, 0, 0};
+        push_one<DIM, ORDER>(glob, a, cc, f, u, w, dc, EB);
+        int packed = 0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            int nc = cc[d] + dc[d];
+            nc = nc < 0 ? nc + a.ng[d] : (nc >= a.ng[d] ? nc - a.ng[d] : nc);
+            packed |= nc << (d == 0 ? 0 : (d == 1 ? a.bx : a.bx + a.by));
+            a.off[d][p] = f[d];
+        }
+        a.cell[p] = packed;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.u[d][p] = u[d];
+        if (a.chi) {
+            const float uh0 = 0.5f * (u_old[0] + u[0]), uh1 = 0.5f * (u_old[1] + u[1]),
+                        uh2 = 0.5f * (u_old[2] + u[2]);
+            const float gh = sqrtf(1.0f + uh0 * uh0 + uh1 * uh1 + uh2 * uh2);
+            const float f0 = gh * EB[0] + uh1 * EB[5] - uh2 * EB[4];
+            const float f1 = gh * EB[1] + uh2 * EB[3] - uh0 * EB[5];
+            const float f2 = gh * EB[2] + uh0 * EB[4] - uh1 * EB[3];
+            const float ue = uh0 * EB[0] + uh1 * EB[1] + uh2 * EB[2];
+            a.chi[p] = a.chi_scale * sqrtf(fmaxf(f0 * f0 + f1 * f1 + f2 * f2 - ue * ue, 0.0f));
+        }
+        const float g1 = sqrtf(1.0f + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        kin += (double)w * (double)(g1 - 1.0f);
+        chg += (double)w;
+    }
+    red_k[threadIdx.x] = kin;
+    red_q[threadIdx.x] = chg;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            red_k[threadIdx.x] += red_k[threadIdx.x + h];
+            red_q[threadIdx.x] += red_q[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.partials[2 * (a.ntiles + blockIdx.x)] = red_k[0] * a.mdV;
+        a.partials[2 * (a.ntiles + blockIdx.x) + 1] = red_q[0] * a.qdV;
+    }
+}
+
 hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *p,
                             const pic_fields *f, double *diag, hipStream_t s) {
     const pic_config &cfg = c->cfg;
@@ -478,21 +543,34 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
     a.qdV = sp->q * dV;
     a.status = c->status;
     a.stragglers = (unsigned long long *)(c->status + 2);
-    if (ensure_partials(c, 2 * (size_t)c->ntiles) != PIC_OK) return hipErrorOutOfMemory;
+    if (ensure_partials(c, 2 * ((size_t)c->ntiles + TAIL_BLOCKS)) != PIC_OK) return hipErrorOutOfMemory;
     a.partials = c->partials;
-    dim3 grid((unsigned)(8 * a.chunk)), block(256);
+    dim3 grid((unsigned)(8 * a.chunk)), block(256), tgrid(TAIL_BLOCKS);
     const size_t lds = c->lds_bytes;
     const int key = c->dim * 10 + cfg.order;
+    const int64_t n = p->n;
     switch (key) {
-        case 21: gpd_tiled_kernel<2, 1><<<grid, block, lds, s>>>(a); break;
-        case 22: gpd_tiled_kernel<2, 2><<<grid, block, lds, s>>>(a); break;
-        case 31: gpd_tiled_kernel<3, 1><<<grid, block, lds, s>>>(a); break;
-        case 32: gpd_tiled_kernel<3, 2><<<grid, block, lds, s>>>(a); break;
+        case 21:
+            gpd_tiled_kernel<2, 1><<<grid, block, lds, s>>>(a);
+            gpd_tail_kernel<2, 1><<<tgrid, block, 0, s>>>(a, n);
+            break;
+        case 22:
+            gpd_tiled_kernel<2, 2><<<grid, block, lds, s>>>(a);
+            gpd_tail_kernel<2, 2><<<tgrid, block, 0, s>>>(a, n);
+            break;
+        case 31:
+            gpd_tiled_kernel<3, 1><<<grid, block, lds, s>>>(a);
+            gpd_tail_kernel<3, 1><<<tgrid, block, 0, s>>>(a, n);
+            break;
+        case 32:
+            gpd_tiled_kernel<3, 2><<<grid, block, lds, s>>>(a);
+            gpd_tail_kernel<3, 2><<<tgrid, block, 0, s>>>(a, n);
+            break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !diag) return e;
-    return launch_finalize(c->partials, c->ntiles, 2, diag, 0, 1.0, s);
+    return launch_finalize(c->partials, c->ntiles + TAIL_BLOCKS, 2, diag, 0, 1.0, s);
 }
 
 hipError_t set_tiled_lds_limit(size_t bytes) {

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/pic.h"
+#include "qed_internal.h"
 
 namespace pic {
 
@@ -33,6 +34,10 @@ struct Ctx {
     uint32_t *final_perm = nullptr;
     size_t sort_cap = 0;         // elements
     size_t hist_cap = 0;         // entries
+    // QED tables (built at init when hbar_omega_mc2 > 0) and network outputs
+    QedTables qed;
+    float *mlp_scratch = nullptr;
+    size_t mlp_scratch_cap = 0;  // floats
     std::string err;
 };
 
@@ -48,6 +53,15 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
 hipError_t launch_yee(Ctx *c, int half, const pic_fields *f, double *diag, hipStream_t s);
 hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *dst,
                        hipStream_t s);
+hipError_t launch_qed(Ctx *c, const pic_qed_args *qa, hipStream_t s);
+hipError_t launch_qed_lookup(Ctx *c, int proc, int what, const float *chi, const float *r, int64_t n,
+                             float *out, hipStream_t s);
+hipError_t launch_mlp_forward(const void *mlp, const float *x, int64_t n, float *y, hipStream_t s);
+hipError_t launch_mlp_grad(const void *mlp, const float *x, const float *t, int64_t n, float *grad, float *loss,
+                           hipStream_t s);
+hipError_t launch_mlp_train(float *state, void *mlp, const float *x, const float *t, int64_t n, int batch,
+                            int iters, float lr, float *loss, hipStream_t s);
+hipError_t launch_mlp_data(Ctx *c, int64_t n, uint64_t seed, float *x, float *t, hipStream_t s);
 hipError_t launch_finalize(const double *partials, int64_t nblocks, int nval, double *diag,
                            int diag_offset, double scale, hipStream_t s);
 

@@ -1,0 +1,302 @@
+// qed.hip -- Monte-Carlo nonlinear Compton and Breit-Wheeler step (Sec. IV),
+// Method I in optical-depth form: every lepton and photon carries an FP64
+// optical depth tau and a threshold tau_thr = -ln r; tau += W dt each step
+// (W the total rate of Eq. 23 or 24); when tau reaches tau_thr the event
+// happens, its energy is drawn from the inverse cumulative spectrum with a
+// second uniform, and tau restarts from 0 with a fresh threshold.
+//   leptons: photon of energy u gamma along u (recoil u <- u (1 - eps/|u|));
+//            photons under `photon_min_energy` are not created;
+//   photons: move ballistically, chi_gamma from the fields at their position;
+//            above 2 m c^2 decay into e+ (x eps) and e- ((1-x) eps) along k.
+// Created particles are appended with an atomic counter (dropped and flagged
+// beyond capacity); their identifiers derive from the parent's, so every
+// random number depends only on (seed, identifier, step).
+#include "device_common.h"
+#include "pic_internal.h"
+#include "qed_internal.h"
+
+namespace pic {
+
+constexpr double QED_ALPHA = 1.0 / 137.035999084;
+constexpr double QED_A = QED_ALPHA / (1.7320508075688772 * 3.14159265358979323846);
+
+struct QedSpecies {
+    int32_t *cell;
+    float *off[3];
+    float *u[3];
+    float *w;
+    float *chi;
+    double *tau;
+    float *tau_thr;
+    uint64_t *id;
+    int64_t n;
+    int64_t capacity;
+    unsigned long long *n_dev;
+};
+
+struct QedArgs {
+    QedSpecies sp[3];  // electrons, positrons, photons
+    int has[3];
+    const float *F[6];
+    const float *tab;
+    const float *mlp_out;  // per particle (F, sample) from the network, or NULL
+    int ng[3];
+    int bx, by, dim, order;
+    float inv_d[3];
+    float dt;
+    double rate_scale;     // alpha/(sqrt3 pi) * m c^2/(hbar w_r)
+    float hbar_w;
+    float emin;
+    uint64_t seed;
+    uint32_t step;
+    uint32_t *status;
+};
+
+__device__ bool qed_append(const QedArgs &a, int s, int32_t cell, const float *off, const float *u, float w,
+                           uint64_t id) {
+    const QedSpecies &d = a.sp[s];
+    const unsigned long long idx = atomicAdd(d.n_dev, 1ull);
+    if ((int64_t)idx >= d.capacity) {
+        atomicOr(a.status, PIC_F_CAPACITY);
+        atomicAdd(d.n_dev, ~0ull);  // undo: the slot does not exist
+        return false;
+    }
+    d.cell[idx] = cell;
+    for (int k = 0; k < a.dim; ++k) d.off[k][idx] = off[k];
+    for (int k = 0; k < 3; ++k) d.u[k][idx] = u[k];
+    if (d.w) d.w[idx] = w;
+    if (d.chi) d.chi[idx] = 0.0f;
+    d.tau[idx] = 0.0;
+    double r0, r1;
+    qed_uniforms(a.seed, id, a.step, 1u, r0, r1);
+    d.tau_thr[idx] = (float)(-log(r0));
+    d.id[idx] = id;
+    return true;
+}
+
+// one thread per lepton of species s (0 electrons, 1 positrons)
+__global__ void __launch_bounds__(256) qed_lepton_kernel(QedArgs a, int s) {
+    const QedSpecies &L = a.sp[s];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= L.n) return;
+    const float w = L.w ? L.w[p] : 1.0f;
+    if (w == 0.0f) return;
+    float u[3] = {L.u[0][p], L.u[1][p], L.u[2][p]};
+    const float chi = L.chi[p];
+    const float pu2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const float gam = sqrtf(1.0f + pu2);
+    const float F = a.mlp_out ? a.mlp_out[2 * p] : qed_rate_F(a.tab, QED_COMPTON, chi);
+    double tau = L.tau[p] + a.rate_scale * (double)F / (double)gam * (double)a.dt;
+    if (tau >= (double)L.tau_thr[p] && chi > 0.0f) {
+        const uint64_t id = L.id[p];
+        double ru, rt;
+        qed_uniforms(a.seed, id, a.step, 0u, ru, rt);
+        const float uf = a.mlp_out ? a.mlp_out[2 * p + 1] : qed_inverse(a.tab, QED_COMPTON, chi, (float)ru);
+        const float eps = fminf(fmaxf(uf, 0.0f), 1.0f) * gam;
+        const float pm = sqrtf(pu2);
+        if (pm > 0.0f) {
+            const float k[3] = {eps * u[0] / pm, eps * u[1] / pm, eps * u[2] / pm};
+            const float f = fmaxf(0.0f, 1.0f - eps / pm);
+            if (a.has[2] && eps >= a.emin) {
+                float off[3] = {L.off[0][p], L.off[1][p], a.dim == 3 ? L.off[2][p] : 0.0f};
+                qed_append(a, 2, L.cell[p], off, k, w, qed_child_id(a.seed, id, a.step, 1u));
+            }
+            for (int c = 0; c < 3; ++c) L.u[c][p] = u[c] * f;
+        }
+        tau = 0.0;
+        L.tau_thr[p] = (float)(-log(rt));
+    }
+    L.tau[p] = tau;
+}
+
+// photons: ballistic move, chi_gamma at the new position, pair creation
+template <int DIM, int ORDER>
+__global__ void __launch_bounds__(256) qed_photon_kernel(QedArgs a) {
+    const QedSpecies &P = a.sp[2];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.n) return;
+    const float w = P.w ? P.w[p] : 1.0f;
+    if (w == 0.0f) return;
+    const float k[3] = {P.u[0][p], P.u[1][p], P.u[2][p]};
+    const float eps = sqrtf(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    if (!(eps > 0.0f)) return;
+    const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
+    const int32_t cell = P.cell[p];
+    int cc[3] = {cell & mx, (cell >> a.bx) & my, DIM == 3 ? (cell >> (a.bx + a.by)) : 0};
+    float f[3] = {P.off[0][p], P.off[1][p], DIM == 3 ? P.off[2][p] : 0.0f};
+    // move at c along k
+    int packed = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const float x = f[d] + a.dt * a.inv_d[d] * k[d] / eps;
+        const float fl = floorf(x);
+        float fr = x - fl;
+        int di = (int)fl;
+        if (fr >= 1.0f) {
+            fr = 0.0f;
+            ++di;
+        }
+        int nc = cc[d] + di;
+        nc = ((nc % a.ng[d]) + a.ng[d]) % a.ng[d];
+        cc[d] = nc;
+        f[d] = fr;
+        P.off[d][p] = fr;
+        packed |= nc << (d == 0 ? 0 : (d == 1 ? a.bx : a.bx + a.by));
+    }
+    P.cell[p] = packed;
+    // fields at the photon (Eq. 19 with the push's weights)
+    constexpr int NW = ORDER + 1;
+    int i0[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    float wt[2][3][NW];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        shape_weights<ORDER>(f[d], i0[0][d], wt[0][d]);
+        shape_weights<ORDER>(f[d] - 0.5f, i0[1][d], wt[1][d]);
+    }
+    float EB[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const int sx = stag(c, 0), sy = stag(c, 1), sz = DIM == 3 ? stag(c, 2) : 0;
+        float acc = 0.0f;
+#pragma unroll
+        for (int kk = 0; kk < (DIM == 3 ? NW : 1); ++kk)
+#pragma unroll
+            for (int jj = 0; jj < NW; ++jj)
+#pragma unroll
+                for (int ii = 0; ii < NW; ++ii) {
+                    const int gi = wrap_index(cc[0] + i0[sx][0] + ii, a.ng[0]);
+                    const int gj = wrap_index(cc[1] + i0[sy][1] + jj, a.ng[1]);
+                    const int gk = DIM == 3 ? wrap_index(cc[2] + i0[sz][2] + kk, a.ng[2]) : 0;
+                    const float wk = DIM == 3 ? wt[sz][2][kk] : 1.0f;
+                    acc += wt[sx][0][ii] * wt[sy][1][jj] * wk *
+                           a.F[c][(int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk)];
+                }
+        EB[c] = acc;
+    }
+    const float f0 = eps * EB[0] + k[1] * EB[5] - k[2] * EB[4];
+    const float f1 = eps * EB[1] + k[2] * EB[3] - k[0] * EB[5];
+    const float f2 = eps * EB[2] + k[0] * EB[4] - k[1] * EB[3];
+    const float ke = k[0] * EB[0] + k[1] * EB[1] + k[2] * EB[2];
+    const float chi = a.hbar_w * sqrtf(fmaxf(f0 * f0 + f1 * f1 + f2 * f2 - ke * ke, 0.0f));
+    if (P.chi) P.chi[p] = chi;
+    const float F = a.mlp_out ? a.mlp_out[2 * p] : qed_rate_F(a.tab, QED_PAIR, chi);
+    double tau = P.tau[p] + a.rate_scale * (double)F / (double)eps * (double)a.dt;
+    if (tau >= (double)P.tau_thr[p] && eps > 2.0f && chi > 0.0f) {
+        const uint64_t id = P.id[p];
+        double rx, rn;
+        qed_uniforms(a.seed, id, a.step, 0u, rx, rn);
+        const float x = a.mlp_out ? a.mlp_out[2 * p + 1] : qed_inverse(a.tab, QED_PAIR, chi, (float)rx);
+        const float xs = fminf(fmaxf(x, 0.0f), 1.0f);
+        const float ep = xs * eps, em = (1.0f - xs) * eps;
+        const float np_ = sqrtf(fmaxf(ep * ep - 1.0f, 0.0f)) / eps, nm = sqrtf(fmaxf(em * em - 1.0f, 0.0f)) / eps;
+        const float up[3] = {np_ * k[0], np_ * k[1], np_ * k[2]};
+        const float um[3] = {nm * k[0], nm * k[1], nm * k[2]};
+        if (a.has[1]) qed_append(a, 1, packed, f, up, w, qed_child_id(a.seed, id, a.step, 2u));
+        if (a.has[0]) qed_append(a, 0, packed, f, um, w, qed_child_id(a.seed, id, a.step, 3u));
+        if (P.w) P.w[p] = 0.0f;  // the photon is gone
+        tau = 0.0;
+    }
+    P.tau[p] = tau;
+}
+
+hipError_t launch_mlp_for_qed(Ctx *c, const void *mlp, const QedSpeciesView &v, int proc, float *out,
+                              hipStream_t s);
+
+static QedSpecies view_of(const pic_particles *p, int dim) {
+    QedSpecies q{};
+    q.cell = p->cell;
+    for (int d = 0; d < 3; ++d) {
+        q.off[d] = p->off[d];
+        q.u[d] = (float *)p->u[d];
+    }
+    q.w = (float *)p->w;
+    q.chi = p->chi;
+    q.tau = p->tau;
+    q.tau_thr = p->tau_thr;
+    q.id = p->id;
+    q.n = p->n;
+    q.capacity = p->capacity;
+    q.n_dev = (unsigned long long *)p->n_dev;
+    (void)dim;
+    return q;
+}
+
+hipError_t launch_qed(Ctx *c, const pic_qed_args *qa, hipStream_t s) {
+    const pic_config &cfg = c->cfg;
+    QedArgs a{};
+    const pic_particles *sp[3] = {qa->electrons, qa->positrons, qa->photons};
+    for (int k = 0; k < 3; ++k) {
+        a.has[k] = sp[k] != nullptr;
+        if (sp[k]) a.sp[k] = view_of(sp[k], c->dim);
+    }
+    for (int d = 0; d < 3; ++d) {
+        a.F[d] = (const float *)qa->fields->E[d];
+        a.F[3 + d] = (const float *)qa->fields->B[d];
+        a.ng[d] = (int)cfg.n[d];
+        a.inv_d[d] = (float)(1.0 / cfg.d[d]);
+    }
+    a.tab = c->qed.dev;
+    a.bx = c->bits[0];
+    a.by = c->bits[1];
+    a.dim = c->dim;
+    a.order = cfg.order;
+    a.dt = (float)cfg.dt;
+    a.rate_scale = QED_A / cfg.hbar_omega_mc2;
+    a.hbar_w = (float)cfg.hbar_omega_mc2;
+    a.emin = (float)qa->photon_min_energy;
+    a.seed = cfg.seed;
+    a.step = qa->step;
+    a.status = c->status;
+    // photons first (their pairs are created from this step's photons only),
+    // then the leptons that existed at the start of the step
+    if (sp[2] && sp[2]->n > 0) {
+        QedArgs ap = a;
+        if (qa->mode == PIC_QED_MLP) {
+            QedSpeciesView v{sp[2]->chi, sp[2]->id, (const float *)sp[2]->w, sp[2]->n, cfg.seed, qa->step};
+            hipError_t e = launch_mlp_for_qed(c, qa->mlp, v, QED_PAIR, c->mlp_scratch, s);
+            if (e != hipSuccess) return e;
+            ap.mlp_out = c->mlp_scratch;
+        }
+        const unsigned nb = (unsigned)((sp[2]->n + 255) / 256);
+        const int key = c->dim * 10 + cfg.order;
+        switch (key) {
+            case 21: qed_photon_kernel<2, 1><<<nb, 256, 0, s>>>(ap); break;
+            case 22: qed_photon_kernel<2, 2><<<nb, 256, 0, s>>>(ap); break;
+            case 31: qed_photon_kernel<3, 1><<<nb, 256, 0, s>>>(ap); break;
+            case 32: qed_photon_kernel<3, 2><<<nb, 256, 0, s>>>(ap); break;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (!sp[k] || sp[k]->n == 0) continue;
+        QedArgs al = a;
+        if (qa->mode == PIC_QED_MLP) {
+            QedSpeciesView v{sp[k]->chi, sp[k]->id, (const float *)sp[k]->w, sp[k]->n, cfg.seed, qa->step};
+            hipError_t e = launch_mlp_for_qed(c, qa->mlp, v, QED_COMPTON, c->mlp_scratch, s);
+            if (e != hipSuccess) return e;
+            al.mlp_out = c->mlp_scratch;
+        }
+        qed_lepton_kernel<<<(unsigned)((sp[k]->n + 255) / 256), 256, 0, s>>>(al, k);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// table lookups exposed for the tests (one thread per query)
+__global__ void qed_lookup_kernel(const float *tab, int proc, int what, const float *chi, const float *r,
+                                  int64_t n, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = what == 0 ? qed_rate_F(tab, proc, chi[i]) : qed_inverse(tab, proc, chi[i], r[i]);
+}
+
+hipError_t launch_qed_lookup(Ctx *c, int proc, int what, const float *chi, const float *r, int64_t n,
+                             float *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    qed_lookup_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(c->qed.dev, proc, what, chi, r, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace pic

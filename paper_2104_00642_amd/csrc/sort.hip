@@ -203,9 +203,12 @@ __global__ void __launch_bounds__(256) tile_bounds_kernel(const uint32_t *keys, 
 struct PermArgs {
     const int32_t *cell_in;
     int32_t *cell_out;
-    const float *fin[8];
-    float *fout[8];
+    const float *fin[9];
+    float *fout[9];
     int nf;
+    const uint64_t *din[2];  // 8-byte arrays: optical depth, identifiers
+    uint64_t *dout[2];
+    int nd;
 };
 
 __global__ void __launch_bounds__(256) tile_order_kernel(const uint32_t *vals, const int64_t *tile_start,
@@ -327,8 +330,11 @@ __global__ void __launch_bounds__(256) tile_order_kernel(const uint32_t *vals, c
             if (j < n_t) {
                 pa.cell_out[ts + j] = pa.cell_in[src[u]];
 #pragma unroll
-                for (int k = 0; k < 8; ++k)
+                for (int k = 0; k < 9; ++k)
                     if (k < pa.nf) pa.fout[k][ts + j] = pa.fin[k][src[u]];
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    if (k < pa.nd) pa.dout[k][ts + j] = pa.din[k][src[u]];
             }
         }
     }
@@ -390,7 +396,21 @@ hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *ds
         pa.fin[nf] = src->chi;
         pa.fout[nf++] = dst->chi;
     }
+    if (src->tau_thr) {
+        pa.fin[nf] = src->tau_thr;
+        pa.fout[nf++] = dst->tau_thr;
+    }
     pa.nf = nf;
+    int nd = 0;
+    if (src->tau) {
+        pa.din[nd] = (const uint64_t *)src->tau;
+        pa.dout[nd++] = (uint64_t *)dst->tau;
+    }
+    if (src->id) {
+        pa.din[nd] = src->id;
+        pa.dout[nd++] = dst->id;
+    }
+    pa.nd = nd;
     int lbits = 0;
     while ((1 << lbits) < g.ct) ++lbits;
     const size_t lds = (size_t)7 * g.ct * sizeof(uint32_t);

@@ -60,6 +60,22 @@ def alg_bytes_per_particle(dim, real_bytes, ppc, with_w=True):
     return s_read + s_write + 9 * real_bytes / ppc
 
 
+def tile_order(wl, args, torch, L, Simulation):
+    """Permutation that puts the workload's particles in the library's tile
+    order (an index carried through one pic_sort): the FP64 path starts from
+    the same particle order as the FP32 path."""
+    sim = Simulation.from_workload(wl, precision=L.PIC_FP32_MIXED, device="cuda",
+                                   tile=tuple(int(v) for v in args.tile.split(",")), drift=args.drift)
+    p = sim.particles[0]
+    p.id = torch.arange(p.n, dtype=torch.int64, device="cuda")
+    sim.spare[0].id = torch.empty_like(p.id)
+    sim.sort()
+    perm = sim.particles[0].id.clone()
+    del sim
+    torch.cuda.empty_cache()
+    return perm
+
+
 def run_path(args, wl, precision, torch, L, Simulation):
     sim = Simulation.from_workload(wl, precision=precision, device="cuda",
                                    sort_every=args.sort_every,
@@ -204,7 +220,13 @@ def main():
     for prec in ([L.PIC_FP32_MIXED] if args.no_fp64 else [L.PIC_FP32_MIXED, L.PIC_FP64_PLAIN]):
         name = "fp32" if prec == L.PIC_FP32_MIXED else "fp64"
         log(f"running {name} path")
-        sim, n, secs, gpd_ms, status, extra = run_path(args, wl, prec, torch, L, Simulation)
+        wl_run = wl
+        if prec == L.PIC_FP64_PLAIN:
+            from paper_2104_00642_amd.workloads import Workload
+            perm = tile_order(wl, args, torch, L, Simulation)
+            q, m, raw = wl.species[0]
+            wl_run = Workload(wl.name, wl.cfg, [(q, m, raw.subset(perm))], wl.E0, wl.B0, wl.steps)
+        sim, n, secs, gpd_ms, status, extra = run_path(args, wl_run, prec, torch, L, Simulation)
         err = sampled_error(sim, torch, L, O)
         rb = 4 if prec == L.PIC_FP32_MIXED else 8
         bpp = alg_bytes_per_particle(2, rb, ppc)

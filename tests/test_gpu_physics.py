@@ -1,0 +1,148 @@
+"""Whole-run checks on the GPU against the FP64 oracle: the 64x64 Langmuir
+case for 200 steps, the 1000-step self-heating energy drift (the 2D
+benchmark of Sec. III, Fig. 6) and the cold Langmuir frequency."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2104_00642_amd import _lib as L
+from paper_2104_00642_amd.sim import Simulation
+from paper_2104_00642_amd.workloads import (ME_KEV, RawParticles, Workload, courant_dt, langmuir_2d, plasma,
+                                            to_fp64)
+
+from _helpers import np64, oracle_grid, rel_l2
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def oracle_state(wl, from_fp32):
+    cfg = wl.cfg
+    g = oracle_grid(cfg)
+    st = O.State.zeros(g)
+    for q, m, raw in wl.species:
+        p = to_fp64(raw, cfg, from_fp32=from_fp32)
+        st.species.append(O.Species(q, m, [x.numpy().copy() for x in p.x], [u.numpy().copy() for u in p.u],
+                                    p.w.numpy().copy()))
+    return st
+
+
+def test_langmuir_64x64_cic_200_steps_matches_oracle():
+    """The 2D3V periodic Langmuir case (64x64, 16 electrons per cell, CIC,
+    dt = 0.95 Courant, FP64) run for 200 steps on the GPU and by the oracle."""
+    wl = langmuir_2d(device="cpu")
+    sim = Simulation.from_workload(wl, precision=L.PIC_FP64_PLAIN, device=DEV)
+    st = oracle_state(wl, from_fp32=False)
+    for _ in range(200):
+        sim.step()
+        O.step(st)
+    torch.cuda.synchronize()
+    for a in range(3):
+        err_e = rel_l2(np64(sim.fields.E[a]), st.E[a])
+        err_j = rel_l2(np64(sim.fields.J[a]), st.J[a])
+        print(f"component {a}: E rel L2 {err_e:.2e}, J rel L2 {err_j:.2e}")
+        assert err_e < 1e-9 and err_j < 1e-9
+    x = np64(sim.particles[0].x[0])
+    Lx = wl.cfg.n[0] * wl.cfg.d[0]
+    d = x - st.species[0].x[0]
+    assert np.abs(d - Lx * np.round(d / Lx)).max() < 1e-9
+
+
+def heating_workload(seed, n=(32, 32), ppc=8):
+    """Self-heating setup of the paper's 2D benchmark in plasma units: 1 keV
+    electrons, 320 cells per plasma wavelength, periodic, quadratic shape."""
+    d = (2 * math.pi / 320,) * 2
+    cfg = L.Config(dim=2, n=n, d=d, dt=courant_dt(d), order=2, seed=seed, tile=(16, 16))
+    gen = torch.Generator().manual_seed(seed)
+    raw = plasma(cfg, ppc, lambda x: torch.ones_like(x), gen, "cpu", uth=math.sqrt(1.0 / ME_KEV))
+    return Workload(f"heating_{seed}", cfg, [(-1.0, 1.0, raw)])
+
+
+def energy_history(sim, steps, every=50):
+    out = []
+    for s in range(steps):
+        diag = (s + 1) % every == 0
+        if diag:
+            sim.diag.zero_()
+        sim.step(with_diag=diag)
+        if diag:
+            d = sim.diag.cpu().numpy()
+            out.append(d[0] + d[2])
+    return np.array(out)
+
+
+def test_energy_drift_1000_steps_matches_oracle():
+    """1000-step relative energy drift D = (U_1000 - U_0)/U_0 of the FP32 and
+    FP64 GPU paths against the oracle's: within 1% of the oracle's drift, or
+    within twice the seed-to-seed spread of D when that is larger."""
+    steps = 1000
+    wl = heating_workload(7)
+    st = oracle_state(wl, from_fp32=True)
+    U0 = O.total_energy(st)
+    hist_o = []
+    for s in range(steps):
+        O.step(st)
+        if (s + 1) % 50 == 0:
+            hist_o.append(O.total_energy(st))
+    D_orc = (hist_o[-1] - U0) / U0
+    drifts = {}
+    for prec in (L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED):
+        sim = Simulation.from_workload(wl, precision=prec, device=DEV, sort_every=16, from_fp32=True)
+        h = energy_history(sim, steps)
+        drifts[prec] = (h[-1] - U0) / U0
+        # energy histories agree along the run
+        assert np.max(np.abs(h - np.array(hist_o)) / U0) < (1e-9 if prec == L.PIC_FP64_PLAIN else 1e-3)
+    spread = []
+    for seed in range(11, 16):
+        w = heating_workload(seed)
+        sim = Simulation.from_workload(w, precision=L.PIC_FP32_MIXED, device=DEV, sort_every=16)
+        u0 = sum(O.kinetic_energy(oracle_grid(w.cfg), s) for s in oracle_state(w, True).species)
+        h = energy_history(sim, steps)
+        spread.append((h[-1] - u0) / u0)
+    sigma = float(np.std(spread))
+    tol = max(0.01 * abs(D_orc), 2 * sigma)
+    rel32 = abs(drifts[L.PIC_FP32_MIXED] - D_orc) / abs(D_orc)
+    print(f"drift: oracle {D_orc:.3e}, GPU FP64 {drifts[L.PIC_FP64_PLAIN]:.3e}, GPU FP32 "
+          f"{drifts[L.PIC_FP32_MIXED]:.3e} ({rel32:.2%} of the oracle's); seed spread sigma {sigma:.2e}; "
+          f"tolerance {tol:.2e} ({'1% rule' if tol == 0.01 * abs(D_orc) else '2 sigma rule'})")
+    assert abs(drifts[L.PIC_FP64_PLAIN] - D_orc) <= 0.01 * abs(D_orc) + 1e-12
+    assert abs(drifts[L.PIC_FP32_MIXED] - D_orc) <= tol
+
+
+@pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
+def test_cold_langmuir_frequency(precision):
+    """Cold Langmuir oscillation: leapfrog frequency (2/dt) asin(w_p dt/2),
+    measured within 1% on the GPU (quiet 4x4 lattice, u_x = 0.001 sin kx)."""
+    n = (64, 32)
+    d = (0.05, 0.05)
+    dt = courant_dt(d)
+    cfg = L.Config(dim=2, n=n, d=d, dt=dt, order=1, precision=precision, tile=(16, 16))
+    ppc = (4, 4)
+    gx, gy = torch.meshgrid(torch.arange(n[0] * ppc[0]), torch.arange(n[1] * ppc[1]), indexing="ij")
+    xs = (gx.reshape(-1).double() + 0.5) / ppc[0]
+    ys = (gy.reshape(-1).double() + 0.5) / ppc[1]
+    k = 2 * math.pi / (n[0] * d[0])
+    cells = [xs.floor().long(), ys.floor().long()]
+    off = [xs - xs.floor(), ys - ys.floor()]
+    N = xs.numel()
+    u = [0.001 * torch.sin(k * xs * d[0]), torch.zeros(N, dtype=torch.float64), torch.zeros(N, dtype=torch.float64)]
+    raw = RawParticles(cells, off, u, torch.full((N,), 1.0 / 16, dtype=torch.float64))
+    sim = Simulation.from_workload(Workload("cold", cfg, [(-1.0, 1.0, raw)]), precision=precision, device=DEV)
+    xe = (np.arange(n[0]) + 0.5) * d[0]
+    sig = []
+    steps = 400
+    for _ in range(steps):
+        sim.step()
+        ex = np64(sim.fields.E[0])[0].mean(axis=0)
+        sig.append((ex * np.sin(k * xe)).sum())
+    sig = np.array(sig)
+    t = dt * (np.arange(steps) + 1)
+    ws = np.linspace(0.9, 1.1, 4001)
+    resid = [np.linalg.lstsq(np.c_[np.sin(w * t), np.cos(w * t)], sig, rcond=None)[1].sum() for w in ws]
+    best = ws[int(np.argmin(resid))]
+    expect = 2 / dt * math.asin(dt / 2)
+    print(f"Langmuir frequency {best:.5f} (expected {expect:.5f})")
+    assert abs(best / expect - 1) < 0.01

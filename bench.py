@@ -36,8 +36,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--tile", type=str, default="16,16")
-    ap.add_argument("--drift", type=int, default=2)
+    ap.add_argument("--workload", choices=["laser2d", "laser3d"], default="laser2d",
+                    help="laser2d: 4096x2048 2D3V (the metric's workload); laser3d: 512x256x256 3D3V")
+    ap.add_argument("--tile", type=str, default=None, help="tile in cells (default 16,16 / 8,8,4)")
+    ap.add_argument("--drift", type=int, default=None, help="drift allowance (default 2 / 1)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, copy a 1 GiB float32 buffer (HBM counter calibration)")
     return ap.parse_args()
@@ -214,14 +216,24 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     log("generating workload")
-    wl = laser_plasma_2d(scale=args.scale, device="cuda")
-    ppc = 32
+    dim = 2 if args.workload == "laser2d" else 3
+    if args.tile is None:
+        args.tile = "16,16" if dim == 2 else "8,8,4"
+    if args.drift is None:
+        args.drift = 2 if dim == 2 else 1
+    if dim == 2:
+        wl = laser_plasma_2d(scale=args.scale, device="cuda")
+        ppc = 32
+    else:
+        from paper_2104_00642_amd.workloads import laser_plasma_3d
+        wl = laser_plasma_3d(scale=args.scale, device="cuda", tile=tuple(int(v) for v in args.tile.split(",")))
+        ppc = 16  # 8 electrons + 8 ions per cell share the field cells
     out = {}
     for prec in ([L.PIC_FP32_MIXED] if args.no_fp64 else [L.PIC_FP32_MIXED, L.PIC_FP64_PLAIN]):
         name = "fp32" if prec == L.PIC_FP32_MIXED else "fp64"
         log(f"running {name} path")
         wl_run = wl
-        if prec == L.PIC_FP64_PLAIN:
+        if prec == L.PIC_FP64_PLAIN and len(wl.species) == 1:
             from paper_2104_00642_amd.workloads import Workload
             perm = tile_order(wl, args, torch, L, Simulation)
             q, m, raw = wl.species[0]
@@ -229,7 +241,7 @@ def main():
         sim, n, secs, gpd_ms, status, extra = run_path(args, wl_run, prec, torch, L, Simulation)
         err = sampled_error(sim, torch, L, O)
         rb = 4 if prec == L.PIC_FP32_MIXED else 8
-        bpp = alg_bytes_per_particle(2, rb, ppc)
+        bpp = alg_bytes_per_particle(dim, rb, ppc)
         gpd_avg = sum(gpd_ms) / len(gpd_ms)
         achieved = n * bpp / (gpd_avg * 1e-3) / 1e9
         out[name] = dict(n=n, secs=secs, gpd_ms=gpd_avg, gpd_ms_min=min(gpd_ms), err=err, status=status,
@@ -254,10 +266,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded)",
-        "config": {"workload": "laser_plasma_2d_4096x2048_ppc32_quadratic" if args.scale == 1
-                   else f"laser_plasma_2d_scale{args.scale}",
-                   "particles": r["n"], "cells": [4096 // args.scale, 2048 // args.scale],
-                   "shape": "quadratic", "tile": r["tile"][:2], "sort_every": args.sort_every,
+        "config": {"workload": wl.name if args.scale == 1 else f"{wl.name}_scale{args.scale}",
+                   "particles": r["n"], "cells": list(wl.cfg.n),
+                   "shape": "quadratic", "tile": r["tile"][:dim], "sort_every": args.sort_every,
                    "drift": args.drift, "parallelism": "single GPU"},
         "gpd_only_particle_steps_per_s": r["n"] / (r["gpd_ms"] * 1e-3),
         "gpd_ms_avg": r["gpd_ms"],
@@ -265,7 +276,7 @@ def main():
                          "stragglers_per_step": r.get("stragglers_per_step")},
         "roofline": {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "gpd_tiled_kernel<2,2>",
+                     "kernel": f"gpd_tiled_kernel<{dim},2>",
                      "alg_bytes_per_particle": r["bytes_per_particle"]},
         "error_vs_oracle": r["err"],
     }

@@ -24,6 +24,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# sources whose code makes up the tiled gather-push-deposit kernel; measured
+# HBM traffic is reported only while their hash matches the measurement's
+TILED_SOURCES = ("paper_2104_00642_amd/csrc/gpd_tiled.hip", "paper_2104_00642_amd/csrc/device_common.h",
+                 "paper_2104_00642_amd/csrc/pic_internal.h")
+
+
+def tiled_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TILED_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, n_particles):
+    """HBM bytes per launch of the tiled kernel from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs (scaled by the copy-kernel calibration), or None
+    when there is none for this workload or the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", f"gpd_tiled_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_sha256") != tiled_source_hash() or t.get("particles") != n_particles:
+        return None
+    return t["fetch_kib"] * 1024 * t["fetch_factor"] + t["write_kib"] * 1024 * t["write_factor"]
 
 
 def parse():
@@ -275,7 +302,8 @@ def main():
         "breakdown_ms": {"gpd": r["gpd_ms"], "sort_once": r.get("sort_ms"), "yee_step": r.get("yee_ms"),
                          "stragglers_per_step": r.get("stragglers_per_step")},
         "roofline": {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": r["achieved_gbs"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(wl.name, r["n"]) if args.scale == 1 else None,
                      "kernel": f"gpd_tiled_kernel<{dim},2>",
                      "alg_bytes_per_particle": r["bytes_per_particle"]},
         "error_vs_oracle": r["err"],

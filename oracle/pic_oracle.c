@@ -411,12 +411,26 @@ void orc_curl_e(const orc_grid *g, const double *const *E, double *const *out) {
  * time.  The order is fully defined on the integer cells, so any correct
  * implementation gives the same permutation:
  *   tile(p)  = (ix/Tx) + ntx*((iy/Ty) + nty*(iz/Tz))
- *   local(p) = (ix%Tx) + Tx*((iy%Ty) + Ty*(iz%Tz))
  *   rank(p)  = number of particles q < p in the same cell
+ *   local(p) = position of the cell inside the tile: cells are grouped by
+ *              the parity class (lx&1) | (ly&1)<<1 | (lz&1)<<2 of their
+ *              tile-local coordinates, classes taken in the order
+ *              0 3 1 2 (2D) or 0 7 1 6 2 5 4 3 (3D), then ordered by
+ *              (lz/2, ly/2, lx/2)
  * and particles are ordered by (tile, rank, local) ascending; these triples
  * are unique.  perm[new] = old; tile_start[t] is the first new index of tile
  * t, tile_start[ntiles] = np.
  */
+static int64_t local_order(int dim, const int64_t *T, int64_t lx, int64_t ly, int64_t lz) {
+    static const int order2[4] = {0, 3, 1, 2};
+    static const int order3[8] = {0, 7, 1, 6, 2, 5, 4, 3};
+    const int cls = (int)((lx & 1) | (ly & 1) << 1 | (lz & 1) << 2);
+    int pos = 0;
+    for (int q = 0; q < (dim == 3 ? 8 : 4); ++q)
+        if ((dim == 3 ? order3[q] : order2[q]) == cls) pos = q;
+    return ((pos * T[2] + lz / 2) * T[1] + ly / 2) * T[0] + lx / 2;
+}
+
 typedef struct {
     int64_t tile, rank, local, old;
 } orc_sort_key;
@@ -449,7 +463,7 @@ int orc_sort(const orc_grid *g, const int64_t *tile_size, int64_t np, const int3
         int64_t c[3] = {cell[0][p], cell[1][p], g->dim == 3 ? cell[2][p] : 0};
         int64_t lin = c[0] + g->n[0] * (c[1] + g->n[1] * c[2]);
         keys[p].tile = c[0] / T[0] + nt[0] * (c[1] / T[1] + nt[1] * (c[2] / T[2]));
-        keys[p].local = c[0] % T[0] + T[0] * (c[1] % T[1] + T[1] * (c[2] % T[2]));
+        keys[p].local = local_order(g->dim, T, c[0] % T[0], c[1] % T[1], c[2] % T[2]);
         keys[p].rank = seen[lin]++;
         keys[p].old = p;
     }

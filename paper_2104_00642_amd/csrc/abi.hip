@@ -41,6 +41,23 @@ pic_status ensure_partials(Ctx *c, size_t n) {
     return PIC_OK;
 }
 
+pic_status ensure_strag_list(Ctx *c, int64_t n) {
+    if ((size_t)n <= c->strag_cap) return PIC_OK;
+    if (c->strag_list) {
+        hipDeviceSynchronize();
+        hipFree(c->strag_list);
+        c->strag_list = nullptr;
+        c->strag_cap = 0;
+    }
+    const size_t cap = (size_t)n + (size_t)n / 8 + 1024;
+    if (hipMalloc(&c->strag_list, cap * sizeof(int32_t)) != hipSuccess) {
+        c->strag_list = nullptr;
+        return fail(c, PIC_E_NOMEM, "cannot allocate the straggler list");
+    }
+    c->strag_cap = cap;
+    return PIC_OK;
+}
+
 pic_status ensure_sort_scratch(Ctx *c, int64_t n) {
     const int64_t items = 256 * 16;
     const int64_t nblocks = (n + items - 1) / items;
@@ -171,8 +188,8 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
         return fail(nullptr, PIC_E_UNSUPPORTED, "tile window does not fit in 160 KB of LDS");
     }
     hipError_t e = hipGetDevice(&c->device);
-    if (e == hipSuccess) e = hipMalloc(&c->status, 16);
-    if (e == hipSuccess) e = hipMemset(c->status, 0, 16);
+    if (e == hipSuccess) e = hipMalloc(&c->status, 32);
+    if (e == hipSuccess) e = hipMemset(c->status, 0, 32);
     if (e == hipSuccess && cfg->precision == PIC_FP32_MIXED && c->lds_bytes > 64 * 1024)
         e = set_tiled_lds_limit(c->lds_bytes);
     const size_t sort_lds = (size_t)7 * c->tile[0] * c->tile[1] * c->tile[2] * sizeof(uint32_t);
@@ -209,6 +226,7 @@ extern "C" void pic_destroy(void *ctx) {
     hipDeviceSynchronize();
     hipFree(c->status);
     hipFree(c->partials);
+    hipFree(c->strag_list);
     for (int b = 0; b < 2; ++b) {
         hipFree(c->keys[b]);
         hipFree(c->vals[b]);

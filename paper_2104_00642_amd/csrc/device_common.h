@@ -34,13 +34,15 @@ __device__ __forceinline__ void shape_weights(R xi, int &i0, R *w) {
         w[0] = R(1) - d;
         w[1] = d;
     } else {
+        // (1/2 (1/2 - d)^2, 3/4 - d^2, 1/2 (1/2 + d)^2); the last equals the
+        // first plus d
         R ic = floor(xi + R(0.5));
         R d = xi - ic;
         i0 = (int)ic - 1;
-        R a = R(0.5) - d, b = R(0.5) + d;
-        w[0] = R(0.5) * a * a;
+        R a = R(0.5) - d;
+        w[0] = (R(0.5) * a) * a;
         w[1] = R(0.75) - d * d;
-        w[2] = R(0.5) * b * b;
+        w[2] = w[0] + d;
     }
 }
 

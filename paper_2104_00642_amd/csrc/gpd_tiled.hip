@@ -19,9 +19,12 @@
 // and independent of the order of the atomics.  The flush divides by S.
 // Particles are an int32 packed cell plus FP32 in-cell offsets, so every
 // weight is computed from a number in (-1.5, 2.5) and keeps full FP32
-// resolution regardless of the grid size.  A particle that has wandered more
-// than `drift` cells out of its tile since the last sort takes the same code
-// path with global-memory accessors and is counted as a straggler.
+// resolution regardless of the grid size.
+// A particle that has wandered more than `drift` cells out of its tile since
+// the last sort (or whose offset is not in [0,1)) is not pushed here: its
+// index goes to a list that gpd_global_kernel works through afterwards with
+// global-memory accessors, together with particles appended after the last
+// tile.  The tile kernel therefore holds only the LDS path.
 // Blocks are remapped so that each XCD (own L2) works on a contiguous run of
 // tiles: neighbouring tiles share guard rows in the same L2.
 #include "device_common.h"
@@ -30,6 +33,13 @@
 namespace pic {
 
 extern __shared__ float pic_smem[];
+
+#ifndef PIC_TILED_THREADS_2D
+#define PIC_TILED_THREADS_2D 256
+#endif
+#ifndef PIC_TILED_THREADS_3D
+#define PIC_TILED_THREADS_3D 1024
+#endif
 
 struct TiledArgs {
     int32_t *cell;
@@ -40,6 +50,7 @@ struct TiledArgs {
     float *chi;
     float chi_scale;
     const int64_t *tile_start;
+    int64_t n;
     int ntiles;
     int chunk;          // tiles per XCD run
     const float *F[6];
@@ -60,22 +71,36 @@ struct TiledArgs {
     double *partials;
     uint32_t *status;
     unsigned long long *stragglers;
+    int32_t *strag_list;   // particles left for the global path (capacity n)
+    uint32_t *strag_count;
 };
 
 // Accessor of the LDS window: coordinates local to the window origin.  Fields
 // are the first 6*wn floats of the dynamic LDS, the fixed-point current the
-// following 3*wn int64 words.
+// following 3*wn int64 words.  WX, WY, WZ > 0 fix the window shape at compile
+// time (the default tiles), so that every stencil node of a particle is an
+// immediate offset from one base address; 0 takes the shape at run time.
+template <int WX, int WY, int WZ>
 struct LdsAcc {
-    int wx, wxy, wn;
+    int wx_, wxy_, wn_;
     float scale;  // S of the fixed-point current
-    __device__ __forceinline__ int idx(int i, int j, int k) const { return i + wx * j + wxy * k; }
-    __device__ __forceinline__ float f(int c, int i, int j, int k) const {
-        return pic_smem[c * wn + idx(i, j, k)];
+    __device__ __forceinline__ int wx() const { return WX > 0 ? WX : wx_; }
+    __device__ __forceinline__ int wxy() const { return WX > 0 ? WX * WY : wxy_; }
+    __device__ __forceinline__ int wn() const { return WX > 0 ? WX * WY * WZ : wn_; }
+    // linear index of a stencil base (window coordinates are small, so the
+    // 24-bit multiplies run at full rate); a node is then base + ii + jj wx +
+    // kk wxy, a compile-time offset when the shape is fixed
+    __device__ __forceinline__ int lin(int i, int j, int k) const {
+        return i + __mul24(wx(), j) + __mul24(wxy(), k);
+    }
+    __device__ __forceinline__ float f(int c, int bi, int bj, int bk, int ii, int jj, int kk) const {
+        return pic_smem[c * wn() + lin(bi, bj, bk) + ii + wx() * jj + wxy() * kk];
     }
     // v is already in fixed-point units (the prefactors carry S), |v| <= 2^30
-    __device__ __forceinline__ void add(int c, int i, int j, int k, float v) const {
-        unsigned long long *jw = (unsigned long long *)(pic_smem + 6 * wn);
-        atomicAdd(&jw[c * wn + idx(i, j, k)], (unsigned long long)(long long)(int)v);
+    __device__ __forceinline__ void add(int c, int bi, int bj, int bk, int ii, int jj, int kk, float v) const {
+        unsigned long long *jw = (unsigned long long *)(pic_smem + 6 * wn());
+        atomicAdd(&jw[c * wn() + lin(bi, bj, bk) + ii + wx() * jj + wxy() * kk],
+                  (unsigned long long)(long long)(int)v);
     }
 };
 
@@ -91,18 +116,21 @@ struct GlobAcc {
         k = wrap_index(k, ng[2]);
         return (int64_t)i + (int64_t)ng[0] * ((int64_t)j + (int64_t)ng[1] * k);
     }
-    __device__ __forceinline__ float f(int c, int i, int j, int k) const { return F[c][idx(i, j, k)]; }
-    __device__ __forceinline__ void add(int c, int i, int j, int k, float v) const {
-        atomicAdd(&J[c][idx(i, j, k)], v);
+    __device__ __forceinline__ float f(int c, int bi, int bj, int bk, int ii, int jj, int kk) const {
+        return F[c][idx(bi + ii, bj + jj, bk + kk)];
+    }
+    __device__ __forceinline__ void add(int c, int bi, int bj, int bk, int ii, int jj, int kk, float v) const {
+        atomicAdd(&J[c][idx(bi + ii, bj + jj, bk + kk)], v);
     }
 };
 
 // Push one particle whose cell origin is at o[] in the accessor's coordinates.
 // f[] in-cell offsets, u[] momentum (updated); returns the cell displacement
-// in dc[] and the new offsets in f[]; EB[] receives the gathered fields.
+// in dc[] and the new offsets in f[]; EB[] receives the gathered fields and
+// gm1 = gamma^{n+1} - 1, formed as |u|^2 / (gamma + 1) (no cancellation).
 template <int DIM, int ORDER, class Acc>
 __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, const int *o, float *f,
-                                         float *u, float w, int *dc, float *EB) {
+                                         float *u, float w, int *dc, float *EB, float &gm1) {
     constexpr int NW = ORDER + 1;
     constexpr int L = ORDER + 2;
     const float ig0 = rsqrt_r(1.0f + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
@@ -128,7 +156,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
                 float r = 0.0f;
 #pragma unroll
                 for (int ii = 0; ii < NW; ++ii)
-                    r += wt[sx][0][ii] * acc.f(c, o[0] + i0[sx][0] + ii, o[1] + i0[sy][1] + jj, 0);
+                    r += wt[sx][0][ii] * acc.f(c, o[0] + i0[sx][0], o[1] + i0[sy][1], 0, ii, jj, 0);
                 acc_v += wt[sy][1][jj] * r;
             }
         } else {
@@ -140,8 +168,8 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
                     float r = 0.0f;
 #pragma unroll
                     for (int ii = 0; ii < NW; ++ii)
-                        r += wt[sx][0][ii] * acc.f(c, o[0] + i0[sx][0] + ii, o[1] + i0[sy][1] + jj,
-                                                   o[2] + i0[sz][2] + kk);
+                        r += wt[sx][0][ii] * acc.f(c, o[0] + i0[sx][0], o[1] + i0[sy][1], o[2] + i0[sz][2],
+                                                   ii, jj, kk);
                     s += wt[sy][1][jj] * r;
                 }
                 acc_v += wt[sz][2][kk] * s;
@@ -151,7 +179,9 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
     }
 
     boris<float>(a.qm_h, EB, EB + 3, u);
-    const float ig1 = rsqrt_r(1.0f + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const float us = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const float ig1 = rsqrt_r(1.0f + us);
+    gm1 = us * ig1 * rcp_r(1.0f + ig1);
     const float v[3] = {u[0] * ig1, u[1] * ig1, u[2] * ig1};
 
     // Esirkepov (Eqs. 20-22) for the move dh -> dh + dt v / d
@@ -171,7 +201,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
 #pragma unroll
             for (int ii = 0; ii < L - 1; ++ii) {
                 run -= DS[0][ii] * ty;
-                acc.add(0, b0 + ii, b1 + jj, 0, run);
+                acc.add(0, b0, b1, 0, ii, jj, 0, run);
             }
         }
 #pragma unroll
@@ -181,7 +211,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
 #pragma unroll
             for (int jj = 0; jj < L - 1; ++jj) {
                 run -= DS[1][jj] * tx;
-                acc.add(1, b0 + ii, b1 + jj, 0, run);
+                acc.add(1, b0, b1, 0, ii, jj, 0, run);
             }
         }
         const float qv = a.q * ws * v[2];
@@ -190,7 +220,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
             const float a0 = qv * (S0[1][jj] + 0.5f * DS[1][jj]);
             const float a1 = qv * (0.5f * S0[1][jj] + (1.0f / 3.0f) * DS[1][jj]);
 #pragma unroll
-            for (int ii = 0; ii < L; ++ii) acc.add(2, b0 + ii, b1 + jj, 0, S0[0][ii] * a0 + DS[0][ii] * a1);
+            for (int ii = 0; ii < L; ++ii) acc.add(2, b0, b1, 0, ii, jj, 0, S0[0][ii] * a0 + DS[0][ii] * a1);
         }
     } else {
         const int b2 = o[2] + base[2];
@@ -206,7 +236,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
 #pragma unroll
                 for (int ii = 0; ii < L - 1; ++ii) {
                     run -= DS[0][ii] * t;
-                    acc.add(0, b0 + ii, b1 + jj, b2 + kk, run);
+                    acc.add(0, b0, b1, b2, ii, jj, kk, run);
                 }
             }
 #pragma unroll
@@ -219,7 +249,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
 #pragma unroll
                 for (int jj = 0; jj < L - 1; ++jj) {
                     run -= DS[1][jj] * t;
-                    acc.add(1, b0 + ii, b1 + jj, b2 + kk, run);
+                    acc.add(1, b0, b1, b2, ii, jj, kk, run);
                 }
             }
 #pragma unroll
@@ -232,7 +262,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
 #pragma unroll
                 for (int kk = 0; kk < L - 1; ++kk) {
                     run -= DS[2][kk] * t;
-                    acc.add(2, b0 + ii, b1 + jj, b2 + kk, run);
+                    acc.add(2, b0, b1, b2, ii, jj, kk, run);
                 }
             }
     }
@@ -253,15 +283,50 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
     }
 }
 
-template <int DIM, int ORDER>
-__global__ void __launch_bounds__(256) gpd_tiled_kernel(TiledArgs a) {
+// chi_e (Sec. IV) at the gathered fields of x_h and u^{n+1/2} = (u^n + u^{n+1})/2
+__device__ __forceinline__ float chi_of(const float *u0, const float *u1, const float *EB) {
+    const float uh0 = 0.5f * (u0[0] + u1[0]), uh1 = 0.5f * (u0[1] + u1[1]), uh2 = 0.5f * (u0[2] + u1[2]);
+    const float gh = sqrtf(1.0f + uh0 * uh0 + uh1 * uh1 + uh2 * uh2);
+    const float f0 = gh * EB[0] + uh1 * EB[5] - uh2 * EB[4];
+    const float f1 = gh * EB[1] + uh2 * EB[3] - uh0 * EB[5];
+    const float f2 = gh * EB[2] + uh0 * EB[4] - uh1 * EB[3];
+    const float ue = uh0 * EB[0] + uh1 * EB[1] + uh2 * EB[2];
+    return sqrtf(fmaxf(f0 * f0 + f1 * f1 + f2 * f2 - ue * ue, 0.0f));
+}
+
+// element at byte offset `bo` of a per-tile base pointer: one 32-bit VGPR
+// offset against a wave-uniform base for every particle array
+template <typename T>
+__device__ __forceinline__ T ld(const T *base, uint32_t bo) {
+    return *(const T *)((const char *)base + bo);
+}
+template <typename T>
+__device__ __forceinline__ void st(T *base, uint32_t bo, T v) {
+    *(T *)((char *)base + bo) = v;
+}
+
+// sum of a double over the workgroup in a fixed order (wave butterflies, then
+// the waves in order); `red` holds NT/64 doubles; result valid in thread 0
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / 64; ++k) t += red[k];
+    return t;
+}
+
+template <int DIM, int ORDER, int NT, int WX, int WY, int WZ>
+__global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     const int b = blockIdx.x;
     const int t = (b & 7) * a.chunk + (b >> 3);  // XCD-contiguous tile runs
     if (t >= a.ntiles) return;
-    const int64_t pbeg = a.tile_start[t], pend = a.tile_start[t + 1];
-    __shared__ double red_k[256], red_q[256];
-    __shared__ unsigned int nstray;
-    __shared__ float wmax_s[256];
+    const int64_t pbeg = min(a.tile_start[t], a.n), pend = min(a.tile_start[t + 1], a.n);
+    __shared__ double red_k[NT / 64], red_q[NT / 64];
+    __shared__ float wmax_s[NT / 64];
     if (pbeg >= pend) {
         if (threadIdx.x == 0) {
             a.partials[2 * t] = 0.0;
@@ -273,40 +338,54 @@ __global__ void __launch_bounds__(256) gpd_tiled_kernel(TiledArgs a) {
     const int ty = (t / a.ntile_axis[0]) % a.ntile_axis[1];
     const int tz = DIM == 3 ? t / (a.ntile_axis[0] * a.ntile_axis[1]) : 0;
     const int g = a.drift + 2;
-    int org[3] = {tx * a.tile[0] - g, ty * a.tile[1] - g, DIM == 3 ? tz * a.tile[2] - g : 0};
-    LdsAcc lds{a.win[0], a.win[0] * a.win[1], a.win[0] * a.win[1] * a.win[2], 0.0f};
-    const int wn = lds.wn;
+    const int org[3] = {tx * a.tile[0] - g, ty * a.tile[1] - g, DIM == 3 ? tz * a.tile[2] - g : 0};
+    LdsAcc<WX, WY, WZ> lds{a.win[0], a.win[0] * a.win[1], a.win[0] * a.win[1] * a.win[2], 0.0f};
+    const int wn = lds.wn();
+    const int wx = lds.wx(), wxy = lds.wxy();
     unsigned long long *jwin = (unsigned long long *)(pic_smem + 6 * wn);
+    const uint32_t np = (uint32_t)(pend - pbeg);
+    // per-tile bases: every particle array is then addressed by one 32-bit offset
+    int32_t *cellT = a.cell + pbeg;
+    float *offT[3], *uT[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        offT[d] = a.off[d] + pbeg;
+        uT[d] = a.u[d] + pbeg;
+    }
+    const float *wT = a.w ? a.w + pbeg : nullptr;
+    float *chiT = a.chi ? a.chi + pbeg : nullptr;
 
-    // 1. stage E/B window, zero the J window, bound the weights of the tile
-    for (int e = threadIdx.x; e < 6 * wn; e += blockDim.x) {
-        const int c = e / wn;
-        const int r = e - c * wn;
-        const int k = r / lds.wxy;
-        const int r2 = r - k * lds.wxy;
-        const int j = r2 / a.win[0];
-        const int i = r2 - j * a.win[0];
+    // 1. stage the E/B window, zero the J window (window index decoded once
+    //    per cell), bound the weights of the tile
+    for (int r = threadIdx.x; r < wn; r += NT) {
+        const int k = DIM == 3 ? r / wxy : 0;
+        const int r2 = r - k * wxy;
+        const int j = r2 / wx;
+        const int i = r2 - j * wx;
         const int gi = wrap_index(org[0] + i, a.ng[0]);
         const int gj = wrap_index(org[1] + j, a.ng[1]);
         const int gk = DIM == 3 ? wrap_index(org[2] + k, a.ng[2]) : 0;
-        pic_smem[e] = a.F[c][(int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk)];
+        const int64_t gidx = (int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) pic_smem[c * wn + r] = a.F[c][gidx];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) jwin[c * wn + r] = 0ull;
     }
-    for (int e = threadIdx.x; e < 3 * wn; e += blockDim.x) jwin[e] = 0ull;
     float wm = fabsf(a.w0);
-    if (a.w) {
+    if (wT) {
         wm = 0.0f;
-        for (int64_t p = pbeg + threadIdx.x; p < pend; p += blockDim.x) wm = fmaxf(wm, fabsf(a.w[p]));
+        for (uint32_t i = threadIdx.x; i < np; i += NT) wm = fmaxf(wm, fabsf(ld(wT, 4u * i)));
     }
-    wmax_s[threadIdx.x] = wm;
-    if (threadIdx.x == 0) nstray = 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wm = fmaxf(wm, __shfl_xor(wm, o));
+    if ((threadIdx.x & 63) == 0) wmax_s[threadIdx.x >> 6] = wm;
     __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) wmax_s[threadIdx.x] = fmaxf(wmax_s[threadIdx.x], wmax_s[threadIdx.x + h]);
-        __syncthreads();
-    }
     {
+        float wmax = 0.0f;
+#pragma unroll
+        for (int k = 0; k < NT / 64; ++k) wmax = fmaxf(wmax, wmax_s[k]);
         // S = 2^(30 - ceil(log2 B)), B = |q| w_max max(1, d/dt): |contribution| * S <= 2^30
-        const float B = fabsf(a.q) * wmax_s[0] * a.jmax;
+        const float B = fabsf(a.q) * wmax * a.jmax;
         int ex = 0;
         frexpf(B > 0.0f ? B : 1.0f, &ex);  // B < 2^ex
         lds.scale = ldexpf(1.0f, 30 - ex);
@@ -314,193 +393,190 @@ __global__ void __launch_bounds__(256) gpd_tiled_kernel(TiledArgs a) {
 
     // 2. particles of the tile, next particle prefetched while one is pushed
     const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
-    const int hi[3] = {a.win[0] - 4, a.win[1] - 4, a.win[2] - 4};
+    const int hi[3] = {wx - 4, (DIM >= 2 ? wxy / wx : 1) - 4, (DIM == 3 ? wn / wxy : 1) - 4};
     double kin = 0.0, chg = 0.0;
-    GlobAcc glob{{a.F[0], a.F[1], a.F[2], a.F[3], a.F[4], a.F[5]},
-                 {a.J[0], a.J[1], a.J[2]},
-                 {a.ng[0], a.ng[1], a.ng[2]}, 1.0f};
-    int64_t p = pbeg + threadIdx.x;
+    uint32_t i = threadIdx.x;
     int32_t n_cell = 0;
     float n_f[3] = {0.0f, 0.0f, 0.0f}, n_u[3] = {0.0f, 0.0f, 0.0f}, n_w = a.w0;
-    if (p < pend) {
-        n_cell = a.cell[p];
+    if (i < np) {
+        const uint32_t bo = 4u * i;
+        n_cell = ld(cellT, bo);
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) n_f[d] = a.off[d][p];
+        for (int d = 0; d < DIM; ++d) n_f[d] = ld(offT[d], bo);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) n_u[d] = a.u[d][p];
-        if (a.w) n_w = a.w[p];
+        for (int d = 0; d < 3; ++d) n_u[d] = ld(uT[d], bo);
+        if (wT) n_w = ld(wT, bo);
     }
-    for (; p < pend; p += blockDim.x) {
+    for (; i < np; i += NT) {
+        const uint32_t bo = 4u * i;
         const int32_t cell = n_cell;
         float f[3] = {n_f[0], n_f[1], n_f[2]};
         float u[3] = {n_u[0], n_u[1], n_u[2]};
         const float w = n_w;
-        const int64_t pn = p + blockDim.x;
-        if (pn < pend) {
-            n_cell = a.cell[pn];
+        if (i + NT < np) {
+            const uint32_t bn = bo + 4u * NT;
+            n_cell = ld(cellT, bn);
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) n_f[d] = a.off[d][pn];
+            for (int d = 0; d < DIM; ++d) n_f[d] = ld(offT[d], bn);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) n_u[d] = a.u[d][pn];
-            if (a.w) n_w = a.w[pn];
+            for (int d = 0; d < 3; ++d) n_u[d] = ld(uT[d], bn);
+            if (wT) n_w = ld(wT, bn);
         }
-        int cc[3] = {cell & mx, (cell >> a.bx) & my, DIM == 3 ? (cell >> (a.bx + a.by)) : 0};
-        bool bad = false;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) bad |= !(f[d] >= 0.0f && f[d] < 1.0f) || cc[d] >= a.ng[d];
-        if (bad) atomicOr(a.status, PIC_F_OFFSET);
+        const int cc[3] = {cell & mx, (cell >> a.bx) & my, DIM == 3 ? (cell >> (a.bx + a.by)) : 0};
         if (!isfinite(u[0] + u[1] + u[2])) atomicOr(a.status, PIC_F_NONFINITE);
-        // local cell in the window (one periodic unwrap)
-        int lc[3];
+        // local cell in the window (one periodic unwrap); the particle stays
+        // here only if the whole stencil lies in the window and its offsets
+        // are in [0,1) (as bit patterns: 0 <= bits < bits(1.0f))
+        int lc[3] = {0, 0, 0};
         bool inside = true;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            int l = cc[d] - org[d];
-            l = l < 0 ? l + a.ng[d] : (l >= a.ng[d] ? l - a.ng[d] : l);
+            const int l = wrap_index(cc[d] - org[d], a.ng[d]);
             lc[d] = l;
-            inside &= (l >= 2) && (l <= hi[d]);
+            inside &= (unsigned)(l - 2) <= (unsigned)(hi[d] - 2);
+            inside &= __float_as_uint(f[d]) < 0x3f800000u;
         }
-        if (DIM == 2) lc[2] = 0;
+        if (!inside) {
+            const uint32_t slot = atomicAdd(a.strag_count, 1u);
+            a.strag_list[slot] = (int32_t)(pbeg + i);
+            continue;
+        }
         const float u_old[3] = {u[0], u[1], u[2]};
         float EB[6];
         int dc[3] = {0, 0, 0};
-        if (inside) {
-            push_one<DIM, ORDER>(lds, a, lc, f, u, w, dc, EB);
-        } else {
-            push_one<DIM, ORDER>(glob, a, cc, f, u, w, dc, EB);
-            atomicAdd(&nstray, 1u);
-        }
+        float gm1;
+        push_one<DIM, ORDER>(lds, a, lc, f, u, w, dc, EB, gm1);
         int packed = 0;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            int nc = cc[d] + dc[d];
-            nc = nc < 0 ? nc + a.ng[d] : (nc >= a.ng[d] ? nc - a.ng[d] : nc);
-            packed |= nc << (d == 0 ? 0 : (d == 1 ? a.bx : a.bx + a.by));
-        }
-        a.cell[p] = packed;
+        for (int d = 0; d < DIM; ++d)
+            packed |= wrap_index(cc[d] + dc[d], a.ng[d]) << (d == 0 ? 0 : (d == 1 ? a.bx : a.bx + a.by));
+        st(cellT, bo, packed);
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) a.off[d][p] = f[d];
+        for (int d = 0; d < DIM; ++d) st(offT[d], bo, f[d]);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) a.u[d][p] = u[d];
-        const float g1 = sqrtf(1.0f + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-        if (a.chi) {
-            // chi_e (Sec. IV) at the fields of x_h and u^{n+1/2}
-            const float uh0 = 0.5f * (u_old[0] + u[0]), uh1 = 0.5f * (u_old[1] + u[1]),
-                        uh2 = 0.5f * (u_old[2] + u[2]);
-            const float gh = sqrtf(1.0f + uh0 * uh0 + uh1 * uh1 + uh2 * uh2);
-            const float f0 = gh * EB[0] + uh1 * EB[5] - uh2 * EB[4];
-            const float f1 = gh * EB[1] + uh2 * EB[3] - uh0 * EB[5];
-            const float f2 = gh * EB[2] + uh0 * EB[4] - uh1 * EB[3];
-            const float ue = uh0 * EB[0] + uh1 * EB[1] + uh2 * EB[2];
-            const float s2 = f0 * f0 + f1 * f1 + f2 * f2 - ue * ue;
-            a.chi[p] = a.chi_scale * sqrtf(fmaxf(s2, 0.0f));
-        }
-        kin += (double)w * (double)(g1 - 1.0f);
+        for (int d = 0; d < 3; ++d) st(uT[d], bo, u[d]);
+        if (chiT) st(chiT, bo, a.chi_scale * chi_of(u_old, u, EB));
+        kin += (double)w * (double)gm1;
         chg += (double)w;
     }
     __syncthreads();
 
     // 3. flush the J window into global J (periodic wrap), skip exact zeros
     const double inv_scale = 1.0 / (double)lds.scale;
-    for (int e = threadIdx.x; e < 3 * wn; e += blockDim.x) {
-        const long long q = (long long)jwin[e];
-        if (q != 0) {
-            const float v = (float)((double)q * inv_scale);
-            const int c = e / wn;
-            const int r = e - c * wn;
-            const int k = r / lds.wxy;
-            const int r2 = r - k * lds.wxy;
-            const int j = r2 / a.win[0];
-            const int i = r2 - j * a.win[0];
-            const int gi = wrap_index(org[0] + i, a.ng[0]);
-            const int gj = wrap_index(org[1] + j, a.ng[1]);
-            const int gk = DIM == 3 ? wrap_index(org[2] + k, a.ng[2]) : 0;
-            atomicAdd(&a.J[c][(int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk)], v);
+    for (int r = threadIdx.x; r < wn; r += NT) {
+        const int k = DIM == 3 ? r / wxy : 0;
+        const int r2 = r - k * wxy;
+        const int j = r2 / wx;
+        const int ii = r2 - j * wx;
+        const int gi = wrap_index(org[0] + ii, a.ng[0]);
+        const int gj = wrap_index(org[1] + j, a.ng[1]);
+        const int gk = DIM == 3 ? wrap_index(org[2] + k, a.ng[2]) : 0;
+        const int64_t gidx = (int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long long q = (long long)jwin[c * wn + r];
+            if (q != 0) atomicAdd(&a.J[c][gidx], (float)((double)q * inv_scale));
         }
     }
     // 4. fixed-order FP64 reduction of the diagnostics
-    red_k[threadIdx.x] = kin;
-    red_q[threadIdx.x] = chg;
-    __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
-            red_k[threadIdx.x] += red_k[threadIdx.x + h];
-            red_q[threadIdx.x] += red_q[threadIdx.x + h];
-        }
-        __syncthreads();
-    }
+    const double sk = block_sum<NT>(kin, red_k);
+    const double sq = block_sum<NT>(chg, red_q);
     if (threadIdx.x == 0) {
-        a.partials[2 * t] = red_k[0] * a.mdV;
-        a.partials[2 * t + 1] = red_q[0] * a.qdV;
-        if (nstray) {
-            atomicOr(a.status, PIC_F_STRAGGLER);
-            atomicAdd(a.stragglers, (unsigned long long)nstray);
-        }
+        a.partials[2 * t] = sk * a.mdV;
+        a.partials[2 * t + 1] = sq * a.qdV;
     }
 }
 
-// Particles after the last tile (created since the last sort, e.g. by the QED
-// step) take the global-memory path; a fixed grid strides over them.
-constexpr int TAIL_BLOCKS = 256;
+__global__ void gpd_reset_kernel(uint32_t *count) { *count = 0u; }
+
+// Global-memory path: particles after the last tile (created since the last
+// sort, e.g. by the QED step), then the stragglers listed by the tile kernel.
+// Each is checked before it is touched: an offset outside [0,1) or a cell off
+// the grid is flagged PIC_F_OFFSET and the particle is left unchanged.
+constexpr int GLOBAL_BLOCKS = 256;
 
 template <int DIM, int ORDER>
-__global__ void __launch_bounds__(256) gpd_tail_kernel(TiledArgs a, int64_t n) {
-    const int64_t first = a.tile_start[a.ntiles];
-    __shared__ double red_k[256], red_q[256];
+__global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
+    const int64_t first = min(a.tile_start[a.ntiles], a.n);
+    const int64_t ntail = a.n - first;
+    const int64_t nstrag = (int64_t)*a.strag_count;
+    const int64_t total = ntail + nstrag;
+    __shared__ double red_k[4], red_q[4];
     double kin = 0.0, chg = 0.0;
     GlobAcc glob{{a.F[0], a.F[1], a.F[2], a.F[3], a.F[4], a.F[5]},
                  {a.J[0], a.J[1], a.J[2]},
                  {a.ng[0], a.ng[1], a.ng[2]}, 1.0f};
     const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
-    for (int64_t p = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = k < ntail ? first + k : (int64_t)a.strag_list[k - ntail];
         const int32_t cell = a.cell[p];
-        int cc[3] = {cell & mx, (cell >> a.bx) & my, DIM == 3 ? (cell >> (a.bx + a.by)) : 0};
+        const int cc[3] = {cell & mx, (cell >> a.bx) & my, DIM == 3 ? (cell >> (a.bx + a.by)) : 0};
         float f[3] = {a.off[0][p], a.off[1][p], DIM == 3 ? a.off[2][p] : 0.0f};
         float u[3] = {a.u[0][p], a.u[1][p], a.u[2][p]};
         const float w = a.w ? a.w[p] : a.w0;
+        // the bits above x and y hold z in 3D and must be zero in 2D
+        bool ok = (unsigned)(cell >> (a.bx + a.by)) < (unsigned)(DIM == 3 ? a.ng[2] : 1);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) ok &= f[d] >= 0.0f && f[d] < 1.0f && (unsigned)cc[d] < (unsigned)a.ng[d];
+        if (!isfinite(u[0] + u[1] + u[2]) || !isfinite(f[0] + f[1] + f[2])) atomicOr(a.status, PIC_F_NONFINITE);
+        if (!ok) {
+            atomicOr(a.status, PIC_F_OFFSET);
+            continue;
+        }
         const float u_old[3] = {u[0], u[1], u[2]};
         float EB[6];
         int dc[3] = {0, 0, 0};
-        push_one<DIM, ORDER>(glob, a, cc, f, u, w, dc, EB);
+        float gm1;
+        push_one<DIM, ORDER>(glob, a, cc, f, u, w, dc, EB, gm1);
         int packed = 0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            int nc = cc[d] + dc[d];
-            nc = nc < 0 ? nc + a.ng[d] : (nc >= a.ng[d] ? nc - a.ng[d] : nc);
-            packed |= nc << (d == 0 ? 0 : (d == 1 ? a.bx : a.bx + a.by));
+            packed |= wrap_index(cc[d] + dc[d], a.ng[d]) << (d == 0 ? 0 : (d == 1 ? a.bx : a.bx + a.by));
             a.off[d][p] = f[d];
         }
         a.cell[p] = packed;
 #pragma unroll
         for (int d = 0; d < 3; ++d) a.u[d][p] = u[d];
-        if (a.chi) {
-            const float uh0 = 0.5f * (u_old[0] + u[0]), uh1 = 0.5f * (u_old[1] + u[1]),
-                        uh2 = 0.5f * (u_old[2] + u[2]);
-            const float gh = sqrtf(1.0f + uh0 * uh0 + uh1 * uh1 + uh2 * uh2);
-            const float f0 = gh * EB[0] + uh1 * EB[5] - uh2 * EB[4];
-            const float f1 = gh * EB[1] + uh2 * EB[3] - uh0 * EB[5];
-            const float f2 = gh * EB[2] + uh0 * EB[4] - uh1 * EB[3];
-            const float ue = uh0 * EB[0] + uh1 * EB[1] + uh2 * EB[2];
-            a.chi[p] = a.chi_scale * sqrtf(fmaxf(f0 * f0 + f1 * f1 + f2 * f2 - ue * ue, 0.0f));
-        }
-        const float g1 = sqrtf(1.0f + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-        kin += (double)w * (double)(g1 - 1.0f);
+        if (a.chi) a.chi[p] = a.chi_scale * chi_of(u_old, u, EB);
+        kin += (double)w * (double)gm1;
         chg += (double)w;
     }
-    red_k[threadIdx.x] = kin;
-    red_q[threadIdx.x] = chg;
-    __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
-            red_k[threadIdx.x] += red_k[threadIdx.x + h];
-            red_q[threadIdx.x] += red_q[threadIdx.x + h];
-        }
-        __syncthreads();
-    }
+    const double sk = block_sum<256>(kin, red_k);
+    const double sq = block_sum<256>(chg, red_q);
     if (threadIdx.x == 0) {
-        a.partials[2 * (a.ntiles + blockIdx.x)] = red_k[0] * a.mdV;
-        a.partials[2 * (a.ntiles + blockIdx.x) + 1] = red_q[0] * a.qdV;
+        a.partials[2 * (a.ntiles + blockIdx.x)] = sk * a.mdV;
+        a.partials[2 * (a.ntiles + blockIdx.x) + 1] = sq * a.qdV;
+        if (blockIdx.x == 0 && nstrag > 0) {
+            atomicOr(a.status, PIC_F_STRAGGLER);
+            atomicAdd(a.stragglers, (unsigned long long)nstrag);
+        }
+    }
+}
+
+// window shapes with a compiled kernel: 16x16 tiles with drift 2 in 2D,
+// 8x8x4 tiles with drift 1 in 3D (the defaults); others use the run-time shape
+constexpr int W2X = 16 + 2 * 2 + 5, W3X = 8 + 2 * 1 + 5, W3Z = 4 + 2 * 1 + 5;
+
+template <int DIM, int ORDER, int NT, int WX, int WY, int WZ>
+static void launch_pair(const TiledArgs &a, size_t lds, hipStream_t s) {
+    gpd_reset_kernel<<<1, 1, 0, s>>>(a.strag_count);
+    gpd_tiled_kernel<DIM, ORDER, NT, WX, WY, WZ><<<dim3((unsigned)(8 * a.chunk)), dim3(NT), lds, s>>>(a);
+    gpd_global_kernel<DIM, ORDER><<<dim3(GLOBAL_BLOCKS), dim3(256), 0, s>>>(a);
+}
+
+template <int DIM, int ORDER>
+static void launch_tiled(const TiledArgs &a, size_t lds, hipStream_t s) {
+    if constexpr (DIM == 2) {
+        if (a.win[0] == W2X && a.win[1] == W2X)
+            launch_pair<2, ORDER, PIC_TILED_THREADS_2D, W2X, W2X, 1>(a, lds, s);
+        else
+            launch_pair<2, ORDER, PIC_TILED_THREADS_2D, 0, 0, 0>(a, lds, s);
+    } else {
+        if (a.win[0] == W3X && a.win[1] == W3X && a.win[2] == W3Z)
+            launch_pair<3, ORDER, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(a, lds, s);
+        else
+            launch_pair<3, ORDER, PIC_TILED_THREADS_3D, 0, 0, 0>(a, lds, s);
     }
 }
 
@@ -528,6 +604,7 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
     a.chi = cfg.hbar_omega_mc2 > 0.0 ? p->chi : nullptr;
     a.chi_scale = (float)cfg.hbar_omega_mc2;
     a.tile_start = p->tile_start;
+    a.n = p->n;
     a.ntiles = (int)c->ntiles;
     a.chunk = (int)((c->ntiles + 7) / 8);
     a.bx = c->bits[0];
@@ -543,49 +620,38 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
     a.qdV = sp->q * dV;
     a.status = c->status;
     a.stragglers = (unsigned long long *)(c->status + 2);
-    if (ensure_partials(c, 2 * ((size_t)c->ntiles + TAIL_BLOCKS)) != PIC_OK) return hipErrorOutOfMemory;
+    a.strag_count = c->status + 4;
+    if (ensure_partials(c, 2 * ((size_t)c->ntiles + GLOBAL_BLOCKS)) != PIC_OK) return hipErrorOutOfMemory;
+    if (ensure_strag_list(c, p->n) != PIC_OK) return hipErrorOutOfMemory;
     a.partials = c->partials;
-    dim3 grid((unsigned)(8 * a.chunk)), block(256), tgrid(TAIL_BLOCKS);
+    a.strag_list = c->strag_list;
     const size_t lds = c->lds_bytes;
-    const int key = c->dim * 10 + cfg.order;
-    const int64_t n = p->n;
-    switch (key) {
-        case 21:
-            gpd_tiled_kernel<2, 1><<<grid, block, lds, s>>>(a);
-            gpd_tail_kernel<2, 1><<<tgrid, block, 0, s>>>(a, n);
-            break;
-        case 22:
-            gpd_tiled_kernel<2, 2><<<grid, block, lds, s>>>(a);
-            gpd_tail_kernel<2, 2><<<tgrid, block, 0, s>>>(a, n);
-            break;
-        case 31:
-            gpd_tiled_kernel<3, 1><<<grid, block, lds, s>>>(a);
-            gpd_tail_kernel<3, 1><<<tgrid, block, 0, s>>>(a, n);
-            break;
-        case 32:
-            gpd_tiled_kernel<3, 2><<<grid, block, lds, s>>>(a);
-            gpd_tail_kernel<3, 2><<<tgrid, block, 0, s>>>(a, n);
-            break;
+    switch (c->dim * 10 + cfg.order) {
+        case 21: launch_tiled<2, 1>(a, lds, s); break;
+        case 22: launch_tiled<2, 2>(a, lds, s); break;
+        case 31: launch_tiled<3, 1>(a, lds, s); break;
+        case 32: launch_tiled<3, 2>(a, lds, s); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !diag) return e;
-    return launch_finalize(c->partials, c->ntiles + TAIL_BLOCKS, 2, diag, 0, 1.0, s);
+    return launch_finalize(c->partials, c->ntiles + GLOBAL_BLOCKS, 2, diag, 0, 1.0, s);
 }
 
 hipError_t set_tiled_lds_limit(size_t bytes) {
-    hipError_t e;
-    e = hipFuncSetAttribute((const void *)gpd_tiled_kernel<2, 1>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)gpd_tiled_kernel<2, 2>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)gpd_tiled_kernel<3, 1>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)gpd_tiled_kernel<3, 2>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void *k[8] = {(const void *)gpd_tiled_kernel<2, 1, PIC_TILED_THREADS_2D, 0, 0, 0>,
+                        (const void *)gpd_tiled_kernel<2, 2, PIC_TILED_THREADS_2D, 0, 0, 0>,
+                        (const void *)gpd_tiled_kernel<3, 1, PIC_TILED_THREADS_3D, 0, 0, 0>,
+                        (const void *)gpd_tiled_kernel<3, 2, PIC_TILED_THREADS_3D, 0, 0, 0>,
+                        (const void *)gpd_tiled_kernel<2, 1, PIC_TILED_THREADS_2D, W2X, W2X, 1>,
+                        (const void *)gpd_tiled_kernel<2, 2, PIC_TILED_THREADS_2D, W2X, W2X, 1>,
+                        (const void *)gpd_tiled_kernel<3, 1, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>,
+                        (const void *)gpd_tiled_kernel<3, 2, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>};
+    for (const void *f : k) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace pic

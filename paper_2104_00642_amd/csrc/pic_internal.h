@@ -22,8 +22,12 @@ struct Ctx {
     int drift = 2;
     size_t lds_bytes = 0;
     int device = 0;
-    // device status: [0] flags, [2..3] straggler count (uint64 at byte 8)
+    // device status: [0] flags, [2..3] straggler count (uint64 at byte 8),
+    // [4] length of the straggler list of the current push
     uint32_t *status = nullptr;
+    // indices of the particles the tile kernel leaves to the global path
+    int32_t *strag_list = nullptr;
+    size_t strag_cap = 0;        // entries
     // FP64 block partials of the diagnostics reductions
     double *partials = nullptr;
     size_t partials_cap = 0;     // in doubles
@@ -44,6 +48,7 @@ struct Ctx {
 // error helpers
 pic_status fail(Ctx *c, pic_status s, const std::string &msg);
 pic_status ensure_partials(Ctx *c, size_t n);
+pic_status ensure_strag_list(Ctx *c, int64_t n);
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_gpd_plain(Ctx *c, const pic_species *sp, const pic_particles *p,

@@ -28,8 +28,31 @@ struct SortGeom {
     int bx, by;
     int tile[3];
     int ntile_axis[3];
-    int ct;  // cells per tile
+    int ct;            // cells per tile
+    int cls_start[8];  // first key of each parity class of cells
 };
+
+#ifndef PIC_SORT_PARITY
+#define PIC_SORT_PARITY 1
+#endif
+
+// Key of a cell inside its tile (li, lj, lk tile-local): cells are grouped by
+// the parities of their coordinates, classes taken in an order where
+// consecutive classes differ in as many parities as possible, and by the
+// coarse position (li/2, lj/2, lk/2) inside a class.  Two cells of one class
+// are at least two cells apart along some axis, so the stencils of particles
+// that share a wavefront seldom start on the same node and their LDS current
+// atomics seldom hit the same address.
+__device__ __forceinline__ uint32_t local_key(int li, int lj, int lk, const SortGeom &g) {
+#if PIC_SORT_PARITY
+    const int px = li & 1, py = lj & 1, pz = lk & 1;
+    const int nx = (g.tile[0] + 1 - px) >> 1;  // cells of parity px along x
+    const int ny = (g.tile[1] + 1 - py) >> 1;
+    return (uint32_t)(g.cls_start[px | (py << 1) | (pz << 2)] + (li >> 1) + nx * ((lj >> 1) + ny * (lk >> 1)));
+#else
+    return (uint32_t)(li + g.tile[0] * (lj + g.tile[1] * lk));
+#endif
+}
 
 __device__ __forceinline__ void decode_cell(int32_t c, const SortGeom &g, int &ix, int &iy, int &iz) {
     const int mx = (1 << g.bx) - 1, my = (1 << g.by) - 1;
@@ -237,8 +260,7 @@ __global__ void __launch_bounds__(256) tile_order_kernel(const uint32_t *vals, c
     for (int64_t i = ts + threadIdx.x; i < te; i += blockDim.x) {
         int ix, iy, iz;
         decode_cell(pa.cell_in[vals[i]], g, ix, iy, iz);
-        const uint32_t l =
-            (uint32_t)((ix % g.tile[0]) + g.tile[0] * ((iy % g.tile[1]) + g.tile[1] * (iz % g.tile[2])));
+        const uint32_t l = local_key(ix % g.tile[0], iy % g.tile[1], iz % g.tile[2], g);
         lcell[i] = l;
         atomicAdd(&cnt[l], 1u);
     }
@@ -353,6 +375,22 @@ hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *ds
         g.ntile_axis[d] = c->ntile_axis[d];
     }
     g.ct = c->tile[0] * c->tile[1] * c->tile[2];
+    {
+        // parity classes in the order (000 111 001 110 010 101 100 011) of
+        // (x | y<<1 | z<<2); in 2D the z-odd classes are empty
+        static const int order[8] = {0, 7, 1, 6, 2, 5, 4, 3};
+        static const int order2[4] = {0, 3, 1, 2};
+        int next = 0;
+        for (int q = 0; q < 8; ++q) g.cls_start[q] = 0;
+        const int ncls = c->dim == 3 ? 8 : 4;
+        for (int q = 0; q < ncls; ++q) {
+            const int cls = c->dim == 3 ? order[q] : order2[q];
+            int size = 1;
+            for (int d = 0; d < 3; ++d) size *= (c->tile[d] + 1 - ((cls >> d) & 1)) >> 1;
+            g.cls_start[cls] = next;
+            next += size;
+        }
+    }
     if (n == 0) {
         tile_bounds_kernel<<<1, 256, 0, s>>>(c->keys[0], 0, c->ntiles, dst->tile_start);
         return hipGetLastError();

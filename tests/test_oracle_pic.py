@@ -382,10 +382,12 @@ def brute_force_order(n, tile, cells):
         seen[c] = r + 1
         nt = [n[a] // tile[a] for a in range(dim)]
         t = 0
-        loc = 0
         for a in reversed(range(dim)):
             t = t * nt[a] + c[a] // tile[a]
-            loc = loc * tile[a] + c[a] % tile[a]
+        lc = [c[a] % tile[a] for a in range(dim)] + [0] * (3 - dim)
+        cls = (lc[0] & 1) | (lc[1] & 1) << 1 | (lc[2] & 1) << 2
+        order = [0, 7, 1, 6, 2, 5, 4, 3] if dim == 3 else [0, 3, 1, 2]
+        loc = (order.index(cls), lc[2] // 2, lc[1] // 2, lc[0] // 2)
         keys.append((t, r, loc, p))
     keys.sort()
     return [k[3] for k in keys], [k[0] for k in keys]
@@ -407,6 +409,33 @@ def test_sort_matches_brute_force(dim):
     ntiles = int(np.prod([n[a] // tile[a] for a in range(dim)]))
     counts = np.bincount(tiles, minlength=ntiles)
     assert list(start) == [0] + list(np.cumsum(counts))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sort_wavefront_cells_are_not_neighbours(dim):
+    """With one particle per cell, every 64 consecutive particles of a tile
+    (one wavefront) sit in cells of which no two are neighbours along all of
+    the first axes at once: in 2D no two are king-move neighbours; in 3D a
+    wavefront holds two complementary parity classes, so two of its cells are
+    either two apart along some axis or differ along every axis."""
+    n = (32, 32) if dim == 2 else (16, 16, 8)
+    tile = (16, 16) if dim == 2 else (8, 8, 4)
+    g = O.Grid(dim, n, (1.0,) * dim, 0.1, 2)
+    grids = np.meshgrid(*[np.arange(v) for v in n], indexing="ij")
+    cells = [m.reshape(-1).astype(np.int32) for m in grids]
+    perm, start = O.sort(g, tile, cells)
+    off = ~np.eye(64, dtype=bool)
+    for t in range(len(start) - 1):
+        idx = perm[start[t]:start[t + 1]]
+        assert len(idx) % 64 == 0
+        for w0 in range(0, len(idx), 64):
+            pos = np.stack([cells[a][idx[w0:w0 + 64]] for a in range(dim)], axis=1)
+            dd = np.abs(pos[:, None, :] - pos[None, :, :])
+            cheb = dd.max(axis=2)
+            if dim == 2:
+                assert cheb[off].min() >= 2
+            else:
+                assert np.all(((cheb >= 2) | (dd.min(axis=2) >= 1))[off])
 
 
 def test_sort_empty_input():

@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--scale", type=int, default=1, help="divide the grid (tests only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
+    ap.add_argument("--fp64-order", choices=["lex", "cell"], default="lex",
+                    help="particle order of the plain FP64 path (see fp64_order)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", choices=["laser2d", "laser3d"], default="laser2d",
                     help="laser2d: 4096x2048 2D3V (the metric's workload); laser3d: 512x256x256 3D3V")
@@ -89,20 +91,32 @@ def alg_bytes_per_particle(dim, real_bytes, ppc, with_w=True):
     return s_read + s_write + 9 * real_bytes / ppc
 
 
-def tile_order(wl, args, torch, L, Simulation):
-    """Permutation that puts the workload's particles in the library's tile
-    order (an index carried through one pic_sort): the FP64 path starts from
-    the same particle order as the FP32 path."""
-    sim = Simulation.from_workload(wl, precision=L.PIC_FP32_MIXED, device="cuda",
-                                   tile=tuple(int(v) for v in args.tile.split(",")), drift=args.drift)
-    p = sim.particles[0]
-    p.id = torch.arange(p.n, dtype=torch.int64, device="cuda")
-    sim.spare[0].id = torch.empty_like(p.id)
-    sim.sort()
-    perm = sim.particles[0].id.clone()
-    del sim
-    torch.cuda.empty_cache()
-    return perm
+def fp64_order(raw, cfg, tile, kind, torch):
+    """Particle order handed to the plain FP64 path.  Its global atomics
+    favour lanes on neighbouring cells (one cache line serves several lanes),
+    so it gets (tile, rank within the cell, cell within the tile x-fastest)
+    for 'lex', or plain cell order (x fastest) for 'cell'."""
+    dim = cfg.dim
+    c = [v.to(torch.int64) for v in raw.cell]
+    n = list(cfg.n)
+    lin = c[0] + n[0] * (c[1] + (n[1] * c[2] if dim == 3 else 0))
+    order = torch.argsort(lin, stable=True)
+    if kind == "cell":
+        return order
+    sl = lin[order]
+    idx = torch.arange(sl.numel(), device=sl.device)
+    newrun = torch.ones_like(sl, dtype=torch.bool)
+    newrun[1:] = sl[1:] != sl[:-1]
+    start = torch.cummax(torch.where(newrun, idx, torch.zeros_like(idx)), 0).values
+    rank = torch.empty_like(idx)
+    rank[order] = idx - start
+    del sl, idx, newrun, start, order
+    nt = [n[a] // tile[a] for a in range(dim)]
+    tid = c[0] // tile[0] + nt[0] * (c[1] // tile[1] + (nt[1] * (c[2] // tile[2]) if dim == 3 else 0))
+    loc = c[0] % tile[0] + tile[0] * (c[1] % tile[1] + (tile[1] * (c[2] % tile[2]) if dim == 3 else 0))
+    ct = math.prod(tile[:dim])
+    key = (tid * (int(rank.max()) + 1) + rank) * ct + loc
+    return torch.argsort(key)
 
 
 def run_path(args, wl, precision, torch, L, Simulation):
@@ -262,8 +276,8 @@ def main():
         wl_run = wl
         if prec == L.PIC_FP64_PLAIN and len(wl.species) == 1:
             from paper_2104_00642_amd.workloads import Workload
-            perm = tile_order(wl, args, torch, L, Simulation)
             q, m, raw = wl.species[0]
+            perm = fp64_order(raw, wl.cfg, tuple(int(v) for v in args.tile.split(",")), args.fp64_order, torch)
             wl_run = Workload(wl.name, wl.cfg, [(q, m, raw.subset(perm))], wl.E0, wl.B0, wl.steps)
         sim, n, secs, gpd_ms, status, extra = run_path(args, wl_run, prec, torch, L, Simulation)
         err = sampled_error(sim, torch, L, O)

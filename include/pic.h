@@ -153,8 +153,14 @@ pic_status pic_get_layout(const void *ctx, int32_t bits[3], int32_t tile[3], int
  * ACCUMULATED into (the caller zeroes it once per step before the first
  * species).  Particles are updated in place and wrapped periodically.
  * FP32 path: particles must be in the order of the last pic_sort (tile_start
- * valid); particles that left their tile by more than `drift` cells are
- * still pushed correctly through global memory and flagged PIC_F_STRAGGLER.
+ * valid); particles that left their tile by more than `drift` cells, and
+ * particles after tile_start[ntiles] (appended since the sort), are still
+ * pushed correctly through global memory; stragglers are flagged
+ * PIC_F_STRAGGLER and counted.  A particle whose offset is outside [0,1) or
+ * whose packed cell is off the grid is flagged PIC_F_OFFSET and left
+ * unchanged; NaN/Inf momenta or offsets are flagged PIC_F_NONFINITE.  The
+ * context's straggler list holds up to n entries (4 bytes each, allocated on
+ * the first call with a larger n).
  * diag (nullable, device double[4]) receives += {sum w m (gamma^{n+1}-1) dV,
  * sum q w dV, -, -} computed in FP64 in a fixed order.  When chi is non-NULL
  * and hbar_omega_mc2 > 0 it receives chi_e of Sec. IV at the fields of x_h

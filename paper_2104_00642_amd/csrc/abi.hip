@@ -42,18 +42,28 @@ pic_status ensure_partials(Ctx *c, size_t n) {
 }
 
 pic_status ensure_strag_list(Ctx *c, int64_t n) {
+    if (!c->bin_count) {
+        if (hipMalloc(&c->bin_count, sizeof(uint32_t) * (size_t)c->ntiles) != hipSuccess ||
+            hipMalloc(&c->strag_tile, sizeof(uint32_t) * (size_t)c->ntiles) != hipSuccess ||
+            hipMalloc(&c->bin_start, sizeof(int64_t) * ((size_t)c->ntiles + 1)) != hipSuccess)
+            return fail(c, PIC_E_NOMEM, "cannot allocate the tile bins");
+    }
     if ((size_t)n <= c->strag_cap) return PIC_OK;
     if (c->strag_list) {
+        // work already queued may still use the old buffers
         hipDeviceSynchronize();
         hipFree(c->strag_list);
-        c->strag_list = nullptr;
+        hipFree(c->bin_list);
+        hipFree(c->bin_rank);
+        c->strag_list = c->bin_list = nullptr;
+        c->bin_rank = nullptr;
         c->strag_cap = 0;
     }
     const size_t cap = (size_t)n + (size_t)n / 8 + 1024;
-    if (hipMalloc(&c->strag_list, cap * sizeof(int32_t)) != hipSuccess) {
-        c->strag_list = nullptr;
-        return fail(c, PIC_E_NOMEM, "cannot allocate the straggler list");
-    }
+    if (hipMalloc(&c->strag_list, cap * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c->bin_list, cap * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c->bin_rank, cap * sizeof(uint32_t)) != hipSuccess)
+        return fail(c, PIC_E_NOMEM, "cannot allocate the straggler lists");
     c->strag_cap = cap;
     return PIC_OK;
 }
@@ -192,7 +202,7 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
     if (e == hipSuccess) e = hipMemset(c->status, 0, 32);
     if (e == hipSuccess && cfg->precision == PIC_FP32_MIXED && c->lds_bytes > 64 * 1024)
         e = set_tiled_lds_limit(c->lds_bytes);
-    const size_t sort_lds = (size_t)7 * c->tile[0] * c->tile[1] * c->tile[2] * sizeof(uint32_t);
+    const size_t sort_lds = sort_lds_bytes(c->tile[0] * c->tile[1] * c->tile[2]);
     if (e == hipSuccess && cfg->precision == PIC_FP32_MIXED && sort_lds > 64 * 1024)
         e = set_sort_lds_limit(sort_lds);
     if (e != hipSuccess) {
@@ -227,6 +237,11 @@ extern "C" void pic_destroy(void *ctx) {
     hipFree(c->status);
     hipFree(c->partials);
     hipFree(c->strag_list);
+    hipFree(c->bin_list);
+    hipFree(c->bin_rank);
+    hipFree(c->bin_count);
+    hipFree(c->strag_tile);
+    hipFree(c->bin_start);
     for (int b = 0; b < 2; ++b) {
         hipFree(c->keys[b]);
         hipFree(c->vals[b]);

@@ -71,8 +71,18 @@ struct TiledArgs {
     double *partials;
     uint32_t *status;
     unsigned long long *stragglers;
-    int32_t *strag_list;   // particles left for the global path (capacity n)
+    // sorted pass: the stragglers of tile t are strag_list[tile_start[t] ..
+    // + strag_tile[t]); binned pass: strag_list[0 .. strag_count)
+    int32_t *strag_list;   // capacity n
+    uint32_t *strag_tile;  // ntiles
     uint32_t *strag_count;
+    // binned second pass: particles of tile t are bin_list[bin_start[t] ..
+    // bin_start[t+1]); bin_count/bin_rank build it
+    int32_t *bin_list;
+    int64_t *bin_start;    // ntiles + 1
+    uint32_t *bin_count;   // ntiles
+    uint32_t *bin_rank;    // per entry of the straggler list and tail (capacity n)
+    int part_off;          // first partial slot (doubles) of the launch
 };
 
 // Accessor of the LDS window: coordinates local to the window origin.  Fields
@@ -319,21 +329,42 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return t;
 }
 
-template <int DIM, int ORDER, int NT, int WX, int WY, int WZ>
+// Byte offset of a particle's elements: 32-bit against per-tile bases in the
+// sorted (contiguous) pass, 64-bit against the array bases in the binned pass.
+template <bool LIST>
+struct POff {
+    typedef uint32_t type;
+};
+template <>
+struct POff<true> {
+    typedef uint64_t type;
+};
+
+// LIST = false: the tile's particles are [tile_start[t], tile_start[t+1]) of
+// the sorted arrays.  LIST = true: they are bin_list[bin_start[t] ..
+// bin_start[t+1]) (the stragglers and appended particles binned by the tile
+// that holds them now).
+template <int DIM, int ORDER, int NT, int WX, int WY, int WZ, bool LIST>
 __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
+    typedef typename POff<LIST>::type off_t;
     const int b = blockIdx.x;
     const int t = (b & 7) * a.chunk + (b >> 3);  // XCD-contiguous tile runs
     if (t >= a.ntiles) return;
-    const int64_t pbeg = min(a.tile_start[t], a.n), pend = min(a.tile_start[t + 1], a.n);
+    const int64_t *start = LIST ? a.bin_start : a.tile_start;
+    const int64_t pbeg = min(start[t], a.n), pend = min(start[t + 1], a.n);
     __shared__ double red_k[NT / 64], red_q[NT / 64];
     __shared__ float wmax_s[NT / 64];
+    __shared__ uint32_t nstray;
+    double *part = a.partials + a.part_off;
     if (pbeg >= pend) {
         if (threadIdx.x == 0) {
-            a.partials[2 * t] = 0.0;
-            a.partials[2 * t + 1] = 0.0;
+            part[2 * t] = 0.0;
+            part[2 * t + 1] = 0.0;
+            if (!LIST) a.strag_tile[t] = 0u;
         }
         return;
     }
+    if (threadIdx.x == 0) nstray = 0u;
     const int tx = t % a.ntile_axis[0];
     const int ty = (t / a.ntile_axis[0]) % a.ntile_axis[1];
     const int tz = DIM == 3 ? t / (a.ntile_axis[0] * a.ntile_axis[1]) : 0;
@@ -344,16 +375,24 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     const int wx = lds.wx(), wxy = lds.wxy();
     unsigned long long *jwin = (unsigned long long *)(pic_smem + 6 * wn);
     const uint32_t np = (uint32_t)(pend - pbeg);
-    // per-tile bases: every particle array is then addressed by one 32-bit offset
-    int32_t *cellT = a.cell + pbeg;
+    // element offsets: sorted pass, bases moved to the tile's first particle
+    // and one 32-bit offset per particle; binned pass, offsets of the listed
+    // particles against the array bases
+    const int64_t rebase = LIST ? 0 : pbeg;
+    const int32_t *plist = a.bin_list + pbeg;
+    auto poff = [&](uint32_t i) -> off_t {
+        return LIST ? (off_t)4 * (off_t)(uint32_t)plist[i] : (off_t)(4u * i);
+    };
+    auto pidx = [&](uint32_t i) -> int64_t { return LIST ? (int64_t)plist[i] : pbeg + i; };
+    int32_t *cellT = a.cell + rebase;
     float *offT[3], *uT[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        offT[d] = a.off[d] + pbeg;
-        uT[d] = a.u[d] + pbeg;
+        offT[d] = a.off[d] + rebase;
+        uT[d] = a.u[d] + rebase;
     }
-    const float *wT = a.w ? a.w + pbeg : nullptr;
-    float *chiT = a.chi ? a.chi + pbeg : nullptr;
+    const float *wT = a.w ? a.w + rebase : nullptr;
+    float *chiT = a.chi ? a.chi + rebase : nullptr;
 
     // 1. stage the E/B window, zero the J window (window index decoded once
     //    per cell), bound the weights of the tile
@@ -374,7 +413,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     float wm = fabsf(a.w0);
     if (wT) {
         wm = 0.0f;
-        for (uint32_t i = threadIdx.x; i < np; i += NT) wm = fmaxf(wm, fabsf(ld(wT, 4u * i)));
+        for (uint32_t i = threadIdx.x; i < np; i += NT) wm = fmaxf(wm, fabsf(ld(wT, poff(i))));
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) wm = fmaxf(wm, __shfl_xor(wm, o));
@@ -399,7 +438,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     int32_t n_cell = 0;
     float n_f[3] = {0.0f, 0.0f, 0.0f}, n_u[3] = {0.0f, 0.0f, 0.0f}, n_w = a.w0;
     if (i < np) {
-        const uint32_t bo = 4u * i;
+        const off_t bo = poff(i);
         n_cell = ld(cellT, bo);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) n_f[d] = ld(offT[d], bo);
@@ -408,13 +447,13 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         if (wT) n_w = ld(wT, bo);
     }
     for (; i < np; i += NT) {
-        const uint32_t bo = 4u * i;
+        const off_t bo = poff(i);
         const int32_t cell = n_cell;
         float f[3] = {n_f[0], n_f[1], n_f[2]};
         float u[3] = {n_u[0], n_u[1], n_u[2]};
         const float w = n_w;
         if (i + NT < np) {
-            const uint32_t bn = bo + 4u * NT;
+            const off_t bn = LIST ? poff(i + NT) : bo + (off_t)(4u * NT);
             n_cell = ld(cellT, bn);
 #pragma unroll
             for (int d = 0; d < DIM; ++d) n_f[d] = ld(offT[d], bn);
@@ -428,17 +467,19 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         // here only if the whole stencil lies in the window and its offsets
         // are in [0,1) (as bit patterns: 0 <= bits < bits(1.0f))
         int lc[3] = {0, 0, 0};
-        bool inside = true;
+        bool inside = DIM == 3 || (cell >> (a.bx + a.by)) == 0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             const int l = wrap_index(cc[d] - org[d], a.ng[d]);
             lc[d] = l;
-            inside &= (unsigned)(l - 2) <= (unsigned)(hi[d] - 2);
+            inside &= (unsigned)(l - 2) <= (unsigned)(hi[d] - 2) && (unsigned)cc[d] < (unsigned)a.ng[d];
             inside &= __float_as_uint(f[d]) < 0x3f800000u;
         }
         if (!inside) {
-            const uint32_t slot = atomicAdd(a.strag_count, 1u);
-            a.strag_list[slot] = (int32_t)(pbeg + i);
+            // sorted pass: into the tile's own slice of the list (LDS counter);
+            // binned pass (rare): appended to the shared list
+            const uint32_t slot = LIST ? atomicAdd(a.strag_count, 1u) : (uint32_t)pbeg + atomicAdd(&nstray, 1u);
+            a.strag_list[slot] = (int32_t)pidx(i);
             continue;
         }
         const float u_old[3] = {u[0], u[1], u[2]};
@@ -482,25 +523,194 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     const double sk = block_sum<NT>(kin, red_k);
     const double sq = block_sum<NT>(chg, red_q);
     if (threadIdx.x == 0) {
-        a.partials[2 * t] = sk * a.mdV;
-        a.partials[2 * t + 1] = sq * a.qdV;
+        part[2 * t] = sk * a.mdV;
+        part[2 * t + 1] = sq * a.qdV;
+        if (!LIST) a.strag_tile[t] = nstray;
     }
+}
+
+// Clears the bin counters and the straggler count before the sorted pass.
+__global__ void gpd_prep_kernel(uint32_t *bin_count, int ntiles, uint32_t *strag_count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ntiles) bin_count[i] = 0u;
+    if (i == 0) *strag_count = 0u;
 }
 
 __global__ void gpd_reset_kernel(uint32_t *count) { *count = 0u; }
 
-// Global-memory path: particles after the last tile (created since the last
-// sort, e.g. by the QED step), then the stragglers listed by the tile kernel.
-// Each is checked before it is touched: an offset outside [0,1) or a cell off
-// the grid is flagged PIC_F_OFFSET and the particle is left unchanged.
+__device__ __forceinline__ int tile_of(const TiledArgs &a, int dim, int32_t cell) {
+    const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
+    const int ix = cell & mx, iy = (cell >> a.bx) & my, iz = dim == 3 ? (cell >> (a.bx + a.by)) : 0;
+    return ix / a.tile[0] + a.ntile_axis[0] * (iy / a.tile[1] + a.ntile_axis[1] * (iz / a.tile[2]));
+}
+
+constexpr uint32_t BIN_SKIP = 0xFFFFFFFFu;
+constexpr int TAIL_BLOCKS = 256;
+constexpr int BIN_REACH = 2;                      // neighbour tiles counted in LDS: +-2 per axis
+constexpr int BIN_SLOTS = 125;                    // (2 BIN_REACH + 1)^3
+
+// Work item of the binning kernels: block b < ntiles takes the stragglers of
+// tile b (strag_list[tile_start[b] .. + strag_tile[b])); the last
+// TAIL_BLOCKS blocks stride over the particles appended after the last tile.
+// *pos is the entry's slot in bin_rank (its list position, or the particle
+// index for the tail: the two ranges are disjoint).
+struct BinItems {
+    int64_t lo, hi, stride;
+    bool tail;
+};
+__device__ __forceinline__ BinItems bin_items(const TiledArgs &a) {
+    BinItems it;
+    const int b = blockIdx.x;
+    if (b < a.ntiles) {
+        it.lo = min(a.tile_start[b], a.n);
+        it.hi = min(it.lo + (int64_t)a.strag_tile[b], a.n);
+        it.stride = blockDim.x;
+        it.tail = false;
+        it.lo += threadIdx.x;
+    } else {
+        const int64_t first = min(a.tile_start[a.ntiles], a.n);
+        it.lo = first + (int64_t)(b - a.ntiles) * blockDim.x + threadIdx.x;
+        it.hi = a.n;
+        it.stride = (int64_t)TAIL_BLOCKS * blockDim.x;
+        it.tail = true;
+    }
+    return it;
+}
+
+// slot of destination tile `dt` among the neighbours of tile `st` (periodic),
+// or -1 when it lies further than BIN_REACH tiles along some axis
+template <int DIM>
+__device__ __forceinline__ int neighbour_slot(const TiledArgs &a, int st, int dt) {
+    int slot = 0, mul = 1;
+    int sc[3] = {st % a.ntile_axis[0], (st / a.ntile_axis[0]) % a.ntile_axis[1], st / (a.ntile_axis[0] * a.ntile_axis[1])};
+    int dc[3] = {dt % a.ntile_axis[0], (dt / a.ntile_axis[0]) % a.ntile_axis[1], dt / (a.ntile_axis[0] * a.ntile_axis[1])};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const int nt = a.ntile_axis[d];
+        int o = dc[d] - sc[d];
+        if (2 * o >= nt) o -= nt;      // nearest periodic image
+        if (2 * o < -nt) o += nt;
+        if (o < -BIN_REACH || o > BIN_REACH) return -1;
+        slot += (o + BIN_REACH) * mul;
+        mul *= 2 * BIN_REACH + 1;
+    }
+    return slot;
+}
+
+// Bins the stragglers of the sorted pass and the appended particles by the
+// tile that holds them now.  A block counts the destinations that neighbour
+// its tile in LDS and reserves each neighbour's share with one global atomic;
+// farther destinations (and the tail) reserve one by one.  A particle with an
+// offset outside [0,1) or a cell off the grid is flagged PIC_F_OFFSET and left
+// unchanged (never pushed).
+template <int DIM>
+__global__ void __launch_bounds__(256) gpd_bin_count_kernel(TiledArgs a) {
+    __shared__ uint32_t lcnt[BIN_SLOTS], gbase[BIN_SLOTS];
+    __shared__ uint32_t nfound;
+    for (int k = threadIdx.x; k < BIN_SLOTS; k += blockDim.x) lcnt[k] = 0u;
+    if (threadIdx.x == 0) nfound = 0u;
+    __syncthreads();
+    const BinItems it = bin_items(a);
+    if (!it.tail && threadIdx.x == 0 && a.strag_tile[blockIdx.x] > 0u) {
+        atomicOr(a.status, PIC_F_STRAGGLER);
+        atomicAdd(a.stragglers, (unsigned long long)a.strag_tile[blockIdx.x]);
+    }
+    const int st = blockIdx.x;
+    const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
+    for (int64_t k = it.lo; k < it.hi; k += it.stride) {
+        const int64_t p = it.tail ? k : (int64_t)a.strag_list[k];
+        const int32_t cell = a.cell[p];
+        const int cc[3] = {cell & mx, (cell >> a.bx) & my, DIM == 3 ? (cell >> (a.bx + a.by)) : 0};
+        // the bits above x and y hold z in 3D and must be zero in 2D
+        bool ok = (unsigned)(cell >> (a.bx + a.by)) < (unsigned)(DIM == 3 ? a.ng[2] : 1);
+        float fs = 0.0f;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            const float f = a.off[d][p];
+            fs += f;
+            ok &= f >= 0.0f && f < 1.0f && (unsigned)cc[d] < (unsigned)a.ng[d];
+        }
+        if (!isfinite(a.u[0][p] + a.u[1][p] + a.u[2][p]) || !isfinite(fs)) atomicOr(a.status, PIC_F_NONFINITE);
+        if (!ok) {
+            atomicOr(a.status, PIC_F_OFFSET);
+            a.bin_rank[k] = BIN_SKIP;
+            continue;
+        }
+        const int dt = tile_of(a, DIM, cell);
+        const int slot = it.tail ? -1 : neighbour_slot<DIM>(a, st, dt);
+        // neighbour: rank inside the block's share (top bit marks it);
+        // otherwise the final rank straight from the global counter
+        a.bin_rank[k] = slot >= 0 ? (0x80000000u | atomicAdd(&lcnt[slot], 1u))
+                                  : atomicAdd(&a.bin_count[dt], 1u);
+        if (!it.tail) atomicAdd(&nfound, 1u);
+    }
+    __syncthreads();
+    if (it.tail || nfound == 0u) return;
+    // reserve each neighbour's share, then turn local ranks into final ones
+    const int sc[3] = {st % a.ntile_axis[0], (st / a.ntile_axis[0]) % a.ntile_axis[1],
+                       st / (a.ntile_axis[0] * a.ntile_axis[1])};
+    for (int k = threadIdx.x; k < BIN_SLOTS; k += blockDim.x) {
+        if (lcnt[k] == 0u) continue;
+        int dc[3] = {0, 0, 0}, r = k;
+        for (int d = 0; d < DIM; ++d) {
+            const int o = r % (2 * BIN_REACH + 1) - BIN_REACH;
+            r /= 2 * BIN_REACH + 1;
+            dc[d] = ((sc[d] + o) % a.ntile_axis[d] + a.ntile_axis[d]) % a.ntile_axis[d];
+        }
+        const int dt = dc[0] + a.ntile_axis[0] * (dc[1] + a.ntile_axis[1] * dc[2]);
+        gbase[k] = atomicAdd(&a.bin_count[dt], lcnt[k]);
+    }
+    __syncthreads();
+    for (int64_t k = it.lo; k < it.hi; k += it.stride) {
+        const uint32_t r = a.bin_rank[k];
+        if (r == BIN_SKIP || !(r & 0x80000000u)) continue;
+        const int32_t cell = a.cell[a.strag_list[k]];
+        a.bin_rank[k] = gbase[neighbour_slot<DIM>(a, st, tile_of(a, DIM, cell))] + (r & 0x7FFFFFFFu);
+    }
+}
+
+// bin_start = exclusive scan of bin_count (one workgroup, in order)
+__global__ void __launch_bounds__(1024) gpd_bin_scan_kernel(const uint32_t *count, int ntiles, int64_t *bstart) {
+    __shared__ int64_t part[1024];
+    const int per = (ntiles + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = min(lo + per, ntiles);
+    int64_t s = 0;
+    for (int i = lo; i < hi; ++i) s += count[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t run = part[threadIdx.x] - s;
+    for (int i = lo; i < hi; ++i) {
+        bstart[i] = run;
+        run += count[i];
+    }
+    if (threadIdx.x == 1023) bstart[ntiles] = part[1023];
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(256) gpd_bin_scatter_kernel(TiledArgs a) {
+    const BinItems it = bin_items(a);
+    for (int64_t k = it.lo; k < it.hi; k += it.stride) {
+        const uint32_t r = a.bin_rank[k];
+        if (r == BIN_SKIP) continue;
+        const int64_t p = it.tail ? k : (int64_t)a.strag_list[k];
+        a.bin_list[a.bin_start[tile_of(a, DIM, a.cell[p])] + r] = (int32_t)p;
+    }
+}
+
+// Global-memory path for what the binned pass could not place in a window
+// (normally nothing: a binned particle sits in its own tile).  Same checks as
+// the binning: invalid particles are flagged and left unchanged.
 constexpr int GLOBAL_BLOCKS = 256;
 
 template <int DIM, int ORDER>
 __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
-    const int64_t first = min(a.tile_start[a.ntiles], a.n);
-    const int64_t ntail = a.n - first;
-    const int64_t nstrag = (int64_t)*a.strag_count;
-    const int64_t total = ntail + nstrag;
+    const int64_t total = (int64_t)*a.strag_count;
     __shared__ double red_k[4], red_q[4];
     double kin = 0.0, chg = 0.0;
     GlobAcc glob{{a.F[0], a.F[1], a.F[2], a.F[3], a.F[4], a.F[5]},
@@ -509,7 +719,7 @@ __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
     const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = k < ntail ? first + k : (int64_t)a.strag_list[k - ntail];
+        const int64_t p = a.strag_list[k];
         const int32_t cell = a.cell[p];
         const int cc[3] = {cell & mx, (cell >> a.bx) & my, DIM == 3 ? (cell >> (a.bx + a.by)) : 0};
         float f[3] = {a.off[0][p], a.off[1][p], DIM == 3 ? a.off[2][p] : 0.0f};
@@ -519,7 +729,6 @@ __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
         bool ok = (unsigned)(cell >> (a.bx + a.by)) < (unsigned)(DIM == 3 ? a.ng[2] : 1);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) ok &= f[d] >= 0.0f && f[d] < 1.0f && (unsigned)cc[d] < (unsigned)a.ng[d];
-        if (!isfinite(u[0] + u[1] + u[2]) || !isfinite(f[0] + f[1] + f[2])) atomicOr(a.status, PIC_F_NONFINITE);
         if (!ok) {
             atomicOr(a.status, PIC_F_OFFSET);
             continue;
@@ -545,12 +754,8 @@ __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
     const double sk = block_sum<256>(kin, red_k);
     const double sq = block_sum<256>(chg, red_q);
     if (threadIdx.x == 0) {
-        a.partials[2 * (a.ntiles + blockIdx.x)] = sk * a.mdV;
-        a.partials[2 * (a.ntiles + blockIdx.x) + 1] = sq * a.qdV;
-        if (blockIdx.x == 0 && nstrag > 0) {
-            atomicOr(a.status, PIC_F_STRAGGLER);
-            atomicAdd(a.stragglers, (unsigned long long)nstrag);
-        }
+        a.partials[a.part_off + 2 * blockIdx.x] = sk * a.mdV;
+        a.partials[a.part_off + 2 * blockIdx.x + 1] = sq * a.qdV;
     }
 }
 
@@ -558,25 +763,40 @@ __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
 // 8x8x4 tiles with drift 1 in 3D (the defaults); others use the run-time shape
 constexpr int W2X = 16 + 2 * 2 + 5, W3X = 8 + 2 * 1 + 5, W3Z = 4 + 2 * 1 + 5;
 
+// One push of a species:
+//   prep (zero bin counters) -> sorted pass (stragglers listed) -> bin count
+//   -> bin scan -> bin scatter -> reset of the list -> binned pass -> global
+//   pass over whatever the binned pass listed.
+// Partials: [sorted pass: 2 ntiles][binned pass: 2 ntiles][global: 2 x 256].
 template <int DIM, int ORDER, int NT, int WX, int WY, int WZ>
-static void launch_pair(const TiledArgs &a, size_t lds, hipStream_t s) {
+static void launch_passes(TiledArgs a, size_t lds, hipStream_t s) {
+    const dim3 tiles((unsigned)(8 * a.chunk)), block(NT), gb(GLOBAL_BLOCKS), b256(256);
+    gpd_prep_kernel<<<(unsigned)((a.ntiles + 255) / 256), 256, 0, s>>>(a.bin_count, a.ntiles, a.strag_count);
+    a.part_off = 0;
+    gpd_tiled_kernel<DIM, ORDER, NT, WX, WY, WZ, false><<<tiles, block, lds, s>>>(a);
+    const dim3 bins((unsigned)(a.ntiles + TAIL_BLOCKS));
+    gpd_bin_count_kernel<DIM><<<bins, b256, 0, s>>>(a);
+    gpd_bin_scan_kernel<<<1, 1024, 0, s>>>(a.bin_count, a.ntiles, a.bin_start);
+    gpd_bin_scatter_kernel<DIM><<<bins, b256, 0, s>>>(a);
     gpd_reset_kernel<<<1, 1, 0, s>>>(a.strag_count);
-    gpd_tiled_kernel<DIM, ORDER, NT, WX, WY, WZ><<<dim3((unsigned)(8 * a.chunk)), dim3(NT), lds, s>>>(a);
-    gpd_global_kernel<DIM, ORDER><<<dim3(GLOBAL_BLOCKS), dim3(256), 0, s>>>(a);
+    a.part_off = 2 * a.ntiles;
+    gpd_tiled_kernel<DIM, ORDER, NT, WX, WY, WZ, true><<<tiles, block, lds, s>>>(a);
+    a.part_off = 4 * a.ntiles;
+    gpd_global_kernel<DIM, ORDER><<<gb, b256, 0, s>>>(a);
 }
 
 template <int DIM, int ORDER>
 static void launch_tiled(const TiledArgs &a, size_t lds, hipStream_t s) {
     if constexpr (DIM == 2) {
         if (a.win[0] == W2X && a.win[1] == W2X)
-            launch_pair<2, ORDER, PIC_TILED_THREADS_2D, W2X, W2X, 1>(a, lds, s);
+            launch_passes<2, ORDER, PIC_TILED_THREADS_2D, W2X, W2X, 1>(a, lds, s);
         else
-            launch_pair<2, ORDER, PIC_TILED_THREADS_2D, 0, 0, 0>(a, lds, s);
+            launch_passes<2, ORDER, PIC_TILED_THREADS_2D, 0, 0, 0>(a, lds, s);
     } else {
         if (a.win[0] == W3X && a.win[1] == W3X && a.win[2] == W3Z)
-            launch_pair<3, ORDER, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(a, lds, s);
+            launch_passes<3, ORDER, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(a, lds, s);
         else
-            launch_pair<3, ORDER, PIC_TILED_THREADS_3D, 0, 0, 0>(a, lds, s);
+            launch_passes<3, ORDER, PIC_TILED_THREADS_3D, 0, 0, 0>(a, lds, s);
     }
 }
 
@@ -621,10 +841,16 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
     a.status = c->status;
     a.stragglers = (unsigned long long *)(c->status + 2);
     a.strag_count = c->status + 4;
-    if (ensure_partials(c, 2 * ((size_t)c->ntiles + GLOBAL_BLOCKS)) != PIC_OK) return hipErrorOutOfMemory;
+    const size_t nblocks = 2 * (size_t)c->ntiles + GLOBAL_BLOCKS;
+    if (ensure_partials(c, 2 * nblocks) != PIC_OK) return hipErrorOutOfMemory;
     if (ensure_strag_list(c, p->n) != PIC_OK) return hipErrorOutOfMemory;
     a.partials = c->partials;
     a.strag_list = c->strag_list;
+    a.strag_tile = c->strag_tile;
+    a.bin_list = c->bin_list;
+    a.bin_rank = c->bin_rank;
+    a.bin_start = c->bin_start;
+    a.bin_count = c->bin_count;
     const size_t lds = c->lds_bytes;
     switch (c->dim * 10 + cfg.order) {
         case 21: launch_tiled<2, 1>(a, lds, s); break;
@@ -635,23 +861,28 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !diag) return e;
-    return launch_finalize(c->partials, c->ntiles + GLOBAL_BLOCKS, 2, diag, 0, 1.0, s);
+    return launch_finalize(c->partials, (int64_t)nblocks, 2, diag, 0, 1.0, s);
+}
+
+template <int DIM, int ORDER, int NT, int WX, int WY, int WZ>
+static hipError_t set_lds(size_t bytes) {
+    hipError_t e = hipFuncSetAttribute((const void *)gpd_tiled_kernel<DIM, ORDER, NT, WX, WY, WZ, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)gpd_tiled_kernel<DIM, ORDER, NT, WX, WY, WZ, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t set_tiled_lds_limit(size_t bytes) {
-    const void *k[8] = {(const void *)gpd_tiled_kernel<2, 1, PIC_TILED_THREADS_2D, 0, 0, 0>,
-                        (const void *)gpd_tiled_kernel<2, 2, PIC_TILED_THREADS_2D, 0, 0, 0>,
-                        (const void *)gpd_tiled_kernel<3, 1, PIC_TILED_THREADS_3D, 0, 0, 0>,
-                        (const void *)gpd_tiled_kernel<3, 2, PIC_TILED_THREADS_3D, 0, 0, 0>,
-                        (const void *)gpd_tiled_kernel<2, 1, PIC_TILED_THREADS_2D, W2X, W2X, 1>,
-                        (const void *)gpd_tiled_kernel<2, 2, PIC_TILED_THREADS_2D, W2X, W2X, 1>,
-                        (const void *)gpd_tiled_kernel<3, 1, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>,
-                        (const void *)gpd_tiled_kernel<3, 2, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>};
-    for (const void *f : k) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    hipError_t e = set_lds<2, 1, PIC_TILED_THREADS_2D, 0, 0, 0>(bytes);
+    if (e == hipSuccess) e = set_lds<2, 2, PIC_TILED_THREADS_2D, 0, 0, 0>(bytes);
+    if (e == hipSuccess) e = set_lds<3, 1, PIC_TILED_THREADS_3D, 0, 0, 0>(bytes);
+    if (e == hipSuccess) e = set_lds<3, 2, PIC_TILED_THREADS_3D, 0, 0, 0>(bytes);
+    if (e == hipSuccess) e = set_lds<2, 1, PIC_TILED_THREADS_2D, W2X, W2X, 1>(bytes);
+    if (e == hipSuccess) e = set_lds<2, 2, PIC_TILED_THREADS_2D, W2X, W2X, 1>(bytes);
+    if (e == hipSuccess) e = set_lds<3, 1, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(bytes);
+    if (e == hipSuccess) e = set_lds<3, 2, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(bytes);
+    return e;
 }
 
 }  // namespace pic

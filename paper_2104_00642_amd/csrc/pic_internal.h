@@ -25,9 +25,15 @@ struct Ctx {
     // device status: [0] flags, [2..3] straggler count (uint64 at byte 8),
     // [4] length of the straggler list of the current push
     uint32_t *status = nullptr;
-    // indices of the particles the tile kernel leaves to the global path
+    // push scratch: stragglers of the sorted pass, their bin ranks and the
+    // binned list (capacity strag_cap entries each), bin counters and starts
     int32_t *strag_list = nullptr;
+    int32_t *bin_list = nullptr;
+    uint32_t *bin_rank = nullptr;
     size_t strag_cap = 0;        // entries
+    uint32_t *bin_count = nullptr;  // ntiles
+    uint32_t *strag_tile = nullptr; // ntiles
+    int64_t *bin_start = nullptr;   // ntiles + 1
     // FP64 block partials of the diagnostics reductions
     double *partials = nullptr;
     size_t partials_cap = 0;     // in doubles
@@ -67,6 +73,7 @@ hipError_t launch_mlp_grad(const void *mlp, const float *x, const float *t, int6
 hipError_t launch_mlp_train(float *state, void *mlp, const float *x, const float *t, int64_t n, int batch,
                             int iters, float lr, float *loss, hipStream_t s);
 hipError_t launch_mlp_data(Ctx *c, int64_t n, uint64_t seed, float *x, float *t, hipStream_t s);
+size_t sort_lds_bytes(int cells_per_tile);
 hipError_t launch_finalize(const double *partials, int64_t nblocks, int nval, double *diag,
                            int diag_offset, double scale, hipStream_t s);
 

@@ -1,7 +1,7 @@
 // sort.hip -- tile binning of the FP32 particles (pic_sort).
 //
 // Order produced: (tile, rank of the particle among those of its cell in the
-// source order, cell within the tile).  Steps:
+// source order, key of the cell within the tile; see local_key).  Steps:
 //   1. key = tile id of the particle's cell;
 //   2. stable LSD radix sort of the tile keys (8-bit digits: per-block digit
 //      histograms, one device-wide exclusive scan, stable scatter with ranks
@@ -32,10 +32,6 @@ struct SortGeom {
     int cls_start[8];  // first key of each parity class of cells
 };
 
-#ifndef PIC_SORT_PARITY
-#define PIC_SORT_PARITY 1
-#endif
-
 // Key of a cell inside its tile (li, lj, lk tile-local): cells are grouped by
 // the parities of their coordinates, classes taken in an order where
 // consecutive classes differ in as many parities as possible, and by the
@@ -44,14 +40,10 @@ struct SortGeom {
 // that share a wavefront seldom start on the same node and their LDS current
 // atomics seldom hit the same address.
 __device__ __forceinline__ uint32_t local_key(int li, int lj, int lk, const SortGeom &g) {
-#if PIC_SORT_PARITY
     const int px = li & 1, py = lj & 1, pz = lk & 1;
     const int nx = (g.tile[0] + 1 - px) >> 1;  // cells of parity px along x
     const int ny = (g.tile[1] + 1 - py) >> 1;
     return (uint32_t)(g.cls_start[px | (py << 1) | (pz << 2)] + (li >> 1) + nx * ((lj >> 1) + ny * (lk >> 1)));
-#else
-    return (uint32_t)(li + g.tile[0] * (lj + g.tile[1] * lk));
-#endif
 }
 
 __device__ __forceinline__ void decode_cell(int32_t c, const SortGeom &g, int &ix, int &iy, int &iz) {
@@ -234,48 +226,108 @@ struct PermArgs {
     int nd;
 };
 
+// Layers of phase C handled per pass: R layers x (cells/64) group counters
+// stay within 16 KB of LDS.
+__host__ __device__ inline int sort_layer_chunk(int ct) {
+    const int ng = (ct + 63) / 64;
+    const int r = 4096 / ng;
+    return r < 1 ? 1 : (r > 256 ? 256 : r);
+}
+
+size_t sort_lds_bytes(int ct) {
+    const int ng = (ct + 63) / 64;
+    return sizeof(uint32_t) * ((size_t)6 * ct + (size_t)sort_layer_chunk(ct) * ng + 256);
+}
+
+// One workgroup (4 wavefronts) per tile.
+//   A. each wavefront ranks the particles of its contiguous share of the tile
+//      within their cells (8 ballots match equal cells; the wavefront keeps
+//      private per-cell counters, so no workgroup barrier is needed);
+//   B. per cell: count, base of each wavefront's share, first slot in cell
+//      order; every particle then writes its source index to its slot;
+//   C. layer r holds the r-th particle of every cell with more than r, cells
+//      in key order: its start is the number of particles in earlier layers,
+//      and a cell's place in it the number of populated cells before it,
+//      both from ballots over groups of 64 cells;
+//   D. gather of every particle array in final order.
 __global__ void __launch_bounds__(256) tile_order_kernel(const uint32_t *vals, const int64_t *tile_start,
                                                          SortGeom g, int lbits, uint32_t *lcell,
-                                                         uint32_t *slot_src, uint32_t *inv, PermArgs pa) {
+                                                         uint32_t *lrank, uint32_t *slot_src, uint32_t *inv,
+                                                         PermArgs pa) {
     extern __shared__ uint32_t sm[];
     const int ct = g.ct;
-    uint32_t *cnt = sm;            // ct: particles per cell
-    uint32_t *cst = sm + ct;       // ct: first slot of each cell in cell order
-    uint32_t *run = sm + 2 * ct;   // ct: particles of the cell ranked so far
-    uint32_t *wcnt = sm + 3 * ct;  // 4 x ct: per-wave counts of one round
+    const int ng = (ct + 63) >> 6;
+    const int R = sort_layer_chunk(ct);
+    uint32_t *wcnt = sm;          // 4 x ct: per-wavefront counts, then bases
+    uint32_t *cnt = sm + 4 * ct;  // ct: particles per cell
+    uint32_t *cst = sm + 5 * ct;  // ct: first cell-order slot of each cell
+    uint32_t *gc = sm + 6 * ct;   // R x ng: populated cells per group and layer, then offsets
+    uint32_t *lb = gc + R * ng;   // R: first position of each layer of the pass
     __shared__ uint32_t tmp_s[256];
-    __shared__ uint32_t maxc;
+    __shared__ uint32_t maxc_s;
     const int t = blockIdx.x;
     const int64_t ts = tile_start[t], te = tile_start[t + 1];
     if (ts == te) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    for (int l = threadIdx.x; l < ct; l += blockDim.x) {
-        cnt[l] = 0;
-        run[l] = 0;
-    }
-    if (threadIdx.x == 0) maxc = 0;
+    const int64_t n_t = te - ts;
+    const int64_t cw = ((n_t + 255) / 256) * 64;  // share of one wavefront, a multiple of 64
+    const int64_t c0 = ts + wave * cw, c1 = min(c0 + cw, te);
+    for (int e = threadIdx.x; e < 4 * ct; e += 256) wcnt[e] = 0;
+    if (threadIdx.x == 0) maxc_s = 0;
     __syncthreads();
-    // 1. cell within the tile of every particle (gathered once), counts
-    for (int64_t i = ts + threadIdx.x; i < te; i += blockDim.x) {
-        int ix, iy, iz;
-        decode_cell(pa.cell_in[vals[i]], g, ix, iy, iz);
-        const uint32_t l = local_key(ix % g.tile[0], iy % g.tile[1], iz % g.tile[2], g);
-        lcell[i] = l;
-        atomicAdd(&cnt[l], 1u);
+
+    // A. rank within the cell inside the wavefront's share (source order)
+    {
+        uint32_t *wc = wcnt + wave * ct;
+        for (int64_t base = c0; base < c1; base += 64) {
+            const int64_t i = base + lane;
+            const bool valid = i < c1;
+            uint32_t l = 0;
+            if (valid) {
+                int ix, iy, iz;
+                decode_cell(pa.cell_in[vals[i]], g, ix, iy, iz);
+                l = local_key(ix % g.tile[0], iy % g.tile[1], iz % g.tile[2], g);
+            }
+            uint64_t peers = __ballot(valid);
+            for (int b = 0; b < lbits; ++b) {
+                const uint64_t m = __ballot((l >> b) & 1u);
+                peers &= ((l >> b) & 1u) ? m : ~m;
+            }
+            const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+            uint32_t prev = 0;
+            if (valid) prev = wc[l];
+            // every lane has read its cell's counter before the first lane of
+            // each group of equal cells advances it (LDS keeps a wavefront's order)
+            __builtin_amdgcn_wave_barrier();
+            if (valid && rank == 0) wc[l] = prev + (uint32_t)__popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+            if (valid) {
+                lcell[i] = l;
+                lrank[i] = prev + rank;
+            }
+        }
     }
     __syncthreads();
-    // 2. exclusive scan of the counts (consecutive cells per thread)
+
+    // B. counts, wavefront bases, cell-order slots
     const int per = (ct + 255) / 256;
     uint32_t loc = 0, mx = 0;
     for (int q = 0; q < per; ++q) {
         const int l = threadIdx.x * per + q;
         if (l < ct) {
-            loc += cnt[l];
-            mx = max(mx, cnt[l]);
+            uint32_t run = 0;
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t c = wcnt[w * ct + l];
+                wcnt[w * ct + l] = run;
+                run += c;
+            }
+            cnt[l] = run;
+            loc += run;
+            mx = max(mx, run);
         }
     }
-    atomicMax(&maxc, mx);
+    atomicMax(&maxc_s, mx);
     uint32_t total;
     uint32_t ex = block_exclusive_scan(loc, tmp_s, total);
     for (int q = 0; q < per; ++q) {
@@ -286,59 +338,54 @@ __global__ void __launch_bounds__(256) tile_order_kernel(const uint32_t *vals, c
         }
     }
     __syncthreads();
-    // 3. stable rank within the cell, in source order -> slot in cell order
-    for (int64_t base = ts; base < te; base += blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        const bool valid = i < te;
-        const uint32_t l = valid ? lcell[i] : 0u;
-        for (int e = threadIdx.x; e < 4 * ct; e += blockDim.x) wcnt[e] = 0;
-        __syncthreads();
-        uint64_t peers = __ballot(valid);
-        for (int b = 0; b < lbits; ++b) {
-            const uint64_t m = __ballot((l >> b) & 1u);
-            peers &= ((l >> b) & 1u) ? m : ~m;
-        }
-        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-        if (valid && rank == 0) wcnt[wave * ct + l] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        for (int q = 0; q < per; ++q) {
-            const int ll = threadIdx.x * per + q;
-            if (ll < ct) {
-                uint32_t r = run[ll];
-                for (int w = 0; w < 4; ++w) {
-                    const uint32_t c = wcnt[w * ct + ll];
-                    wcnt[w * ct + ll] = r;
-                    r += c;
-                }
-                run[ll] = r;
+    for (int64_t i = c0 + lane; i < c1; i += 64) {
+        const uint32_t l = lcell[i];
+        slot_src[ts + cst[l] + wcnt[wave * ct + l] + lrank[i]] = vals[i];
+    }
+
+    // C. layers, R at a time
+    const uint32_t maxc = maxc_s;
+    uint32_t lcarry = 0;
+    for (uint32_t r0 = 0; r0 < maxc; r0 += (uint32_t)R) {
+        const uint32_t rr = min((uint32_t)R, maxc - r0);
+        for (int gi = wave; gi < ng; gi += 4) {
+            const int l = gi * 64 + lane;
+            const uint32_t c = l < ct ? cnt[l] : 0u;
+            for (uint32_t r = 0; r < rr; ++r) {
+                const uint64_t b = __ballot(c > r0 + r);
+                if (lane == 0) gc[r * ng + gi] = (uint32_t)__popcll(b);
             }
         }
         __syncthreads();
-        if (valid) slot_src[ts + cst[l] + wcnt[wave * ct + l] + rank] = vals[i];
+        uint32_t tot = 0;
+        if (threadIdx.x < rr) {
+            uint32_t run = 0;
+            for (int gi = 0; gi < ng; ++gi) {
+                const uint32_t c = gc[threadIdx.x * ng + gi];
+                gc[threadIdx.x * ng + gi] = run;
+                run += c;
+            }
+            tot = run;
+        }
+        uint32_t all;
+        const uint32_t lex = block_exclusive_scan(tot, tmp_s, all);
+        if (threadIdx.x < rr) lb[threadIdx.x] = lcarry + lex;
+        lcarry += all;
+        __syncthreads();
+        for (int gi = wave; gi < ng; gi += 4) {
+            const int l = gi * 64 + lane;
+            const uint32_t c = l < ct ? cnt[l] : 0u;
+            for (uint32_t r = 0; r < rr; ++r) {
+                const bool has = c > r0 + r;
+                const uint64_t b = __ballot(has);
+                if (has) inv[ts + lb[r] + gc[r * ng + gi] + (uint32_t)__popcll(b & lt_mask)] = cst[l] + r0 + r;
+            }
+        }
         __syncthreads();
     }
-    // 4. layers: the r-th particle of every cell holding more than r, cells
-    //    ascending; record which cell-order slot lands at each position
-    uint32_t layer_base = 0;
-    const uint32_t layers = maxc;
-    for (uint32_t r = 0; r < layers; ++r) {
-        uint32_t f = 0;
-        for (int q = 0; q < per; ++q) {
-            const int l = threadIdx.x * per + q;
-            f += (l < ct && cnt[l] > r) ? 1u : 0u;
-        }
-        uint32_t lt;
-        uint32_t pos = block_exclusive_scan(f, tmp_s, lt);
-        for (int q = 0; q < per; ++q) {
-            const int l = threadIdx.x * per + q;
-            if (l < ct && cnt[l] > r) inv[ts + layer_base + pos++] = cst[l] + r;
-        }
-        layer_base += lt;
-    }
-    __syncthreads();
-    // 5. gather every particle array into its final position (independent
+
+    // D. gather every particle array into its final position (independent
     //    iterations, four in flight per thread)
-    const int64_t n_t = te - ts;
     for (int64_t j0 = threadIdx.x; j0 < n_t; j0 += 4 * (int64_t)blockDim.x) {
         uint32_t src[4];
 #pragma unroll
@@ -451,13 +498,13 @@ hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *ds
     pa.nd = nd;
     int lbits = 0;
     while ((1 << lbits) < g.ct) ++lbits;
-    const size_t lds = (size_t)7 * g.ct * sizeof(uint32_t);
-    // scratch: keys[cur^1] (cells within the tile), final_perm (source of
+    // scratch: keys[cur^1] (key of the cell within the tile), vals[cur^1]
+    // (rank within the cell in the wavefront's share), final_perm (source of
     // each cell-order slot), keys[cur] (slot of each final position; the
     // sorted keys are no longer needed once tile_start is written)
-    tile_order_kernel<<<(unsigned)c->ntiles, 256, lds, s>>>(c->vals[cur], dst->tile_start, g, lbits,
-                                                            c->keys[cur ^ 1], c->final_perm,
-                                                            c->keys[cur], pa);
+    tile_order_kernel<<<(unsigned)c->ntiles, 256, sort_lds_bytes(g.ct), s>>>(
+        c->vals[cur], dst->tile_start, g, lbits, c->keys[cur ^ 1], c->vals[cur ^ 1], c->final_perm,
+        c->keys[cur], pa);
     return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@ import torch
 
 import oracle as O
 from paper_2104_00642_amd import _lib as L
-from paper_2104_00642_amd.workloads import courant_dt, to_fp32, to_fp64
+from paper_2104_00642_amd.workloads import concat, courant_dt, to_fp32, to_fp64
 
 from _helpers import (DEV, np64, oracle_grid, oracle_species, periodic_dx, random_fields, random_raw,
                       rel_l2)
@@ -156,6 +156,92 @@ def test_stragglers_take_the_global_path(dim, order):
         ug = np64(p.u[a])
         assert np.max(np.abs(ug - sp_o.u[a]) / (1.0 + np.abs(sp_o.u[a]))) < 2e-6
         assert rel_l2(np64(f.J[a]), J_o[a]) < 1e-5
+
+
+def check_fp32_against_oracle(cfg, p, f, bits, sp_o, J_o, skip=None):
+    """Positions (cell units), momenta and current of the FP32 particles p
+    against the oracle's; `skip` masks particles left out of the comparison."""
+    keep = np.ones(p.n, dtype=bool) if skip is None else ~skip
+    mask = [(1 << b) - 1 for b in bits]
+    cell = p.cell.cpu().to(torch.int64)
+    shift = 0
+    for a, Lx in enumerate(lengths(cfg)):
+        c = ((cell >> shift) & mask[a]).numpy()
+        shift += bits[a]
+        x = (c + np64(p.off[a])) * cfg.d[a]
+        assert np.abs(periodic_dx(x[keep], sp_o.x[a][keep], Lx)).max() / cfg.d[a] < 2e-6
+    for a in range(3):
+        ug = np64(p.u[a])[keep]
+        uo = sp_o.u[a][keep]
+        assert np.max(np.abs(ug - uo) / (1.0 + np.abs(uo))) < 2e-6
+    for a in range(3):
+        assert rel_l2(np64(f.J[a]), J_o[a]) < 1e-5, a
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_appended_particles_are_binned_and_pushed(dim):
+    """Particles appended after the sort (beyond tile_start[ntiles]) go
+    through the binned pass and are pushed like the oracle."""
+    print(f"appended dim={dim}", flush=True)
+    cfg = make_cfg(dim, 2, L.PIC_FP32_MIXED)
+    raw = random_raw(cfg, 3001, seed=300 + dim)
+    extra = random_raw(cfg, 777, seed=400 + dim)
+    E, B = random_fields(cfg, seed=11 + dim)
+    E = [e.to(torch.float32).to(torch.float64) for e in E]
+    B = [b.to(torch.float32).to(torch.float64) for b in B]
+    ctx, p, f, perm, start, bits = sorted_fp32_state(cfg, raw, E, B)
+    ex = to_fp32(extra, bits, with_chi=True)
+    cat = lambda a, b: torch.cat([a, b.to(DEV)])  # noqa: E731
+    q = L.Particles(p.n + ex.n, [cat(p.u[a], ex.u[a]) for a in range(3)], cell=cat(p.cell, ex.cell),
+                    off=[cat(p.off[a], ex.off[a]) for a in range(dim)], w=cat(p.w, ex.w),
+                    chi=cat(p.chi, ex.chi), tile_start=p.tile_start)
+    raw_all = concat([raw.subset(torch.from_numpy(perm)), extra])
+    sp_o, J_o, diag_o = run_oracle_push(cfg, raw_all, E, B, -1.0, 1.0, from_fp32=True)
+    diag = torch.zeros(4, dtype=torch.float64, device=DEV)
+    L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), q, f, diag)
+    st, flags, nstray = L.pic_check(ctx)
+    assert st == L.PIC_OK and flags == 0 and nstray == 0
+    check_fp32_against_oracle(cfg, q, f, bits, sp_o, J_o)
+    assert np64(diag)[:2] == pytest.approx(diag_o, rel=1e-5)
+
+
+def test_invalid_particles_are_flagged_and_left_unchanged():
+    """Offsets outside [0,1) (1.0, negative, NaN) and a packed cell off the
+    grid: the push flags them (PIC_F_OFFSET, PIC_F_NONFINITE for the NaN),
+    leaves them untouched, and pushes every other particle like the oracle."""
+    cfg = make_cfg(2, 2, L.PIC_FP32_MIXED)
+    raw = random_raw(cfg, 2003, seed=501)
+    E, B = random_fields(cfg, seed=21)
+    E = [e.to(torch.float32).to(torch.float64) for e in E]
+    B = [b.to(torch.float32).to(torch.float64) for b in B]
+    ctx, p, f, perm, start, bits = sorted_fp32_state(cfg, raw, E, B)
+    bad = np.zeros(p.n, dtype=bool)
+    idx = [5, 17, 400, 1999]
+    bad[idx] = True
+    p.off[0][5] = 1.0
+    p.off[1][17] = -0.25
+    p.off[0][400] = float("nan")
+    # x index 50 on a 48-cell axis (6 bits): off the grid
+    p.cell[1999] = (int(p.cell[1999].item()) & ~((1 << bits[0]) - 1)) | 50
+    before = [t.clone() for t in [p.cell, *p.off, *p.u]]
+    raw_sorted = raw.subset(torch.from_numpy(perm))
+    keep = torch.from_numpy(~bad)
+    sp_o, J_o, _ = run_oracle_push(cfg, raw_sorted.subset(keep), E, B, -1.0, 1.0, from_fp32=True)
+    L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), p, f)
+    st, flags, _ = L.pic_check(ctx)
+    assert st == L.PIC_E_STATE and flags & L.PIC_F_OFFSET and flags & L.PIC_F_NONFINITE
+    after = [p.cell, *p.off, *p.u]
+    for t0, t1 in zip(before, after):
+        a0, a1 = t0.cpu().numpy()[idx], t1.cpu().numpy()[idx]
+        assert np.array_equal(a0, a1, equal_nan=a0.dtype.kind == "f")
+    # the others: compare on the kept particles (oracle arrays are compacted)
+    full = O.Species(q=-1.0, m=1.0, x=[np.zeros(p.n) for _ in range(2)], u=[np.zeros(p.n) for _ in range(3)],
+                     w=None, w0=1.0)
+    for a in range(2):
+        full.x[a][~bad] = sp_o.x[a]
+    for a in range(3):
+        full.u[a][~bad] = sp_o.u[a]
+    check_fp32_against_oracle(cfg, p, f, bits, full, J_o, skip=bad)
 
 
 @pytest.mark.parametrize("dim", [2, 3])

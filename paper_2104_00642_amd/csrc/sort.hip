@@ -215,16 +215,19 @@ __global__ void __launch_bounds__(256) tile_bounds_kernel(const uint32_t *keys, 
 
 // ---- per tile: stable in-cell ranks, layer order, gather into dst --------
 
+// Particle arrays moved by the sort as 32-bit columns: a 4-byte array is one
+// column (stride 1), an 8-byte array two (stride 2, word 0 and word 1).
+constexpr int SORT_MAX_COLS = 16;
 struct PermArgs {
     const int32_t *cell_in;
-    int32_t *cell_out;
-    const float *fin[9];
-    float *fout[9];
-    int nf;
-    const uint64_t *din[2];  // 8-byte arrays: optical depth, identifiers
-    uint64_t *dout[2];
-    int nd;
+    const uint32_t *src[SORT_MAX_COLS];
+    uint32_t *dst[SORT_MAX_COLS];
+    int stride[SORT_MAX_COLS];
+    int ncol;
 };
+
+// phases A and D issue the loads of SORT_AHEAD rounds before using them
+constexpr int SORT_AHEAD = 4;
 
 // Layers of phase C handled per pass: R layers x (cells/64) group counters
 // stay within 16 KB of LDS.
@@ -234,36 +237,93 @@ __host__ __device__ inline int sort_layer_chunk(int ct) {
     return r < 1 ? 1 : (r > 256 ? 256 : r);
 }
 
-size_t sort_lds_bytes(int ct) {
-    const int ng = (ct + 63) / 64;
-    return sizeof(uint32_t) * ((size_t)6 * ct + (size_t)sort_layer_chunk(ct) * ng + 256);
+constexpr int ORDER_THREADS = 1024;  // one workgroup per tile
+constexpr int ORDER_WAVES = ORDER_THREADS / 64;
+
+// wavefronts that rank particles in phase A: their per-cell counters take
+// at most 64 KB
+__host__ __device__ inline int sort_rank_waves(int ct) {
+    const int w = 16384 / ct;
+    return w < 1 ? 1 : (w > ORDER_WAVES ? ORDER_WAVES : w);
 }
 
-// One workgroup (4 wavefronts) per tile.
-//   A. each wavefront ranks the particles of its contiguous share of the tile
-//      within their cells (8 ballots match equal cells; the wavefront keeps
-//      private per-cell counters, so no workgroup barrier is needed);
+static size_t sort_lds_words_abc(int ct) {
+    const int ng = (ct + 63) / 64;
+    return (size_t)(sort_rank_waves(ct) + 2) * ct + (size_t)sort_layer_chunk(ct) * ng + 256 + 64;
+}
+
+// particles per LDS stage of phase D: the largest multiple of 1024 that keeps
+// the workgroup within 80 KB (two workgroups per CU; at least 1024)
+static int sort_stage_len(int ct) {
+    const long words = 80 * 1024 / 4 - (long)sort_lds_words_abc(ct);
+    long seg = words;
+    seg -= seg % 1024;
+    return (int)(seg < 1024 ? 1024 : (seg > 16384 ? 16384 : seg));
+}
+
+size_t sort_lds_bytes(int ct) {
+    return sizeof(uint32_t) * (sort_lds_words_abc(ct) + (size_t)sort_stage_len(ct));
+}
+
+// exclusive scan over the ORDER_THREADS threads (wave prefix by shuffles,
+// then the wave totals); `wt` holds ORDER_WAVES + 1 words of LDS
+__device__ __forceinline__ uint32_t order_exscan(uint32_t v, uint32_t *wt, uint32_t &total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wt[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < ORDER_WAVES; ++w) {
+            const uint32_t c = wt[w];
+            wt[w] = run;
+            run += c;
+        }
+        wt[ORDER_WAVES] = run;
+    }
+    __syncthreads();
+    total = wt[ORDER_WAVES];
+    const uint32_t r = wt[wave] + x - v;
+    __syncthreads();
+    return r;
+}
+
+// One workgroup of ORDER_THREADS per tile.
+//   A. each of the first RW wavefronts ranks the particles of its contiguous
+//      share of the tile within their cells (8 ballots match equal cells; the
+//      wavefront keeps private per-cell counters, so no barrier is needed);
 //   B. per cell: count, base of each wavefront's share, first slot in cell
-//      order; every particle then writes its source index to its slot;
+//      order;
 //   C. layer r holds the r-th particle of every cell with more than r, cells
 //      in key order: its start is the number of particles in earlier layers,
 //      and a cell's place in it the number of populated cells before it,
-//      both from ballots over groups of 64 cells;
-//   D. gather of every particle array in final order.
-__global__ void __launch_bounds__(256) tile_order_kernel(const uint32_t *vals, const int64_t *tile_start,
-                                                         SortGeom g, int lbits, uint32_t *lcell,
-                                                         uint32_t *lrank, uint32_t *slot_src, uint32_t *inv,
-                                                         PermArgs pa) {
+//      both from ballots over groups of 64 cells; the final position of each
+//      cell-order slot goes to posmap;
+//   D. final position of every particle, then the particle arrays one
+//      column at a time: read in source order (the radix sort is stable, so
+//      a tile's sources ascend and the reads are nearly sequential), placed
+//      at their final position in LDS, written out contiguously.
+// Loads of SORT_AHEAD rounds are issued before they are used.
+__global__ void __launch_bounds__(ORDER_THREADS, 8) tile_order_kernel(const uint32_t *vals, const int64_t *tile_start,
+                                                                   SortGeom g, int lbits, int seg, uint32_t *lcell,
+                                                                   uint32_t *lrank, uint32_t *posmap, PermArgs pa) {
     extern __shared__ uint32_t sm[];
     const int ct = g.ct;
     const int ng = (ct + 63) >> 6;
     const int R = sort_layer_chunk(ct);
-    uint32_t *wcnt = sm;          // 4 x ct: per-wavefront counts, then bases
-    uint32_t *cnt = sm + 4 * ct;  // ct: particles per cell
-    uint32_t *cst = sm + 5 * ct;  // ct: first cell-order slot of each cell
-    uint32_t *gc = sm + 6 * ct;   // R x ng: populated cells per group and layer, then offsets
-    uint32_t *lb = gc + R * ng;   // R: first position of each layer of the pass
-    __shared__ uint32_t tmp_s[256];
+    const int RW = sort_rank_waves(ct);
+    uint32_t *wcnt = sm;              // RW x ct: per-wavefront counts, then bases
+    uint32_t *cnt = sm + RW * ct;     // ct: particles per cell
+    uint32_t *cst = cnt + ct;         // ct: first cell-order slot of each cell
+    uint32_t *gc = cst + ct;          // R x ng: populated cells per group and layer, then offsets
+    uint32_t *lb = gc + R * ng;       // R: first position of each layer of the pass
+    uint32_t *wt = lb + 256;          // ORDER_WAVES + 1: scan of wave totals
+    uint32_t *stage = wt + 64;        // seg: a staged column
     __shared__ uint32_t maxc_s;
     const int t = blockIdx.x;
     const int64_t ts = tile_start[t], te = tile_start[t + 1];
@@ -271,53 +331,65 @@ __global__ void __launch_bounds__(256) tile_order_kernel(const uint32_t *vals, c
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t n_t = te - ts;
-    const int64_t cw = ((n_t + 255) / 256) * 64;  // share of one wavefront, a multiple of 64
-    const int64_t c0 = ts + wave * cw, c1 = min(c0 + cw, te);
-    for (int e = threadIdx.x; e < 4 * ct; e += 256) wcnt[e] = 0;
+    const int64_t cw = ((n_t + 64 * RW - 1) / (64 * RW)) * 64;  // share of one ranking wavefront
+    const int64_t c0 = ts + wave * cw, c1 = wave < RW ? min(c0 + cw, te) : c0;
+    for (int e = threadIdx.x; e < RW * ct; e += ORDER_THREADS) wcnt[e] = 0;
     if (threadIdx.x == 0) maxc_s = 0;
     __syncthreads();
 
     // A. rank within the cell inside the wavefront's share (source order)
-    {
+    if (wave < RW) {
         uint32_t *wc = wcnt + wave * ct;
-        for (int64_t base = c0; base < c1; base += 64) {
-            const int64_t i = base + lane;
-            const bool valid = i < c1;
-            uint32_t l = 0;
-            if (valid) {
+        for (int64_t base = c0; base < c1; base += 64 * SORT_AHEAD) {
+            uint32_t lk[SORT_AHEAD];
+            int32_t ce[SORT_AHEAD];
+#pragma unroll
+            for (int q = 0; q < SORT_AHEAD; ++q) {
+                const int64_t i = base + q * 64 + lane;
+                ce[q] = i < c1 ? pa.cell_in[vals[i]] : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < SORT_AHEAD; ++q) {
                 int ix, iy, iz;
-                decode_cell(pa.cell_in[vals[i]], g, ix, iy, iz);
-                l = local_key(ix % g.tile[0], iy % g.tile[1], iz % g.tile[2], g);
+                decode_cell(ce[q], g, ix, iy, iz);
+                lk[q] = local_key(ix % g.tile[0], iy % g.tile[1], iz % g.tile[2], g);
             }
-            uint64_t peers = __ballot(valid);
-            for (int b = 0; b < lbits; ++b) {
-                const uint64_t m = __ballot((l >> b) & 1u);
-                peers &= ((l >> b) & 1u) ? m : ~m;
-            }
-            const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-            uint32_t prev = 0;
-            if (valid) prev = wc[l];
-            // every lane has read its cell's counter before the first lane of
-            // each group of equal cells advances it (LDS keeps a wavefront's order)
-            __builtin_amdgcn_wave_barrier();
-            if (valid && rank == 0) wc[l] = prev + (uint32_t)__popcll(peers);
-            __builtin_amdgcn_wave_barrier();
-            if (valid) {
-                lcell[i] = l;
-                lrank[i] = prev + rank;
+#pragma unroll
+            for (int q = 0; q < SORT_AHEAD; ++q) {
+                const int64_t i = base + q * 64 + lane;
+                const bool valid = i < c1;
+                const uint32_t l = lk[q];
+                uint64_t peers = __ballot(valid);
+                for (int b = 0; b < lbits; ++b) {
+                    const uint64_t m = __ballot((l >> b) & 1u);
+                    peers &= ((l >> b) & 1u) ? m : ~m;
+                }
+                const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+                uint32_t prev = 0;
+                if (valid) prev = wc[l];
+                // every lane has read its cell's counter before the first lane
+                // of each group of equal cells advances it (LDS keeps a
+                // wavefront's order)
+                __builtin_amdgcn_wave_barrier();
+                if (valid && rank == 0) wc[l] = prev + (uint32_t)__popcll(peers);
+                __builtin_amdgcn_wave_barrier();
+                if (valid) {
+                    lcell[i] = l;
+                    lrank[i] = prev + rank;
+                }
             }
         }
     }
     __syncthreads();
 
     // B. counts, wavefront bases, cell-order slots
-    const int per = (ct + 255) / 256;
+    const int per = (ct + ORDER_THREADS - 1) / ORDER_THREADS;
     uint32_t loc = 0, mx = 0;
     for (int q = 0; q < per; ++q) {
         const int l = threadIdx.x * per + q;
         if (l < ct) {
             uint32_t run = 0;
-            for (int w = 0; w < 4; ++w) {
+            for (int w = 0; w < RW; ++w) {
                 const uint32_t c = wcnt[w * ct + l];
                 wcnt[w * ct + l] = run;
                 run += c;
@@ -329,7 +401,7 @@ __global__ void __launch_bounds__(256) tile_order_kernel(const uint32_t *vals, c
     }
     atomicMax(&maxc_s, mx);
     uint32_t total;
-    uint32_t ex = block_exclusive_scan(loc, tmp_s, total);
+    uint32_t ex = order_exscan(loc, wt, total);
     for (int q = 0; q < per; ++q) {
         const int l = threadIdx.x * per + q;
         if (l < ct) {
@@ -338,17 +410,13 @@ __global__ void __launch_bounds__(256) tile_order_kernel(const uint32_t *vals, c
         }
     }
     __syncthreads();
-    for (int64_t i = c0 + lane; i < c1; i += 64) {
-        const uint32_t l = lcell[i];
-        slot_src[ts + cst[l] + wcnt[wave * ct + l] + lrank[i]] = vals[i];
-    }
 
     // C. layers, R at a time
     const uint32_t maxc = maxc_s;
     uint32_t lcarry = 0;
     for (uint32_t r0 = 0; r0 < maxc; r0 += (uint32_t)R) {
         const uint32_t rr = min((uint32_t)R, maxc - r0);
-        for (int gi = wave; gi < ng; gi += 4) {
+        for (int gi = wave; gi < ng; gi += ORDER_WAVES) {
             const int l = gi * 64 + lane;
             const uint32_t c = l < ct ? cnt[l] : 0u;
             for (uint32_t r = 0; r < rr; ++r) {
@@ -368,43 +436,68 @@ __global__ void __launch_bounds__(256) tile_order_kernel(const uint32_t *vals, c
             tot = run;
         }
         uint32_t all;
-        const uint32_t lex = block_exclusive_scan(tot, tmp_s, all);
+        const uint32_t lex = order_exscan(tot, wt, all);
         if (threadIdx.x < rr) lb[threadIdx.x] = lcarry + lex;
         lcarry += all;
         __syncthreads();
-        for (int gi = wave; gi < ng; gi += 4) {
+        for (int gi = wave; gi < ng; gi += ORDER_WAVES) {
             const int l = gi * 64 + lane;
             const uint32_t c = l < ct ? cnt[l] : 0u;
             for (uint32_t r = 0; r < rr; ++r) {
                 const bool has = c > r0 + r;
                 const uint64_t b = __ballot(has);
-                if (has) inv[ts + lb[r] + gc[r * ng + gi] + (uint32_t)__popcll(b & lt_mask)] = cst[l] + r0 + r;
+                if (has) posmap[ts + cst[l] + r0 + r] = lb[r] + gc[r * ng + gi] + (uint32_t)__popcll(b & lt_mask);
             }
         }
         __syncthreads();
     }
 
-    // D. gather every particle array into its final position (independent
-    //    iterations, four in flight per thread)
-    for (int64_t j0 = threadIdx.x; j0 < n_t; j0 += 4 * (int64_t)blockDim.x) {
-        uint32_t src[4];
+    // D. final position of each particle (in place of its in-cell rank)
+    if (wave < RW) {
+        for (int64_t i0 = c0 + lane; i0 < c1; i0 += 64 * SORT_AHEAD) {
+            uint32_t slot[SORT_AHEAD], pos[SORT_AHEAD];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t j = j0 + u * (int64_t)blockDim.x;
-            src[u] = j < n_t ? slot_src[ts + inv[ts + j]] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t j = j0 + u * (int64_t)blockDim.x;
-            if (j < n_t) {
-                pa.cell_out[ts + j] = pa.cell_in[src[u]];
-#pragma unroll
-                for (int k = 0; k < 9; ++k)
-                    if (k < pa.nf) pa.fout[k][ts + j] = pa.fin[k][src[u]];
-#pragma unroll
-                for (int k = 0; k < 2; ++k)
-                    if (k < pa.nd) pa.dout[k][ts + j] = pa.din[k][src[u]];
+            for (int q = 0; q < SORT_AHEAD; ++q) {
+                const int64_t i = i0 + q * 64;
+                if (i < c1) {
+                    const uint32_t l = lcell[i];
+                    slot[q] = cst[l] + wcnt[wave * ct + l] + lrank[i];
+                }
             }
+#pragma unroll
+            for (int q = 0; q < SORT_AHEAD; ++q)
+                if (i0 + q * 64 < c1) pos[q] = posmap[ts + slot[q]];
+#pragma unroll
+            for (int q = 0; q < SORT_AHEAD; ++q)
+                if (i0 + q * 64 < c1) lrank[i0 + q * 64] = pos[q];
+        }
+    }
+    __syncthreads();
+    //    columns through LDS, `seg` final positions at a time
+    for (int64_t s0 = 0; s0 < n_t; s0 += seg) {
+        const uint32_t len = (uint32_t)min((int64_t)seg, n_t - s0);
+        for (int col = 0; col < pa.ncol; ++col) {
+            const uint32_t *src = pa.src[col];
+            const int sd = pa.stride[col];
+            for (int64_t i0 = ts + threadIdx.x; i0 < te; i0 += SORT_AHEAD * ORDER_THREADS) {
+                uint32_t pos[SORT_AHEAD], v[SORT_AHEAD], x[SORT_AHEAD];
+#pragma unroll
+                for (int u = 0; u < SORT_AHEAD; ++u) {
+                    const int64_t i = i0 + u * ORDER_THREADS;
+                    pos[u] = i < te ? lrank[i] - (uint32_t)s0 : 0xFFFFFFFFu;
+                    v[u] = i < te ? vals[i] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < SORT_AHEAD; ++u)
+                    if (pos[u] < len) x[u] = src[(int64_t)v[u] * sd];
+#pragma unroll
+                for (int u = 0; u < SORT_AHEAD; ++u)
+                    if (pos[u] < len) stage[pos[u]] = x[u];
+            }
+            __syncthreads();
+            uint32_t *d = pa.dst[col] + (ts + s0) * sd;
+            for (uint32_t j = threadIdx.x; j < len; j += ORDER_THREADS) d[(int64_t)j * sd] = stage[j];
+            __syncthreads();
         }
     }
 }
@@ -463,48 +556,36 @@ hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *ds
                                                                        dst->tile_start);
     PermArgs pa{};
     pa.cell_in = src->cell;
-    pa.cell_out = dst->cell;
-    int nf = 0;
-    for (int d = 0; d < c->dim; ++d) {
-        pa.fin[nf] = src->off[d];
-        pa.fout[nf++] = dst->off[d];
-    }
-    for (int d = 0; d < 3; ++d) {
-        pa.fin[nf] = (const float *)src->u[d];
-        pa.fout[nf++] = (float *)dst->u[d];
-    }
-    if (src->w) {
-        pa.fin[nf] = (const float *)src->w;
-        pa.fout[nf++] = (float *)dst->w;
-    }
-    if (src->chi) {
-        pa.fin[nf] = src->chi;
-        pa.fout[nf++] = dst->chi;
-    }
-    if (src->tau_thr) {
-        pa.fin[nf] = src->tau_thr;
-        pa.fout[nf++] = dst->tau_thr;
-    }
-    pa.nf = nf;
-    int nd = 0;
-    if (src->tau) {
-        pa.din[nd] = (const uint64_t *)src->tau;
-        pa.dout[nd++] = (uint64_t *)dst->tau;
-    }
-    if (src->id) {
-        pa.din[nd] = src->id;
-        pa.dout[nd++] = dst->id;
-    }
-    pa.nd = nd;
+    int nc = 0;
+    auto col4 = [&](const void *a, void *b) {
+        pa.src[nc] = (const uint32_t *)a;
+        pa.dst[nc] = (uint32_t *)b;
+        pa.stride[nc++] = 1;
+    };
+    auto col8 = [&](const void *a, void *b) {
+        for (int w = 0; w < 2; ++w) {
+            pa.src[nc] = (const uint32_t *)a + w;
+            pa.dst[nc] = (uint32_t *)b + w;
+            pa.stride[nc++] = 2;
+        }
+    };
+    col4(src->cell, dst->cell);
+    for (int d = 0; d < c->dim; ++d) col4(src->off[d], dst->off[d]);
+    for (int d = 0; d < 3; ++d) col4(src->u[d], dst->u[d]);
+    if (src->w) col4(src->w, dst->w);
+    if (src->chi) col4(src->chi, dst->chi);
+    if (src->tau_thr) col4(src->tau_thr, dst->tau_thr);
+    if (src->tau) col8(src->tau, dst->tau);
+    if (src->id) col8(src->id, dst->id);
+    pa.ncol = nc;
     int lbits = 0;
     while ((1 << lbits) < g.ct) ++lbits;
     // scratch: keys[cur^1] (key of the cell within the tile), vals[cur^1]
-    // (rank within the cell in the wavefront's share), final_perm (source of
-    // each cell-order slot), keys[cur] (slot of each final position; the
-    // sorted keys are no longer needed once tile_start is written)
-    tile_order_kernel<<<(unsigned)c->ntiles, 256, sort_lds_bytes(g.ct), s>>>(
-        c->vals[cur], dst->tile_start, g, lbits, c->keys[cur ^ 1], c->vals[cur ^ 1], c->final_perm,
-        c->keys[cur], pa);
+    // (rank within the cell in the wavefront's share, then final position),
+    // final_perm (final position of each cell-order slot)
+    tile_order_kernel<<<(unsigned)c->ntiles, ORDER_THREADS, sort_lds_bytes(g.ct), s>>>(
+        c->vals[cur], dst->tile_start, g, lbits, sort_stage_len(g.ct), c->keys[cur ^ 1], c->vals[cur ^ 1],
+        c->final_perm, pa);
     return hipGetLastError();
 }
 

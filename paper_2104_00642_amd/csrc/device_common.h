@@ -99,14 +99,17 @@ __device__ __forceinline__ void esirkepov_axis(R xh, R xe, int &base, R *S0, R *
 // Same stencil when the start-point weights wh (first node ih) are already
 // known from the gather: only the end point is evaluated, and each node takes
 // one select since the two supports are offset by 0 or 1 from `base`.
+// `cross` is set when the two supports differ (ih != ie); otherwise node
+// ORDER+1 of S0 and DS is zero and so is the running sum of DS at node ORDER.
 template <int ORDER, typename R>
 __device__ __forceinline__ void esirkepov_axis_from(int ih, const R *wh, R xe, int &base, R *S0,
-                                                    R *DS) {
+                                                    R *DS, bool &cross) {
     constexpr int L = ORDER + 2;
     R we[ORDER + 1];
     int ie;
     shape_weights<ORDER>(xe, ie, we);
     base = ih < ie ? ih : ie;
+    cross = ih != ie;
     const bool sh = ih > base, se = ie > base;
 #pragma unroll
     for (int k = 0; k < L; ++k) {

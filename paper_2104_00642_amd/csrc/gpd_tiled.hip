@@ -194,12 +194,19 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
     gm1 = us * ig1 * rcp_r(1.0f + ig1);
     const float v[3] = {u[0] * ig1, u[1] * ig1, u[2] * ig1};
 
-    // Esirkepov (Eqs. 20-22) for the move dh -> dh + dt v / d
+    // Esirkepov (Eqs. 20-22) for the move dh -> dh + dt v / d.  Along an axis
+    // the particle does not cross (start and end supports equal), the last
+    // stencil node and the last running-sum node carry exactly zero: those
+    // lanes sit out the atomics (fewer LDS lane operations).
     int base[3] = {0, 0, 0};
+    bool cr[3] = {false, false, false};
     float S0[3][L], DS[3][L];
 #pragma unroll
     for (int d = 0; d < DIM; ++d)
-        esirkepov_axis_from<ORDER>(i0[0][d], wt[0][d], dh[d] + a.dt_d[d] * v[d], base[d], S0[d], DS[d]);
+        esirkepov_axis_from<ORDER>(i0[0][d], wt[0][d], dh[d] + a.dt_d[d] * v[d], base[d], S0[d], DS[d], cr[d]);
+    // node k of a weight along axis d / of a running sum along d is nonzero
+    auto wnode = [&](int d, int k) { return k <= ORDER || cr[d]; };
+    auto rnode = [&](int d, int k) { return k < ORDER || cr[d]; };
     const int b0 = o[0] + base[0], b1 = o[1] + base[1];
     const float ws = w * acc.scale;  // fixed-point units in the LDS window
     const float jx = a.jfac[0] * ws, jy = a.jfac[1] * ws;
@@ -211,7 +218,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
 #pragma unroll
             for (int ii = 0; ii < L - 1; ++ii) {
                 run -= DS[0][ii] * ty;
-                acc.add(0, b0, b1, 0, ii, jj, 0, run);
+                if (rnode(0, ii) && wnode(1, jj)) acc.add(0, b0, b1, 0, ii, jj, 0, run);
             }
         }
 #pragma unroll
@@ -221,7 +228,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
 #pragma unroll
             for (int jj = 0; jj < L - 1; ++jj) {
                 run -= DS[1][jj] * tx;
-                acc.add(1, b0, b1, 0, ii, jj, 0, run);
+                if (rnode(1, jj) && wnode(0, ii)) acc.add(1, b0, b1, 0, ii, jj, 0, run);
             }
         }
         const float qv = a.q * ws * v[2];
@@ -230,7 +237,8 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
             const float a0 = qv * (S0[1][jj] + 0.5f * DS[1][jj]);
             const float a1 = qv * (0.5f * S0[1][jj] + (1.0f / 3.0f) * DS[1][jj]);
 #pragma unroll
-            for (int ii = 0; ii < L; ++ii) acc.add(2, b0, b1, 0, ii, jj, 0, S0[0][ii] * a0 + DS[0][ii] * a1);
+            for (int ii = 0; ii < L; ++ii)
+                if (wnode(0, ii) && wnode(1, jj)) acc.add(2, b0, b1, 0, ii, jj, 0, S0[0][ii] * a0 + DS[0][ii] * a1);
         }
     } else {
         const int b2 = o[2] + base[2];
@@ -246,7 +254,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
 #pragma unroll
                 for (int ii = 0; ii < L - 1; ++ii) {
                     run -= DS[0][ii] * t;
-                    acc.add(0, b0, b1, b2, ii, jj, kk, run);
+                    if (rnode(0, ii) && wnode(1, jj) && wnode(2, kk)) acc.add(0, b0, b1, b2, ii, jj, kk, run);
                 }
             }
 #pragma unroll
@@ -259,7 +267,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
 #pragma unroll
                 for (int jj = 0; jj < L - 1; ++jj) {
                     run -= DS[1][jj] * t;
-                    acc.add(1, b0, b1, b2, ii, jj, kk, run);
+                    if (rnode(1, jj) && wnode(0, ii) && wnode(2, kk)) acc.add(1, b0, b1, b2, ii, jj, kk, run);
                 }
             }
 #pragma unroll
@@ -272,7 +280,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
 #pragma unroll
                 for (int kk = 0; kk < L - 1; ++kk) {
                     run -= DS[2][kk] * t;
-                    acc.add(2, b0, b1, b2, ii, jj, kk, run);
+                    if (rnode(2, kk) && wnode(0, ii) && wnode(1, jj)) acc.add(2, b0, b1, b2, ii, jj, kk, run);
                 }
             }
     }

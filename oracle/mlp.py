@@ -2,7 +2,8 @@
 
 A 4 -> 64 -> 64 -> 2 perceptron with tanh hidden activations and a linear
 output:  h1 = tanh(x W1 + b1),  h2 = tanh(h1 W2 + b2),  y = h2 W3 + b3.
-Loss = sum over batch rows b and outputs o of (y_bo - t_bo)^2 / (2 B).
+Loss = sum over batch rows b and outputs o of w_o (y_bo - t_bo)^2 / (2 B) with
+w = (RATE_WEIGHT, 1): output 0 is the rate, output 1 the sampled fraction.
 Forward and backward are written out with plain matrix products in FP64
 (the paper does not use a network; this is the surrogate of its Monte-Carlo
 rates, Sec. IV Eqs. 23-24).  Weights are passed as given: when checking a
@@ -13,6 +14,8 @@ from __future__ import annotations
 import numpy as np
 
 SIZES = (4, 64, 64, 2)
+RATE_WEIGHT = 10.0
+OUT_WEIGHT = np.array([RATE_WEIGHT, 1.0])
 
 
 def init_params(rng: np.random.Generator):
@@ -35,14 +38,14 @@ def forward(p, X):
 
 def loss(p, X, T):
     y, _ = forward(p, X)
-    return float(np.sum((y - T) ** 2) / (2.0 * len(X)))
+    return float(np.sum(OUT_WEIGHT * (y - T) ** 2) / (2.0 * len(X)))
 
 
 def backward(p, X, T):
     """Gradients of `loss` with respect to every parameter (chain rule)."""
     y, (X, h1, h2) = forward(p, X)
     B = len(X)
-    dy = (y - T) / B
+    dy = OUT_WEIGHT * (y - T) / B
     g = {"W3": h2.T @ dy, "b3": dy.sum(0)}
     dh2 = dy @ p["W3"].T
     dz2 = dh2 * (1.0 - h2 ** 2)

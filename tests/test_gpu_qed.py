@@ -281,8 +281,9 @@ def test_mlp_forward_matches_oracle():
     got = y.cpu().numpy()
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     print(f"network forward relative L2 vs FP64: {err:.2e}")
-    # activations enter the matrix cores rounded to BF16 (8-bit mantissa)
-    assert err < 1.5e-2
+    # same BF16 weights; activations enter the matrix cores as hi + lo BF16
+    # terms (about 16 significant bits)
+    assert err < 2e-4
 
 
 def test_mlp_gradient_matches_oracle_backward():
@@ -311,7 +312,7 @@ def test_mlp_gradient_matches_oracle_backward():
     assert loss.item() == pytest.approx(OM.loss(p, X.astype(np.float64), T.astype(np.float64)), rel=2e-2)
 
 
-def trained_network(ctx, iters=4000, n=1 << 18, batch=4096, lr=2e-3):
+def trained_network(ctx, iters=30000, n=1 << 20, batch=4096, lr=2e-3):
     X = torch.empty(n, 4, device=DEV)
     T = torch.empty(n, 2, device=DEV)
     L.pic_qed_training_data(ctx, n, 99, X, T)
@@ -337,23 +338,31 @@ def trained():
 
 def test_mlp_training_learns_the_rates(trained):
     """Training on the library's own tables with the BF16 MFMA kernels; the
-    trained rates are judged against the oracle's quadrature."""
+    trained rates of both processes are judged against the oracle's
+    quadrature over the trained chi range (target: 1e-3 relative)."""
     ctx, net, loss, secs = trained
-    chis = np.logspace(-3.9, 2.9, 25)
-    X = np.zeros((len(chis), 4), dtype=np.float32)
-    X[:, 0] = (np.log10(chis) + 0.5) / 3.5
-    X[:, 1] = 0.0
-    X[:, 2] = 1.0
-    y = torch.empty(len(chis), 2, device=DEV)
-    L.pic_mlp_forward(ctx, net, torch.from_numpy(X).to(DEV), y)
-    torch.cuda.synchronize()
-    F_net = chis * np.exp(y.cpu().numpy()[:, 0].astype(np.float64))
-    F_ref = np.array([O.frad(c) for c in chis])
-    rel = np.abs(F_net / F_ref - 1)
-    print(f"training: {secs:.2f}s, final batch loss {loss:.2e}; emission rate error median "
-          f"{np.median(rel):.2e} max {rel.max():.2e}")
+    errs = {}
+    for proc, lo, fn in ((0, -4.0, O.frad), (1, -1.7, O.fpair)):
+        lcs = np.linspace(lo + 0.1, 2.9, 41)
+        chis = 10.0 ** lcs
+        c, h = 0.5 * (lo + 3.0), 0.5 * (3.0 - lo)
+        X = np.zeros((len(chis), 4), dtype=np.float32)
+        X[:, 0] = (lcs - c) / h
+        X[:, 2 + proc] = 1.0
+        y = torch.empty(len(chis), 2, device=DEV)
+        L.pic_mlp_forward(ctx, net, torch.from_numpy(X).to(DEV), y)
+        torch.cuda.synchronize()
+        g = y.cpu().numpy()[:, 0].astype(np.float64)
+        F_net = chis * np.exp(g) if proc == 0 else np.exp(g - 8.0 / (3.0 * chis))
+        F_ref = np.array([fn(v) for v in chis])
+        errs[proc] = np.abs(F_net / F_ref - 1)
+    print(f"training: {secs:.2f}s, final batch loss {loss:.2e}; rate error emission median "
+          f"{np.median(errs[0]):.2e} max {errs[0].max():.2e}, pairs median {np.median(errs[1]):.2e} "
+          f"max {errs[1].max():.2e}")
     assert loss < 1e-3
-    assert np.median(rel) < 2e-2
+    for proc in (0, 1):
+        assert np.median(errs[proc]) < 1e-3
+        assert errs[proc].max() < 3e-3
 
 
 @pytest.mark.parametrize("chi", [0.49, 4.9, 49.0])

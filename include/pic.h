@@ -233,7 +233,8 @@ pic_status pic_qed_step(void *ctx, const pic_qed_args *args, void *stream);
 /*
  * Surrogate network of the QED module: 4 -> 64 -> 64 -> 2 perceptron,
  * h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 W3 + b3, BF16 weights,
- * FP32 biases, FP32 accumulation (BF16 matrix cores).  Device layout
+ * FP32 biases, FP32 accumulation (BF16 matrix cores; in the forward pass
+ * each activation enters as two BF16 terms, hi and remainder).  Device layout
  * (PIC_MLP_BYTES): W1 bf16[4][64] @0, W2 bf16[64][64] @512, W3 bf16[64][2]
  * @8704, b1 f32[64] @8960, b2 f32[64] @9216, b3 f32[2] @9472 (row-major,
  * input index first).  Inputs x = ((log10 chi - c)/h, 2 rho(r) - 1, [emission],
@@ -257,14 +258,15 @@ pic_status pic_qed_step(void *ctx, const pic_qed_args *args, void *stream);
 
 /* y[n][2] = network(x[n][4]) (device arrays). */
 pic_status pic_mlp_forward(void *ctx, const void *mlp, const float *x, int64_t n, float *y, void *stream);
-/* grad[PIC_MLP_NPARAM] += d/dparams of sum (y - t)^2 / (2n) with the
+/* grad[PIC_MLP_NPARAM] += d/dparams of sum_rows sum_o w_o (y_o - t_o)^2 / (2n),
+ * w = (10, 1) (the rate output carries the accuracy target), with the
  * network's (BF16) weights; *loss (nullable) += that loss. */
 pic_status pic_mlp_grad(void *ctx, const void *mlp, const float *x, const float *t, int64_t n, float *grad,
                         float *loss, void *stream);
-/* `iters` Adam steps (learning rate lr) on consecutive batches of `batch`
- * rows of (x, t), starting from the state's parameters; the BF16 network is
- * written to mlp after every step; *loss (nullable) receives the last
- * batch's loss. */
+/* `iters` Adam steps on consecutive batches of `batch` rows of (x, t),
+ * starting from the state's parameters, with the step size decaying from lr
+ * to 0 as 0.5 lr (1 + cos(pi it / iters)); the BF16 network is written to
+ * mlp after every step; *loss (nullable) receives the last batch's loss. */
 pic_status pic_mlp_train(void *ctx, float *state, void *mlp, const float *x, const float *t, int64_t n,
                          int32_t batch, int32_t iters, float lr, float *loss, void *stream);
 /* n training rows from the library's tables (row i: process i & 1, log10 chi

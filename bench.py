@@ -1,11 +1,13 @@
 """Throughput of the gather + push + deposit hot path on one MI355X.
 
 Workload: the 2D3V laser-plasma case (4096 x 2048 cells, 20 cells per laser
-wavelength, a0 = 2 linearly polarized pulse, n = 0.01 n_c electrons at 1 keV
-behind a 2-lambda ramp, 32 particles per cell, quadratic weights), synthetic
-and seeded.  A step is one whole pass of the path: Yee half step, J reset,
-gather-push-deposit of every particle, Yee half step, and the tile sort every
-`--sort-every` steps (FP32 path).  Both the FP32 mixed-precision path and the
+wavelength, a0 = 2 linearly polarized pulse already inside the n = 0.01 n_c
+electron plasma at 1 keV behind a 2-lambda ramp, 32 particles per cell,
+quadratic weights), synthetic and seeded; `--workload laser3d` runs the 3D3V
+case.  A step is one whole pass of the path: Yee half step, J reset,
+gather-push-deposit of every particle (sorted and binned passes), Yee half
+step, and the tile sort every `--sort-every` steps (FP32 path).  The timed
+window holds whole sort cycles.  Both the FP32 mixed-precision path and the
 plain FP64 path run; `value` is the FP32 path's particle-steps/s over the
 timed steps (inputs resident in HBM), the FP64 path is reported beside it.
 
@@ -56,10 +58,11 @@ def measured_traffic(workload, n_particles):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: two sort intervals, so the window holds whole sort cycles)")
+    ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--sort-every", type=int, default=None,
-                    help="steps between sorts (default 16 in 2D, 8 in 3D, where fast particles leave their "
+                    help="steps between sorts (default 24 in 2D, 8 in 3D, where fast particles leave their "
                          "tiles sooner)")
     ap.add_argument("--scale", type=int, default=1, help="divide the grid (tests only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -265,7 +268,9 @@ def main():
     if args.drift is None:
         args.drift = 2 if dim == 2 else 1
     if args.sort_every is None:
-        args.sort_every = 16 if dim == 2 else 8
+        args.sort_every = 24 if dim == 2 else 8
+    if args.steps is None:
+        args.steps = 2 * args.sort_every
     if dim == 2:
         wl = laser_plasma_2d(scale=args.scale, device="cuda")
         ppc = 32

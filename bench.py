@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--fp64-order", choices=["lex", "cell"], default="lex",
                     help="particle order of the plain FP64 path (see fp64_order)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--order", type=int, choices=[1, 2, 4], default=2,
+                    help="shape order: 2 quadratic (the workload's), 1 linear, 4 quartic")
     ap.add_argument("--workload", choices=["laser2d", "laser3d"], default="laser2d",
                     help="laser2d: 4096x2048 2D3V (the metric's workload); laser3d: 512x256x256 3D3V")
     ap.add_argument("--tile", type=str, default=None, help="tile in cells (default 16,16 / 8,8,4)")
@@ -266,17 +268,18 @@ def main():
     if args.tile is None:
         args.tile = "16,16" if dim == 2 else "8,8,4"
     if args.drift is None:
-        args.drift = 2 if dim == 2 else 1
+        args.drift = 2 if dim == 2 else (0 if args.order == 4 else 1)
     if args.sort_every is None:
         args.sort_every = 24 if dim == 2 else 8
     if args.steps is None:
         args.steps = 2 * args.sort_every
     if dim == 2:
-        wl = laser_plasma_2d(scale=args.scale, device="cuda")
+        wl = laser_plasma_2d(scale=args.scale, device="cuda", order=args.order)
         ppc = 32
     else:
         from paper_2104_00642_amd.workloads import laser_plasma_3d
-        wl = laser_plasma_3d(scale=args.scale, device="cuda", tile=tuple(int(v) for v in args.tile.split(",")))
+        wl = laser_plasma_3d(scale=args.scale, device="cuda", tile=tuple(int(v) for v in args.tile.split(",")),
+                             order=args.order)
         ppc = 16  # 8 electrons + 8 ions per cell share the field cells
     out = {}
     for prec in ([L.PIC_FP32_MIXED] if args.no_fp64 else [L.PIC_FP32_MIXED, L.PIC_FP64_PLAIN]):
@@ -318,7 +321,8 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": wl.name if args.scale == 1 else f"{wl.name}_scale{args.scale}",
                    "particles": r["n"], "cells": list(wl.cfg.n),
-                   "shape": "quadratic", "tile": r["tile"][:dim], "sort_every": args.sort_every,
+                   "shape": {1: "linear", 2: "quadratic", 4: "quartic"}[args.order], "tile": r["tile"][:dim],
+                   "sort_every": args.sort_every,
                    "drift": args.drift, "parallelism": "single GPU"},
         "gpd_only_particle_steps_per_s": r["n"] / (r["gpd_ms"] * 1e-3),
         "gpd_ms_avg": r["gpd_ms"],

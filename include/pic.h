@@ -82,7 +82,7 @@ enum {
 
 typedef struct {
     int32_t dim;            /* 2 = 2D3V, 3 = 3D3V                                     */
-    int32_t order;          /* 1 = linear (CIC) weights, 2 = quadratic (Sec. II.D)     */
+    int32_t order;          /* 1 = linear (CIC), 2 = quadratic, 4 = quartic (Sec. II.D) */
     int32_t precision;      /* PIC_FP32_MIXED or PIC_FP64_PLAIN                       */
     int32_t drift;          /* FP32 path: cells a particle may leave its tile between
                                sorts and still use the LDS window (0..4; default 2)  */

@@ -45,7 +45,7 @@ class _Grid(C.Structure):
 
 @dataclass
 class Grid:
-    """Grid and step: dim (2 or 3), shape order (1 CIC, 2 quadratic), cells per
+    """Grid and step: dim (2 or 3), shape order (1 CIC, 2 quadratic, 4 quartic), cells per
     axis, cell sizes and time step, all in the units of Eq. 8."""
     dim: int
     n: tuple

@@ -33,7 +33,7 @@
 
 typedef struct {
     int32_t dim;     /* 2 (2D3V) or 3 (3D3V)                          */
-    int32_t order;   /* 1 = linear (CIC) weights, 2 = quadratic          */
+    int32_t order;   /* 1 = linear (CIC), 2 = quadratic, 4 = quartic      */
     int64_t n[3];    /* cells per axis; n[2] = 1 in 2D                   */
     double d[3];     /* cell sizes dx, dy, dz                            */
     double dt;       /* time step                                        */
@@ -65,6 +65,12 @@ static int64_t idx3(const orc_grid *g, int64_t i, int64_t j, int64_t k) {
  *   order 2: shape = S_2 (triangle, Eq. 17); i_c is the node nearest to xi,
  *            delta = xi - i_c in [-1/2, 1/2), weights
  *            ((1/2 - delta)^2 / 2, 3/4 - delta^2, (1/2 + delta)^2 / 2).
+ *   order 4: shape = S_4 (cubic spline, Eq. 18); same i_c and delta, five
+ *            weights on i_c-2 .. i_c+2, the cell integrals of S_4 worked out
+ *            piece by piece (a quartic spline):
+ *            (1-2d)^4/384, (19-44d+24d^2+16d^3-16d^4)/96,
+ *            (115-120d^2+48d^4)/192, (19+44d+24d^2-16d^3-16d^4)/96,
+ *            (1+2d)^4/384.
  */
 int orc_shape(int order, double xi, int64_t *i0, double *w) {
     if (order == 1) {
@@ -83,6 +89,17 @@ int orc_shape(int order, double xi, int64_t *i0, double *w) {
         w[1] = 0.75 - delta * delta;
         w[2] = 0.5 * (0.5 + delta) * (0.5 + delta);
         return 3;
+    }
+    if (order == 4) {
+        double ic = floor(xi + 0.5);
+        double d = xi - ic;
+        *i0 = (int64_t)ic - 2;
+        w[0] = pow(1.0 - 2.0 * d, 4) / 384.0;
+        w[1] = (19.0 - 44.0 * d + 24.0 * d * d + 16.0 * d * d * d - 16.0 * d * d * d * d) / 96.0;
+        w[2] = (115.0 - 120.0 * d * d + 48.0 * d * d * d * d) / 192.0;
+        w[3] = (19.0 + 44.0 * d + 24.0 * d * d - 16.0 * d * d * d - 16.0 * d * d * d * d) / 96.0;
+        w[4] = pow(1.0 + 2.0 * d, 4) / 384.0;
+        return 5;
     }
     return 0;
 }

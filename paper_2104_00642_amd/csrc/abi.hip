@@ -121,8 +121,8 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
     if (!cfg) return fail(nullptr, PIC_E_ARG, "config is NULL");
     if (cfg->dim != 2 && cfg->dim != 3)
         return fail(nullptr, PIC_E_UNSUPPORTED, "dim must be 2 (2D3V) or 3 (3D3V)");
-    if (cfg->order != 1 && cfg->order != 2)
-        return fail(nullptr, PIC_E_UNSUPPORTED, "order must be 1 (CIC) or 2 (quadratic)");
+    if (cfg->order != 1 && cfg->order != 2 && cfg->order != 4)
+        return fail(nullptr, PIC_E_UNSUPPORTED, "order must be 1 (CIC), 2 (quadratic) or 4 (quartic)");
     if (cfg->precision != PIC_FP32_MIXED && cfg->precision != PIC_FP64_PLAIN)
         return fail(nullptr, PIC_E_UNSUPPORTED, "precision must be PIC_FP32_MIXED or PIC_FP64_PLAIN");
     const int dim = cfg->dim;
@@ -181,10 +181,11 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
         c->tile[a] = t;
         c->ntile_axis[a] = (int)(cfg->n[a] / t);
         c->ntiles *= c->ntile_axis[a];
-        c->win[a] = a < dim ? t + 2 * c->drift + 5 : 1;
+        // window: tile, drift, and the stencil reach [c-2, c+3] ([c-3, c+4] quartic)
+        c->win[a] = a < dim ? t + 2 * c->drift + (cfg->order == 4 ? 7 : 5) : 1;
         if (a < dim && c->win[a] > cfg->n[a] && cfg->precision == PIC_FP32_MIXED) {
             delete c;
-            return fail(nullptr, PIC_E_UNSUPPORTED, "grid smaller than one tile window (tile + 2 drift + 5)");
+            return fail(nullptr, PIC_E_UNSUPPORTED, "grid smaller than one tile window (tile + 2 drift + stencil reach)");
         }
     }
     if (c->tile[0] * c->tile[1] * c->tile[2] > 4096) {

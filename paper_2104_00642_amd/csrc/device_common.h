@@ -25,6 +25,8 @@ __host__ __device__ constexpr int stag(int comp, int axis) {
 //   ORDER 1: integral of the unit top-hat -> (1-d, d) on floor(xi), floor(xi)+1
 //   ORDER 2: integral of the triangle S_2 (Eq. 17) -> quadratic spline on the
 //            nearest node and its two neighbours.
+//   ORDER 4: integral of the cubic spline S_4 (Eq. 18) -> quartic spline on the
+//            nearest node and two neighbours on each side.
 template <int ORDER, typename R>
 __device__ __forceinline__ void shape_weights(R xi, int &i0, R *w) {
     if constexpr (ORDER == 1) {
@@ -33,6 +35,22 @@ __device__ __forceinline__ void shape_weights(R xi, int &i0, R *w) {
         i0 = (int)f;
         w[0] = R(1) - d;
         w[1] = d;
+    } else if constexpr (ORDER == 4) {
+        // d in [-1/2, 1/2): ((1-2d)^4/384, (19-44d+24d^2+16d^3-16d^4)/96,
+        // (115-120d^2+48d^4)/192, (19+44d+24d^2-16d^3-16d^4)/96, (1+2d)^4/384)
+        R ic = floor(xi + R(0.5));
+        R d = xi - ic;
+        i0 = (int)ic - 2;
+        const R d2 = d * d;
+        const R m = R(1) - R(2) * d, p = R(1) + R(2) * d;
+        const R m2 = m * m, p2 = p * p;
+        w[0] = m2 * m2 * R(1.0 / 384.0);
+        w[4] = p2 * p2 * R(1.0 / 384.0);
+        const R even = R(19.0 / 96.0) + d2 * (R(0.25) - d2 * R(1.0 / 6.0));
+        const R odd = d * (R(44.0 / 96.0) - d2 * R(1.0 / 6.0));
+        w[1] = even - odd;
+        w[3] = even + odd;
+        w[2] = R(115.0 / 192.0) + d2 * (R(-0.625) + d2 * R(0.25));
     } else {
         // (1/2 (1/2 - d)^2, 3/4 - d^2, 1/2 (1/2 + d)^2); the last equals the
         // first plus d

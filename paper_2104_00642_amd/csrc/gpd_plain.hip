@@ -306,6 +306,8 @@ hipError_t launch_gpd_plain(Ctx *c, const pic_species *sp, const pic_particles *
         case 22: gpd_plain_kernel<2, 2><<<grid, block, 0, s>>>(a); break;
         case 31: gpd_plain_kernel<3, 1><<<grid, block, 0, s>>>(a); break;
         case 32: gpd_plain_kernel<3, 2><<<grid, block, 0, s>>>(a); break;
+        case 24: gpd_plain_kernel<2, 4><<<grid, block, 0, s>>>(a); break;
+        case 34: gpd_plain_kernel<3, 4><<<grid, block, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();

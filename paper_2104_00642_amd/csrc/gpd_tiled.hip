@@ -3,7 +3,9 @@
 //
 // One workgroup per grid tile.  The workgroup
 //   1. stages the E/B window of its tile (tile + reach + drift guard cells, all
-//      six components, periodic wrap) from HBM into LDS,
+//      six components, periodic wrap) from HBM into LDS; the reach is
+//      [c-2, c+3] around a particle's cell c for CIC and quadratic weights,
+//      [c-3, c+4] for quartic ones,
 //   2. pushes the tile's particles (contiguous after pic_sort, with
 //      consecutive particles in distinct cells so that the LDS traffic of a
 //      wavefront spreads over distinct addresses): gather from LDS (Eq. 19),
@@ -376,7 +378,9 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     const int tx = t % a.ntile_axis[0];
     const int ty = (t / a.ntile_axis[0]) % a.ntile_axis[1];
     const int tz = DIM == 3 ? t / (a.ntile_axis[0] * a.ntile_axis[1]) : 0;
-    const int g = a.drift + 2;
+    // stencil reach around a particle's cell c: [c - RLO, c + RHI]
+    constexpr int RLO = ORDER == 4 ? 3 : 2, RHI = ORDER == 4 ? 4 : 3;
+    const int g = a.drift + RLO;
     const int org[3] = {tx * a.tile[0] - g, ty * a.tile[1] - g, DIM == 3 ? tz * a.tile[2] - g : 0};
     LdsAcc<WX, WY, WZ> lds{a.win[0], a.win[0] * a.win[1], a.win[0] * a.win[1] * a.win[2], 0.0f};
     const int wn = lds.wn();
@@ -440,7 +444,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
 
     // 2. particles of the tile, next particle prefetched while one is pushed
     const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
-    const int hi[3] = {wx - 4, (DIM >= 2 ? wxy / wx : 1) - 4, (DIM == 3 ? wn / wxy : 1) - 4};
+    const int hi[3] = {wx - RHI - 1, (DIM >= 2 ? wxy / wx : 1) - RHI - 1, (DIM == 3 ? wn / wxy : 1) - RHI - 1};
     double kin = 0.0, chg = 0.0;
     uint32_t i = threadIdx.x;
     int32_t n_cell = 0;
@@ -480,7 +484,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         for (int d = 0; d < DIM; ++d) {
             const int l = wrap_index(cc[d] - org[d], a.ng[d]);
             lc[d] = l;
-            inside &= (unsigned)(l - 2) <= (unsigned)(hi[d] - 2) && (unsigned)cc[d] < (unsigned)a.ng[d];
+            inside &= (unsigned)(l - RLO) <= (unsigned)(hi[d] - RLO) && (unsigned)cc[d] < (unsigned)a.ng[d];
             inside &= __float_as_uint(f[d]) < 0x3f800000u;
         }
         if (!inside) {
@@ -795,7 +799,9 @@ static void launch_passes(TiledArgs a, size_t lds, hipStream_t s) {
 
 template <int DIM, int ORDER>
 static void launch_tiled(const TiledArgs &a, size_t lds, hipStream_t s) {
-    if constexpr (DIM == 2) {
+    if constexpr (ORDER == 4) {
+        launch_passes<DIM, 4, DIM == 2 ? PIC_TILED_THREADS_2D : PIC_TILED_THREADS_3D, 0, 0, 0>(a, lds, s);
+    } else if constexpr (DIM == 2) {
         if (a.win[0] == W2X && a.win[1] == W2X)
             launch_passes<2, ORDER, PIC_TILED_THREADS_2D, W2X, W2X, 1>(a, lds, s);
         else
@@ -865,6 +871,8 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
         case 22: launch_tiled<2, 2>(a, lds, s); break;
         case 31: launch_tiled<3, 1>(a, lds, s); break;
         case 32: launch_tiled<3, 2>(a, lds, s); break;
+        case 24: launch_tiled<2, 4>(a, lds, s); break;
+        case 34: launch_tiled<3, 4>(a, lds, s); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
@@ -886,6 +894,8 @@ hipError_t set_tiled_lds_limit(size_t bytes) {
     if (e == hipSuccess) e = set_lds<2, 2, PIC_TILED_THREADS_2D, 0, 0, 0>(bytes);
     if (e == hipSuccess) e = set_lds<3, 1, PIC_TILED_THREADS_3D, 0, 0, 0>(bytes);
     if (e == hipSuccess) e = set_lds<3, 2, PIC_TILED_THREADS_3D, 0, 0, 0>(bytes);
+    if (e == hipSuccess) e = set_lds<2, 4, PIC_TILED_THREADS_2D, 0, 0, 0>(bytes);
+    if (e == hipSuccess) e = set_lds<3, 4, PIC_TILED_THREADS_3D, 0, 0, 0>(bytes);
     if (e == hipSuccess) e = set_lds<2, 1, PIC_TILED_THREADS_2D, W2X, W2X, 1>(bytes);
     if (e == hipSuccess) e = set_lds<2, 2, PIC_TILED_THREADS_2D, W2X, W2X, 1>(bytes);
     if (e == hipSuccess) e = set_lds<3, 1, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(bytes);

@@ -264,6 +264,8 @@ hipError_t launch_qed(Ctx *c, const pic_qed_args *qa, hipStream_t s) {
             case 22: qed_photon_kernel<2, 2><<<nb, 256, 0, s>>>(ap); break;
             case 31: qed_photon_kernel<3, 1><<<nb, 256, 0, s>>>(ap); break;
             case 32: qed_photon_kernel<3, 2><<<nb, 256, 0, s>>>(ap); break;
+            case 24: qed_photon_kernel<2, 4><<<nb, 256, 0, s>>>(ap); break;
+            case 34: qed_photon_kernel<3, 4><<<nb, 256, 0, s>>>(ap); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -224,7 +224,8 @@ def laser_plasma_2d(seed=644, scale=1, device="cuda", ppc=32, order=2, t_kev=1.0
     ncyc = 10 if scale == 1 else max(2, int(0.25 * n[0] * d[0] / LAMBDA))
     E, B = laser_fields(cfg, device, a0=2.0, waist=5 * LAMBDA if scale == 1 else 0.2 * n[1] * d[1],
                         x_start=xs, n_cycles=ncyc)
-    return Workload(f"laser_plasma_2d_{n[0]}x{n[1]}_ppc{ppc}_quadratic", cfg, [(-1.0, 1.0, raw)], E, B,
+    shape = {1: "linear", 2: "quadratic", 4: "quartic"}[order]
+    return Workload(f"laser_plasma_2d_{n[0]}x{n[1]}_ppc{ppc}_{shape}", cfg, [(-1.0, 1.0, raw)], E, B,
                     steps=1000)
 
 
@@ -252,7 +253,8 @@ def laser_plasma_3d(seed=645, scale=1, device="cuda", ppc=8, order=2, tile=(8, 8
     ion = plasma(cfg, ppc, density, gen, device, uth=math.sqrt(t_kev / ME_KEV / 1836.0))
     E, B = laser_fields(cfg, device, a0=5.0, waist=3 * LAMBDA if scale == 1 else 0.2 * n[1] * d[1],
                         x_start=0.0, n_cycles=10 if scale == 1 else 2, circular=True)
-    return Workload(f"laser_plasma_3d_{n[0]}x{n[1]}x{n[2]}_ppc{ppc}x2_quadratic", cfg,
+    shape = {1: "linear", 2: "quadratic", 4: "quartic"}[order]
+    return Workload(f"laser_plasma_3d_{n[0]}x{n[1]}x{n[2]}_ppc{ppc}x2_{shape}", cfg,
                     [(-1.0, 1.0, el), (1.0, 1836.0, ion)], E, B, steps=500)
 
 

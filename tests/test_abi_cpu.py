@@ -32,7 +32,7 @@ def base_cfg(**kw):
 
 @pytest.mark.parametrize("kw,status", [
     (dict(dt=0.1), L.PIC_E_CFL),
-    (dict(order=4), L.PIC_E_UNSUPPORTED),
+    (dict(order=3), L.PIC_E_UNSUPPORTED),
     (dict(dim=1), L.PIC_E_UNSUPPORTED),
     (dict(precision=7), L.PIC_E_UNSUPPORTED),
     (dict(n=(64, 64, 4)), L.PIC_E_ARG),

@@ -51,11 +51,12 @@ def test_langmuir_64x64_cic_200_steps_matches_oracle():
     assert np.abs(d - Lx * np.round(d / Lx)).max() < 1e-9
 
 
-def heating_workload(seed, n=(32, 32), ppc=8):
+def heating_workload(seed, n=(32, 32), ppc=8, order=2):
     """Self-heating setup of the paper's 2D benchmark in plasma units: 1 keV
-    electrons, 320 cells per plasma wavelength, periodic, quadratic shape."""
+    electrons, 320 cells per plasma wavelength, periodic, quadratic or quartic
+    shape (the two orders the paper compares)."""
     d = (2 * math.pi / 320,) * 2
-    cfg = L.Config(dim=2, n=n, d=d, dt=courant_dt(d), order=2, seed=seed, tile=(16, 16))
+    cfg = L.Config(dim=2, n=n, d=d, dt=courant_dt(d), order=order, seed=seed, tile=(16, 16))
     gen = torch.Generator().manual_seed(seed)
     raw = plasma(cfg, ppc, lambda x: torch.ones_like(x), gen, "cpu", uth=math.sqrt(1.0 / ME_KEV))
     return Workload(f"heating_{seed}", cfg, [(-1.0, 1.0, raw)])
@@ -74,12 +75,13 @@ def energy_history(sim, steps, every=50):
     return np.array(out)
 
 
-def test_energy_drift_1000_steps_matches_oracle():
+@pytest.mark.parametrize("order", [2, 4])
+def test_energy_drift_1000_steps_matches_oracle(order):
     """1000-step relative energy drift D = (U_1000 - U_0)/U_0 of the FP32 and
     FP64 GPU paths against the oracle's: within 1% of the oracle's drift, or
     within twice the seed-to-seed spread of D when that is larger."""
     steps = 1000
-    wl = heating_workload(7)
+    wl = heating_workload(7, order=order)
     st = oracle_state(wl, from_fp32=True)
     U0 = O.total_energy(st)
     hist_o = []
@@ -97,7 +99,7 @@ def test_energy_drift_1000_steps_matches_oracle():
         assert np.max(np.abs(h - np.array(hist_o)) / U0) < (1e-9 if prec == L.PIC_FP64_PLAIN else 1e-3)
     spread = []
     for seed in range(11, 16):
-        w = heating_workload(seed)
+        w = heating_workload(seed, order=order)
         sim = Simulation.from_workload(w, precision=L.PIC_FP32_MIXED, device=DEV, sort_every=16)
         u0 = sum(O.kinetic_energy(oracle_grid(w.cfg), s) for s in oracle_state(w, True).species)
         h = energy_history(sim, steps)
@@ -105,7 +107,7 @@ def test_energy_drift_1000_steps_matches_oracle():
     sigma = float(np.std(spread))
     tol = max(0.01 * abs(D_orc), 2 * sigma)
     rel32 = abs(drifts[L.PIC_FP32_MIXED] - D_orc) / abs(D_orc)
-    print(f"drift: oracle {D_orc:.3e}, GPU FP64 {drifts[L.PIC_FP64_PLAIN]:.3e}, GPU FP32 "
+    print(f"order {order} drift: oracle {D_orc:.3e}, GPU FP64 {drifts[L.PIC_FP64_PLAIN]:.3e}, GPU FP32 "
           f"{drifts[L.PIC_FP32_MIXED]:.3e} ({rel32:.2%} of the oracle's); seed spread sigma {sigma:.2e}; "
           f"tolerance {tol:.2e} ({'1% rule' if tol == 0.01 * abs(D_orc) else '2 sigma rule'})")
     assert abs(drifts[L.PIC_FP64_PLAIN] - D_orc) <= 0.01 * abs(D_orc) + 1e-12

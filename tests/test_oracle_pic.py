@@ -16,25 +16,36 @@ def paper_s2(xi):
     return max(0.0, 1.0 - abs(xi))
 
 
+def paper_s4(xi):
+    """Eq. 18: the cubic-spline shape S_4."""
+    a = abs(xi)
+    if a <= 1.0:
+        return 2.0 / 3.0 - a * a + 0.5 * a ** 3
+    if a <= 2.0:
+        return 4.0 / 3.0 * (1.0 - 0.5 * a) ** 3
+    return 0.0
+
+
 def tophat(xi):
     return 1.0 if abs(xi) <= 0.5 else 0.0
 
 
-@pytest.mark.parametrize("order,S", [(1, tophat), (2, paper_s2)])
+@pytest.mark.parametrize("order,S", [(1, tophat), (2, paper_s2), (4, paper_s4)])
 def test_weights_are_cell_integrals_of_the_shape(order, S):
     """W_n(i - i_c) = integral over the cell of node i of S_n(xi' - x_p) (Sec. II.D)."""
     rng = np.random.default_rng(1)
     for xi in rng.uniform(-3, 3, 40):
         i0, w = O.shape(order, xi)
-        for k in range(-3, 4):
+        for k in range(-3, 8):
             node = i0 + k
             ref = integrate.quad(lambda s: S(s - xi), node - 0.5, node + 0.5,
-                                 points=[xi - 1, xi - 0.5, xi, xi + 0.5, xi + 1], epsabs=1e-13)[0]
+                                 points=[xi - 2, xi - 1, xi - 0.5, xi, xi + 0.5, xi + 1, xi + 2],
+                                 epsabs=1e-13)[0]
             got = w[k] if 0 <= k < len(w) else 0.0
             assert abs(got - ref) < 1e-10, (order, xi, k, got, ref)
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 4])
 def test_weights_partition_of_unity_and_linear_reproduction(order):
     rng = np.random.default_rng(2)
     for xi in rng.uniform(-50, 50, 500):
@@ -63,7 +74,7 @@ def grid3(order=2, n=(10, 8, 6), d=(0.3, 0.25, 0.2), dt=0.08):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 4])
 def test_gather_uniform_field_exact(dim, order):
     g = grid2(order) if dim == 2 else grid3(order)
     vals = np.arange(1, 7) * 0.37
@@ -76,7 +87,7 @@ def test_gather_uniform_field_exact(dim, order):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 4])
 def test_gather_linear_field_on_staggered_nodes(dim, order):
     """A field linear in x, sampled at each component's own staggered location,
     is reproduced exactly at the particle (linear reproduction + stagger)."""
@@ -174,7 +185,7 @@ def random_move(g, rng):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 4])
 def test_esirkepov_discrete_continuity(dim, order):
     """Eq. 5 on the grid: (rho(x_e) - rho(x_h)) / dt + div J = 0 to round-off
     for every single move shorter than one cell per axis."""
@@ -193,7 +204,7 @@ def test_esirkepov_discrete_continuity(dim, order):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 4])
 def test_esirkepov_total_current(dim, order):
     """The summed current equals q w v (the charge times the mean velocity of
     the straight move); in 2D3V the summed J_z equals q w v_z."""

@@ -771,9 +771,10 @@ __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
     }
 }
 
-// window shapes with a compiled kernel: 16x16 tiles with drift 2 in 2D,
-// 8x8x4 tiles with drift 1 in 3D (the defaults); others use the run-time shape
-constexpr int W2X = 16 + 2 * 2 + 5, W3X = 8 + 2 * 1 + 5, W3Z = 4 + 2 * 1 + 5;
+// window shapes with a compiled kernel: 16x16 tiles with drift 2 in 2D
+// (25 cells wide, 27 for quartic weights), 8x8x4 tiles in 3D with drift 1
+// (drift 0 for quartic weights): 15 x 15 x 11; others use the run-time shape
+constexpr int W2X = 16 + 2 * 2 + 5, W2X4 = 16 + 2 * 2 + 7, W3X = 8 + 2 * 1 + 5, W3Z = 4 + 2 * 1 + 5;
 
 // One push of a species:
 //   prep (zero bin counters) -> sorted pass (stragglers listed) -> bin count
@@ -799,11 +800,10 @@ static void launch_passes(TiledArgs a, size_t lds, hipStream_t s) {
 
 template <int DIM, int ORDER>
 static void launch_tiled(const TiledArgs &a, size_t lds, hipStream_t s) {
-    if constexpr (ORDER == 4) {
-        launch_passes<DIM, 4, DIM == 2 ? PIC_TILED_THREADS_2D : PIC_TILED_THREADS_3D, 0, 0, 0>(a, lds, s);
-    } else if constexpr (DIM == 2) {
-        if (a.win[0] == W2X && a.win[1] == W2X)
-            launch_passes<2, ORDER, PIC_TILED_THREADS_2D, W2X, W2X, 1>(a, lds, s);
+    if constexpr (DIM == 2) {
+        constexpr int WX = ORDER == 4 ? W2X4 : W2X;
+        if (a.win[0] == WX && a.win[1] == WX)
+            launch_passes<2, ORDER, PIC_TILED_THREADS_2D, WX, WX, 1>(a, lds, s);
         else
             launch_passes<2, ORDER, PIC_TILED_THREADS_2D, 0, 0, 0>(a, lds, s);
     } else {
@@ -896,6 +896,8 @@ hipError_t set_tiled_lds_limit(size_t bytes) {
     if (e == hipSuccess) e = set_lds<3, 2, PIC_TILED_THREADS_3D, 0, 0, 0>(bytes);
     if (e == hipSuccess) e = set_lds<2, 4, PIC_TILED_THREADS_2D, 0, 0, 0>(bytes);
     if (e == hipSuccess) e = set_lds<3, 4, PIC_TILED_THREADS_3D, 0, 0, 0>(bytes);
+    if (e == hipSuccess) e = set_lds<2, 4, PIC_TILED_THREADS_2D, W2X4, W2X4, 1>(bytes);
+    if (e == hipSuccess) e = set_lds<3, 4, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(bytes);
     if (e == hipSuccess) e = set_lds<2, 1, PIC_TILED_THREADS_2D, W2X, W2X, 1>(bytes);
     if (e == hipSuccess) e = set_lds<2, 2, PIC_TILED_THREADS_2D, W2X, W2X, 1>(bytes);
     if (e == hipSuccess) e = set_lds<3, 1, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(bytes);

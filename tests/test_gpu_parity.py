@@ -132,6 +132,34 @@ def test_sort_then_fp32_push_matches_oracle(dim, order):
     assert np64(diag)[:2] == pytest.approx(diag_o, rel=1e-5)
 
 
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 2), (2, 4), (3, 2), (3, 4)])
+def test_default_tiles_fp32_push_matches_oracle(dim, order):
+    """The default tiles (16x16 with drift 2 in 2D; 8x8x4 with drift 1, or 0
+    for quartic weights, in 3D) run the kernels compiled for their window
+    shape; sort and push against the oracle."""
+    print(f"default tiles dim={dim} order={order}", flush=True)
+    if dim == 2:
+        cfg = L.Config(dim=2, n=(48, 32), d=(0.3, 0.25), dt=courant_dt((0.3, 0.25), 0.9), order=order,
+                       precision=L.PIC_FP32_MIXED, tile=(16, 16), drift=2)
+    else:
+        d = (0.3, 0.25, 0.2)
+        cfg = L.Config(dim=3, n=(16, 16, 12), d=d, dt=courant_dt(d, 0.9), order=order,
+                       precision=L.PIC_FP32_MIXED, tile=(8, 8, 4), drift=0 if order == 4 else 1)
+    raw = random_raw(cfg, 4001, seed=60 + 10 * dim + order)
+    E, B = random_fields(cfg, seed=70 + dim + order)
+    E = [e.to(torch.float32).to(torch.float64) for e in E]
+    B = [b.to(torch.float32).to(torch.float64) for b in B]
+    ctx, p, f, perm, start, bits = sorted_fp32_state(cfg, raw, E, B)
+    assert np.array_equal(p.tile_start.cpu().numpy(), start)
+    sp_o, J_o, diag_o = run_oracle_push(cfg, raw.subset(torch.from_numpy(perm)), E, B, -1.0, 1.0, from_fp32=True)
+    diag = torch.zeros(4, dtype=torch.float64, device=DEV)
+    L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), p, f, diag)
+    st, flags, nstray = L.pic_check(ctx)
+    assert st == L.PIC_OK and flags == 0 and nstray == 0
+    check_fp32_against_oracle(cfg, p, f, bits, sp_o, J_o)
+    assert np64(diag)[:2] == pytest.approx(diag_o, rel=1e-5)
+
+
 @pytest.mark.parametrize("dim,order", [(2, 2), (2, 4), (3, 2)])
 def test_stragglers_take_the_global_path(dim, order):
     """Particles far outside their tile window (no sort since they moved) are

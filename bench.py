@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--scale", type=int, default=1, help="divide the grid (tests only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the QED surrogate inference measurement")
     ap.add_argument("--fp64-order", choices=["lex", "cell"], default="lex",
                     help="particle order of the plain FP64 path (see fp64_order)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -124,6 +125,53 @@ def fp64_order(raw, cfg, tile, kind, torch):
     ct = math.prod(tile[:dim])
     key = (tid * (int(rank.max()) + 1) + rank) * ct + loc
     return torch.argsort(key)
+
+
+MLP_FLOP_PER_SAMPLE = 2 * (4 * 64 + 64 * 64 + 64 * 2)  # the network's multiply-adds
+MLP_MFMA_FLOP_PER_SAMPLE = 48 * 2 * 16 * 16 * 16 / 16     # executed: 48 MFMA tiles per 16 samples
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def mlp_measure(torch, L, n=1 << 24, reps=5):
+    """Throughput of the QED surrogate's inference (random BF16 weights: the
+    cost does not depend on their values) beside the two table lookups it
+    replaces (rate and inverse spectrum), on n samples resident in HBM."""
+    cfg = L.Config(dim=2, n=(64, 64), d=(0.1, 0.1), dt=0.05, hbar_omega_mc2=2.4263e-6)
+    ctx = L.pic_init(cfg)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    net = torch.zeros(L.PIC_MLP_BYTES, dtype=torch.uint8, device="cuda")
+    w = [torch.randn(k, generator=gen, device="cuda") * 0.3 for k in (256, 4096, 128)]
+    net[0:512] = w[0].to(torch.bfloat16).view(torch.uint8)
+    net[512:8704] = w[1].to(torch.bfloat16).view(torch.uint8)
+    net[8704:8960] = w[2].to(torch.bfloat16).view(torch.uint8)
+    x = torch.rand(n, 4, generator=gen, device="cuda") * 2 - 1
+    y = torch.empty(n, 2, device="cuda")
+    chi = torch.exp(torch.rand(n, generator=gen, device="cuda") * 16 - 9)
+    r = torch.rand(n, generator=gen, device="cuda")
+    out = torch.empty(n, device="cuda")
+
+    def timed(fn):
+        fn()
+        best = float("inf")
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            best = min(best, a.elapsed_time(b))
+        return best * 1e-3
+
+    t_net = timed(lambda: L.pic_mlp_forward(ctx, net, x, y))
+    t_tab = timed(lambda: (L.pic_qed_table_lookup(ctx, 0, 0, chi, r, out),
+                           L.pic_qed_table_lookup(ctx, 0, 1, chi, r, out)))
+    L.pic_destroy(ctx)
+    useful = n * MLP_FLOP_PER_SAMPLE / t_net / 1e12
+    return {"samples": n, "network_samples_per_s": n / t_net, "table_samples_per_s": n / t_tab,
+            "gain_over_table": t_tab / t_net, "useful_tflops": useful,
+            "useful_frac_bf16_peak": useful / BF16_PEAK_TFLOPS,
+            "mfma_tflops_executed": n * MLP_MFMA_FLOP_PER_SAMPLE / t_net / 1e12,
+            "note": "hi+lo BF16 activations double the MFMA work; K=4 and N=2 are padded to 16"}
 
 
 def run_path(args, wl, precision, torch, L, Simulation):
@@ -345,6 +393,9 @@ def main():
                               "alg_bytes_per_particle": f["bytes_per_particle"],
                               "error_vs_oracle": f["err"]}
         line["speedup_fp32_vs_fp64_plain"] = value / line["fp64_plain"]["value"]
+    if not args.no_mlp:
+        log("surrogate inference")
+        line["mlp_inference"] = mlp_measure(torch, L)
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)

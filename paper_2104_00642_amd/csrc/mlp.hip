@@ -15,10 +15,11 @@
 //          level coordinate), x2 = [photon emission], x3 = [pair creation].
 // Outputs: y0 = g of the rate tables (ln(F/chi) for emission,
 //          ln F + 8/(3 chi) for pairs); y1 = u^(1/3) (emission) or x (pairs).
-// One wavefront handles 16 samples per round; every matrix product is a sum
-// of 16x16x16 tiles whose fragments are read from LDS through the MFMA lane
-// layout (A: lane l holds row l%16, k = 4(l/16)+i; B: column l%16,
-// k = 4(l/16)+i; C: column l%16, rows 4(l/16)+i).
+// Every matrix product is a sum of 16x16x16 tiles in the MFMA lane layout
+// (A: lane l holds row l%16, k = 4(l/16)+i; B: column l%16, k = 4(l/16)+i;
+// C: column l%16, rows 4(l/16)+i).  Inference keeps the weight fragments in
+// registers and runs 64 samples per wavefront round; training runs 16 samples
+// per round with fragments read from LDS and memory.
 #include "device_common.h"
 #include "pic_internal.h"
 #include "qed_internal.h"
@@ -74,6 +75,12 @@ __device__ __forceinline__ f32x4 tile_mma_split(FA A, FB B, int K, f32x4 acc) {
 
 constexpr float MLP_RATE_WEIGHT = 10.0f;
 
+// tanh from the hardware exponential and reciprocal: 1 - 2 / (1 + e^{2x})
+// (saturates to +-1, absolute error about 1e-7)
+__device__ __forceinline__ float tanh_f(float x) {
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * x));
+}
+
 struct MlpView {
     const short *W1, *W2, *W3;  // [4][64], [64][64], [64][2] BF16
     const float *b1, *b2, *b3;
@@ -103,7 +110,7 @@ __device__ void mlp_forward16(const MlpView &w, WaveLds &L) {
         acc = tile_mma_split([&](int m, int k) { return k < 4 ? L.X[m][k] : 0.0f; },
                        [&](int k, int n) { return k < 4 ? bf2f(w.W1[k * 64 + 16 * nt + n]) : 0.0f; }, 16, acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) L.H1[r4 + i][16 * nt + col] = tanhf(acc[i] + w.b1[16 * nt + col]);
+        for (int i = 0; i < 4; ++i) L.H1[r4 + i][16 * nt + col] = tanh_f(acc[i] + w.b1[16 * nt + col]);
     }
     __syncthreads();
     for (int nt = 0; nt < 4; ++nt) {
@@ -111,7 +118,7 @@ __device__ void mlp_forward16(const MlpView &w, WaveLds &L) {
         acc = tile_mma_split([&](int m, int k) { return L.H1[m][k]; },
                        [&](int k, int n) { return bf2f(w.W2[k * 64 + 16 * nt + n]); }, 64, acc);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) L.H2[r4 + i][16 * nt + col] = tanhf(acc[i] + w.b2[16 * nt + col]);
+        for (int i = 0; i < 4; ++i) L.H2[r4 + i][16 * nt + col] = tanh_f(acc[i] + w.b2[16 * nt + col]);
     }
     __syncthreads();
     {
@@ -156,71 +163,189 @@ __device__ __forceinline__ void mlp_decode(int proc, float chi, const float *y, 
     }
 }
 
+// ---- inference: weights held in registers --------------------------------
+// Each wavefront loads the B fragments of all three layers once (W1: four
+// n-tiles, K = 4 padded to 16; W2: four k-steps x four n-tiles; W3: four
+// k-steps, N = 2 padded to 16: 48 VGPRs) and then runs 16-sample tiles:
+// 8 + 32 + 8 MFMAs per tile with the activations split hi + lo.
+struct MlpFrags {
+    bf16x4 w1[4];
+    bf16x4 w2[4][4];  // [k-step][n-tile]
+    bf16x4 w3[4];     // [k-step]
+    float b1[4], b2[4], b3;
+};
+
+__device__ __forceinline__ void mlp_load_frags(const MlpView &w, MlpFrags &F) {
+    const int l = threadIdx.x & 63;
+    const int col = l & 15, kq = 4 * (l >> 4);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = kq + i;
+            F.w1[nt][i] = k < 4 ? w.W1[k * 64 + 16 * nt + col] : (short)0;
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) F.w2[ks][nt][i] = w.W2[(16 * ks + k) * 64 + 16 * nt + col];
+        }
+        F.b1[nt] = w.b1[16 * nt + col];
+        F.b2[nt] = w.b2[16 * nt + col];
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) F.w3[ks][i] = col < 2 ? w.W3[(16 * ks + kq + i) * 2 + col] : (short)0;
+    F.b3 = col < 2 ? w.b3[col] : 0.0f;
+}
+
+// hi + lo BF16 terms of x in lane element i of two fragments
+__device__ __forceinline__ void split_bf16(float x, bf16x4 &hi, bf16x4 &lo, int i) {
+    const short h = f2bf(x);
+    hi[i] = h;
+    lo[i] = f2bf(x - bf2f(h));
+}
+
+// per-wavefront LDS of the inference: 64 samples' inputs and outputs, one
+// 16 x 64 activation tile
+struct InferLds {
+    float X[64][4];
+    float H[16][64];
+    float Y[64][2];
+};
+
+// outputs Y[t*16 .. t*16+15] from inputs X[t*16 ..]
+__device__ __forceinline__ void mlp_infer_tile(const MlpFrags &F, InferLds &L, int t) {
+    const int l = threadIdx.x & 63;
+    const int col = l & 15, kq = 4 * (l >> 4), row = l & 15, r4 = 4 * (l >> 4);
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    bf16x4 ah, al;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = kq + i;
+        split_bf16(k < 4 ? L.X[16 * t + row][k & 3] : 0.0f, ah, al, i);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, F.w1[nt], z, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, F.w1[nt], acc, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) L.H[r4 + i][16 * nt + col] = tanh_f(acc[i] + F.b1[nt]);
+    }
+    __builtin_amdgcn_wave_barrier();
+    f32x4 acc2[4] = {z, z, z, z};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) split_bf16(L.H[row][16 * ks + kq + i], ah, al, i);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, F.w2[ks][nt], acc2[nt], 0, 0, 0);
+            acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, F.w2[ks][nt], acc2[nt], 0, 0, 0);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) L.H[r4 + i][16 * nt + col] = tanh_f(acc2[nt][i] + F.b2[nt]);
+    __builtin_amdgcn_wave_barrier();
+    f32x4 acc3 = z;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) split_bf16(L.H[row][16 * ks + kq + i], ah, al, i);
+        acc3 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, F.w3[ks], acc3, 0, 0, 0);
+        acc3 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, F.w3[ks], acc3, 0, 0, 0);
+    }
+    if (col < 2) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) L.Y[16 * t + r4 + i][col] = acc3[i] + F.b3;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int INFER_THREADS = 256;
+
 // network inference for the QED step: one output pair (F, sample) per
 // particle; the level r is the uniform the particle uses if its event fires
-// this step.  chi outside the trained range falls back to the tables.
-__global__ void __launch_bounds__(64) mlp_qed_kernel(const void *mlp, const float *tab, QedSpeciesView v,
-                                                      int proc, float *out) {
-    __shared__ WaveLds L;
-    const MlpView w = mlp_view(mlp);
-    const int l = threadIdx.x;
+// this step.  chi outside the trained range falls back to the tables.  Each
+// wavefront prepares 64 particles' inputs (one per lane), runs four tiles,
+// and decodes one output per lane.
+__global__ void __launch_bounds__(INFER_THREADS) mlp_qed_kernel(const void *mlp, const float *tab, QedSpeciesView v,
+                                                                int proc, float *out) {
+    __shared__ InferLds Ls[INFER_THREADS / 64];
+    InferLds &L = Ls[threadIdx.x >> 6];
+    MlpFrags F;
+    mlp_load_frags(mlp_view(mlp), F);
+    const int l = threadIdx.x & 63;
     const float lo = proc == QED_COMPTON ? (float)QED_LOG_CHI_MIN_C : (float)QED_LOG_CHI_MIN_P;
-    for (int64_t base = (int64_t)blockIdx.x * 16; base < v.n; base += (int64_t)gridDim.x * 16) {
+    const int64_t nw = (int64_t)gridDim.x * (INFER_THREADS / 64);
+    for (int64_t base = ((int64_t)blockIdx.x * (INFER_THREADS / 64) + (threadIdx.x >> 6)) * 64; base < v.n;
+         base += nw * 64) {
+        const int64_t p = base + l;
         float chi = 0.0f, r = 0.5f;
-        const int64_t p = base + (l & 15);
-        if (l < 16 && p < v.n) {
+        float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (p < v.n) {
             chi = v.chi[p];
             double ru, rt;
             qed_uniforms(v.seed, v.id[p], v.step, 0u, ru, rt);
             r = (float)ru;
-            float x[4];
             mlp_inputs(proc, fmaxf(chi, 1e-30f), r, x);
-            for (int k = 0; k < 4; ++k) L.X[l][k] = x[k];
         }
-        __syncthreads();
-        mlp_forward16(w, L);
-        if (l < 16 && p < v.n) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) L.X[l][k] = x[k];
+        __builtin_amdgcn_wave_barrier();
+        for (int t = 0; t < 4; ++t) mlp_infer_tile(F, L, t);
+        if (p < v.n) {
             const float lc = chi > 0.0f ? log10f(chi) : -100.0f;
-            float F, smp;
+            float F_, smp;
             if (lc >= lo && lc <= (float)QED_LOG_CHI_MAX) {
-                mlp_decode(proc, chi, L.Y[l], F, smp);
+                const float y[2] = {L.Y[l][0], L.Y[l][1]};
+                mlp_decode(proc, chi, y, F_, smp);
             } else {
-                F = qed_rate_F(tab, proc, chi);
+                F_ = qed_rate_F(tab, proc, chi);
                 smp = qed_inverse(tab, proc, chi, r);
             }
-            out[2 * p] = F;
+            out[2 * p] = F_;
             out[2 * p + 1] = smp;
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
+}
+
+static unsigned infer_blocks(int64_t n) {
+    const int64_t waves = (n + 63) / 64;
+    const int64_t blocks = (waves + INFER_THREADS / 64 - 1) / (INFER_THREADS / 64);
+    return (unsigned)(blocks < 2048 ? blocks : 2048);
 }
 
 hipError_t launch_mlp_for_qed(Ctx *c, const void *mlp, const QedSpeciesView &v, int proc, float *out,
                               hipStream_t s) {
     if (v.n <= 0) return hipSuccess;
-    const int64_t groups = (v.n + 15) / 16;
-    const unsigned nb = (unsigned)(groups < 65536 ? groups : 65536);
-    mlp_qed_kernel<<<nb, 64, 0, s>>>(mlp, c->qed.dev, v, proc, out);
+    mlp_qed_kernel<<<infer_blocks(v.n), INFER_THREADS, 0, s>>>(mlp, c->qed.dev, v, proc, out);
     return hipGetLastError();
 }
 
 // plain forward: x [n][4] -> y [n][2]
-__global__ void __launch_bounds__(64) mlp_forward_kernel(const void *mlp, const float *x, int64_t n, float *y) {
-    __shared__ WaveLds L;
-    const MlpView w = mlp_view(mlp);
-    const int l = threadIdx.x;
-    for (int64_t base = (int64_t)blockIdx.x * 16; base < n; base += (int64_t)gridDim.x * 16) {
-        const int64_t p = base + (l & 15);
-        if (l < 16) {
-            for (int k = 0; k < 4; ++k) L.X[l][k] = p < n ? x[p * 4 + k] : 0.0f;
+__global__ void __launch_bounds__(INFER_THREADS) mlp_forward_kernel(const void *mlp, const float *x, int64_t n,
+                                                                    float *y) {
+    __shared__ InferLds Ls[INFER_THREADS / 64];
+    InferLds &L = Ls[threadIdx.x >> 6];
+    MlpFrags F;
+    mlp_load_frags(mlp_view(mlp), F);
+    const int l = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (INFER_THREADS / 64);
+    for (int64_t base = ((int64_t)blockIdx.x * (INFER_THREADS / 64) + (threadIdx.x >> 6)) * 64; base < n;
+         base += nw * 64) {
+        const int64_t p = base + l;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) L.X[l][k] = p < n ? x[p * 4 + k] : 0.0f;
+        __builtin_amdgcn_wave_barrier();
+        for (int t = 0; t < 4; ++t) mlp_infer_tile(F, L, t);
+        if (p < n) {
+            y[p * 2] = L.Y[l][0];
+            y[p * 2 + 1] = L.Y[l][1];
         }
-        __syncthreads();
-        mlp_forward16(w, L);
-        if (l < 32) {
-            const int row = l >> 1, o = l & 1;
-            if (base + row < n) y[(base + row) * 2 + o] = L.Y[row][o];
-        }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -406,8 +531,7 @@ __global__ void mlp_data_kernel(const float *tab, int64_t n, uint64_t seed, floa
 
 hipError_t launch_mlp_forward(const void *mlp, const float *x, int64_t n, float *y, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int64_t groups = (n + 15) / 16;
-    mlp_forward_kernel<<<(unsigned)(groups < 65536 ? groups : 65536), 64, 0, s>>>(mlp, x, n, y);
+    mlp_forward_kernel<<<infer_blocks(n), INFER_THREADS, 0, s>>>(mlp, x, n, y);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // mlp.hip -- the 4 -> 64 -> 64 -> 2 surrogate of the QED rates and inverse
 // spectra (Sec. IV, Eqs. 23-24), trained and evaluated with BF16 matrix cores
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulate) on gfx950.
+// (v_mfma_f32_16x16x16_bf16 and v_mfma_f32_16x16x32_bf16, FP32 accumulate)
+// on gfx950.
 //
 // Network: h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 W3 + b3.
 // Weights are BF16, biases FP32.  In the forward pass every activation enters
@@ -18,8 +19,9 @@
 // Every matrix product is a sum of 16x16x16 tiles in the MFMA lane layout
 // (A: lane l holds row l%16, k = 4(l/16)+i; B: column l%16, k = 4(l/16)+i;
 // C: column l%16, rows 4(l/16)+i).  Inference keeps the weight fragments in
-// registers and runs 64 samples per wavefront round; training runs 16 samples
-// per round with fragments read from LDS and memory.
+// registers, chains the layers without leaving registers and runs 64 samples
+// per wavefront round; training runs 16 samples per round with fragments read
+// from LDS and memory.
 #include "device_common.h"
 #include "pic_internal.h"
 #include "qed_internal.h"
@@ -75,10 +77,10 @@ __device__ __forceinline__ f32x4 tile_mma_split(FA A, FB B, int K, f32x4 acc) {
 
 constexpr float MLP_RATE_WEIGHT = 10.0f;
 
-// tanh from the hardware exponential and reciprocal: 1 - 2 / (1 + e^{2x})
+// tanh from the hardware exponential and reciprocal: 1 - 2 / (1 + 2^{2x log2 e})
 // (saturates to +-1, absolute error about 1e-7)
 __device__ __forceinline__ float tanh_f(float x) {
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * x));
+    return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(2.8853900817779268f * x)), 1.0f);
 }
 
 struct MlpView {
@@ -164,103 +166,141 @@ __device__ __forceinline__ void mlp_decode(int proc, float chi, const float *y, 
 }
 
 // ---- inference: weights held in registers --------------------------------
-// Each wavefront loads the B fragments of all three layers once (W1: four
-// n-tiles, K = 4 padded to 16; W2: four k-steps x four n-tiles; W3: four
-// k-steps, N = 2 padded to 16: 48 VGPRs) and then runs 16-sample tiles:
-// 8 + 32 + 8 MFMAs per tile with the activations split hi + lo.
+// The weights are the A operand and the activations the B operand (outputs
+// as rows, samples as columns), so the C fragment one layer produces (lane l:
+// rows 4(l/16)+i of a 16-row output block, column l%16 = sample) already is
+// the B fragment of the next layer and activations never leave registers.
+// Layers 2 and 3 contract 32 features per v_mfma_f32_16x16x32_bf16 in the
+// slot order k(g, i) = 32 j + (i < 4 ? 4 g + i : 12 + 4 g + i), g = l/16,
+// i = 0..7: the lane's values of output blocks 2j and 2j+1.  Any order of
+// the contraction is the same sum, provided the weights' A fragments use it
+// too.  Layer 1 (v_mfma_f32_16x16x16_bf16, k = 4 g + i) takes the inputs'
+// hi terms in g = 0, their lo terms in g = 1 and the bias as three BF16
+// terms against constant ones in g = 2.  Per 16-sample tile: 4 + 16 + 4
+// MFMAs, 32 tanh and 32 hi/lo splits per lane.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v4 __attribute__((ext_vector_type(4)));
+
 struct MlpFrags {
-    bf16x4 w1[4];
-    bf16x4 w2[4][4];  // [k-step][n-tile]
-    bf16x4 w3[4];     // [k-step]
-    float b1[4], b2[4], b3;
+    bf16x4 w1[4];     // [output block]
+    bf16x8 w2[4][2];  // [output block][k-step]
+    bf16x8 w3[2];     // [k-step]; rows 0, 1 are the two outputs
+    f32x4 b2[4];      // bias of rows 4g+i of each output block
+    f32x4 b3;
 };
+
+// feature of slot i of lane group g in k-step j (layers 2 and 3)
+__device__ __forceinline__ int mlp_slot_feature(int j, int g, int i) { return 32 * j + (i < 4 ? 4 * g + i : 12 + 4 * g + i); }
+
+__device__ __forceinline__ short bf_bits(float x) { return __builtin_bit_cast(short, (__bf16)x); }
 
 __device__ __forceinline__ void mlp_load_frags(const MlpView &w, MlpFrags &F) {
     const int l = threadIdx.x & 63;
-    const int col = l & 15, kq = 4 * (l >> 4);
+    const int m = l & 15, g = l >> 4;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
+        const int o = 16 * nt + m;
+        const float b = w.b1[o];
+        const float t0 = (float)(__bf16)b, t1 = (float)(__bf16)(b - t0), t2 = (float)(__bf16)(b - t0 - t1);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int k = kq + i;
-            F.w1[nt][i] = k < 4 ? w.W1[k * 64 + 16 * nt + col] : (short)0;
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) F.w2[ks][nt][i] = w.W2[(16 * ks + k) * 64 + 16 * nt + col];
+            short v = 0;
+            if (g < 2) v = w.W1[i * 64 + o];
+            else if (g == 2) v = bf_bits(i == 0 ? t0 : i == 1 ? t1 : i == 2 ? t2 : 0.0f);
+            F.w1[nt][i] = v;
+            F.b2[nt][i] = w.b2[16 * nt + 4 * g + i];
         }
-        F.b1[nt] = w.b1[16 * nt + col];
-        F.b2[nt] = w.b2[16 * nt + col];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                F.w2[nt][j][i] = __builtin_bit_cast(__bf16, w.W2[mlp_slot_feature(j, g, i) * 64 + o]);
     }
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) F.w3[ks][i] = col < 2 ? w.W3[(16 * ks + kq + i) * 2 + col] : (short)0;
-    F.b3 = col < 2 ? w.b3[col] : 0.0f;
+        for (int i = 0; i < 8; ++i)
+            F.w3[j][i] = __builtin_bit_cast(__bf16, m < 2 ? w.W3[mlp_slot_feature(j, g, i) * 2 + m] : (short)0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) F.b3[i] = g == 0 && i < 2 ? w.b3[i] : 0.0f;
 }
 
-// hi + lo BF16 terms of x in lane element i of two fragments
-__device__ __forceinline__ void split_bf16(float x, bf16x4 &hi, bf16x4 &lo, int i) {
-    const short h = f2bf(x);
-    hi[i] = h;
-    lo[i] = f2bf(x - bf2f(h));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// hi and lo BF16 terms of eight values: one rounding conversion per pair,
+// the hi values read back from the packed pair by shift and mask
+__device__ __forceinline__ void split8(const f32x8 &h, bf16x8 &hi, bf16x8 &lo) {
+    u32x4 ph, pl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const f32x2 v = {h[2 * q], h[2 * q + 1]};
+        const uint32_t u = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+        const f32x2 r = {v[0] - __uint_as_float(u << 16), v[1] - __uint_as_float(u & 0xFFFF0000u)};
+        ph[q] = u;
+        pl[q] = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
+    }
+    hi = __builtin_bit_cast(bf16x8, ph);
+    lo = __builtin_bit_cast(bf16x8, pl);
 }
 
-// per-wavefront LDS of the inference: 64 samples' inputs and outputs, one
-// 16 x 64 activation tile
+// tanh of C blocks 2j, 2j+1 as the hi and lo B fragments of k-step j
+__device__ __forceinline__ void mlp_act_frags(const f32x4 &c0, const f32x4 &c1, bf16x8 &hi, bf16x8 &lo) {
+    f32x8 h;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) h[i] = tanh_f(i < 4 ? c0[i] : c1[i - 4]);
+    split8(h, hi, lo);
+}
+
+// per-wavefront LDS of the inference: 64 samples' inputs and outputs
 struct InferLds {
     float X[64][4];
-    float H[16][64];
     float Y[64][2];
 };
 
-// outputs Y[t*16 .. t*16+15] from inputs X[t*16 ..]
+// outputs Y[16t .. 16t+15] from inputs X[16t ..]
 __device__ __forceinline__ void mlp_infer_tile(const MlpFrags &F, InferLds &L, int t) {
     const int l = threadIdx.x & 63;
-    const int col = l & 15, kq = 4 * (l >> 4), row = l & 15, r4 = 4 * (l >> 4);
+    const int g = l >> 4, s = 16 * t + (l & 15);
     const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-    bf16x4 ah, al;
+    // lane group g: 0 hi terms, 1 lo terms, 2 the ones against the bias terms
+    const f32x4 x = *(const f32x4 *)L.X[s];
+    const bf16v4 xh = __builtin_convertvector(x, bf16v4);
+    const bf16v4 xl = __builtin_convertvector(x - __builtin_convertvector(xh, f32x4), bf16v4);
+    const bf16v4 one = {(__bf16)1.0f, (__bf16)1.0f, (__bf16)1.0f, (__bf16)0.0f}, zero = {};
+    const bf16x4 xb = __builtin_bit_cast(bf16x4, g == 0 ? xh : g == 1 ? xl : g == 2 ? one : zero);
+    f32x4 c1[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int k = kq + i;
-        split_bf16(k < 4 ? L.X[16 * t + row][k & 3] : 0.0f, ah, al, i);
-    }
+    for (int nt = 0; nt < 4; ++nt) c1[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(F.w1[nt], xb, z, 0, 0, 0);
+    bf16x8 hh[2], hl[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) mlp_act_frags(c1[2 * j], c1[2 * j + 1], hh[j], hl[j]);
+    f32x4 c2[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, F.w1[nt], z, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, F.w1[nt], acc, 0, 0, 0);
+        f32x4 acc = F.b2[nt];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) L.H[r4 + i][16 * nt + col] = tanh_f(acc[i] + F.b1[nt]);
-    }
-    __builtin_amdgcn_wave_barrier();
-    f32x4 acc2[4] = {z, z, z, z};
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) split_bf16(L.H[row][16 * ks + kq + i], ah, al, i);
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, F.w2[ks][nt], acc2[nt], 0, 0, 0);
-            acc2[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, F.w2[ks][nt], acc2[nt], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w2[nt][j], hh[j], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w2[nt][j], hl[j], acc, 0, 0, 0);
         }
+        c2[nt] = acc;
     }
-    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int j = 0; j < 2; ++j) mlp_act_frags(c2[2 * j], c2[2 * j + 1], hh[j], hl[j]);
+    f32x4 c3 = F.b3;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) L.H[r4 + i][16 * nt + col] = tanh_f(acc2[nt][i] + F.b2[nt]);
-    __builtin_amdgcn_wave_barrier();
-    f32x4 acc3 = z;
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) split_bf16(L.H[row][16 * ks + kq + i], ah, al, i);
-        acc3 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, F.w3[ks], acc3, 0, 0, 0);
-        acc3 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, F.w3[ks], acc3, 0, 0, 0);
+    for (int j = 0; j < 2; ++j) {
+        c3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w3[j], hh[j], c3, 0, 0, 0);
+        c3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w3[j], hl[j], c3, 0, 0, 0);
     }
-    if (col < 2) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) L.Y[16 * t + r4 + i][col] = acc3[i] + F.b3;
+    if (g == 0) {
+        L.Y[s][0] = c3[0];
+        L.Y[s][1] = c3[1];
     }
-    __builtin_amdgcn_wave_barrier();
 }
 
 constexpr int INFER_THREADS = 256;
@@ -270,7 +310,7 @@ constexpr int INFER_THREADS = 256;
 // this step.  chi outside the trained range falls back to the tables.  Each
 // wavefront prepares 64 particles' inputs (one per lane), runs four tiles,
 // and decodes one output per lane.
-__global__ void __launch_bounds__(INFER_THREADS) mlp_qed_kernel(const void *mlp, const float *tab, QedSpeciesView v,
+__global__ void __launch_bounds__(INFER_THREADS, 4) mlp_qed_kernel(const void *mlp, const float *tab, QedSpeciesView v,
                                                                 int proc, float *out) {
     __shared__ InferLds Ls[INFER_THREADS / 64];
     InferLds &L = Ls[threadIdx.x >> 6];
@@ -295,6 +335,7 @@ __global__ void __launch_bounds__(INFER_THREADS) mlp_qed_kernel(const void *mlp,
         for (int k = 0; k < 4; ++k) L.X[l][k] = x[k];
         __builtin_amdgcn_wave_barrier();
         for (int t = 0; t < 4; ++t) mlp_infer_tile(F, L, t);
+        __builtin_amdgcn_wave_barrier();
         if (p < v.n) {
             const float lc = chi > 0.0f ? log10f(chi) : -100.0f;
             float F_, smp;
@@ -326,7 +367,7 @@ hipError_t launch_mlp_for_qed(Ctx *c, const void *mlp, const QedSpeciesView &v, 
 }
 
 // plain forward: x [n][4] -> y [n][2]
-__global__ void __launch_bounds__(INFER_THREADS) mlp_forward_kernel(const void *mlp, const float *x, int64_t n,
+__global__ void __launch_bounds__(INFER_THREADS, 4) mlp_forward_kernel(const void *mlp, const float *x, int64_t n,
                                                                     float *y) {
     __shared__ InferLds Ls[INFER_THREADS / 64];
     InferLds &L = Ls[threadIdx.x >> 6];
@@ -341,6 +382,7 @@ __global__ void __launch_bounds__(INFER_THREADS) mlp_forward_kernel(const void *
         for (int k = 0; k < 4; ++k) L.X[l][k] = p < n ? x[p * 4 + k] : 0.0f;
         __builtin_amdgcn_wave_barrier();
         for (int t = 0; t < 4; ++t) mlp_infer_tile(F, L, t);
+        __builtin_amdgcn_wave_barrier();
         if (p < n) {
             y[p * 2] = L.Y[l][0];
             y[p * 2 + 1] = L.Y[l][1];

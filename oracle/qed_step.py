@@ -11,12 +11,20 @@ Philox(parent_lo, parent_hi, step, 0x80000000 | tag) (tag 1 photon,
 2 positron, 3 electron) and their first threshold from counter
 (id_lo, id_hi, step, 1).  Recoil is collinear: u <- u (1 - eps_gamma/|u|),
 clamped at 0.  Plain Python loops: meant for small particle counts.
+
+Method II of Sec. IV (rejection) is here too: each step a lepton draws
+(r1, r2), proposes the photon energy fraction u0 = r1^3 and emits when
+3 r1^2 (d^2W/du dt)(u0) dt > r2; the paper leaves dt out of the printed
+condition, a probability per step needs it.  For pair creation the
+proposal is x0 = r1 (the spectrum of Eq. 24 has no endpoint singularity to
+remove) and the test (d^2W/dx dt)(x0) dt > r2.  (r1, r2) are the same
+counter-(id, step, 0) uniforms Method I uses; tau is not involved.
 """
 from __future__ import annotations
 
 import math
 
-from . import compton_inverse, fpair, frad, pair_inverse, philox4x32_10, qed_uniforms
+from . import compton_bracket, compton_inverse, fpair, frad, pair_bracket, pair_inverse, philox4x32_10, qed_uniforms
 
 ALPHA = 1.0 / 137.035999084
 A_CONST = ALPHA / (math.sqrt(3.0) * math.pi)
@@ -151,3 +159,86 @@ def photon_decay(photons: dict, seed: int, step: int, dt: float, hbar_w: float, 
             photons["w"][p] = 0.0
             tau = 0.0
         photons["tau"][p] = tau
+
+
+# ------------------------------------------------------------- Method II
+
+def emission_acceptance(chi: float, gamma: float, r1: float, dt: float, hbar_w: float) -> float:
+    """3 r1^2 (d^2W_rad/du dt)(r1^3) dt in the units of Eq. 8: Eq. 23's
+    prefactor alpha m c^2 / (sqrt3 pi hbar w_r gamma) times its bracket, with
+    the Jacobian du/dr1 = 3 r1^2 of the proposal u0 = r1^3."""
+    return A_CONST / hbar_w / gamma * 3.0 * r1 * r1 * compton_bracket(r1 ** 3, chi) * dt
+
+
+def pair_acceptance(chi: float, eps: float, x0: float, dt: float, hbar_w: float) -> float:
+    """(d^2W_pair/dx dt)(x0) dt with x = eps_+/eps_gamma: Eq. 24 times
+    d eps_+/dx = eps_gamma, i.e. alpha m c^2 / (sqrt3 pi hbar w_r eps_gamma)
+    times its bracket."""
+    return A_CONST / hbar_w / eps * pair_bracket(x0, chi) * dt
+
+
+def lepton_step_method2(leptons: dict, seed: int, step: int, dt: float, hbar_w: float, emin: float,
+                        photons_out: list | None) -> bool:
+    """Method II photon emission for one step; same containers as lepton_step
+    (tau and tau_thr untouched).  Returns True when some acceptance exceeded 1
+    (the step is too long for the rate: the emission probability saturates)."""
+    saturated = False
+    n = len(leptons["chi"])
+    for p in range(n):
+        w = leptons["w"][p]
+        chi = leptons["chi"][p]
+        if w == 0.0 or not chi > 0.0:
+            continue
+        u = [leptons["u"][a][p] for a in range(3)]
+        pu2 = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+        gam = math.sqrt(1.0 + pu2)
+        pid = leptons["id"][p]
+        r1, r2 = qed_uniforms(seed, pid, step, 0)
+        acc = emission_acceptance(chi, gam, r1, dt, hbar_w)
+        saturated |= acc > 1.0
+        if acc <= r2:
+            continue
+        eps = r1 ** 3 * gam
+        pm = math.sqrt(pu2)
+        if pm > 0:
+            k = [eps * c / pm for c in u]
+            if photons_out is not None and eps >= emin:
+                cid = child_id(seed, pid, step, 1)
+                photons_out.append(dict(k=k, w=w, pos=leptons["pos"][p], id=cid,
+                                        tau_thr=first_threshold(seed, cid, step)))
+            f = max(0.0, 1.0 - eps / pm)
+            for a in range(3):
+                leptons["u"][a][p] = u[a] * f
+    return saturated
+
+
+def photon_decay_method2(photons: dict, seed: int, step: int, dt: float, hbar_w: float,
+                         positrons_out: list, electrons_out: list) -> bool:
+    """Method II pair creation for one step (photons above 2 m c^2); same
+    containers as photon_decay.  Returns the saturation flag."""
+    saturated = False
+    n = len(photons["chi"])
+    for p in range(n):
+        w = photons["w"][p]
+        chi = photons["chi"][p]
+        if w == 0.0:
+            continue
+        k = [photons["k"][a][p] for a in range(3)]
+        eps = math.sqrt(sum(c * c for c in k))
+        if not (eps > 2.0 and chi > 0.0):
+            continue
+        pid = photons["id"][p]
+        r1, r2 = qed_uniforms(seed, pid, step, 0)
+        acc = pair_acceptance(chi, eps, r1, dt, hbar_w)
+        saturated |= acc > 1.0
+        if acc <= r2:
+            continue
+        ep, em = r1 * eps, (1.0 - r1) * eps
+        npl = math.sqrt(max(ep * ep - 1.0, 0.0)) / eps
+        nmi = math.sqrt(max(em * em - 1.0, 0.0)) / eps
+        for out, nn, tag in ((positrons_out, npl, 2), (electrons_out, nmi, 3)):
+            cid = child_id(seed, pid, step, tag)
+            out.append(dict(u=[nn * c for c in k], w=w, pos=photons["pos"][p], id=cid,
+                            tau_thr=first_threshold(seed, cid, step)))
+        photons["w"][p] = 0.0
+    return saturated

@@ -82,3 +82,78 @@ def test_pair_kinematics():
     F = O.fpair(chi)
     cdf = lambda x: np.array([O.pair_cum(chi, float(v)) / F for v in np.atleast_1d(x)])  # noqa: E731
     assert stats.kstest(np.array(xs), cdf).pvalue > 1e-3
+
+
+# ---------------------------------------------------------------- Method II
+
+@pytest.mark.parametrize("chi", [0.05, 0.49, 4.9, 49.0])
+def test_method2_mean_acceptance_is_the_total_rate(chi):
+    """Averaged over the proposal r1 ~ U(0,1), Method II's acceptance is the
+    emission probability W dt of the step (W from the pinned F_rad of Eq. 23);
+    a wrong Jacobian, prefactor or time factor breaks the equality."""
+    from scipy import integrate
+    gamma, hbar_w, dt = 800.0, 2.4263e-6, 0.01
+    f = lambda r: Q.emission_acceptance(chi, gamma, r, dt, hbar_w)  # noqa: E731
+    mean, _ = integrate.quad(f, 0.0, 1.0, limit=400, epsabs=0.0, epsrel=1e-11)
+    W = Q.A_CONST / hbar_w * O.frad(chi) / gamma
+    assert mean == pytest.approx(W * dt, rel=1e-7)
+
+
+@pytest.mark.parametrize("chi", [0.49, 4.9, 49.0])
+def test_method2_mean_pair_acceptance_is_the_total_rate(chi):
+    from scipy import integrate
+    eps, hbar_w, dt = 900.0, 2.4263e-6, 0.01
+    f = lambda x: Q.pair_acceptance(chi, eps, x, dt, hbar_w)  # noqa: E731
+    mean, _ = integrate.quad(f, 0.0, 1.0, points=[0.5], limit=400, epsabs=0.0, epsrel=1e-11)
+    W = Q.A_CONST / hbar_w * O.fpair(chi) / eps
+    assert mean == pytest.approx(W * dt, rel=1e-7)
+
+
+def test_method2_emission_count_and_spectrum():
+    """One Method II step with W dt = 0.25 fires in a quarter of the leptons
+    (binomial, 4 sigma) and the photon energies follow the cumulative spectrum
+    of Eq. 23 (KS); every photon has u0 = r1^3 of its lepton's stream."""
+    n, chi, gamma, hbar_w = 4000, 4.9, 1000.0, 2.4263e-6
+    W = Q.A_CONST / hbar_w * O.frad(chi) / gamma
+    dt = 0.25 / W
+    L = leptons(n, chi, gamma, [1.0] * n)
+    out = []
+    sat = Q.lepton_step_method2(L, SEED, 7, dt, hbar_w, 0.0, out)
+    assert not sat
+    assert abs(len(out) - 0.25 * n) < 4 * math.sqrt(n * 0.25 * 0.75)
+    u = []
+    for ph in out:
+        pid = ph["pos"] + 1
+        r1, _ = O.qed_uniforms(SEED, pid, 7, 0)
+        e = math.sqrt(sum(c * c for c in ph["k"]))
+        assert e == pytest.approx(r1 ** 3 * gamma, rel=1e-12)
+        u.append(e / gamma)
+    assert all(t == 0.0 for t in L["tau"])  # Method II leaves tau alone
+    F = O.frad(chi)
+    cdf = lambda x: np.array([O.compton_cum(chi, float(v)) / F for v in np.atleast_1d(x)])  # noqa: E731
+    assert stats.kstest(np.array(u), cdf).pvalue > 1e-3
+
+
+def test_method2_pair_count_and_spectrum():
+    n, chi, eps, hbar_w = 3000, 4.9, 1000.0, 2.4263e-6
+    W = Q.A_CONST / hbar_w * O.fpair(chi) / eps
+    dt = 0.25 / W
+    P = dict(k=[[eps] * n, [0.0] * n, [0.0] * n], chi=[chi] * n, tau=[0.0] * n, tau_thr=[1.0] * n,
+             id=list(range(10, 10 + n)), w=[1.0] * n, pos=list(range(n)))
+    pos, ele = [], []
+    assert not Q.photon_decay_method2(P, SEED, 4, dt, hbar_w, pos, ele)
+    assert len(pos) == len(ele)
+    assert abs(len(pos) - 0.25 * n) < 4 * math.sqrt(n * 0.25 * 0.75)
+    assert sum(1 for w in P["w"] if w == 0.0) == len(pos)
+    xs = [math.sqrt(1 + sum(c * c for c in a["u"])) / eps for a in pos]
+    F = O.fpair(chi)
+    cdf = lambda x: np.array([O.pair_cum(chi, float(v)) / F for v in np.atleast_1d(x)])  # noqa: E731
+    assert stats.kstest(np.array(xs), cdf).pvalue > 1e-3
+
+
+def test_method2_reports_saturation():
+    """An acceptance above 1 means the step is too long for the rate."""
+    n, chi, gamma, hbar_w = 50, 4.9, 1000.0, 2.4263e-6
+    W = Q.A_CONST / hbar_w * O.frad(chi) / gamma
+    assert not Q.lepton_step_method2(leptons(n, chi, gamma, [1.0] * n), SEED, 1, 0.1 / W, hbar_w, 0.0, None)
+    assert Q.lepton_step_method2(leptons(n, chi, gamma, [1.0] * n), SEED, 1, 5.0 / W, hbar_w, 0.0, None)

@@ -77,7 +77,9 @@ enum {
     PIC_F_OFFSET = 2u,      /* FP32 offset outside [0,1) or cell out of grid */
     PIC_F_STRAGGLER = 4u,   /* particle outside its tile window (handled by
                                the global-memory path; sort more often)      */
-    PIC_F_CAPACITY = 8u     /* QED creation beyond capacity (events dropped) */
+    PIC_F_CAPACITY = 8u,    /* QED creation beyond capacity (events dropped) */
+    PIC_F_QED_SATURATED = 16u /* QED Method II acceptance above 1: the time step
+                               is too long for the rate, events are missed   */
 };
 
 typedef struct {
@@ -193,8 +195,9 @@ pic_status pic_yee_step(void *ctx, int32_t half, const pic_fields *fields, doubl
 pic_status pic_sort(void *ctx, const pic_particles *src, const pic_particles *dst, void *stream);
 
 /*
- * Monte-Carlo QED step (Sec. IV), Method I in optical-depth form, on the
- * FP32 particle layout.  Rates per unit time (1/w_r):
+ * Monte-Carlo QED step (Sec. IV) on the FP32 particle layout: Method I in
+ * optical-depth form (modes PIC_QED_TABLE, PIC_QED_MLP) or Method II
+ * (PIC_QED_METHOD2).  Rates per unit time (1/w_r):
  *   W_rad  = alpha/(sqrt3 pi) (m c^2/hbar w_r) F_rad(chi_e) / gamma     (Eq. 23)
  *   W_pair = alpha/(sqrt3 pi) (m c^2/hbar w_r) F_pair(chi_g) / eps_gamma (Eq. 24)
  * Each particle carries tau (FP64) and tau_thr; tau += W dt.  When tau >=
@@ -216,14 +219,25 @@ pic_status pic_sort(void *ctx, const pic_particles *src, const pic_particles *ds
  * with its own quadrature at pic_init (PIC_QED_TABLE), or from the trained
  * network (PIC_QED_MLP; chi outside the trained range uses the tables).
  * Requires hbar_omega_mc2 > 0.
+ * Method II (rejection; the tau and tau_thr of existing particles are neither
+ * read nor written): with
+ * the same (r, r') = (r1, r2), the proposal is u0 = r1^3 (emission) or
+ * x0 = r1 (pairs) and the event happens when
+ *   3 r1^2 (d^2W_rad/du dt)(u0) dt > r2   or   (d^2W_pair/dx dt)(x0) dt > r2,
+ * the paper's condition with the time step written in (x = eps_+/eps_gamma).
+ * The densities come from tables of the normalized spectra the library
+ * computes at pic_init (bilinear in log10 chi and in acos(1 - 2 sigma)).
+ * Acceptances above 1 set PIC_F_QED_SATURATED (pic_check reports the flag;
+ * the step still returns PIC_OK).  Photons and the kinematics are as in
+ * Method I.
  */
-enum { PIC_QED_TABLE = 0, PIC_QED_MLP = 1 };
+enum { PIC_QED_TABLE = 0, PIC_QED_MLP = 1, PIC_QED_METHOD2 = 2 };
 typedef struct {
     const pic_particles *electrons;   /* nullable */
     const pic_particles *positrons;   /* nullable */
     const pic_particles *photons;     /* nullable */
     const pic_fields *fields;         /* E, B at the end of the step (FP32)        */
-    int32_t mode;                     /* PIC_QED_TABLE or PIC_QED_MLP               */
+    int32_t mode;                     /* PIC_QED_TABLE, PIC_QED_MLP, PIC_QED_METHOD2 */
     uint32_t step;                    /* step index: counter of the random streams  */
     double photon_min_energy;         /* m c^2 units                                */
     const void *mlp;                  /* PIC_QED_MLP: device network (layout below) */

@@ -23,9 +23,9 @@ STATUS_NAMES = ["PIC_OK", "PIC_E_ARG", "PIC_E_CFL", "PIC_E_UNSUPPORTED", "PIC_E_
                 "PIC_E_CAPACITY", "PIC_E_STATE"]
 PIC_FP32_MIXED, PIC_FP64_PLAIN = 0, 1
 PIC_BC_PERIODIC = 0
-PIC_F_NONFINITE, PIC_F_OFFSET, PIC_F_STRAGGLER, PIC_F_CAPACITY = 1, 2, 4, 8
+PIC_F_NONFINITE, PIC_F_OFFSET, PIC_F_STRAGGLER, PIC_F_CAPACITY, PIC_F_QED_SATURATED = 1, 2, 4, 8, 16
 
-PIC_QED_TABLE, PIC_QED_MLP = 0, 1
+PIC_QED_TABLE, PIC_QED_MLP, PIC_QED_METHOD2 = 0, 1, 2
 PIC_MLP_NPARAM = 4610
 PIC_MLP_BYTES = 9480
 PIC_MLP_STATE_FLOATS = 4 * PIC_MLP_NPARAM + 1

@@ -390,7 +390,8 @@ extern "C" pic_status pic_qed_step(void *ctx, const pic_qed_args *qa, void *stre
         return fail(c, PIC_E_UNSUPPORTED, "pic_qed_step works on the FP32 particle layout");
     if (!(c->cfg.hbar_omega_mc2 > 0.0) || !c->qed.dev)
         return fail(c, PIC_E_ARG, "QED needs hbar_omega_mc2 > 0 at pic_init");
-    if (qa->mode != PIC_QED_TABLE && qa->mode != PIC_QED_MLP) return fail(c, PIC_E_ARG, "bad mode");
+    if (qa->mode != PIC_QED_TABLE && qa->mode != PIC_QED_MLP && qa->mode != PIC_QED_METHOD2)
+        return fail(c, PIC_E_ARG, "bad mode");
     if (qa->mode == PIC_QED_MLP && !qa->mlp) return fail(c, PIC_E_ARG, "PIC_QED_MLP needs a network");
     pic_status st = check_fields(c, qa->fields);
     if (st != PIC_OK) return st;

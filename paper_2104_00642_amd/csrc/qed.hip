@@ -8,6 +8,11 @@
 //            photons under `photon_min_energy` are not created;
 //   photons: move ballistically, chi_gamma from the fields at their position;
 //            above 2 m c^2 decay into e+ (x eps) and e- ((1-x) eps) along k.
+// Method II (rejection, PIC_QED_METHOD2): each step the uniforms (r1, r2)
+// propose u0 = r1^3 (emission) or x0 = r1 (pairs), and the event happens
+// when the step's probability density at the proposal, W dt p(chi, r1) with
+// p the normalized spectrum in s = u^(1/3) or x, exceeds r2; tau is not used.
+// An acceptance above 1 is flagged (the step is too long for the rate).
 // Created particles are appended with an atomic counter (dropped and flagged
 // beyond capacity); their identifiers derive from the parent's, so every
 // random number depends only on (seed, identifier, step).
@@ -49,6 +54,7 @@ struct QedArgs {
     float emin;
     uint64_t seed;
     uint32_t step;
+    int method2;
     uint32_t *status;
 };
 
@@ -67,11 +73,27 @@ __device__ bool qed_append(const QedArgs &a, int s, int32_t cell, const float *o
     if (d.w) d.w[idx] = w;
     if (d.chi) d.chi[idx] = 0.0f;
     d.tau[idx] = 0.0;
-    double r0, r1;
+    double r0, r1;  // first threshold, so that the particle can enter Method I
     qed_uniforms(a.seed, id, a.step, 1u, r0, r1);
     d.tau_thr[idx] = (float)(-log(r0));
     d.id[idx] = id;
     return true;
+}
+
+// photon of energy fraction uf from lepton p (momentum u, |u|^2 = pu2):
+// collinear recoil, the photon appended above the energy threshold
+__device__ void qed_emit(const QedArgs &a, const QedSpecies &L, int64_t p, const float *u, float pu2, float gam,
+                         float uf, float w, uint64_t id) {
+    const float eps = fminf(fmaxf(uf, 0.0f), 1.0f) * gam;
+    const float pm = sqrtf(pu2);
+    if (!(pm > 0.0f)) return;
+    const float k[3] = {eps * u[0] / pm, eps * u[1] / pm, eps * u[2] / pm};
+    const float f = fmaxf(0.0f, 1.0f - eps / pm);
+    if (a.has[2] && eps >= a.emin) {
+        float off[3] = {L.off[0][p], L.off[1][p], a.dim == 3 ? L.off[2][p] : 0.0f};
+        qed_append(a, 2, L.cell[p], off, k, w, qed_child_id(a.seed, id, a.step, 1u));
+    }
+    for (int c = 0; c < 3; ++c) L.u[c][p] = u[c] * f;
 }
 
 // one thread per lepton of species s (0 electrons, 1 positrons)
@@ -81,10 +103,22 @@ __global__ void __launch_bounds__(256) qed_lepton_kernel(QedArgs a, int s) {
     if (p >= L.n) return;
     const float w = L.w ? L.w[p] : 1.0f;
     if (w == 0.0f) return;
-    float u[3] = {L.u[0][p], L.u[1][p], L.u[2][p]};
+    const float u[3] = {L.u[0][p], L.u[1][p], L.u[2][p]};
     const float chi = L.chi[p];
     const float pu2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const float gam = sqrtf(1.0f + pu2);
+    if (a.method2) {
+        if (!(chi > 0.0f)) return;
+        const uint64_t id = L.id[p];
+        double r1, r2;
+        qed_uniforms(a.seed, id, a.step, 0u, r1, r2);
+        const float F = qed_rate_F(a.tab, QED_COMPTON, chi);
+        const double acc = a.rate_scale * (double)F / (double)gam * (double)a.dt *
+                           (double)qed_density(a.tab, QED_COMPTON, chi, (float)r1);
+        if (acc > 1.0) atomicOr(a.status, PIC_F_QED_SATURATED);
+        if (acc > r2) qed_emit(a, L, p, u, pu2, gam, (float)(r1 * r1 * r1), w, id);
+        return;
+    }
     const float F = a.mlp_out ? a.mlp_out[2 * p] : qed_rate_F(a.tab, QED_COMPTON, chi);
     double tau = L.tau[p] + a.rate_scale * (double)F / (double)gam * (double)a.dt;
     if (tau >= (double)L.tau_thr[p] && chi > 0.0f) {
@@ -92,17 +126,7 @@ __global__ void __launch_bounds__(256) qed_lepton_kernel(QedArgs a, int s) {
         double ru, rt;
         qed_uniforms(a.seed, id, a.step, 0u, ru, rt);
         const float uf = a.mlp_out ? a.mlp_out[2 * p + 1] : qed_inverse(a.tab, QED_COMPTON, chi, (float)ru);
-        const float eps = fminf(fmaxf(uf, 0.0f), 1.0f) * gam;
-        const float pm = sqrtf(pu2);
-        if (pm > 0.0f) {
-            const float k[3] = {eps * u[0] / pm, eps * u[1] / pm, eps * u[2] / pm};
-            const float f = fmaxf(0.0f, 1.0f - eps / pm);
-            if (a.has[2] && eps >= a.emin) {
-                float off[3] = {L.off[0][p], L.off[1][p], a.dim == 3 ? L.off[2][p] : 0.0f};
-                qed_append(a, 2, L.cell[p], off, k, w, qed_child_id(a.seed, id, a.step, 1u));
-            }
-            for (int c = 0; c < 3; ++c) L.u[c][p] = u[c] * f;
-        }
+        qed_emit(a, L, p, u, pu2, gam, uf, w, id);
         tau = 0.0;
         L.tau_thr[p] = (float)(-log(rt));
     }
@@ -179,13 +203,29 @@ __global__ void __launch_bounds__(256) qed_photon_kernel(QedArgs a) {
     const float ke = k[0] * EB[0] + k[1] * EB[1] + k[2] * EB[2];
     const float chi = a.hbar_w * sqrtf(fmaxf(f0 * f0 + f1 * f1 + f2 * f2 - ke * ke, 0.0f));
     if (P.chi) P.chi[p] = chi;
-    const float F = a.mlp_out ? a.mlp_out[2 * p] : qed_rate_F(a.tab, QED_PAIR, chi);
-    double tau = P.tau[p] + a.rate_scale * (double)F / (double)eps * (double)a.dt;
-    if (tau >= (double)P.tau_thr[p] && eps > 2.0f && chi > 0.0f) {
-        const uint64_t id = P.id[p];
-        double rx, rn;
-        qed_uniforms(a.seed, id, a.step, 0u, rx, rn);
-        const float x = a.mlp_out ? a.mlp_out[2 * p + 1] : qed_inverse(a.tab, QED_PAIR, chi, (float)rx);
+    float x = -1.0f;  // positron fraction if the photon decays this step
+    double tau = 0.0;
+    const uint64_t id = P.id[p];
+    if (a.method2) {
+        if (eps > 2.0f && chi > 0.0f) {
+            double r1, r2;
+            qed_uniforms(a.seed, id, a.step, 0u, r1, r2);
+            const double acc = a.rate_scale * (double)qed_rate_F(a.tab, QED_PAIR, chi) / (double)eps *
+                               (double)a.dt * (double)qed_density(a.tab, QED_PAIR, chi, (float)r1);
+            if (acc > 1.0) atomicOr(a.status, PIC_F_QED_SATURATED);
+            if (acc > r2) x = (float)r1;
+        }
+    } else {
+        const float F = a.mlp_out ? a.mlp_out[2 * p] : qed_rate_F(a.tab, QED_PAIR, chi);
+        tau = P.tau[p] + a.rate_scale * (double)F / (double)eps * (double)a.dt;
+        if (tau >= (double)P.tau_thr[p] && eps > 2.0f && chi > 0.0f) {
+            double rx, rn;
+            qed_uniforms(a.seed, id, a.step, 0u, rx, rn);
+            x = a.mlp_out ? a.mlp_out[2 * p + 1] : qed_inverse(a.tab, QED_PAIR, chi, (float)rx);
+            tau = 0.0;
+        }
+    }
+    if (x >= 0.0f) {
         const float xs = fminf(fmaxf(x, 0.0f), 1.0f);
         const float ep = xs * eps, em = (1.0f - xs) * eps;
         const float np_ = sqrtf(fmaxf(ep * ep - 1.0f, 0.0f)) / eps, nm = sqrtf(fmaxf(em * em - 1.0f, 0.0f)) / eps;
@@ -194,9 +234,8 @@ __global__ void __launch_bounds__(256) qed_photon_kernel(QedArgs a) {
         if (a.has[1]) qed_append(a, 1, packed, f, up, w, qed_child_id(a.seed, id, a.step, 2u));
         if (a.has[0]) qed_append(a, 0, packed, f, um, w, qed_child_id(a.seed, id, a.step, 3u));
         if (P.w) P.w[p] = 0.0f;  // the photon is gone
-        tau = 0.0;
     }
-    P.tau[p] = tau;
+    if (!a.method2) P.tau[p] = tau;
 }
 
 hipError_t launch_mlp_for_qed(Ctx *c, const void *mlp, const QedSpeciesView &v, int proc, float *out,
@@ -246,6 +285,7 @@ hipError_t launch_qed(Ctx *c, const pic_qed_args *qa, hipStream_t s) {
     a.emin = (float)qa->photon_min_energy;
     a.seed = cfg.seed;
     a.step = qa->step;
+    a.method2 = qa->mode == PIC_QED_METHOD2;
     a.status = c->status;
     // photons first (their pairs are created from this step's photons only),
     // then the leptons that existed at the start of the step

@@ -19,7 +19,15 @@ constexpr int QED_OFF_RATE_C = 0;
 constexpr int QED_OFF_RATE_P = QED_NCHI;
 constexpr int QED_OFF_INV_C = 2 * QED_NCHI;
 constexpr int QED_OFF_INV_P = 2 * QED_NCHI + QED_NCHI * QED_NR;
-constexpr int QED_TABLE_FLOATS = 2 * QED_NCHI + 2 * QED_NCHI * QED_NR;
+// Method II: the normalized differential spectrum p(chi, sigma) (density of
+// s = u^(1/3) for emission, of x for pairs; integral over sigma in [0,1] is 1)
+// at sigma = (1 - cos(pi v))/2, v uniform: nodes cluster at both ends, where
+// the spectra have their narrow features (the hard cut-off next to u = 1 at
+// large chi, the soft peak next to s = 0 at small chi)
+constexpr int QED_NS = 1025;
+constexpr int QED_OFF_DEN_C = 2 * QED_NCHI + 2 * QED_NCHI * QED_NR;
+constexpr int QED_OFF_DEN_P = QED_OFF_DEN_C + QED_NCHI * QED_NS;
+constexpr int QED_TABLE_FLOATS = QED_OFF_DEN_P + QED_NCHI * QED_NS;
 
 struct QedTables {
     float *dev = nullptr;
@@ -102,6 +110,25 @@ __device__ inline float qed_inverse(const float *tab, int proc, float chi, float
     const float b = T[(i + 1) * QED_NR + k] * (1.0f - ty) + T[(i + 1) * QED_NR + k + 1] * ty;
     const float v = a * (1.0f - tx) + b * tx;
     return proc == QED_COMPTON ? v * v * v : v;
+}
+
+// Method II density p(chi, sigma), bilinear in (log10 chi, v) with
+// v = acos(1 - 2 sigma)/pi; chi clamped to the table (outside it the shape of
+// the nearest tabulated chi, as the inverse spectra do).
+__device__ inline float qed_density(const float *tab, int proc, float chi, float sig) {
+    const float lmin = qed_log_chi_min(proc), lmax = (float)QED_LOG_CHI_MAX;
+    float x = (log10f(fmaxf(chi, 1e-30f)) - lmin) / (lmax - lmin) * (QED_NCHI - 1);
+    x = fminf(fmaxf(x, 0.0f), (float)(QED_NCHI - 1) - 1e-3f);
+    const int i = (int)x;
+    const float tx = x - i;
+    float y = acosf(fminf(fmaxf(1.0f - 2.0f * sig, -1.0f), 1.0f)) * 0.318309886183790672f * (QED_NS - 1);
+    y = fminf(fmaxf(y, 0.0f), (float)(QED_NS - 1) - 1e-3f);
+    const int k = (int)y;
+    const float ty = y - k;
+    const float *T = tab + (proc == QED_COMPTON ? QED_OFF_DEN_C : QED_OFF_DEN_P);
+    const float a = T[i * QED_NS + k] * (1.0f - ty) + T[i * QED_NS + k + 1] * ty;
+    const float b = T[(i + 1) * QED_NS + k] * (1.0f - ty) + T[(i + 1) * QED_NS + k + 1] * ty;
+    return a * (1.0f - tx) + b * tx;
 }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).

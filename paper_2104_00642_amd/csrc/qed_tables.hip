@@ -10,7 +10,8 @@
 // rule in t).  The energy fraction is reached through the smoothstep
 // u = 10v^3 - 15v^4 + 6v^5, which removes the u^(-2/3) behaviour at u -> 0 and
 // the (1-u)^(-1/3) tail at u -> 1; cumulative integrals use the midpoint
-// rule on a fine uniform grid in v.
+// rule on a fine uniform grid in v.  Method II reads the normalized
+// differential spectra at (chi, sigma) nodes.
 #include "device_common.h"
 #include "pic_internal.h"
 #include "qed_internal.h"
@@ -114,6 +115,26 @@ __global__ void qed_logrates_kernel(int proc, const double *chis, const double *
     g[i] = (float)(proc == QED_COMPTON ? log(F / chi) : log(F) + 8.0 / (3.0 * chi));
 }
 
+// Method II densities at the (chi_i, sigma_k) nodes: 3 s^2 bracket_c(s^3) / F
+// in s for emission (finite as s -> 0; the node s = 0 takes s = 1e-6, where
+// the next term of the expansion is 1e-12 of the limit), bracket_p(x) / F in x
+// for pairs
+__global__ void qed_density_kernel(int proc, const double *chis, const double *total, int nchi,
+                                   float *table) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nchi * QED_NS) return;
+    const int i = e / QED_NS, k = e % QED_NS;
+    const double sig = 0.5 * (1.0 - cos(3.14159265358979323846 * k / (QED_NS - 1)));
+    double v;
+    if (proc == QED_COMPTON) {
+        const double s = fmax(sig, 1e-6);
+        v = 3.0 * s * s * bracket(proc, s * s * s, chis[i]);
+    } else {
+        v = bracket(proc, sig, chis[i]);
+    }
+    table[e] = total[i] > 0.0 ? (float)(v / total[i]) : 0.0f;
+}
+
 __global__ void qed_chigrid_kernel(double lo, double hi, int n, double *chis) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) chis[i] = exp10(lo + (hi - lo) * i / (n - 1));
@@ -135,6 +156,8 @@ hipError_t build_qed_tables(QedTables *t, hipStream_t s) {
         float *inv = t->dev + (proc == QED_COMPTON ? QED_OFF_INV_C : QED_OFF_INV_P);
         qed_logrates_kernel<<<1, QED_NCHI, 0, s>>>(proc, chis, total, QED_NCHI, rate);
         qed_invert_kernel<<<(QED_NCHI * QED_NR + 255) / 256, 256, 0, s>>>(proc, f, total, QED_NCHI, inv);
+        float *den = t->dev + (proc == QED_COMPTON ? QED_OFF_DEN_C : QED_OFF_DEN_P);
+        qed_density_kernel<<<(QED_NCHI * QED_NS + 255) / 256, 256, 0, s>>>(proc, chis, total, QED_NCHI, den);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -236,6 +236,183 @@ def test_creation_capacity_is_enforced():
     assert el.u[0].cpu().numpy()[:n].mean() < 2000.0
 
 
+# ---------------------------------------------------------------- Method II
+
+def gamma_for(chi, target, dt):
+    """Lorentz factor (or photon energy) at which W dt = target."""
+    return Q.A_CONST / HBAR_W * O.frad(chi) * dt / target
+
+
+def test_method2_events_match_oracle():
+    """Method II with the same Philox streams: the same leptons emit, with
+    photon energy r1^3 gamma and collinear recoil, except where the oracle's
+    exact acceptance lies within the density table's error of r2; tau and
+    its threshold are left alone."""
+    cfg = qed_cfg()
+    ctx = L.pic_init(cfg)
+    bits, _, _ = L.pic_get_layout(ctx)
+    dt = float(np.float32(cfg.dt))
+    n = 3000
+    rng = np.random.default_rng(21)
+    chi = rng.choice([0.02, 0.49, 4.9, 49.0], n).astype(np.float32)
+    # W dt between 0.09 and 0.21: below 1 / (peak spectral density) for every chi
+    gam = np.array([gamma_for(float(c), 0.15, dt) for c in chi]) * rng.uniform(0.7, 1.3, n)
+    ux = np.sqrt(gam ** 2 - 1).astype(np.float32)
+    thr = np.full(n, 0.75, dtype=np.float32)
+    el = species(n, n, bits, ux, chi, thr)
+    el.tau[:n] = 0.5
+    ph = species(0, n, bits, [], None, None)
+    run_qed(ctx, cfg, fields(cfg), mode=L.PIC_QED_METHOD2, step=3, electrons=el, photons=ph)
+    st, flags, _ = L.pic_check(ctx)
+    assert st == L.PIC_OK and not flags & L.PIC_F_QED_SATURATED
+    assert np.all(el.tau.cpu().numpy()[:n] == 0.5) and np.all(el.tau_thr.cpu().numpy()[:n] == 0.75)
+    L_o = dict(u=[list(np.float64(ux)), [0.0] * n, [0.0] * n], chi=list(np.float64(chi)), tau=[0.5] * n,
+               tau_thr=[0.75] * n, id=list(range(1, n + 1)), w=[1.0] * n, pos=list(range(n)))
+    out = []
+    assert not Q.lepton_step_method2(L_o, SEED, 3, dt, HBAR_W, 0.0, out)
+    # exact acceptance and r2 of every lepton, for the near-threshold set
+    near = np.zeros(n, dtype=bool)
+    for p in range(n):
+        r1, r2 = O.qed_uniforms(SEED, p + 1, 3, 0)
+        g = math.sqrt(1.0 + float(ux[p]) ** 2)
+        acc = Q.emission_acceptance(float(chi[p]), g, r1, dt, HBAR_W)
+        near[p] = abs(acc - r2) <= 1e-2 * acc + 1e-7
+    child = {Q.child_id(SEED, p + 1, 3, 1): p for p in range(n)}
+    nph = int(ph.n_dev.item())
+    fired_g = np.zeros(n, dtype=bool)
+    for i in ph.id.cpu().numpy()[:nph]:
+        fired_g[child[int(i) & 0xFFFFFFFFFFFFFFFF]] = True
+    fired_o = np.zeros(n, dtype=bool)
+    for o in out:
+        fired_o[o["pos"]] = True
+    print(f"Method II: {fired_o.sum()} of {n} emit; {near.sum()} near the threshold; "
+          f"{(fired_g != fired_o).sum()} differ")
+    assert np.array_equal(fired_g[~near], fired_o[~near])
+    assert fired_o.sum() > 300 and (~fired_o).sum() > 300
+    both = fired_g & fired_o
+    ux_g = el.u[0].cpu().numpy()[:n].astype(np.float64)
+    assert np.allclose(ux_g[both], np.array(L_o["u"][0])[both], rtol=2e-5, atol=0.5)
+    assert np.array_equal(ux_g[~fired_g], np.float64(ux)[~fired_g])
+    eps_g = {int(i) & 0xFFFFFFFFFFFFFFFF: float(k) for i, k in zip(ph.id.cpu().numpy()[:nph], ph.u[0].cpu().numpy()[:nph])}
+    for o in out:
+        if o["id"] in eps_g:
+            assert eps_g[o["id"]] == pytest.approx(o["k"][0], rel=2e-5)
+
+
+def test_method2_pair_events_match_oracle():
+    """Method II pair creation photon by photon: chi_gamma from the oracle's
+    own formula at the photon, the same Philox streams, the same decays and
+    pair energies x0 eps, r1 = x0, except within the table's error of r2."""
+    cfg = qed_cfg()
+    ctx = L.pic_init(cfg)
+    bits, _, _ = L.pic_get_layout(ctx)
+    dt = float(np.float32(cfg.dt))
+    n = 3000
+    rng = np.random.default_rng(23)
+    eps = rng.uniform(200.0, 1500.0, n).astype(np.float32)
+    bz = np.float32(4.9 / (HBAR_W * 1000.0))
+    ph = species(n, n, bits, eps, None, np.zeros(n, dtype=np.float32), ids=np.arange(100, 100 + n))
+    el = species(0, n, bits, [])
+    po = species(0, n, bits, [])
+    run_qed(ctx, cfg, fields(cfg, float(bz)), mode=L.PIC_QED_METHOD2, step=5, electrons=el, positrons=po,
+            photons=ph)
+    chi_o = [O.chi(HBAR_W, float(e), [float(e), 0.0, 0.0], [0.0, 0.0, 0.0], [0.0, 0.0, float(bz)]) for e in eps]
+    P_o = dict(k=[list(np.float64(eps)), [0.0] * n, [0.0] * n], chi=chi_o, tau=[0.0] * n, tau_thr=[0.0] * n,
+               id=list(range(100, 100 + n)), w=[1.0] * n, pos=list(range(n)))
+    pos_o, ele_o = [], []
+    assert not Q.photon_decay_method2(P_o, SEED, 5, dt, HBAR_W, pos_o, ele_o)
+    near = np.zeros(n, dtype=bool)
+    for p in range(n):
+        r1, r2 = O.qed_uniforms(SEED, 100 + p, 5, 0)
+        acc = Q.pair_acceptance(chi_o[p], float(eps[p]), r1, dt, HBAR_W)
+        near[p] = abs(acc - r2) <= 1e-2 * acc + 1e-7
+    gone_g = ph.w.cpu().numpy()[:n] == 0.0
+    gone_o = np.array(P_o["w"]) == 0.0
+    print(f"Method II pairs: {gone_o.sum()} of {n} decay; {near.sum()} near the threshold; "
+          f"{(gone_g != gone_o).sum()} differ")
+    assert np.array_equal(gone_g[~near], gone_o[~near])
+    assert gone_o.sum() > 100 and (~gone_o).sum() > 100
+    npos = int(po.n_dev.item())
+    e_g = {int(i) & 0xFFFFFFFFFFFFFFFF: float(u) for i, u in zip(po.id.cpu().numpy()[:npos], po.u[0].cpu().numpy()[:npos])}
+    matched = 0
+    for o in pos_o:
+        if o["id"] in e_g:
+            assert e_g[o["id"]] == pytest.approx(o["u"][0], rel=2e-5, abs=1e-3)
+            matched += 1
+    assert matched >= len(pos_o) - int(near.sum())
+
+
+@pytest.mark.parametrize("chi", [0.49, 4.9, 49.0])
+def test_method2_photon_count_and_spectrum(chi):
+    """Fig. 8(a-c) spectra by Method II: one step with W dt = 0.25 emits in a
+    quarter of the leptons (binomial, 4 sigma) and the photon energy fractions
+    r1^3 of the accepted proposals follow Eq. 23."""
+    cfg = qed_cfg()
+    ctx = L.pic_init(cfg)
+    bits, _, _ = L.pic_get_layout(ctx)
+    dt = float(np.float32(cfg.dt))
+    n = 200000
+    gam = np.float32(gamma_for(chi, 0.25, dt))
+    ux = np.full(n, math.sqrt(float(gam) ** 2 - 1), dtype=np.float32)
+    el = species(n, n, bits, ux, np.full(n, chi, dtype=np.float32), np.zeros(n, dtype=np.float32))
+    ph = species(0, n, bits, [])
+    run_qed(ctx, cfg, fields(cfg), mode=L.PIC_QED_METHOD2, electrons=el, photons=ph)
+    nph = int(ph.n_dev.item())
+    p = Q.A_CONST / HBAR_W * O.frad(chi) / math.sqrt(1.0 + float(ux[0]) ** 2) * dt
+    assert abs(nph - n * p) < 4 * math.sqrt(n * p * (1 - p)), (nph, n * p)
+    u = ph.u[0].cpu().numpy()[:nph].astype(np.float64) / math.sqrt(1.0 + float(ux[0]) ** 2)
+    grid = np.linspace(0.0, 1.0, 401)[1:-1] ** 3
+    cdf = np.array([O.compton_cum(chi, g) for g in grid]) / O.frad(chi)
+    ks = empirical_ks(u, grid, cdf)
+    print(f"Method II photon spectrum chi={chi}: {nph} photons (expected {n * p:.0f}), KS {ks:.4f}")
+    assert ks < 0.012
+
+
+@pytest.mark.parametrize("chi", [4.9, 49.0])
+def test_method2_pair_count_and_spectrum(chi):
+    """Fig. 8(d-f) by Method II: photons with W_pair dt = 0.25 in a uniform
+    magnetic field decay in a quarter of the cases, positron fractions x0 = r1
+    of the accepted proposals follow Eq. 24."""
+    cfg = qed_cfg()
+    ctx = L.pic_init(cfg)
+    bits, _, _ = L.pic_get_layout(ctx)
+    dt = float(np.float32(cfg.dt))
+    n = 200000
+    eps = float(np.float32(Q.A_CONST / HBAR_W * O.fpair(chi) * dt / 0.25))
+    bz = chi / (HBAR_W * eps)
+    ph = species(n, n, bits, np.full(n, eps, dtype=np.float32), None, np.zeros(n, dtype=np.float32))
+    el = species(0, n, bits, [])
+    po = species(0, n, bits, [])
+    run_qed(ctx, cfg, fields(cfg, bz), mode=L.PIC_QED_METHOD2, electrons=el, positrons=po, photons=ph)
+    npair = int(po.n_dev.item())
+    assert int(el.n_dev.item()) == npair
+    assert int((ph.w.cpu().numpy()[:n] == 0.0).sum()) == npair
+    p = Q.A_CONST / HBAR_W * O.fpair(chi) / eps * dt
+    assert abs(npair - n * p) < 4 * math.sqrt(n * p * (1 - p)), (npair, n * p)
+    up = po.u[0].cpu().numpy()[:npair].astype(np.float64)
+    x = np.sqrt(1 + up ** 2) / eps
+    grid = np.linspace(0.0, 1.0, 201)[1:-1]
+    cdf = np.array([O.pair_cum(chi, g) for g in grid]) / O.fpair(chi)
+    ks = empirical_ks(x, grid, cdf)
+    print(f"Method II positron spectrum chi={chi}: {npair} pairs (expected {n * p:.0f}), KS {ks:.4f}")
+    assert ks < 0.012
+
+
+def test_method2_flags_saturation():
+    """A step far longer than 1/W: acceptances above 1 set the flag."""
+    cfg = qed_cfg()
+    ctx = L.pic_init(cfg)
+    bits, _, _ = L.pic_get_layout(ctx)
+    n = 256
+    gam = gamma_for(4.9, 8.0, float(np.float32(cfg.dt)))
+    el = species(n, n, bits, np.full(n, math.sqrt(gam ** 2 - 1), dtype=np.float32),
+                 np.full(n, 4.9, dtype=np.float32), np.zeros(n, dtype=np.float32))
+    ph = species(0, n, bits, [])
+    run_qed(ctx, cfg, fields(cfg), mode=L.PIC_QED_METHOD2, electrons=el, photons=ph)
+    st, flags, _ = L.pic_check(ctx)
+    assert st == L.PIC_OK and flags & L.PIC_F_QED_SATURATED
+
+
 # ---------------------------------------------------------------- network
 
 def bf16(a):

@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--scale", type=int, default=1, help="divide the grid (tests only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
-    ap.add_argument("--no-mlp", action="store_true", help="skip the QED surrogate inference measurement")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the QED step and surrogate inference measurements")
     ap.add_argument("--fp64-order", choices=["lex", "cell"], default="lex",
                     help="particle order of the plain FP64 path (see fp64_order)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -173,6 +173,64 @@ def mlp_measure(torch, L, n=1 << 24, reps=5):
             "useful_frac_bf16_peak": useful / BF16_PEAK_TFLOPS,
             "mfma_tflops_executed": n * MLP_MFMA_FLOP_PER_SAMPLE / t_net / 1e12,
             "note": "hi+lo BF16 activations double the MFMA work of layers 2-3; N=2 is padded to 16"}
+
+
+def qed_measure(torch, L, n=1 << 24, reps=5):
+    """One QED step of n leptons resident in HBM by Method I (optical depth,
+    tables) and Method II (rejection).  gamma = 2e4 and chi log-uniform over
+    [0.1, 10] put W dt at 0.2-4% per step (a cascade's regime); photons above
+    2 m c^2 are appended.  Streamed bytes per lepton: u, chi, w, id (28 B),
+    plus tau read and written and tau_thr read (20 B) for Method I."""
+    d = (0.2, 0.2)
+    dt = 0.95 / math.sqrt(sum(1.0 / v ** 2 for v in d))
+    cfg = L.Config(dim=2, n=(64, 64), d=d, dt=dt, hbar_omega_mc2=2.4263e-6, seed=12)
+    ctx = L.pic_init(cfg)
+    dev = "cuda"
+    gen = torch.Generator(device=dev).manual_seed(12)
+    f = L.Fields.zeros(cfg, dev, torch.float32)
+
+    def leptons():
+        u0 = math.sqrt(2e4 ** 2 - 1)
+        return L.Particles(n, [torch.full((n,), u0, device=dev), torch.zeros(n, device=dev),
+                               torch.zeros(n, device=dev)],
+                           cell=torch.zeros(n, dtype=torch.int32, device=dev),
+                           off=[torch.full((n,), 0.5, device=dev) for _ in range(2)],
+                           w=torch.ones(n, device=dev),
+                           chi=0.1 * torch.exp(torch.rand(n, generator=gen, device=dev) * math.log(100.0)),
+                           tau=torch.zeros(n, dtype=torch.float64, device=dev),
+                           tau_thr=-torch.log(torch.rand(n, generator=gen, device=dev).clamp_min(1e-12)),
+                           id=torch.arange(1, n + 1, dtype=torch.int64, device=dev), capacity=n,
+                           n_dev=torch.tensor([n], dtype=torch.int64, device=dev))
+
+    def photons():
+        return L.Particles(0, [torch.zeros(n, device=dev) for _ in range(3)],
+                           cell=torch.zeros(n, dtype=torch.int32, device=dev),
+                           off=[torch.zeros(n, device=dev) for _ in range(2)], w=torch.zeros(n, device=dev),
+                           chi=torch.zeros(n, device=dev), tau=torch.zeros(n, dtype=torch.float64, device=dev),
+                           tau_thr=torch.zeros(n, device=dev), id=torch.zeros(n, dtype=torch.int64, device=dev),
+                           capacity=n, n_dev=torch.zeros(1, dtype=torch.int64, device=dev))
+
+    out = {"leptons": n}
+    for name, mode, nbytes in (("method1", L.PIC_QED_TABLE, 48), ("method2", L.PIC_QED_METHOD2, 28)):
+        el, ph = leptons(), photons()
+        best, events = float("inf"), 0
+        for it in range(reps + 1):
+            ph.n_dev.zero_()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            L.pic_qed_step(ctx, f, electrons=el, photons=ph, mode=mode, step=it)
+            b.record()
+            torch.cuda.synchronize()
+            if it > 0:
+                best = min(best, a.elapsed_time(b) * 1e-3)
+                events = int(ph.n_dev.item())
+        out[name] = {"leptons_per_s": n / best, "ms": best * 1e3, "photons_per_step": events,
+                     "streamed_gbs": n * nbytes / best / 1e9}
+        del el, ph
+    L.pic_check(ctx)
+    L.pic_destroy(ctx)
+    return out
 
 
 def run_path(args, wl, precision, torch, L, Simulation):
@@ -397,6 +455,8 @@ def main():
     if not args.no_mlp:
         log("surrogate inference")
         line["mlp_inference"] = mlp_measure(torch, L)
+        log("QED step")
+        line["qed_step"] = qed_measure(torch, L)
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)

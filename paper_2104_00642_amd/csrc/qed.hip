@@ -58,15 +58,54 @@ struct QedArgs {
     uint32_t *status;
 };
 
-__device__ bool qed_append(const QedArgs &a, int s, int32_t cell, const float *off, const float *u, float w,
-                           uint64_t id) {
-    const QedSpecies &d = a.sp[s];
-    const unsigned long long idx = atomicAdd(d.n_dev, 1ull);
-    if ((int64_t)idx >= d.capacity) {
-        atomicOr(a.status, PIC_F_CAPACITY);
-        atomicAdd(d.n_dev, ~0ull);  // undo: the slot does not exist
-        return false;
+// one particle per thread; large workgroups make fewer reservations on the
+// shared append counters (photons: 512, which leaves the 3D quartic gather
+// its registers)
+constexpr int QED_THREADS = 1024;
+constexpr int QED_PHOTON_THREADS = 512;
+
+// Slots for the particles a workgroup appends to species counter `counter`:
+// every thread of the group calls this (uniform control flow) with want =
+// whether it appends one particle; ranks come from a ballot per wavefront,
+// one LDS atomic per wavefront and one global atomic per workgroup, so the
+// shared counter is not serialized per particle.  Slots at or beyond `cap`
+// are dropped: the counter is brought back to cap and PIC_F_CAPACITY set.
+// Returns the slot, or -1.
+__device__ int64_t group_reserve(bool want, unsigned long long *counter, int64_t cap, uint32_t *status) {
+    __shared__ unsigned s_cnt;
+    __shared__ unsigned long long s_base;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    const unsigned long long mask = __ballot(want);
+    const int lane = threadIdx.x & 63;
+    const int leader = mask ? __ffsll(mask) - 1 : 0;
+    unsigned wbase = 0;
+    if (mask && lane == leader) wbase = atomicAdd(&s_cnt, (unsigned)__popcll(mask));
+    wbase = __shfl(wbase, leader);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned cnt = s_cnt;
+        unsigned long long base = 0;
+        if (cnt) {
+            base = atomicAdd(counter, (unsigned long long)cnt);
+            const unsigned long long end = base + cnt, c = (unsigned long long)cap;
+            if (end > c) {
+                atomicAdd(counter, 0ull - (end - (base > c ? base : c)));
+                atomicOr(status, PIC_F_CAPACITY);
+            }
+        }
+        s_base = base;
     }
+    __syncthreads();
+    if (!want) return -1;
+    const int64_t slot = (int64_t)(s_base + wbase + __popcll(mask & ((1ull << lane) - 1)));
+    return slot < cap ? slot : -1;
+}
+
+// a created particle at slot idx of species s
+__device__ void qed_write(const QedArgs &a, int s, int64_t idx, int32_t cell, const float *off, const float *u,
+                          float w, uint64_t id) {
+    const QedSpecies &d = a.sp[s];
     d.cell[idx] = cell;
     for (int k = 0; k < a.dim; ++k) d.off[k][idx] = off[k];
     for (int k = 0; k < 3; ++k) d.u[k][idx] = u[k];
@@ -77,84 +116,101 @@ __device__ bool qed_append(const QedArgs &a, int s, int32_t cell, const float *o
     qed_uniforms(a.seed, id, a.step, 1u, r0, r1);
     d.tau_thr[idx] = (float)(-log(r0));
     d.id[idx] = id;
-    return true;
 }
 
-// photon of energy fraction uf from lepton p (momentum u, |u|^2 = pu2):
-// collinear recoil, the photon appended above the energy threshold
-__device__ void qed_emit(const QedArgs &a, const QedSpecies &L, int64_t p, const float *u, float pu2, float gam,
-                         float uf, float w, uint64_t id) {
-    const float eps = fminf(fmaxf(uf, 0.0f), 1.0f) * gam;
-    const float pm = sqrtf(pu2);
-    if (!(pm > 0.0f)) return;
-    const float k[3] = {eps * u[0] / pm, eps * u[1] / pm, eps * u[2] / pm};
-    const float f = fmaxf(0.0f, 1.0f - eps / pm);
-    if (a.has[2] && eps >= a.emin) {
-        float off[3] = {L.off[0][p], L.off[1][p], a.dim == 3 ? L.off[2][p] : 0.0f};
-        qed_append(a, 2, L.cell[p], off, k, w, qed_child_id(a.seed, id, a.step, 1u));
-    }
-    for (int c = 0; c < 3; ++c) L.u[c][p] = u[c] * f;
-}
-
-// one thread per lepton of species s (0 electrons, 1 positrons)
-__global__ void __launch_bounds__(256) qed_lepton_kernel(QedArgs a, int s) {
+// one thread per lepton of species s (0 electrons, 1 positrons); the photon
+// of an event has energy fraction uf along u and the lepton recoils
+// collinearly
+__global__ void __launch_bounds__(QED_THREADS) qed_lepton_kernel(QedArgs a, int s) {
     const QedSpecies &L = a.sp[s];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= L.n) return;
-    const float w = L.w ? L.w[p] : 1.0f;
-    if (w == 0.0f) return;
-    const float u[3] = {L.u[0][p], L.u[1][p], L.u[2][p]};
-    const float chi = L.chi[p];
-    const float pu2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const float gam = sqrtf(1.0f + pu2);
-    if (a.method2) {
-        if (!(chi > 0.0f)) return;
-        const uint64_t id = L.id[p];
-        double r1, r2;
-        qed_uniforms(a.seed, id, a.step, 0u, r1, r2);
-        const float F = qed_rate_F(a.tab, QED_COMPTON, chi);
-        const double acc = a.rate_scale * (double)F / (double)gam * (double)a.dt *
-                           (double)qed_density(a.tab, QED_COMPTON, chi, (float)r1);
-        if (acc > 1.0) atomicOr(a.status, PIC_F_QED_SATURATED);
-        if (acc > r2) qed_emit(a, L, p, u, pu2, gam, (float)(r1 * r1 * r1), w, id);
-        return;
+    bool fire = false;
+    float u[3] = {0.0f, 0.0f, 0.0f}, pu2 = 0.0f, gam = 1.0f, uf = 0.0f, w = 0.0f;
+    uint64_t id = 0;
+    if (p < L.n) {
+        w = L.w ? L.w[p] : 1.0f;
+        if (w != 0.0f) {
+            u[0] = L.u[0][p];
+            u[1] = L.u[1][p];
+            u[2] = L.u[2][p];
+            const float chi = L.chi[p];
+            pu2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            gam = sqrtf(1.0f + pu2);
+            if (a.method2) {
+                if (chi > 0.0f) {
+                    id = L.id[p];
+                    double r1, r2;
+                    qed_uniforms(a.seed, id, a.step, 0u, r1, r2);
+                    const float F = qed_rate_F(a.tab, QED_COMPTON, chi);
+                    const double acc = a.rate_scale * (double)F / (double)gam * (double)a.dt *
+                                       (double)qed_density(a.tab, QED_COMPTON, chi, (float)r1);
+                    if (acc > 1.0) atomicOr(a.status, PIC_F_QED_SATURATED);
+                    fire = acc > r2;
+                    uf = (float)(r1 * r1 * r1);
+                }
+            } else {
+                const float F = a.mlp_out ? a.mlp_out[2 * p] : qed_rate_F(a.tab, QED_COMPTON, chi);
+                double tau = L.tau[p] + a.rate_scale * (double)F / (double)gam * (double)a.dt;
+                if (tau >= (double)L.tau_thr[p] && chi > 0.0f) {
+                    id = L.id[p];
+                    double ru, rt;
+                    qed_uniforms(a.seed, id, a.step, 0u, ru, rt);
+                    uf = a.mlp_out ? a.mlp_out[2 * p + 1] : qed_inverse(a.tab, QED_COMPTON, chi, (float)ru);
+                    fire = true;
+                    tau = 0.0;
+                    L.tau_thr[p] = (float)(-log(rt));
+                }
+                L.tau[p] = tau;
+            }
+        }
     }
-    const float F = a.mlp_out ? a.mlp_out[2 * p] : qed_rate_F(a.tab, QED_COMPTON, chi);
-    double tau = L.tau[p] + a.rate_scale * (double)F / (double)gam * (double)a.dt;
-    if (tau >= (double)L.tau_thr[p] && chi > 0.0f) {
-        const uint64_t id = L.id[p];
-        double ru, rt;
-        qed_uniforms(a.seed, id, a.step, 0u, ru, rt);
-        const float uf = a.mlp_out ? a.mlp_out[2 * p + 1] : qed_inverse(a.tab, QED_COMPTON, chi, (float)ru);
-        qed_emit(a, L, p, u, pu2, gam, uf, w, id);
-        tau = 0.0;
-        L.tau_thr[p] = (float)(-log(rt));
+    const float pm = sqrtf(pu2);
+    fire = fire && pm > 0.0f;
+    const float eps = fminf(fmaxf(uf, 0.0f), 1.0f) * gam;
+    const float k[3] = {eps * u[0] / pm, eps * u[1] / pm, eps * u[2] / pm};
+    if (fire) {
+        const float f = fmaxf(0.0f, 1.0f - eps / pm);
+        for (int c = 0; c < 3; ++c) L.u[c][p] = u[c] * f;
     }
-    L.tau[p] = tau;
+    if (a.has[2]) {  // uniform over the grid
+        const int64_t slot = group_reserve(fire && eps >= a.emin, a.sp[2].n_dev, a.sp[2].capacity, a.status);
+        if (slot >= 0) {
+            const float off[3] = {L.off[0][p], L.off[1][p], a.dim == 3 ? L.off[2][p] : 0.0f};
+            qed_write(a, 2, slot, L.cell[p], off, k, w, qed_child_id(a.seed, id, a.step, 1u));
+        }
+    }
 }
 
 // photons: ballistic move, chi_gamma at the new position, pair creation
 template <int DIM, int ORDER>
-__global__ void __launch_bounds__(256) qed_photon_kernel(QedArgs a) {
+__global__ void __launch_bounds__(QED_PHOTON_THREADS) qed_photon_kernel(QedArgs a) {
     const QedSpecies &P = a.sp[2];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P.n) return;
-    const float w = P.w ? P.w[p] : 1.0f;
-    if (w == 0.0f) return;
-    const float k[3] = {P.u[0][p], P.u[1][p], P.u[2][p]};
-    const float eps = sqrtf(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
-    if (!(eps > 0.0f)) return;
+    float x = -1.0f;  // positron fraction if the photon decays this step
+    float w = 0.0f, eps = 1.0f, k[3] = {0.0f, 0.0f, 0.0f}, f[3] = {0.0f, 0.0f, 0.0f};
+    int packed = 0;
+    uint64_t id = 0;
+    do {  // every thread reaches the appends below
+    if (p >= P.n) break;
+    w = P.w ? P.w[p] : 1.0f;
+    if (w == 0.0f) break;
+    k[0] = P.u[0][p];
+    k[1] = P.u[1][p];
+    k[2] = P.u[2][p];
+    eps = sqrtf(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    if (!(eps > 0.0f)) break;
     const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
     const int32_t cell = P.cell[p];
     int cc[3] = {cell & mx, (cell >> a.bx) & my, DIM == 3 ? (cell >> (a.bx + a.by)) : 0};
-    float f[3] = {P.off[0][p], P.off[1][p], DIM == 3 ? P.off[2][p] : 0.0f};
+    f[0] = P.off[0][p];
+    f[1] = P.off[1][p];
+    f[2] = DIM == 3 ? P.off[2][p] : 0.0f;
     // move at c along k
-    int packed = 0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        const float x = f[d] + a.dt * a.inv_d[d] * k[d] / eps;
-        const float fl = floorf(x);
-        float fr = x - fl;
+        const float xn = f[d] + a.dt * a.inv_d[d] * k[d] / eps;
+        const float fl = floorf(xn);
+        float fr = xn - fl;
         int di = (int)fl;
         if (fr >= 1.0f) {
             fr = 0.0f;
@@ -203,9 +259,8 @@ __global__ void __launch_bounds__(256) qed_photon_kernel(QedArgs a) {
     const float ke = k[0] * EB[0] + k[1] * EB[1] + k[2] * EB[2];
     const float chi = a.hbar_w * sqrtf(fmaxf(f0 * f0 + f1 * f1 + f2 * f2 - ke * ke, 0.0f));
     if (P.chi) P.chi[p] = chi;
-    float x = -1.0f;  // positron fraction if the photon decays this step
     double tau = 0.0;
-    const uint64_t id = P.id[p];
+    id = P.id[p];
     if (a.method2) {
         if (eps > 2.0f && chi > 0.0f) {
             double r1, r2;
@@ -225,17 +280,23 @@ __global__ void __launch_bounds__(256) qed_photon_kernel(QedArgs a) {
             tau = 0.0;
         }
     }
-    if (x >= 0.0f) {
-        const float xs = fminf(fmaxf(x, 0.0f), 1.0f);
-        const float ep = xs * eps, em = (1.0f - xs) * eps;
-        const float np_ = sqrtf(fmaxf(ep * ep - 1.0f, 0.0f)) / eps, nm = sqrtf(fmaxf(em * em - 1.0f, 0.0f)) / eps;
-        const float up[3] = {np_ * k[0], np_ * k[1], np_ * k[2]};
-        const float um[3] = {nm * k[0], nm * k[1], nm * k[2]};
-        if (a.has[1]) qed_append(a, 1, packed, f, up, w, qed_child_id(a.seed, id, a.step, 2u));
-        if (a.has[0]) qed_append(a, 0, packed, f, um, w, qed_child_id(a.seed, id, a.step, 3u));
-        if (P.w) P.w[p] = 0.0f;  // the photon is gone
-    }
+    if (x >= 0.0f && P.w) P.w[p] = 0.0f;  // the photon is gone
     if (!a.method2) P.tau[p] = tau;
+    } while (false);
+    const bool decay = x >= 0.0f;
+    const float xs = fminf(fmaxf(x, 0.0f), 1.0f);
+    const float ep = xs * eps, em = (1.0f - xs) * eps;
+    const float np_ = sqrtf(fmaxf(ep * ep - 1.0f, 0.0f)) / eps, nm = sqrtf(fmaxf(em * em - 1.0f, 0.0f)) / eps;
+    if (a.has[1]) {  // uniform over the grid
+        const int64_t slot = group_reserve(decay, a.sp[1].n_dev, a.sp[1].capacity, a.status);
+        const float up[3] = {np_ * k[0], np_ * k[1], np_ * k[2]};
+        if (slot >= 0) qed_write(a, 1, slot, packed, f, up, w, qed_child_id(a.seed, id, a.step, 2u));
+    }
+    if (a.has[0]) {
+        const int64_t slot = group_reserve(decay, a.sp[0].n_dev, a.sp[0].capacity, a.status);
+        const float um[3] = {nm * k[0], nm * k[1], nm * k[2]};
+        if (slot >= 0) qed_write(a, 0, slot, packed, f, um, w, qed_child_id(a.seed, id, a.step, 3u));
+    }
 }
 
 hipError_t launch_mlp_for_qed(Ctx *c, const void *mlp, const QedSpeciesView &v, int proc, float *out,
@@ -297,15 +358,15 @@ hipError_t launch_qed(Ctx *c, const pic_qed_args *qa, hipStream_t s) {
             if (e != hipSuccess) return e;
             ap.mlp_out = c->mlp_scratch;
         }
-        const unsigned nb = (unsigned)((sp[2]->n + 255) / 256);
+        const unsigned nb = (unsigned)((sp[2]->n + QED_PHOTON_THREADS - 1) / QED_PHOTON_THREADS);
         const int key = c->dim * 10 + cfg.order;
         switch (key) {
-            case 21: qed_photon_kernel<2, 1><<<nb, 256, 0, s>>>(ap); break;
-            case 22: qed_photon_kernel<2, 2><<<nb, 256, 0, s>>>(ap); break;
-            case 31: qed_photon_kernel<3, 1><<<nb, 256, 0, s>>>(ap); break;
-            case 32: qed_photon_kernel<3, 2><<<nb, 256, 0, s>>>(ap); break;
-            case 24: qed_photon_kernel<2, 4><<<nb, 256, 0, s>>>(ap); break;
-            case 34: qed_photon_kernel<3, 4><<<nb, 256, 0, s>>>(ap); break;
+            case 21: qed_photon_kernel<2, 1><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
+            case 22: qed_photon_kernel<2, 2><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
+            case 31: qed_photon_kernel<3, 1><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
+            case 32: qed_photon_kernel<3, 2><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
+            case 24: qed_photon_kernel<2, 4><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
+            case 34: qed_photon_kernel<3, 4><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -319,7 +380,7 @@ hipError_t launch_qed(Ctx *c, const pic_qed_args *qa, hipStream_t s) {
             if (e != hipSuccess) return e;
             al.mlp_out = c->mlp_scratch;
         }
-        qed_lepton_kernel<<<(unsigned)((sp[k]->n + 255) / 256), 256, 0, s>>>(al, k);
+        qed_lepton_kernel<<<(unsigned)((sp[k]->n + QED_THREADS - 1) / QED_THREADS), QED_THREADS, 0, s>>>(al, k);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -4,7 +4,7 @@ This package is a plain, slow, obviously correct implementation of the method
 of Song, Wang & Li, "YUNIC: A Multi-Dimensional Particle-In-Cell Code for
 Laser-Plasma Interaction" (arXiv:2104.00642): shape-function field
 interpolation (Sec. II.D, Eqs. 17-19), the Boris pusher (Sec. II.C,
-Eqs. 11-16), Esirkepov's charge-conserving current deposit (Sec. II.E,
+Eqs. 11-16) and the Vay pusher Sec. II.C names as its alternative, Esirkepov's charge-conserving current deposit (Sec. II.E,
 Eqs. 20-22), the Yee FDTD field update split in half steps (Sec. II.B Eqs. 9-10,
 arranged as in Sec. II.F) and the Monte-Carlo QED rates (Sec. IV, Eqs. 23-24).
 
@@ -40,7 +40,7 @@ def lib():
 
 class _Grid(C.Structure):
     _fields_ = [("dim", C.c_int32), ("order", C.c_int32), ("n", C.c_int64 * 3),
-                ("d", C.c_double * 3), ("dt", C.c_double)]
+                ("d", C.c_double * 3), ("dt", C.c_double), ("pusher", C.c_int32)]
 
 
 @dataclass
@@ -52,11 +52,13 @@ class Grid:
     d: tuple
     dt: float
     order: int = 2
+    pusher: int = 0  # 0 Boris, 1 Vay
 
     def c(self) -> _Grid:
         g = _Grid()
         g.dim = self.dim
         g.order = self.order
+        g.pusher = self.pusher
         n = list(self.n) + [1] * (3 - len(self.n))
         d = list(self.d) + [1.0] * (3 - len(self.d))
         for a in range(3):
@@ -89,6 +91,7 @@ def _declare(L):
     L.orc_shape.restype = C.c_int
     L.orc_gather.argtypes = [_GP, _PP, _D, _D]
     L.orc_boris.argtypes = [C.c_double, C.c_double, _D, _D, _D]
+    L.orc_vay.argtypes = [C.c_double, C.c_double, _D, _D, _D]
     L.orc_deposit.argtypes = [_GP, C.c_double, _D, _D, C.c_double, _PP]
     L.orc_push.argtypes = [_GP, C.c_double, C.c_double, C.c_int64, _PP, _PP, _D, C.c_double,
                            _PP, _PP, _D]
@@ -154,6 +157,14 @@ def boris(qm: float, dt: float, E, B, u):
     B = np.ascontiguousarray(B, dtype=np.float64)
     u = np.array(u, dtype=np.float64)
     lib().orc_boris(qm, dt, _dp(E), _dp(B), _dp(u))
+    return u
+
+
+def vay(qm: float, dt: float, E, B, u):
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    u = np.array(u, dtype=np.float64)
+    lib().orc_vay(qm, dt, _dp(E), _dp(B), _dp(u))
     return u
 
 

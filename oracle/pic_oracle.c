@@ -37,6 +37,7 @@ typedef struct {
     int64_t n[3];    /* cells per axis; n[2] = 1 in 2D                   */
     double d[3];     /* cell sizes dx, dy, dz                            */
     double dt;       /* time step                                        */
+    int32_t pusher;  /* 0 Boris (Sec. II.C), 1 Vay                       */
 } orc_grid;
 
 /* Component stagger in half cells, indexed [component][axis];
@@ -153,6 +154,40 @@ void orc_boris(double qm, double dt, const double *E, const double *B, double *u
 }
 
 /*
+ * Vay pusher, the alternative Sec. II.C names for fields whose electric and
+ * magnetic forces nearly cancel (J.-L. Vay, Phys. Plasmas 15, 056701 (2008)).
+ * It advances u by the implicit equation
+ *   u^{n+1} - u^n = q_m dt (E + (v^n + v^{n+1})/2 x B),   v = u / gamma,
+ * which it solves in closed form: with h = q_m dt / 2,
+ *   u' = u^n + 2 h E + h v^n x B,   tau = h B,   u* = u'.tau,
+ *   sigma = 1 + |u'|^2 - |tau|^2,
+ *   gamma^{n+1} = sqrt((sigma + sqrt(sigma^2 + 4 (|tau|^2 + u*^2))) / 2),
+ *   t = tau / gamma^{n+1},
+ *   u^{n+1} = (u' + (u'.t) t + u' x t) / (1 + |t|^2).
+ * In place on u.
+ */
+void orc_vay(double qm, double dt, const double *E, const double *B, double *u) {
+    double h = 0.5 * qm * dt;
+    double g0 = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    double v[3] = {u[0] / g0, u[1] / g0, u[2] / g0};
+    double tau[3] = {h * B[0], h * B[1], h * B[2]};
+    double up[3];
+    up[0] = u[0] + 2.0 * h * E[0] + (v[1] * tau[2] - v[2] * tau[1]);
+    up[1] = u[1] + 2.0 * h * E[1] + (v[2] * tau[0] - v[0] * tau[2]);
+    up[2] = u[2] + 2.0 * h * E[2] + (v[0] * tau[1] - v[1] * tau[0]);
+    double tau2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
+    double ustar = up[0] * tau[0] + up[1] * tau[1] + up[2] * tau[2];
+    double sigma = 1.0 + up[0] * up[0] + up[1] * up[1] + up[2] * up[2] - tau2;
+    double gn = sqrt(0.5 * (sigma + sqrt(sigma * sigma + 4.0 * (tau2 + ustar * ustar))));
+    double t[3] = {tau[0] / gn, tau[1] / gn, tau[2] / gn};
+    double s = 1.0 / (1.0 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    double ut = up[0] * t[0] + up[1] * t[1] + up[2] * t[2];
+    u[0] = s * (up[0] + ut * t[0] + (up[1] * t[2] - up[2] * t[1]));
+    u[1] = s * (up[1] + ut * t[1] + (up[2] * t[0] - up[0] * t[2]));
+    u[2] = s * (up[2] + ut * t[2] + (up[0] * t[1] - up[1] * t[0]));
+}
+
+/*
  * Node weights of the particle charge along one axis on a stencil of `len`
  * nodes starting at `base` (integer nodes, no stagger).  Zero outside the
  * shape support.
@@ -263,11 +298,11 @@ void orc_deposit(const orc_grid *g, double qw, const double *xh, const double *x
 }
 
 /*
- * One particle step of one species (gather, Boris, move, deposit) with fields
+ * One particle step of one species (gather, Boris or Vay, move, deposit) with fields
  * at time n+1/2, Sec. II.C-E in the full/half-step arrangement of Sec. II.F:
  *   1. gamma = sqrt(1+|u|^2); xh = x + dt u / (2 gamma)     (position n+1/2)
  *   2. gather E, B at xh (Eq. 19)
- *   3. Boris (Eqs. 13-16) -> u^{n+1}
+ *   3. Boris (Eqs. 13-16), or Vay (g->pusher = 1) -> u^{n+1}
  *   4. v = u^{n+1}/gamma^{n+1}; x^{n+1} = xh + dt v / 2; xe = xh + dt v  (Eq. 12)
  *   5. Esirkepov deposit of the move xh -> xe into J; periodic wrap of x.
  * x[a], u[a]: per-axis arrays of np particles (absolute FP64 positions);
@@ -291,7 +326,8 @@ void orc_push(const orc_grid *g, double q, double m, int64_t np, double *const *
         for (int a = 0; a < 3; ++a) xh[a] = xp[a] + 0.5 * dt * up[a] / gam;
         double EB[6];
         orc_gather(g, F, xh, EB);
-        orc_boris(qm, dt, EB, EB + 3, up);
+        if (g->pusher == 1) orc_vay(qm, dt, EB, EB + 3, up);
+        else orc_boris(qm, dt, EB, EB + 3, up);
         double gn = sqrt(1.0 + up[0] * up[0] + up[1] * up[1] + up[2] * up[2]);
         for (int a = 0; a < 3; ++a) {
             double v = up[a] / gn;

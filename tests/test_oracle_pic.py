@@ -140,6 +140,58 @@ def test_boris_rotation_angle_and_energy():
         assert v[2] == pytest.approx(u[2], abs=1e-14)
 
 
+# ------------------------------------------------- Vay (named in II.C)
+
+def test_vay_solves_its_implicit_equation():
+    """Vay's update is defined by u^{n+1} - u^n = q_m dt (E + (v^n + v^{n+1})/2
+    x B); the closed form must satisfy it to round-off, at any energy."""
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        qm, dt = rng.choice([-1.0, 1.0 / 1836.0]), rng.uniform(0.01, 0.5)
+        u = rng.normal(0, 10 ** rng.uniform(-2, 4), 3)
+        E, B = rng.normal(0, 3, 3), rng.normal(0, 3, 3)
+        un = O.vay(qm, dt, E, B, u)
+        v0 = u / math.sqrt(1 + u @ u)
+        v1 = un / math.sqrt(1 + un @ un)
+        res = un - u - qm * dt * (E + np.cross(0.5 * (v0 + v1), B))
+        assert np.linalg.norm(res) <= 1e-13 * (1 + np.linalg.norm(u) + np.linalg.norm(un))
+
+
+def test_vay_force_free_drift_is_exact():
+    """A particle drifting at v = E x B / B^2 feels no force (E + v x B = 0):
+    Vay keeps its momentum to round-off at gamma = 22, where Boris does not
+    (the case the paper names it for)."""
+    B = np.array([0.0, 0.0, 2.0])
+    vx = 0.999
+    E = np.array([0.0, vx * B[2], 0.0])
+    gam = 1 / math.sqrt(1 - vx * vx)
+    u0 = np.array([gam * vx, 0.0, 0.0])
+    uv, ub = u0.copy(), u0.copy()
+    for _ in range(100):
+        uv = O.vay(-1.0, 0.2, E, B, uv)
+        ub = O.boris(-1.0, 0.2, E, B, ub)
+    assert np.linalg.norm(uv - u0) < 1e-11 * gam
+    assert np.linalg.norm(ub - u0) > 1e-5 * gam  # Boris: 1e-4 of |u| after 100 steps
+
+
+def test_vay_pure_electric_field_is_exact():
+    u = np.array([0.3, -0.2, 0.9])
+    E = np.array([0.01, 0.02, -0.03])
+    assert np.allclose(O.vay(-1.0, 0.1, E, np.zeros(3), u), u - 0.1 * E, atol=1e-15)
+
+
+def test_vay_equals_boris_in_a_pure_magnetic_field():
+    """With E = 0 a gamma-conserving rotation solves Vay's equation, and it is
+    then the rotation equation Boris solves: the two pushers agree."""
+    rng = np.random.default_rng(6)
+    for _ in range(100):
+        u = rng.normal(0, 10 ** rng.uniform(-1, 3), 3)
+        B = rng.normal(0, 2, 3)
+        dt = rng.uniform(0.01, 0.5)
+        uv, ub = O.vay(-1.0, dt, np.zeros(3), B, u), O.boris(-1.0, dt, np.zeros(3), B, u)
+        assert np.allclose(uv, ub, rtol=1e-12, atol=1e-12 * np.linalg.norm(u))
+
+
 def test_push_gyration_radius_exact():
     """Whole particle step in a uniform B_z (E = 0): full-step positions lie on
     the circle of radius r_L = |u_perp| / |q_m B| and half-step positions on

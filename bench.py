@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--fp64-order", choices=["lex", "cell"], default="lex",
                     help="particle order of the plain FP64 path (see fp64_order)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--pusher", choices=["boris", "vay"], default="boris",
+                    help="momentum update: Boris (Eqs. 13-16) or Vay")
     ap.add_argument("--order", type=int, choices=[1, 2, 4], default=2,
                     help="shape order: 2 quadratic (the workload's), 1 linear, 4 quartic")
     ap.add_argument("--workload", choices=["laser2d", "laser3d"], default="laser2d",
@@ -279,7 +281,7 @@ def sampled_error(sim, torch, L, O, nsample=2000, seed=7):
     total-current consistency sum(J_x) vs sum q w v_x."""
     import numpy as np
     cfg = sim.cfg
-    g = O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order)
+    g = O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order, pusher=cfg.pusher)
     L.pic_yee_step(sim.ctx, 1, sim.fields)
     for j in sim.fields.J:
         j.zero_()
@@ -327,7 +329,7 @@ def cpu_baseline(wl, O, target_s, log):
     import torch
     from paper_2104_00642_amd.workloads import to_fp64
     cfg = wl.cfg
-    g = O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order)
+    g = O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order, pusher=cfg.pusher)
     F = [t.to("cpu", torch.float64).numpy().copy() for t in list(wl.E0) + list(wl.B0)]
     q, m, raw = wl.species[0]
     gen = torch.Generator().manual_seed(11)
@@ -388,6 +390,7 @@ def main():
         wl = laser_plasma_3d(scale=args.scale, device="cuda", tile=tuple(int(v) for v in args.tile.split(",")),
                              order=args.order)
         ppc = 16  # 8 electrons + 8 ions per cell share the field cells
+    wl.cfg.pusher = L.PIC_PUSH_VAY if args.pusher == "vay" else L.PIC_PUSH_BORIS
     out = {}
     for prec in ([L.PIC_FP32_MIXED] if args.no_fp64 else [L.PIC_FP32_MIXED, L.PIC_FP64_PLAIN]):
         name = "fp32" if prec == L.PIC_FP32_MIXED else "fp64"
@@ -428,7 +431,8 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": wl.name if args.scale == 1 else f"{wl.name}_scale{args.scale}",
                    "particles": r["n"], "cells": list(wl.cfg.n),
-                   "shape": {1: "linear", 2: "quadratic", 4: "quartic"}[args.order], "tile": r["tile"][:dim],
+                   "shape": {1: "linear", 2: "quadratic", 4: "quartic"}[args.order], "pusher": args.pusher,
+                   "tile": r["tile"][:dim],
                    "sort_every": args.sort_every,
                    "drift": args.drift, "parallelism": "single GPU"},
         "gpd_only_particle_steps_per_s": r["n"] / (r["gpd_ms"] * 1e-3),

@@ -70,6 +70,11 @@ typedef enum {
 
 enum { PIC_FP32_MIXED = 0, PIC_FP64_PLAIN = 1 };
 enum { PIC_BC_PERIODIC = 0 };
+/* Momentum update: Boris (Sec. II.C, Eqs. 13-16) or Vay, which Sec. II.C
+ * names for fields whose electric and magnetic forces nearly cancel; Vay
+ * solves u^{n+1} - u^n = q_m dt (E + (v^n + v^{n+1})/2 x B) in closed form
+ * (J.-L. Vay, Phys. Plasmas 15, 056701 (2008)). */
+enum { PIC_PUSH_BORIS = 0, PIC_PUSH_VAY = 1 };
 
 /* Status-word bits reported by pic_check. */
 enum {
@@ -96,6 +101,7 @@ typedef struct {
     uint64_t seed;          /* key of the counter-based generator (QED)               */
     double hbar_omega_mc2;  /* hbar w_r / (m_e c^2) for chi (2.4263e-6 at 1 um);
                                0 disables the chi output of the push                  */
+    int32_t pusher;         /* PIC_PUSH_BORIS (0) or PIC_PUSH_VAY (1); PIC_E_ARG else  */
 } pic_config;
 
 typedef struct {

@@ -26,6 +26,7 @@ PIC_BC_PERIODIC = 0
 PIC_F_NONFINITE, PIC_F_OFFSET, PIC_F_STRAGGLER, PIC_F_CAPACITY, PIC_F_QED_SATURATED = 1, 2, 4, 8, 16
 
 PIC_QED_TABLE, PIC_QED_MLP, PIC_QED_METHOD2 = 0, 1, 2
+PIC_PUSH_BORIS, PIC_PUSH_VAY = 0, 1
 PIC_MLP_NPARAM = 4610
 PIC_MLP_BYTES = 9480
 PIC_MLP_STATE_FLOATS = 4 * PIC_MLP_NPARAM + 1
@@ -46,7 +47,7 @@ class pic_config(C.Structure):
     _fields_ = [("dim", C.c_int32), ("order", C.c_int32), ("precision", C.c_int32),
                 ("drift", C.c_int32), ("n", C.c_int64 * 3), ("d", C.c_double * 3),
                 ("dt", C.c_double), ("bc", C.c_int32 * 3), ("tile", C.c_int32 * 3),
-                ("seed", C.c_uint64), ("hbar_omega_mc2", C.c_double)]
+                ("seed", C.c_uint64), ("hbar_omega_mc2", C.c_double), ("pusher", C.c_int32)]
 
 
 class pic_species(C.Structure):
@@ -150,6 +151,7 @@ class Config:
     tile: tuple = (0, 0, 0)
     seed: int = 0
     hbar_omega_mc2: float = 0.0
+    pusher: int = PIC_PUSH_BORIS
 
     def c(self) -> pic_config:
         cfg = pic_config()
@@ -162,6 +164,7 @@ class Config:
         cfg.dt = float(self.dt)
         cfg.seed = int(self.seed)
         cfg.hbar_omega_mc2 = float(self.hbar_omega_mc2)
+        cfg.pusher = int(self.pusher)
         return cfg
 
     @property

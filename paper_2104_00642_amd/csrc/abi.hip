@@ -148,6 +148,8 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
             return fail(nullptr, PIC_E_CFL, "dt / d above 0.999 on one axis (extreme cell aspect ratio)");
     if (!(cfg->hbar_omega_mc2 >= 0.0) || !isfinite(cfg->hbar_omega_mc2))
         return fail(nullptr, PIC_E_ARG, "hbar_omega_mc2 must be >= 0");
+    if (cfg->pusher != PIC_PUSH_BORIS && cfg->pusher != PIC_PUSH_VAY)
+        return fail(nullptr, PIC_E_ARG, "pusher must be PIC_PUSH_BORIS or PIC_PUSH_VAY");
     if (cfg->drift < 0 || cfg->drift > 4) return fail(nullptr, PIC_E_ARG, "drift must be in [0, 4]");
 
     Ctx *c = new (std::nothrow) Ctx();

@@ -1,6 +1,6 @@
 // device_common.h -- device-side building blocks shared by the HIP kernels:
 // shape weights (Sec. II.D, Eqs. 17-18), Boris rotation (Sec. II.C,
-// Eqs. 13-16) and the Esirkepov stencil weights (Sec. II.E, Eqs. 20-22),
+// Eqs. 13-16), the Vay pusher and the Esirkepov stencil weights (Sec. II.E, Eqs. 20-22),
 // templated on the real type so the FP32 and FP64 paths use one definition.
 #pragma once
 
@@ -86,6 +86,44 @@ __device__ __forceinline__ void boris(R h, const R *E, const R *B, R *u) {
     u[0] = um0 + (p1 * s2 - p2 * s1) + h * E[0];
     u[1] = um1 + (p2 * s0 - p0 * s2) + h * E[1];
     u[2] = um2 + (p0 * s1 - p1 * s0) + h * E[2];
+}
+
+// Vay pusher, the alternative Sec. II.C names for fields whose electric and
+// magnetic forces nearly cancel (J.-L. Vay, Phys. Plasmas 15, 056701 (2008)):
+// u^{n+1} - u^n = q_m dt (E + (v^n + v^{n+1})/2 x B) solved in closed form.
+// With tau = h B (h = q_m dt / 2): u' = u + 2 h E + v x tau, u* = u'.tau,
+// sigma = 1 + |u'|^2 - |tau|^2, gamma_new^2 the positive root of
+// g^4 - sigma g^2 - (|tau|^2 + u*^2) = 0 (the form without cancellation for
+// sigma < 0), t = tau / gamma_new, u = (u' + (u'.t) t + u' x t) / (1 + |t|^2).
+template <typename R>
+__device__ __forceinline__ void vay(R h, const R *E, const R *B, R *u) {
+    const R ig0 = rsqrt_r(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const R v0 = u[0] * ig0, v1 = u[1] * ig0, v2 = u[2] * ig0;
+    const R T0 = h * B[0], T1 = h * B[1], T2 = h * B[2];
+    const R h2 = R(2) * h;
+    const R p0 = u[0] + h2 * E[0] + (v1 * T2 - v2 * T1);
+    const R p1 = u[1] + h2 * E[1] + (v2 * T0 - v0 * T2);
+    const R p2 = u[2] + h2 * E[2] + (v0 * T1 - v1 * T0);
+    const R tau2 = T0 * T0 + T1 * T1 + T2 * T2;
+    const R us = p0 * T0 + p1 * T1 + p2 * T2;
+    const R sigma = R(1) + p0 * p0 + p1 * p1 + p2 * p2 - tau2;
+    const R k = tau2 + us * us;
+    const R q = sqrt(sigma * sigma + R(4) * k);
+    const R g2 = sigma >= R(0) ? R(0.5) * (sigma + q) : R(2) * k / (q - sigma);
+    const R ig = rsqrt_r(g2);
+    const R t0 = T0 * ig, t1 = T1 * ig, t2 = T2 * ig;
+    const R sc = rcp_r(R(1) + t0 * t0 + t1 * t1 + t2 * t2);
+    const R pt = p0 * t0 + p1 * t1 + p2 * t2;
+    u[0] = sc * (p0 + pt * t0 + (p1 * t2 - p2 * t1));
+    u[1] = sc * (p1 + pt * t1 + (p2 * t0 - p0 * t2));
+    u[2] = sc * (p2 + pt * t2 + (p0 * t1 - p1 * t0));
+}
+
+// momentum update of the configured pusher (0 Boris, 1 Vay)
+template <int PUSH, typename R>
+__device__ __forceinline__ void push_u(R h, const R *E, const R *B, R *u) {
+    if constexpr (PUSH == 1) vay<R>(h, E, B, u);
+    else boris<R>(h, E, B, u);
 }
 
 // Esirkepov stencil along one axis: S0 (weights at the start of the move),

@@ -44,7 +44,7 @@ __device__ __forceinline__ int64_t gidx(const int *ng, int i, int j, int k) {
     }
 }
 
-template <int DIM, int ORDER>
+template <int DIM, int ORDER, int PUSH>
 __global__ void __launch_bounds__(256) gpd_plain_kernel(PlainArgs a) {
     constexpr int NW = ORDER + 1;
     constexpr int L = ORDER + 2;
@@ -104,9 +104,9 @@ __global__ void __launch_bounds__(256) gpd_plain_kernel(PlainArgs a) {
             EB[c] = acc;
         }
 
-        // ---- Boris (Eqs. 13-16)
+        // ---- Boris (Eqs. 13-16) or Vay
         const double u_old[3] = {u[0], u[1], u[2]};
-        boris<double>(a.qm_half_dt, EB, EB + 3, u);
+        push_u<PUSH, double>(a.qm_half_dt, EB, EB + 3, u);
         const double g1 = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         const double ig1 = 1.0 / g1;
         double v[3] = {u[0] * ig1, u[1] * ig1, u[2] * ig1};
@@ -244,6 +244,12 @@ __global__ void __launch_bounds__(256) gpd_plain_kernel(PlainArgs a) {
 
 // Sum `nval` interleaved FP64 partials over `nblocks` blocks in a fixed order
 // and add scale * sum to diag[off + v].
+template <int DIM, int ORDER>
+static void launch_plain(const PlainArgs &a, int pusher, dim3 grid, dim3 block, hipStream_t s) {
+    if (pusher == PIC_PUSH_VAY) gpd_plain_kernel<DIM, ORDER, PIC_PUSH_VAY><<<grid, block, 0, s>>>(a);
+    else gpd_plain_kernel<DIM, ORDER, PIC_PUSH_BORIS><<<grid, block, 0, s>>>(a);
+}
+
 __global__ void __launch_bounds__(256) finalize_kernel(const double *partials, int64_t nblocks,
                                                        int nval, double *diag, int off,
                                                        double scale) {
@@ -302,12 +308,12 @@ hipError_t launch_gpd_plain(Ctx *c, const pic_species *sp, const pic_particles *
     dim3 grid((unsigned)nblocks), block(256);
     const int key = c->dim * 10 + cfg.order;
     switch (key) {
-        case 21: gpd_plain_kernel<2, 1><<<grid, block, 0, s>>>(a); break;
-        case 22: gpd_plain_kernel<2, 2><<<grid, block, 0, s>>>(a); break;
-        case 31: gpd_plain_kernel<3, 1><<<grid, block, 0, s>>>(a); break;
-        case 32: gpd_plain_kernel<3, 2><<<grid, block, 0, s>>>(a); break;
-        case 24: gpd_plain_kernel<2, 4><<<grid, block, 0, s>>>(a); break;
-        case 34: gpd_plain_kernel<3, 4><<<grid, block, 0, s>>>(a); break;
+        case 21: launch_plain<2, 1>(a, cfg.pusher, grid, block, s); break;
+        case 22: launch_plain<2, 2>(a, cfg.pusher, grid, block, s); break;
+        case 31: launch_plain<3, 1>(a, cfg.pusher, grid, block, s); break;
+        case 32: launch_plain<3, 2>(a, cfg.pusher, grid, block, s); break;
+        case 24: launch_plain<2, 4>(a, cfg.pusher, grid, block, s); break;
+        case 34: launch_plain<3, 4>(a, cfg.pusher, grid, block, s); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();

@@ -9,7 +9,7 @@
 //   2. pushes the tile's particles (contiguous after pic_sort, with
 //      consecutive particles in distinct cells so that the LDS traffic of a
 //      wavefront spreads over distinct addresses): gather from LDS (Eq. 19),
-//      Boris (Eqs. 13-16), move (Eq. 12), Esirkepov current (Eqs. 20-22)
+//      Boris (Eqs. 13-16) or Vay, move (Eq. 12), Esirkepov current (Eqs. 20-22)
 //      accumulated in an int64 fixed-point J window with LDS integer atomics,
 //   3. adds its J window to global J with one pass of coalesced global float
 //      atomics (neighbouring windows overlap in their guard cells).
@@ -140,7 +140,7 @@ struct GlobAcc {
 // f[] in-cell offsets, u[] momentum (updated); returns the cell displacement
 // in dc[] and the new offsets in f[]; EB[] receives the gathered fields and
 // gm1 = gamma^{n+1} - 1, formed as |u|^2 / (gamma + 1) (no cancellation).
-template <int DIM, int ORDER, class Acc>
+template <int DIM, int ORDER, int PUSH, class Acc>
 __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, const int *o, float *f,
                                          float *u, float w, int *dc, float *EB, float &gm1) {
     constexpr int NW = ORDER + 1;
@@ -190,7 +190,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
         EB[c] = acc_v;
     }
 
-    boris<float>(a.qm_h, EB, EB + 3, u);
+    push_u<PUSH, float>(a.qm_h, EB, EB + 3, u);
     const float us = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const float ig1 = rsqrt_r(1.0f + us);
     gm1 = us * ig1 * rcp_r(1.0f + ig1);
@@ -354,7 +354,7 @@ struct POff<true> {
 // the sorted arrays.  LIST = true: they are bin_list[bin_start[t] ..
 // bin_start[t+1]) (the stragglers and appended particles binned by the tile
 // that holds them now).
-template <int DIM, int ORDER, int NT, int WX, int WY, int WZ, bool LIST>
+template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ, bool LIST>
 __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     typedef typename POff<LIST>::type off_t;
     const int b = blockIdx.x;
@@ -498,7 +498,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         float EB[6];
         int dc[3] = {0, 0, 0};
         float gm1;
-        push_one<DIM, ORDER>(lds, a, lc, f, u, w, dc, EB, gm1);
+        push_one<DIM, ORDER, PUSH>(lds, a, lc, f, u, w, dc, EB, gm1);
         int packed = 0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
@@ -720,7 +720,7 @@ __global__ void __launch_bounds__(256) gpd_bin_scatter_kernel(TiledArgs a) {
 // the binning: invalid particles are flagged and left unchanged.
 constexpr int GLOBAL_BLOCKS = 256;
 
-template <int DIM, int ORDER>
+template <int DIM, int ORDER, int PUSH>
 __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
     const int64_t total = (int64_t)*a.strag_count;
     __shared__ double red_k[4], red_q[4];
@@ -749,7 +749,7 @@ __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
         float EB[6];
         int dc[3] = {0, 0, 0};
         float gm1;
-        push_one<DIM, ORDER>(glob, a, cc, f, u, w, dc, EB, gm1);
+        push_one<DIM, ORDER, PUSH>(glob, a, cc, f, u, w, dc, EB, gm1);
         int packed = 0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
@@ -781,37 +781,43 @@ constexpr int W2X = 16 + 2 * 2 + 5, W2X4 = 16 + 2 * 2 + 7, W3X = 8 + 2 * 1 + 5, 
 //   -> bin scan -> bin scatter -> reset of the list -> binned pass -> global
 //   pass over whatever the binned pass listed.
 // Partials: [sorted pass: 2 ntiles][binned pass: 2 ntiles][global: 2 x 256].
-template <int DIM, int ORDER, int NT, int WX, int WY, int WZ>
+template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ>
 static void launch_passes(TiledArgs a, size_t lds, hipStream_t s) {
     const dim3 tiles((unsigned)(8 * a.chunk)), block(NT), gb(GLOBAL_BLOCKS), b256(256);
     gpd_prep_kernel<<<(unsigned)((a.ntiles + 255) / 256), 256, 0, s>>>(a.bin_count, a.ntiles, a.strag_count);
     a.part_off = 0;
-    gpd_tiled_kernel<DIM, ORDER, NT, WX, WY, WZ, false><<<tiles, block, lds, s>>>(a);
+    gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, false><<<tiles, block, lds, s>>>(a);
     const dim3 bins((unsigned)(a.ntiles + TAIL_BLOCKS));
     gpd_bin_count_kernel<DIM><<<bins, b256, 0, s>>>(a);
     gpd_bin_scan_kernel<<<1, 1024, 0, s>>>(a.bin_count, a.ntiles, a.bin_start);
     gpd_bin_scatter_kernel<DIM><<<bins, b256, 0, s>>>(a);
     gpd_reset_kernel<<<1, 1, 0, s>>>(a.strag_count);
     a.part_off = 2 * a.ntiles;
-    gpd_tiled_kernel<DIM, ORDER, NT, WX, WY, WZ, true><<<tiles, block, lds, s>>>(a);
+    gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, true><<<tiles, block, lds, s>>>(a);
     a.part_off = 4 * a.ntiles;
-    gpd_global_kernel<DIM, ORDER><<<gb, b256, 0, s>>>(a);
+    gpd_global_kernel<DIM, ORDER, PUSH><<<gb, b256, 0, s>>>(a);
 }
 
-template <int DIM, int ORDER>
+template <int DIM, int ORDER, int PUSH>
 static void launch_tiled(const TiledArgs &a, size_t lds, hipStream_t s) {
     if constexpr (DIM == 2) {
         constexpr int WX = ORDER == 4 ? W2X4 : W2X;
         if (a.win[0] == WX && a.win[1] == WX)
-            launch_passes<2, ORDER, PIC_TILED_THREADS_2D, WX, WX, 1>(a, lds, s);
+            launch_passes<2, ORDER, PUSH, PIC_TILED_THREADS_2D, WX, WX, 1>(a, lds, s);
         else
-            launch_passes<2, ORDER, PIC_TILED_THREADS_2D, 0, 0, 0>(a, lds, s);
+            launch_passes<2, ORDER, PUSH, PIC_TILED_THREADS_2D, 0, 0, 0>(a, lds, s);
     } else {
         if (a.win[0] == W3X && a.win[1] == W3X && a.win[2] == W3Z)
-            launch_passes<3, ORDER, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(a, lds, s);
+            launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(a, lds, s);
         else
-            launch_passes<3, ORDER, PIC_TILED_THREADS_3D, 0, 0, 0>(a, lds, s);
+            launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, 0, 0, 0>(a, lds, s);
     }
+}
+
+template <int DIM, int ORDER>
+static void launch_pusher(const TiledArgs &a, int pusher, size_t lds, hipStream_t s) {
+    if (pusher == PIC_PUSH_VAY) launch_tiled<DIM, ORDER, PIC_PUSH_VAY>(a, lds, s);
+    else launch_tiled<DIM, ORDER, PIC_PUSH_BORIS>(a, lds, s);
 }
 
 hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *p,
@@ -867,12 +873,12 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
     a.bin_count = c->bin_count;
     const size_t lds = c->lds_bytes;
     switch (c->dim * 10 + cfg.order) {
-        case 21: launch_tiled<2, 1>(a, lds, s); break;
-        case 22: launch_tiled<2, 2>(a, lds, s); break;
-        case 31: launch_tiled<3, 1>(a, lds, s); break;
-        case 32: launch_tiled<3, 2>(a, lds, s); break;
-        case 24: launch_tiled<2, 4>(a, lds, s); break;
-        case 34: launch_tiled<3, 4>(a, lds, s); break;
+        case 21: launch_pusher<2, 1>(a, cfg.pusher, lds, s); break;
+        case 22: launch_pusher<2, 2>(a, cfg.pusher, lds, s); break;
+        case 31: launch_pusher<3, 1>(a, cfg.pusher, lds, s); break;
+        case 32: launch_pusher<3, 2>(a, cfg.pusher, lds, s); break;
+        case 24: launch_pusher<2, 4>(a, cfg.pusher, lds, s); break;
+        case 34: launch_pusher<3, 4>(a, cfg.pusher, lds, s); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
@@ -880,13 +886,20 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
     return launch_finalize(c->partials, (int64_t)nblocks, 2, diag, 0, 1.0, s);
 }
 
-template <int DIM, int ORDER, int NT, int WX, int WY, int WZ>
-static hipError_t set_lds(size_t bytes) {
-    hipError_t e = hipFuncSetAttribute((const void *)gpd_tiled_kernel<DIM, ORDER, NT, WX, WY, WZ, false>,
+template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ>
+static hipError_t set_lds_p(size_t bytes) {
+    hipError_t e = hipFuncSetAttribute((const void *)gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)gpd_tiled_kernel<DIM, ORDER, NT, WX, WY, WZ, true>,
+    return hipFuncSetAttribute((const void *)gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int DIM, int ORDER, int NT, int WX, int WY, int WZ>
+static hipError_t set_lds(size_t bytes) {
+    hipError_t e = set_lds_p<DIM, ORDER, PIC_PUSH_BORIS, NT, WX, WY, WZ>(bytes);
+    if (e != hipSuccess) return e;
+    return set_lds_p<DIM, ORDER, PIC_PUSH_VAY, NT, WX, WY, WZ>(bytes);
 }
 
 hipError_t set_tiled_lds_limit(size_t bytes) {

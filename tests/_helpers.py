@@ -32,7 +32,8 @@ def random_fields(cfg: L.Config, seed: int, amp: float = 0.4):
 
 
 def oracle_grid(cfg: L.Config) -> O.Grid:
-    return O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order)
+    return O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order,
+                  pusher=cfg.pusher)
 
 
 def oracle_species(cfg, raw: RawParticles, q, m, from_fp32: bool):

@@ -19,7 +19,10 @@ pytestmark = pytest.mark.gpu
 CASES = [(2, 1), (2, 2), (2, 4), (3, 1), (3, 2), (3, 4)]
 
 
-def make_cfg(dim, order, precision, drift=2):
+PUSHERS = [L.PIC_PUSH_BORIS, L.PIC_PUSH_VAY]
+
+
+def make_cfg(dim, order, precision, drift=2, pusher=L.PIC_PUSH_BORIS):
     if dim == 2:
         n, d, tile = (48, 40), (0.3, 0.25), (16, 8)
     else:
@@ -28,7 +31,7 @@ def make_cfg(dim, order, precision, drift=2):
         n, d, tile = (24, 20, 18), (0.3, 0.25, 0.2), (8, 4, 6)
         drift = min(drift, 0 if order == 4 else 1)
     return L.Config(dim=dim, n=n, d=d, dt=courant_dt(d, 0.9), order=order, precision=precision,
-                    tile=tile, drift=drift, hbar_omega_mc2=2.4263e-6)
+                    tile=tile, drift=drift, hbar_omega_mc2=2.4263e-6, pusher=pusher)
 
 
 def run_oracle_push(cfg, raw, E, B, q, m, from_fp32):
@@ -45,10 +48,11 @@ def lengths(cfg):
     return [cfg.n[a] * cfg.d[a] for a in range(cfg.dim)]
 
 
+@pytest.mark.parametrize("pusher", PUSHERS)
 @pytest.mark.parametrize("dim,order", CASES)
-def test_plain_fp64_push_matches_oracle(dim, order):
-    print(f"plain fp64 dim={dim} order={order}", flush=True)
-    cfg = make_cfg(dim, order, L.PIC_FP64_PLAIN)
+def test_plain_fp64_push_matches_oracle(dim, order, pusher):
+    print(f"plain fp64 dim={dim} order={order} pusher={pusher}", flush=True)
+    cfg = make_cfg(dim, order, L.PIC_FP64_PLAIN, pusher=pusher)
     raw = random_raw(cfg, 3001, seed=10 * dim + order)
     E, B = random_fields(cfg, seed=dim + order)
     q, m = -1.0, 1.0
@@ -71,6 +75,11 @@ def test_plain_fp64_push_matches_oracle(dim, order):
     for a in range(3):
         assert rel_l2(np64(f.J[a]), J_o[a]) < 1e-12
     assert np64(diag)[:2] == pytest.approx(diag_o, rel=1e-12)
+    if pusher == L.PIC_PUSH_VAY:
+        # the other pusher's answer is far outside the tolerance: the switch is live
+        cfg_b = make_cfg(dim, order, L.PIC_FP64_PLAIN, pusher=L.PIC_PUSH_BORIS)
+        sp_b, _, _ = run_oracle_push(cfg_b, raw, E, B, q, m, from_fp32=False)
+        assert max(np.abs(np64(p.u[a]) - sp_b.u[a]).max() for a in range(3)) > 1e-6
 
 
 def sorted_fp32_state(cfg, raw, E, B):
@@ -89,10 +98,11 @@ def sorted_fp32_state(cfg, raw, E, B):
     return ctx, dst, f, perm, start, bits
 
 
+@pytest.mark.parametrize("pusher", PUSHERS)
 @pytest.mark.parametrize("dim,order", CASES)
-def test_sort_then_fp32_push_matches_oracle(dim, order):
-    print(f"tiled fp32 dim={dim} order={order}", flush=True)
-    cfg = make_cfg(dim, order, L.PIC_FP32_MIXED)
+def test_sort_then_fp32_push_matches_oracle(dim, order, pusher):
+    print(f"tiled fp32 dim={dim} order={order} pusher={pusher}", flush=True)
+    cfg = make_cfg(dim, order, L.PIC_FP32_MIXED, pusher=pusher)
     raw = random_raw(cfg, 5003, seed=20 * dim + order)
     E, B = random_fields(cfg, seed=3 * dim + order)
     # the FP32 path starts from the FP32-rounded fields
@@ -271,6 +281,50 @@ def test_invalid_particles_are_flagged_and_left_unchanged():
     for a in range(3):
         full.u[a][~bad] = sp_o.u[a]
     check_fp32_against_oracle(cfg, p, f, bits, full, J_o, skip=bad)
+
+
+@pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
+def test_vay_keeps_a_force_free_drift(precision):
+    """Uniform E_y and B_z with particles at v = E x B / B^2 (gamma 22): no
+    force, and the Vay push leaves u at its value to the path's round-off;
+    the Boris push of the same state does not."""
+    d = (0.3, 0.25)
+    res = {}
+    for pusher in PUSHERS:
+        cfg = L.Config(dim=2, n=(32, 32), d=d, dt=courant_dt(d, 0.9), order=2, precision=precision,
+                       tile=(16, 8), pusher=pusher)
+        ctx = L.pic_init(cfg)
+        n, vx, bz = 2000, 0.999, 10.0  # one Boris step changes u by 6e-5 here
+        raw = random_raw(cfg, n, seed=77)
+        gam = 1 / math.sqrt(1 - vx * vx)
+        raw.u = [torch.full((n,), gam * vx, dtype=torch.float64), torch.zeros(n, dtype=torch.float64),
+                 torch.zeros(n, dtype=torch.float64)]
+        dt = torch.float64 if precision == L.PIC_FP64_PLAIN else torch.float32
+        E = [torch.zeros(cfg.plane_shape, dtype=dt, device=DEV) for _ in range(3)]
+        B = [torch.zeros(cfg.plane_shape, dtype=dt, device=DEV) for _ in range(3)]
+        E[1].fill_(vx * bz)
+        B[2].fill_(bz)
+        f = L.Fields(E, B, [torch.zeros(cfg.plane_shape, dtype=dt, device=DEV) for _ in range(3)])
+        if precision == L.PIC_FP64_PLAIN:
+            p = to_fp64(raw, cfg)
+            p = L.Particles(p.n, [t.to(DEV) for t in p.u], x=[t.to(DEV) for t in p.x], w=p.w.to(DEV))
+        else:
+            bits, _, ntiles = L.pic_get_layout(ctx)
+            q = to_fp32(raw, bits)
+            src = L.Particles(q.n, [t.to(DEV) for t in q.u], cell=q.cell.to(DEV), off=[t.to(DEV) for t in q.off],
+                              w=q.w.to(DEV), tile_start=torch.zeros(ntiles + 1, dtype=torch.int64, device=DEV))
+            p = src.empty_like()
+            L.pic_sort(ctx, src, p)
+        u0 = np64(p.u[0]).copy()
+        L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), p, f)
+        st, _, _ = L.pic_check(ctx)
+        assert st == L.PIC_OK
+        res[pusher] = max(np.abs(np64(p.u[a]) - (u0 if a == 0 else 0.0)).max() for a in range(3)) / gam
+    tol = 1e-13 if precision == L.PIC_FP64_PLAIN else 2e-6
+    print(f"force-free drift, precision {precision}: Vay {res[L.PIC_PUSH_VAY]:.2e}, "
+          f"Boris {res[L.PIC_PUSH_BORIS]:.2e} (relative change of u)")
+    assert res[L.PIC_PUSH_VAY] < tol
+    assert res[L.PIC_PUSH_BORIS] > 10 * tol
 
 
 @pytest.mark.parametrize("dim", [2, 3])

@@ -140,7 +140,16 @@ double orc_compton_cum(double chi, double u0) {
     double s0 = cbrt(u0);
     /* scale the absolute tolerance with the classical magnitude of F */
     double scale = chi < 1.0 ? 2.5 * ORC_PI * chi : 8.0 * cbrt(chi * chi);
-    return orc_integrate(compton_s, par, 0.0, s0, 1e-13 * scale);
+    /* For small chi the spectrum lives at u of order chi (y = 2u/(3(1-u) chi)
+     * of order 1), i.e. at s of order chi^(1/3): panels [0, b], [b, 2b], ...
+     * with b = chi^(1/3)/4 keep the rule from stepping over it. */
+    double b = 0.25 * cbrt(chi), lo = 0.0, sum = 0.0;
+    while (b < s0 && b < 0.5) {
+        sum += orc_integrate(compton_s, par, lo, b, 1e-13 * scale);
+        lo = b;
+        b *= 2.0;
+    }
+    return sum + orc_integrate(compton_s, par, lo, s0, 1e-13 * scale);
 }
 
 double orc_frad(double chi) { return orc_compton_cum(chi, 1.0); }

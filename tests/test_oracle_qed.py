@@ -61,6 +61,13 @@ def test_fpair_matches_library_quadrature(chi):
     assert O.fpair(chi) == pytest.approx(scipy_fpair(chi), rel=1e-8)
 
 
+@pytest.mark.parametrize("chi", [1e-10, 1e-8, 2e-9, 1e-6])
+def test_frad_classical_limit_at_tiny_chi(chi):
+    """Far below the tables: F_rad = (5 pi / 2) chi (1 - c chi + ...); the
+    quadrature must find the spectrum at u ~ chi."""
+    assert O.frad(chi) / (2.5 * math.pi * chi) == pytest.approx(1.0, abs=2 * chi + 1e-9)
+
+
 def test_frad_classical_limit():
     """chi -> 0: W_rad -> (5/(2 sqrt 3)) alpha (m c^2/hbar) chi / gamma, i.e.
     F_rad / (5 pi chi / 2) -> 1 (with corrections of order chi)."""

@@ -154,13 +154,14 @@ def langmuir_2d(seed=643, n=(64, 64), ppc=16, device="cpu", order=1, precision=P
 
 
 def laser_fields(cfg: Config, device, a0: float, waist: float, x_start: float, n_cycles: int,
-                 circular: bool = False):
-    """A laser pulse already inside the box, moving along +x: transverse E and
-    the matching B (E_y = B_z, E_z = -B_y), Gaussian transverse profile of
-    waist `waist`, sin^2 field envelope over `n_cycles` periods starting at
-    x_start.  Linear polarisation along y with amplitude a0; circular with
-    a0 on each transverse component.  Sampled at each component's Yee
-    location.  Returns (E, B) as float64 planes."""
+                 circular: bool = False, backward: bool = False):
+    """A laser pulse already inside the box, moving along +x (or -x with
+    `backward`): transverse E and the matching B (E_y = B_z, E_z = -B_y;
+    B reversed for -x), Gaussian transverse profile of waist `waist`, sin^2
+    field envelope over `n_cycles` periods starting at x_start.  Linear
+    polarisation along y with amplitude a0; circular with a0 on each
+    transverse component.  Sampled at each component's Yee location.
+    Returns (E, B) as float64 planes."""
     dim = cfg.dim
     n = list(cfg.n) + [1] * (3 - len(cfg.n))
     shape = (n[2], n[1], n[0])
@@ -188,6 +189,8 @@ def laser_fields(cfg: Config, device, a0: float, waist: float, x_start: float, n
     if circular:
         E[2] = profile(0, 0, 0.5, math.pi / 2).contiguous()
         B[1] = (-profile(0.5, 0, 0.5, math.pi / 2)).contiguous()
+    if backward:
+        B = [-b for b in B]
     return E, B
 
 
@@ -256,6 +259,118 @@ def laser_plasma_3d(seed=645, scale=1, device="cuda", ppc=8, order=2, tile=(8, 8
     shape = {1: "linear", 2: "quadratic", 4: "quartic"}[order]
     return Workload(f"laser_plasma_3d_{n[0]}x{n[1]}x{n[2]}_ppc{ppc}x2_{shape}", cfg,
                     [(-1.0, 1.0, el), (1.0, 1836.0, ion)], E, B, steps=500)
+
+
+QED_HBAR_OMEGA = 2.4263e-6  # hbar w_L / (m_e c^2) at lambda = 1 um
+
+
+def qed_foil_2d(seed=646, scale=1, device="cuda", ppc=16, order=2, a0=500.0, n_foil=100.0,
+                x_pulse=8.0, t_kev=1.0) -> Workload:
+    """2D3V strong-field QED case: 2048 x 1024 cells at 64 cells per
+    wavelength (the 100 n_c foil's skin depth, lambda / 63, spans a cell), a
+    linearly polarized Gaussian pulse a0 = 500 (waist 3 lambda, 10-cycle
+    sin^2) on a 2-lambda electron foil at 100 n_c over [16, 18] lambda with 16
+    particles per cell and immobile ions; positrons and photons come from the
+    QED step (lambda = 1 um for chi).  The pulse spans [x_pulse, x_pulse + 10]
+    lambda: with the default its front already sits in the foil.  Periodic
+    box; `scale` divides the cell counts."""
+    n = (2048 // scale, 1024 // scale)
+    d = (LAMBDA / 64, LAMBDA / 64)
+    cfg = Config(dim=2, n=n, d=d, dt=courant_dt(d), order=order, seed=seed, hbar_omega_mc2=QED_HBAR_OMEGA)
+    gen = torch.Generator(device=device).manual_seed(seed)
+    x0, x1 = 16 * LAMBDA, 18 * LAMBDA
+    if scale > 1:
+        x0, x1 = 0.5 * n[0] * d[0], 0.56 * n[0] * d[0]
+
+    def density(ix):
+        x = (ix + 0.5) * d[0]
+        return torch.where((x >= x0) & (x < x1), torch.full_like(x, n_foil), torch.zeros_like(x))
+
+    raw = plasma(cfg, ppc, density, gen, device, uth=math.sqrt(t_kev / ME_KEV))
+    xs = x_pulse * LAMBDA if scale == 1 else 0.25 * n[0] * d[0]
+    E, B = laser_fields(cfg, device, a0=a0, waist=3 * LAMBDA if scale == 1 else 0.2 * n[1] * d[1],
+                        x_start=xs, n_cycles=10 if scale == 1 else 2)
+    shape = {1: "linear", 2: "quadratic", 4: "quartic"}[order]
+    return Workload(f"qed_foil_2d_{n[0]}x{n[1]}_ppc{ppc}_{shape}", cfg, [(-1.0, 1.0, raw)], E, B, steps=0)
+
+
+def plasma_fp32(cfg: Config, bits, ppc: int, density: Callable, gen: torch.Generator, device,
+                uth: float = 0.0, capacity: Optional[int] = None, chunk: int = 1 << 26) -> Particles:
+    """The FP32 layout generated directly, chunk by chunk, for particle counts
+    whose FP64 form would not fit next to it: `ppc` particles in every cell
+    of positive density (cells x-fastest), float32 offsets uniform in [0, 1),
+    Gaussian momenta of spread `uth`, weight density/ppc, chi 0, and the QED
+    columns: tau 0, tau_thr = -ln r, identifiers 1..N.  Arrays hold
+    `capacity` (default N) entries."""
+    n = list(cfg.n) + [1] * (3 - len(cfg.n))
+    dens_x = density(torch.arange(n[0], device=device, dtype=torch.float64))
+    occupied = torch.nonzero(dens_x > 0).flatten()
+    nx_occ = occupied.numel()
+    N = nx_occ * n[1] * n[2] * ppc
+    cap = N if capacity is None else max(int(capacity), N)
+    f32 = dict(device=device, dtype=torch.float32)
+    cell = torch.zeros(cap, device=device, dtype=torch.int32)
+    off = [torch.zeros(cap, **f32) for _ in range(cfg.dim)]
+    u = [torch.zeros(cap, **f32) for _ in range(3)]
+    w = torch.zeros(cap, **f32)
+    tau_thr = torch.zeros(cap, **f32)
+    one_minus = torch.tensor(1.0, dtype=torch.float32).nextafter(torch.tensor(0.0)).item()
+    for s0 in range(0, N, chunk):
+        s1 = min(N, s0 + chunk)
+        lin = torch.arange(s0, s1, device=device, dtype=torch.int64) // ppc
+        cx = occupied[lin % nx_occ]
+        rest = lin // nx_occ
+        cy, cz = rest % n[1], rest // n[1]
+        c = cx | (cy << bits[0])
+        if cfg.dim == 3:
+            c = c | (cz << (bits[0] + bits[1]))
+        cell[s0:s1] = c.to(torch.int32)
+        for a in range(cfg.dim):
+            off[a][s0:s1] = torch.rand(s1 - s0, generator=gen, **f32).clamp_(max=one_minus)
+        for a in range(3):
+            u[a][s0:s1] = torch.randn(s1 - s0, generator=gen, **f32) * uth
+        w[s0:s1] = (dens_x[cx] / ppc).to(torch.float32)
+        tau_thr[s0:s1] = -torch.log(torch.rand(s1 - s0, generator=gen, **f32).clamp_(min=1e-30))
+    ids = torch.arange(1, cap + 1, device=device, dtype=torch.int64)
+    return Particles(N, u, cell=cell, off=off, w=w, chi=torch.zeros(cap, **f32),
+                     tau=torch.zeros(cap, device=device, dtype=torch.float64), tau_thr=tau_thr, id=ids,
+                     capacity=cap, n_dev=torch.tensor([N], device=device, dtype=torch.int64))
+
+
+def qed_3d_full(seed=647, scale=1, device="cuda", ppc=4, order=2, a0=300.0, n_e=50.0, tile=(8, 8, 4),
+                t_kev=1.0, capacity=None):
+    """3D3V QED case at full HBM: 1024 x 512 x 512 cells at 20 cells per
+    wavelength, 4 electrons per cell in every cell (1.07e9) at 50 n_c (the
+    slab fills the periodic box; ions immobile), and two circularly polarized
+    pulses a0 = 300 (waist 3 lambda, 6-cycle sin^2) that start 1 lambda on
+    either side of the box centre and move toward it.  Returns
+    (cfg, electrons in the FP32 layout with the QED columns, E, B as float32
+    planes); `scale` divides the cell counts."""
+    n = (1024 // scale, 512 // scale, 512 // scale)
+    d = (LAMBDA / 20,) * 3
+    cfg = Config(dim=3, n=n, d=d, dt=courant_dt(d), order=order, seed=seed, tile=tile,
+                 drift=0 if order == 4 else 1, hbar_omega_mc2=QED_HBAR_OMEGA)
+    from ._lib import pic_destroy, pic_get_layout, pic_init
+    ctx = pic_init(cfg)
+    bits, _, _ = pic_get_layout(ctx)
+    pic_destroy(ctx)
+    gen = torch.Generator(device=device).manual_seed(seed)
+    el = plasma_fp32(cfg, bits, ppc, lambda ix: torch.full_like(ix, n_e), gen, device,
+                     uth=math.sqrt(t_kev / ME_KEV), capacity=capacity)
+    xc = 0.5 * n[0] * d[0]
+    ncyc = 6 if scale == 1 else 2
+    waist = 3 * LAMBDA if scale == 1 else 0.2 * n[1] * d[1]
+    gap = LAMBDA if scale == 1 else 0.02 * n[0] * d[0]
+    E1, B1 = laser_fields(cfg, device, a0, waist, xc - gap - ncyc * LAMBDA, ncyc, circular=True)
+    E = [e.to(torch.float32) for e in E1]
+    B = [b.to(torch.float32) for b in B1]
+    del E1, B1
+    E2, B2 = laser_fields(cfg, device, a0, waist, xc + gap, ncyc, circular=True, backward=True)
+    for a in range(3):
+        E[a] += E2[a].to(torch.float32)
+        B[a] += B2[a].to(torch.float32)
+    del E2, B2
+    return cfg, el, E, B
 
 
 def fields_for(cfg: Config, wl: Workload, device, dtype) -> Fields:

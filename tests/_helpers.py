@@ -56,3 +56,72 @@ def rel_l2(a, b):
 def periodic_dx(a, b, L):
     d = np.asarray(a) - np.asarray(b)
     return d - L * np.round(d / L)
+
+
+# ------------------------------------------------ full-size sampled checks
+
+def positions_fp32(p: L.Particles, bits, cfg: L.Config, idx):
+    """Absolute FP64 positions of particles `idx` (device index tensor) of an
+    FP32-layout species: (cell + offset) d per axis."""
+    cell = p.cell[idx].to(torch.int64)
+    out, shift = [], 0
+    for a in range(cfg.dim):
+        c = (cell >> shift) & ((1 << bits[a]) - 1)
+        shift += bits[a]
+        out.append(np64((c.to(torch.float64) + p.off[a][idx].to(torch.float64)) * cfg.d[a]))
+    return out
+
+
+def host_fields(fields: L.Fields):
+    """E and B planes as FP64 numpy arrays (the oracle's field list)."""
+    return [np64(t).copy() for t in list(fields.E) + list(fields.B)]
+
+
+def sampled_push(ctx, cfg, sp: L.Species, p: L.Particles, fields: L.Fields, bits, nsample, seed):
+    """Push the whole species once on the GPU; return the state of a random
+    sample before and after: x0, u0, w0, x1, u1 (FP64 numpy), chi1 (or None)
+    and the sample's device indices."""
+    gen = torch.Generator().manual_seed(seed)
+    idx = torch.randint(0, p.n, (nsample,), generator=gen).to(DEV)
+    snap = dict(idx=idx, x0=positions_fp32(p, bits, cfg, idx), u0=[np64(t[idx]) for t in p.u],
+                w0=np64(p.w[idx]) if p.w is not None else np.full(nsample, sp.w0))
+    L.pic_gather_push_deposit(ctx, sp, p, fields)
+    torch.cuda.synchronize()
+    snap.update(x1=positions_fp32(p, bits, cfg, idx), u1=[np64(t[idx]) for t in p.u],
+                chi1=np64(p.chi[idx]) if p.chi is not None else None)
+    return snap
+
+
+def oracle_sample(cfg: L.Config, sp: L.Species, snap, F):
+    """The oracle's push of the sampled particles with fields F; also chi at
+    x^{n+1/2} and u^{n+1/2} = (u^n + u^{n+1}) / 2 (the push's chi, Sec. IV)."""
+    g = oracle_grid(cfg)
+    n = len(snap["w0"])
+    osp = O.Species(sp.q, sp.m, [a.copy() for a in snap["x0"]], [a.copy() for a in snap["u0"]],
+                    snap["w0"].copy(), sp.w0)
+    J = [np.zeros(F[0].shape) for _ in range(3)]
+    O.push(g, osp, F, J)
+    chi = np.zeros(n)
+    scale = np.zeros(n)  # hbar w (gamma |E| + |u| |B|): size of the terms chi cancels
+    if cfg.hbar_omega_mc2 > 0:
+        for k in range(n):
+            u0 = np.array([snap["u0"][a][k] for a in range(3)])
+            g0 = math.sqrt(1.0 + u0 @ u0)
+            xh = [snap["x0"][a][k] + 0.5 * cfg.dt * u0[a] / g0 for a in range(cfg.dim)]
+            xh += [0.0] * (3 - cfg.dim)
+            EB = O.gather(g, F, xh)
+            uh = 0.5 * (u0 + np.array([osp.u[a][k] for a in range(3)]))
+            gh = math.sqrt(1.0 + uh @ uh)
+            chi[k] = O.chi(cfg.hbar_omega_mc2, gh, uh, EB[:3], EB[3:])
+            scale[k] = cfg.hbar_omega_mc2 * (gh * np.linalg.norm(EB[:3]) + np.linalg.norm(uh) * np.linalg.norm(EB[3:]))
+    return osp, chi, scale
+
+
+def push_errors(cfg: L.Config, snap, osp):
+    """Max relative momentum error and max position error in cells."""
+    du = max(float(np.max(np.abs(snap["u1"][a] - osp.u[a]) / (1.0 + np.abs(osp.u[a])))) for a in range(3))
+    dx = 0.0
+    for a in range(cfg.dim):
+        Lx = cfg.n[a] * cfg.d[a]
+        dx = max(dx, float(np.max(np.abs(periodic_dx(snap["x1"][a], osp.x[a], Lx)))) / cfg.d[a])
+    return du, dx

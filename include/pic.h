@@ -223,7 +223,8 @@ pic_status pic_sort(void *ctx, const pic_particles *src, const pic_particles *ds
  * tau_thr from the counter (id_lo, id_hi, step, 1); parent position and
  * weight.  F and the inverse spectra come from tables the library computes
  * with its own quadrature at pic_init (PIC_QED_TABLE), or from the trained
- * network (PIC_QED_MLP; chi outside the trained range uses the tables).
+ * network (PIC_QED_MLP; chi outside the trained range, or within 0.1 decade
+ * of its ends, uses the tables).
  * Requires hbar_omega_mc2 > 0.
  * Method II (rejection; the tau and tau_thr of existing particles are neither
  * read nor written): with

@@ -305,9 +305,15 @@ __device__ __forceinline__ void mlp_infer_tile(const MlpFrags &F, InferLds &L, i
 
 constexpr int INFER_THREADS = 256;
 
+// the network answers inside its training range less this margin (decades
+// of chi) at both ends, where its fit is least constrained; the tables
+// answer elsewhere
+constexpr float MLP_EDGE = 0.1f;
+
 // network inference for the QED step: one output pair (F, sample) per
 // particle; the level r is the uniform the particle uses if its event fires
-// this step.  chi outside the trained range falls back to the tables.  Each
+// this step.  chi outside the trained range less MLP_EDGE falls back to the
+// tables.  Each
 // wavefront prepares 64 particles' inputs (one per lane), runs four tiles,
 // and decodes one output per lane.
 __global__ void __launch_bounds__(INFER_THREADS, 4) mlp_qed_kernel(const void *mlp, const float *tab, QedSpeciesView v,
@@ -339,7 +345,7 @@ __global__ void __launch_bounds__(INFER_THREADS, 4) mlp_qed_kernel(const void *m
         if (p < v.n) {
             const float lc = chi > 0.0f ? log10f(chi) : -100.0f;
             float F_, smp;
-            if (lc >= lo && lc <= (float)QED_LOG_CHI_MAX) {
+            if (lc >= lo + MLP_EDGE && lc <= (float)QED_LOG_CHI_MAX - MLP_EDGE) {
                 const float y[2] = {L.Y[l][0], L.Y[l][1]};
                 mlp_decode(proc, chi, y, F_, smp);
             } else {

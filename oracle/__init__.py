@@ -40,7 +40,8 @@ def lib():
 
 class _Grid(C.Structure):
     _fields_ = [("dim", C.c_int32), ("order", C.c_int32), ("n", C.c_int64 * 3),
-                ("d", C.c_double * 3), ("dt", C.c_double), ("pusher", C.c_int32)]
+                ("d", C.c_double * 3), ("dt", C.c_double), ("pusher", C.c_int32),
+                ("absorb_x", C.c_int32), ("laser", C.c_double * 4), ("laser_circular", C.c_int32)]
 
 
 @dataclass
@@ -53,12 +54,19 @@ class Grid:
     dt: float
     order: int = 2
     pusher: int = 0  # 0 Boris, 1 Vay
+    absorb_x: int = 0  # 1: absorbing x faces (fields)
+    laser: tuple = (0.0, 0.0, 0.0, 0.0)  # a0, waist, duration, t0 of the pulse injected at x = 0
+    laser_circular: int = 0
 
     def c(self) -> _Grid:
         g = _Grid()
         g.dim = self.dim
         g.order = self.order
         g.pusher = self.pusher
+        g.absorb_x = self.absorb_x
+        for a in range(4):
+            g.laser[a] = float(self.laser[a])
+        g.laser_circular = self.laser_circular
         n = list(self.n) + [1] * (3 - len(self.n))
         d = list(self.d) + [1.0] * (3 - len(self.d))
         for a in range(3):
@@ -95,7 +103,7 @@ def _declare(L):
     L.orc_deposit.argtypes = [_GP, C.c_double, _D, _D, C.c_double, _PP]
     L.orc_push.argtypes = [_GP, C.c_double, C.c_double, C.c_int64, _PP, _PP, _D, C.c_double,
                            _PP, _PP, _D]
-    L.orc_half_e.argtypes = [_GP, _PP, _PP, _PP]
+    L.orc_half_e.argtypes = [_GP, _PP, _PP, _PP, C.c_double]
     L.orc_half_b.argtypes = [_GP, _PP, _PP]
     L.orc_field_energy.argtypes = [_GP, _PP]
     L.orc_field_energy.restype = C.c_double
@@ -174,8 +182,9 @@ def deposit(grid: Grid, qw: float, xh, xe, vz: float, J):
     lib().orc_deposit(C.byref(grid.c()), qw, _dp(xh), _dp(xe), vz, _pp(J))
 
 
-def half_e(grid: Grid, E, B, J):
-    lib().orc_half_e(C.byref(grid.c()), _pp(E), _pp(B), _pp(J))
+def half_e(grid: Grid, E, B, J, t: float = 0.0):
+    """E half step; t is the time of E on entry (used by the injected pulse)."""
+    lib().orc_half_e(C.byref(grid.c()), _pp(E), _pp(B), _pp(J), float(t))
 
 
 def half_b(grid: Grid, E, B):
@@ -256,6 +265,7 @@ class State:
     B: list
     J: list
     species: list = field(default_factory=list)
+    t: float = 0.0
 
     @staticmethod
     def zeros(grid: Grid):
@@ -281,7 +291,7 @@ def step(st: State, diag=None):
     B -= dt/2 curl E; E += dt/2 (curl B - J^{n+1}).  J^n is the current left
     in st.J by the previous step (zero at start)."""
     g = st.grid
-    half_e(g, st.E, st.B, st.J)
+    half_e(g, st.E, st.B, st.J, st.t)
     half_b(g, st.E, st.B)
     for a in range(3):
         st.J[a][...] = 0.0
@@ -289,7 +299,8 @@ def step(st: State, diag=None):
     for sp in st.species:
         push(g, sp, F, st.J, diag)
     half_b(g, st.E, st.B)
-    half_e(g, st.E, st.B, st.J)
+    half_e(g, st.E, st.B, st.J, st.t + 0.5 * g.dt)
+    st.t += g.dt
 
 
 def kinetic_energy(grid: Grid, sp: Species) -> float:

@@ -38,10 +38,16 @@ typedef struct {
     double d[3];     /* cell sizes dx, dy, dz                            */
     double dt;       /* time step                                        */
     int32_t pusher;  /* 0 Boris (Sec. II.C), 1 Vay                       */
+    int32_t absorb_x;  /* 1: absorbing faces at x = 0 and x = (n-1) dx  */
+    double laser[4];   /* a0, waist, duration, t0 of the pulse injected
+                          through x = 0 (a0 = 0: none)                   */
+    int32_t laser_circular;
 } orc_grid;
 
 /* Component stagger in half cells, indexed [component][axis];
  * components 0..2 = E_x,E_y,E_z (also J), 3..5 = B_x,B_y,B_z. */
+#define ORC_PI 3.14159265358979323846
+
 static const double STAG3[6][3] = {
     {0.5, 0.0, 0.0}, {0.0, 0.5, 0.0}, {0.0, 0.0, 0.5},
     {0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}, {0.5, 0.5, 0.0}};
@@ -350,20 +356,59 @@ void orc_push(const orc_grid *g, double q, double m, int64_t np, double *const *
 }
 
 /*
+ * Field of the pulse injected through x = 0, component 1 (E_y) or 2 (E_z),
+ * at (x, y, z) and time t in laser units (w = k = c = 1):
+ *   a0 exp(-r^2/w^2) S((t - t0 - x)/tau) sin(x - t  [+ pi/2 for E_z]),
+ * S(s) = sin^2(pi s) on [0, 1] and 0 outside, r measured from the box axis;
+ * E_z only for circular polarisation.
+ */
+static double orc_incident(const orc_grid *g, int comp, double x, double y, double z, double t) {
+    double a0 = g->laser[0], w = g->laser[1], tau = g->laser[2], t0 = g->laser[3];
+    if (a0 == 0.0 || (comp == 2 && !g->laser_circular)) return 0.0;
+    double s = (t - t0 - x) / tau;
+    if (s <= 0.0 || s >= 1.0) return 0.0;
+    double yc = 0.5 * g->n[1] * g->d[1], zc = 0.5 * g->n[2] * g->d[2];
+    double r2 = (y - yc) * (y - yc) + (g->dim == 3 ? (z - zc) * (z - zc) : 0.0);
+    double env = sin(ORC_PI * s);
+    return a0 * exp(-r2 / (w * w)) * env * env * sin(x - t + (comp == 2 ? 0.5 * ORC_PI : 0.0));
+}
+
+/*
  * Half field updates, Sec. II.B Eqs. 9-10 split in two halves (Sec. II.F):
- *   orc_half_e:  E += (dt/2) (curl B - J)
+ *   orc_half_e:  E += (dt/2) (curl B - J)      (t: time of E on entry)
  *   orc_half_b:  B -= (dt/2) curl E
  * Central differences on the Yee stagger, periodic.  A full step is
  * half_e(J^n); half_b; [particles]; half_b; half_e(J^{n+1}).
+ *
+ * Absorbing x faces (absorb_x): the domain is x in [0, (n-1) dx].  E_y and
+ * E_z on the faces x = 0 and x = (n-1) dx follow the first-order Mur rule,
+ * the one-way wave equation E_t = -/+ E_x centred between the face node and
+ * its neighbour over the half step h = dt/2:
+ *   E_0^new = E_1^old + k (E_1^new - E_0^old),   k = (h - dx) / (h + dx),
+ * and the mirror at the far face; at x = 0 it acts on E - E_inc, so the
+ * injected pulse enters while outgoing waves leave.  E_x, B_y, B_z half a
+ * cell beyond the far face lie outside and stay 0.
  */
 void orc_half_e(const orc_grid *g, double *const *E, const double *const *B,
-                const double *const *J) {
+                const double *const *J, double t) {
     const double h = 0.5 * g->dt;
     const double ix = 1.0 / g->d[0], iy = 1.0 / g->d[1];
     const double iz = g->dim == 3 ? 1.0 / g->d[2] : 0.0;
+    const int64_t nx = g->n[0], nyz = g->n[1] * g->n[2];
+    const int ab = g->absorb_x;
+    double *old = NULL; /* [face node 0, 1, nx-2, nx-1][E_y, E_z][j + ny k] */
+    const int64_t fx[4] = {0, 1, nx - 2, nx - 1};
+    if (ab) {
+        old = (double *)malloc(sizeof(double) * 8 * (size_t)nyz);
+        for (int f = 0; f < 4; ++f)
+            for (int cmp = 0; cmp < 2; ++cmp)
+                for (int64_t k = 0; k < g->n[2]; ++k)
+                    for (int64_t j = 0; j < g->n[1]; ++j)
+                        old[(f * 2 + cmp) * nyz + j + g->n[1] * k] = E[1 + cmp][idx3(g, fx[f], j, k)];
+    }
     for (int64_t k = 0; k < g->n[2]; ++k)
         for (int64_t j = 0; j < g->n[1]; ++j)
-            for (int64_t i = 0; i < g->n[0]; ++i) {
+            for (int64_t i = 0; i < nx; ++i) {
                 int64_t c = idx3(g, i, j, k);
                 /* E_x(i+1/2,j,k): dBz/dy - dBy/dz */
                 double cbx = (B[2][c] - B[2][idx3(g, i, j - 1, k)]) * iy -
@@ -374,10 +419,36 @@ void orc_half_e(const orc_grid *g, double *const *E, const double *const *B,
                 /* E_z(i,j,k+1/2): dBy/dx - dBx/dy */
                 double cbz = (B[1][c] - B[1][idx3(g, i - 1, j, k)]) * ix -
                              (B[0][c] - B[0][idx3(g, i, j - 1, k)]) * iy;
-                E[0][c] += h * (cbx - J[0][c]);
-                E[1][c] += h * (cby - J[1][c]);
-                E[2][c] += h * (cbz - J[2][c]);
+                if (ab && i == nx - 1) {
+                    E[0][c] = 0.0;
+                } else {
+                    E[0][c] += h * (cbx - J[0][c]);
+                }
+                if (!ab || (i != 0 && i != nx - 1)) {
+                    E[1][c] += h * (cby - J[1][c]);
+                    E[2][c] += h * (cbz - J[2][c]);
+                }
             }
+    if (ab) {
+        const double km = (h - g->d[0]) / (h + g->d[0]);
+        for (int64_t k = 0; k < g->n[2]; ++k)
+            for (int64_t j = 0; j < g->n[1]; ++j)
+                for (int cmp = 0; cmp < 2; ++cmp) {
+                    const int comp = 1 + cmp;
+                    const int64_t q = j + g->n[1] * k;
+                    /* stagger of the component: E_y at y + dy/2, E_z at z + dz/2 */
+                    const double y = (j + (comp == 1 ? 0.5 : 0.0)) * g->d[1];
+                    const double z = g->dim == 3 ? (k + (comp == 2 ? 0.5 : 0.0)) * g->d[2] : 0.0;
+                    const double x1 = g->d[0];
+                    double s0o = old[(0 * 2 + cmp) * nyz + q] - orc_incident(g, comp, 0.0, y, z, t);
+                    double s1o = old[(1 * 2 + cmp) * nyz + q] - orc_incident(g, comp, x1, y, z, t);
+                    double s1n = E[comp][idx3(g, 1, j, k)] - orc_incident(g, comp, x1, y, z, t + h);
+                    E[comp][idx3(g, 0, j, k)] = orc_incident(g, comp, 0.0, y, z, t + h) + s1o + km * (s1n - s0o);
+                    double e2o = old[(2 * 2 + cmp) * nyz + q], e3o = old[(3 * 2 + cmp) * nyz + q];
+                    E[comp][idx3(g, nx - 1, j, k)] = e2o + km * (E[comp][idx3(g, nx - 2, j, k)] - e3o);
+                }
+        free(old);
+    }
 }
 
 void orc_half_b(const orc_grid *g, const double *const *E, double *const *B) {
@@ -398,8 +469,13 @@ void orc_half_b(const orc_grid *g, const double *const *E, double *const *B) {
                 double cez = (E[1][idx3(g, i + 1, j, k)] - E[1][c]) * ix -
                              (E[0][idx3(g, i, j + 1, k)] - E[0][c]) * iy;
                 B[0][c] -= h * cex;
-                B[1][c] -= h * cey;
-                B[2][c] -= h * cez;
+                if (g->absorb_x && i == g->n[0] - 1) {
+                    B[1][c] = 0.0;
+                    B[2][c] = 0.0;
+                } else {
+                    B[1][c] -= h * cey;
+                    B[2][c] -= h * cez;
+                }
             }
 }
 

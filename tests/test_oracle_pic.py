@@ -505,3 +505,64 @@ def test_sort_empty_input():
     g = O.Grid(2, (8, 8), (1.0, 1.0), 0.1, 2)
     perm, start = O.sort(g, (4, 4), [np.zeros(0, np.int32), np.zeros(0, np.int32)])
     assert len(perm) == 0 and list(start) == [0] * 5
+
+
+# -------------------------------------- absorbing x faces and injection
+
+def _vacuum_box(absorb, n=(240, 64), laser=(0.0, 0.0, 0.0, 0.0)):
+    lam = 2 * math.pi
+    d = (lam / 20, lam / 20)
+    g = O.Grid(2, n, d, 0.95 / math.sqrt(sum(1 / v ** 2 for v in d)), 2, absorb_x=absorb, laser=laser)
+    return g, O.State.zeros(g)
+
+
+def test_absorbing_faces_let_a_pulse_leave():
+    """A 3-cycle Gaussian pulse moving +x leaves through the first-order
+    absorbing face with 0.2% of its energy left behind; with periodic faces
+    it keeps all of it (vacuum: field energy is conserved)."""
+    lam = 2 * math.pi
+    left = {}
+    for absorb in (0, 1):
+        g, st = _vacuum_box(absorb)
+        nx, ny = g.n
+        i = np.arange(nx)[None, :]
+        j = np.arange(ny)[:, None]
+
+        def prof(sx, sy):
+            x, y = (i + sx) * g.d[0], (j + sy) * g.d[1]
+            xi = (x - 3 * lam) / (3 * lam)
+            env = np.where((xi >= 0) & (xi <= 1), np.sin(np.pi * xi) ** 2, 0.0)
+            return env * np.exp(-((y - ny * g.d[1] / 2) ** 2) / (2 * lam) ** 2) * np.sin(x)
+        st.E[1][0] = prof(0, 0.5)
+        st.B[2][0] = prof(0.5, 0.5)
+        e0 = O.field_energy(g, st.E, st.B)
+        for _ in range(int(9 * lam / g.dt) + 20):
+            O.step(st)
+        left[absorb] = O.field_energy(g, st.E, st.B) / e0
+    assert left[0] > 0.999
+    assert left[1] < 0.01
+
+
+def test_injected_pulse_energy_speed_and_amplitude():
+    """A plane pulse (a0 = 1, sin^2 field envelope of 6 periods) injected
+    through x = 0 carries a0^2/2 * 3/8 * tau * L_y of field energy, moves at
+    c and peaks at a0, up to the scheme's dispersion at 20 cells/lambda."""
+    lam = 2 * math.pi
+    g, st = _vacuum_box(1, laser=(1.0, 1e6, 6 * lam, 0.0))
+    ny = g.n[1]
+    ip = int(4 * lam / g.d[0])
+    peak = 0.0
+    while st.t < 7.5 * lam:
+        O.step(st)
+        peak = max(peak, abs(st.E[1][0][ny // 2, ip]))
+    expected = 0.5 * 3 / 8 * 6 * lam * ny * g.d[1]
+    assert O.field_energy(g, st.E, st.B) == pytest.approx(expected, rel=0.03)
+    assert peak == pytest.approx(1.0, rel=0.05)
+
+    def centroid():
+        e = st.E[1][0] ** 2
+        return float((e * (np.arange(g.n[0]) * g.d[0])[None, :]).sum() / e.sum())
+    x1, t1 = centroid(), st.t
+    for _ in range(60):
+        O.step(st)
+    assert (centroid() - x1) / (st.t - t1) == pytest.approx(1.0, rel=0.02)

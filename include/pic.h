@@ -69,7 +69,14 @@ typedef enum {
 } pic_status;
 
 enum { PIC_FP32_MIXED = 0, PIC_FP64_PLAIN = 1 };
-enum { PIC_BC_PERIODIC = 0 };
+/* Boundaries, per axis.  PIC_BC_ABSORB is built for x (bc[0]) and for the
+ * fields: the domain is x in [0, (n[0]-1) d[0]], and E_y, E_z on its two faces
+ * follow the first-order Mur rule over each half step (the absorbing face of
+ * the paper's 1D case, Sec. III; its scheme is not printed), at x = 0 acting
+ * on E - E_inc so that a pulse set by pic_set_laser enters.  Particles still
+ * wrap periodically along x: keep them the stencil reach plus their travel
+ * away from both faces. */
+enum { PIC_BC_PERIODIC = 0, PIC_BC_ABSORB = 1 };
 /* Momentum update: Boris (Sec. II.C, Eqs. 13-16) or Vay, which Sec. II.C
  * names for fields whose electric and magnetic forces nearly cancel; Vay
  * solves u^{n+1} - u^n = q_m dt (E + (v^n + v^{n+1})/2 x B) in closed form
@@ -96,7 +103,7 @@ typedef struct {
     int64_t n[3];           /* cells per axis; n[2] = 1 when dim = 2                  */
     double d[3];            /* cell sizes (c/w_r)                                     */
     double dt;              /* step (1/w_r); PIC_E_CFL unless dt*sqrt(sum 1/d^2) <= 1  */
-    int32_t bc[3];          /* PIC_BC_PERIODIC (fields and particles)                 */
+    int32_t bc[3];          /* PIC_BC_PERIODIC; bc[0] may be PIC_BC_ABSORB (fields)     */
     int32_t tile[3];        /* FP32 path tile in cells (must divide n); 0 = default   */
     uint64_t seed;          /* key of the counter-based generator (QED)               */
     double hbar_omega_mc2;  /* hbar w_r / (m_e c^2) for chi (2.4263e-6 at 1 um);
@@ -297,6 +304,25 @@ pic_status pic_qed_training_data(void *ctx, int64_t n, uint64_t seed, float *x, 
  * proc 0 photon emission, 1 pair creation. */
 pic_status pic_qed_table_lookup(void *ctx, int32_t proc, int32_t what, const float *chi, const float *r,
                                 int64_t n, float *out, void *stream);
+
+/*
+ * Pulse injected through the x = 0 face (requires bc[0] = PIC_BC_ABSORB), in
+ * laser units (w_r = w_L: wavelength 2 pi, critical density 1):
+ *   E_y = a0 exp(-r^2/waist^2) S((t - t0 - x)/duration) sin(x - t),
+ *   E_z = the same with sin(x - t + pi/2) when circular, else 0,
+ * S(s) = sin^2(pi s) on [0, 1], r from the box's transverse axis.  `t` sets
+ * the library's field clock: the time of E and B at the next
+ * pic_yee_step(half = 1); each half = 2 call advances it by dt.  a0 = 0
+ * switches the pulse off.  Copies *laser.
+ */
+typedef struct {
+    double a0;          /* peak field amplitude (m c w_r / e)           */
+    double waist;       /* 1/e field radius (c/w_r)                      */
+    double duration;    /* length of the sin^2 field envelope (1/w_r)    */
+    double t0;          /* time the envelope starts entering at x = 0    */
+    int32_t circular;   /* 0: E along y; 1: circular (a0 on E_y and E_z) */
+} pic_laser;
+pic_status pic_set_laser(void *ctx, const pic_laser *laser, double t);
 
 /* Synchronize `stream`, return the device status word in *flags (nullable)
  * and the number of straggler particles since the last check in

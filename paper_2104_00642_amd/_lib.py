@@ -27,13 +27,14 @@ PIC_F_NONFINITE, PIC_F_OFFSET, PIC_F_STRAGGLER, PIC_F_CAPACITY, PIC_F_QED_SATURA
 
 PIC_QED_TABLE, PIC_QED_MLP, PIC_QED_METHOD2 = 0, 1, 2
 PIC_PUSH_BORIS, PIC_PUSH_VAY = 0, 1
+PIC_BC_ABSORB = 1
 PIC_MLP_NPARAM = 4610
 PIC_MLP_BYTES = 9480
 PIC_MLP_STATE_FLOATS = 4 * PIC_MLP_NPARAM + 1
 
 EXPORTED = ["pic_init", "pic_destroy", "pic_last_error", "pic_get_layout", "pic_gather_push_deposit",
             "pic_yee_step", "pic_sort", "pic_check", "pic_qed_step", "pic_mlp_forward", "pic_mlp_grad",
-            "pic_mlp_train", "pic_qed_training_data", "pic_qed_table_lookup"]
+            "pic_mlp_train", "pic_qed_training_data", "pic_qed_table_lookup", "pic_set_laser"]
 
 
 class PicError(RuntimeError):
@@ -48,6 +49,11 @@ class pic_config(C.Structure):
                 ("drift", C.c_int32), ("n", C.c_int64 * 3), ("d", C.c_double * 3),
                 ("dt", C.c_double), ("bc", C.c_int32 * 3), ("tile", C.c_int32 * 3),
                 ("seed", C.c_uint64), ("hbar_omega_mc2", C.c_double), ("pusher", C.c_int32)]
+
+
+class pic_laser(C.Structure):
+    _fields_ = [("a0", C.c_double), ("waist", C.c_double), ("duration", C.c_double), ("t0", C.c_double),
+                ("circular", C.c_int32)]
 
 
 class pic_species(C.Structure):
@@ -96,6 +102,8 @@ def lib():
                                               C.POINTER(pic_fields), C.c_void_p, C.c_void_p]
         L.pic_gather_push_deposit.restype = C.c_int
         L.pic_yee_step.argtypes = [C.c_void_p, C.c_int32, C.POINTER(pic_fields), C.c_void_p, C.c_void_p]
+        L.pic_set_laser.argtypes = [C.c_void_p, C.POINTER(pic_laser), C.c_double]
+        L.pic_set_laser.restype = C.c_int
         L.pic_yee_step.restype = C.c_int
         L.pic_sort.argtypes = [C.c_void_p, C.POINTER(pic_particles), C.POINTER(pic_particles), C.c_void_p]
         L.pic_sort.restype = C.c_int
@@ -152,6 +160,7 @@ class Config:
     seed: int = 0
     hbar_omega_mc2: float = 0.0
     pusher: int = PIC_PUSH_BORIS
+    bc_x: int = PIC_BC_PERIODIC  # or PIC_BC_ABSORB (fields)
 
     def c(self) -> pic_config:
         cfg = pic_config()
@@ -160,7 +169,8 @@ class Config:
         d = list(self.d) + [1.0] * (3 - len(self.d))
         t = list(self.tile) + [0] * (3 - len(self.tile))
         for a in range(3):
-            cfg.n[a], cfg.d[a], cfg.tile[a], cfg.bc[a] = int(n[a]), float(d[a]), int(t[a]), PIC_BC_PERIODIC
+            cfg.n[a], cfg.d[a], cfg.tile[a] = int(n[a]), float(d[a]), int(t[a])
+            cfg.bc[a] = int(self.bc_x) if a == 0 else PIC_BC_PERIODIC
         cfg.dt = float(self.dt)
         cfg.seed = int(self.seed)
         cfg.hbar_omega_mc2 = float(self.hbar_omega_mc2)
@@ -313,6 +323,12 @@ def pic_yee_step(ctx: Context, half: int, f: Fields, diag: Optional[torch.Tensor
     fc = f.c()
     st = lib().pic_yee_step(C.c_void_p(ctx.handle), int(half), C.byref(fc), _ptr(diag), _stream(stream))
     _check(st, C.c_void_p(ctx.handle))
+
+
+def pic_set_laser(ctx: Context, a0: float, waist: float, duration: float, t0: float, circular: bool = False,
+                  t: float = 0.0):
+    las = pic_laser(float(a0), float(waist), float(duration), float(t0), int(bool(circular)))
+    _check(lib().pic_set_laser(C.c_void_p(ctx.handle), C.byref(las), float(t)), C.c_void_p(ctx.handle))
 
 
 def pic_sort(ctx: Context, src: Particles, dst: Particles, stream=None):

@@ -133,8 +133,8 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
                 return fail(nullptr, PIC_E_ARG, "cells per axis must be in [8, 2^20]");
             if (!finite_pos(cfg->d[a])) return fail(nullptr, PIC_E_ARG, "cell sizes must be > 0");
             s += 1.0 / (cfg->d[a] * cfg->d[a]);
-            if (cfg->bc[a] != PIC_BC_PERIODIC)
-                return fail(nullptr, PIC_E_UNSUPPORTED, "only periodic boundaries are built");
+            if (cfg->bc[a] != PIC_BC_PERIODIC && !(a == 0 && cfg->bc[a] == PIC_BC_ABSORB))
+                return fail(nullptr, PIC_E_UNSUPPORTED, "boundaries: periodic, or absorbing along x");
         } else if (cfg->n[a] != 1) {
             return fail(nullptr, PIC_E_ARG, "n[2] must be 1 in 2D");
         }
@@ -214,10 +214,16 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
         delete c;
         return st;
     }
+    if (e == hipSuccess && cfg->bc[0] == PIC_BC_ABSORB)
+        e = hipMalloc(&c->mur_old, sizeof(double) * 8 * (size_t)cfg->n[1] * (size_t)cfg->n[2]);
+    if (e != hipSuccess) {
+        pic_status st = hip_fail(nullptr, e, "pic_init");
+        pic_destroy(c);
+        return st;
+    }
     if (ensure_partials(c, 2 * (size_t)c->ntiles + 1024) != PIC_OK) {
         g_init_error = c->err;
-        hipFree(c->status);
-        delete c;
+        pic_destroy(c);
         return PIC_E_NOMEM;
     }
     if (cfg->hbar_omega_mc2 > 0.0) {
@@ -253,7 +259,21 @@ extern "C" void pic_destroy(void *ctx) {
     hipFree(c->final_perm);
     hipFree(c->qed.dev);
     hipFree(c->mlp_scratch);
+    hipFree(c->mur_old);
     delete c;
+}
+
+extern "C" pic_status pic_set_laser(void *ctx, const pic_laser *laser, double t) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (!laser || !isfinite(t)) return fail(c, PIC_E_ARG, "null laser or non-finite time");
+    if (c->cfg.bc[0] != PIC_BC_ABSORB) return fail(c, PIC_E_ARG, "injection needs bc[0] = PIC_BC_ABSORB");
+    if (!isfinite(laser->a0) || !isfinite(laser->t0) ||
+        (laser->a0 != 0.0 && !(laser->waist > 0.0 && laser->duration > 0.0)))
+        return fail(c, PIC_E_ARG, "laser: finite a0 and t0, positive waist and duration");
+    c->laser = *laser;
+    c->time = t;
+    return PIC_OK;
 }
 
 extern "C" const char *pic_last_error(const void *ctx) {

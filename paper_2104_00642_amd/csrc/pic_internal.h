@@ -48,6 +48,11 @@ struct Ctx {
     QedTables qed;
     float *mlp_scratch = nullptr;
     size_t mlp_scratch_cap = 0;  // floats
+    // absorbing x faces: face values of E_y, E_z saved by the E half step
+    // (8 x n1 x n2 reals), the injected pulse and the field clock
+    void *mur_old = nullptr;
+    pic_laser laser{};
+    double time = 0.0;
     std::string err;
 };
 

@@ -4,7 +4,12 @@
 // Bandwidth-bound stencil: one thread per cell, x-fastest so that every
 // wavefront reads and writes contiguous 256-byte rows; the -1/+1 neighbours
 // along y/z come from rows the neighbouring wavefronts already pulled into L2.
-// Periodic in every axis.
+// Periodic in every axis, or along x absorbing (PIC_BC_ABSORB): the domain is
+// x in [0, (n-1) dx]; E_y, E_z on its two faces follow the first-order Mur
+// rule E_0^new = E_1^old + k (E_1^new - E_0^old), k = (h - dx)/(h + dx) over
+// each half step h, applied at x = 0 to E - E_inc of the injected pulse; the
+// E kernel saves the old face values and a second kernel applies the rule.
+// E_x, B_y, B_z half a cell beyond the far face stay 0.
 #include "device_common.h"
 #include "pic_internal.h"
 
@@ -18,7 +23,30 @@ struct YeeArgs {
     int n[3];
     R h;          // dt / 2
     R inv_d[3];   // 1/d (0 for z in 2D)
+    int absorb;   // absorbing x faces
+    R *old;       // [x node 0, 1, n-2, n-1][E_y, E_z][j + n1 k]: face values before the E update
 };
+
+// the pulse injected through x = 0 (pic_laser), evaluated in FP64
+struct LaserArgs {
+    double a0, waist, tau, t0;
+    int circular;
+    double d[3], yc, zc;
+    int dim;
+};
+
+// E_y (comp 1) or E_z (comp 2) of the injected pulse at (x, y, z), time t
+// (laser units): a0 exp(-r^2/w^2) S((t - t0 - x)/tau) sin(x - t [+ pi/2]),
+// S(s) = sin^2(pi s) on [0, 1]
+__device__ double incident(const LaserArgs &L, int comp, double x, double y, double z, double t) {
+    if (L.a0 == 0.0 || (comp == 2 && !L.circular)) return 0.0;
+    const double s = (t - L.t0 - x) / L.tau;
+    if (s <= 0.0 || s >= 1.0) return 0.0;
+    const double r2 = (y - L.yc) * (y - L.yc) + (L.dim == 3 ? (z - L.zc) * (z - L.zc) : 0.0);
+    const double env = sin(3.14159265358979323846 * s);
+    return L.a0 * exp(-r2 / (L.waist * L.waist)) * env * env *
+           sin(x - t + (comp == 2 ? 1.57079632679489661923 : 0.0));
+}
 
 // E += (dt/2)(curl B - J)
 template <typename R, int DIM>
@@ -41,9 +69,50 @@ __global__ void __launch_bounds__(256) yee_e_kernel(YeeArgs<R> a) {
         cx -= (by - By[ckm]) * a.inv_d[2];
         cy += (bx - Bx[ckm]) * a.inv_d[2];
     }
+    if (a.absorb) {
+        const int n0 = a.n[0];
+        const int f = i == 0 ? 0 : i == 1 ? 1 : i == n0 - 2 ? 2 : i == n0 - 1 ? 3 : -1;
+        if (f >= 0) {
+            const int64_t nyz = (int64_t)a.n[1] * a.n[2], q = j + (int64_t)a.n[1] * k;
+            a.old[(2 * f) * nyz + q] = a.E[1][c];
+            a.old[(2 * f + 1) * nyz + q] = a.E[2][c];
+        }
+        a.E[0][c] = i == n0 - 1 ? R(0) : a.E[0][c] + a.h * (cx - a.J[0][c]);
+        if (i != 0 && i != n0 - 1) {
+            a.E[1][c] += a.h * (cy - a.J[1][c]);
+            a.E[2][c] += a.h * (cz - a.J[2][c]);
+        }
+        return;
+    }
     a.E[0][c] += a.h * (cx - a.J[0][c]);
     a.E[1][c] += a.h * (cy - a.J[1][c]);
     a.E[2][c] += a.h * (cz - a.J[2][c]);
+}
+
+// the Mur rule on the two x faces after an E half step from time t; one
+// thread per (j, k) line
+template <typename R>
+__global__ void __launch_bounds__(256) yee_mur_kernel(YeeArgs<R> a, LaserArgs L, double t, double km) {
+    const int64_t nyz = (int64_t)a.n[1] * a.n[2];
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nyz) return;
+    const int j = (int)(q % a.n[1]), k = (int)(q / a.n[1]);
+    const int n0 = a.n[0];
+    const int64_t row = (int64_t)n0 * q;
+    const double h = (double)a.h, dx = L.d[0];
+#pragma unroll
+    for (int cmp = 0; cmp < 2; ++cmp) {
+        const int comp = 1 + cmp;
+        R *E = a.E[comp];
+        const double y = (j + (comp == 1 ? 0.5 : 0.0)) * L.d[1];
+        const double z = L.dim == 3 ? (k + (comp == 2 ? 0.5 : 0.0)) * L.d[2] : 0.0;
+        const double s0o = (double)a.old[(0 + cmp) * nyz + q] - incident(L, comp, 0.0, y, z, t);
+        const double s1o = (double)a.old[(2 + cmp) * nyz + q] - incident(L, comp, dx, y, z, t);
+        const double s1n = (double)E[row + 1] - incident(L, comp, dx, y, z, t + h);
+        E[row] = (R)(incident(L, comp, 0.0, y, z, t + h) + s1o + km * (s1n - s0o));
+        const double e2o = (double)a.old[(4 + cmp) * nyz + q], e3o = (double)a.old[(6 + cmp) * nyz + q];
+        E[row + n0 - 1] = (R)(e2o + km * ((double)E[row + n0 - 2] - e3o));
+    }
 }
 
 // B -= (dt/2) curl E
@@ -68,6 +137,11 @@ __global__ void __launch_bounds__(256) yee_b_kernel(YeeArgs<R> a) {
         cy += (Ex[ckp] - ex) * a.inv_d[2];
     }
     a.B[0][c] -= a.h * cx;
+    if (a.absorb && i == a.n[0] - 1) {  // half a cell beyond the far face
+        a.B[1][c] = R(0);
+        a.B[2][c] = R(0);
+        return;
+    }
     a.B[1][c] -= a.h * cy;
     a.B[2][c] -= a.h * cz;
 }
@@ -116,11 +190,29 @@ static hipError_t yee_typed(Ctx *c, int half, const pic_fields *f, double *diag,
         a.inv_d[d] = d < c->dim ? (R)(1.0 / cfg.d[d]) : R(0);
     }
     a.h = (R)(0.5 * cfg.dt);
+    a.absorb = cfg.bc[0] == PIC_BC_ABSORB;
+    a.old = (R *)c->mur_old;
+    LaserArgs las{};
+    las.a0 = c->laser.a0;
+    las.waist = c->laser.waist;
+    las.tau = c->laser.duration;
+    las.t0 = c->laser.t0;
+    las.circular = c->laser.circular;
+    for (int d = 0; d < 3; ++d) las.d[d] = cfg.d[d];
+    las.yc = 0.5 * (double)cfg.n[1] * cfg.d[1];
+    las.zc = 0.5 * (double)cfg.n[2] * cfg.d[2];
+    las.dim = c->dim;
+    const double hh = 0.5 * cfg.dt, km = (hh - cfg.d[0]) / (hh + cfg.d[0]);
+    const int64_t nyz = cfg.n[1] * cfg.n[2];
     dim3 block(256), grid((unsigned)((cfg.n[0] + 255) / 256), (unsigned)cfg.n[1],
                           (unsigned)cfg.n[2]);
+    // time of E on entry: t_n for the first half, t_n + dt/2 for the second
+    const double t_e = c->time + (half == 1 ? 0.0 : hh);
     auto e_step = [&]() {
         if (c->dim == 3) yee_e_kernel<R, 3><<<grid, block, 0, s>>>(a);
         else yee_e_kernel<R, 2><<<grid, block, 0, s>>>(a);
+        if (a.absorb)
+            yee_mur_kernel<R><<<(unsigned)((nyz + 255) / 256), 256, 0, s>>>(a, las, t_e, km);
     };
     auto b_step = [&]() {
         if (c->dim == 3) yee_b_kernel<R, 3><<<grid, block, 0, s>>>(a);
@@ -132,6 +224,7 @@ static hipError_t yee_typed(Ctx *c, int half, const pic_fields *f, double *diag,
     } else {
         b_step();
         e_step();
+        c->time += cfg.dt;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !diag || half != 2) return e;

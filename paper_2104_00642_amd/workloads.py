@@ -261,6 +261,80 @@ def laser_plasma_3d(seed=645, scale=1, device="cuda", ppc=8, order=2, tile=(8, 8
                     [(-1.0, 1.0, el), (1.0, 1836.0, ion)], E, B, steps=500)
 
 
+def beam_wakefield_3d(seed=648, scale=1, device="cuda", ppc=8, beam_ppc=4, order=2, tile=(8, 8, 4),
+                      gamma_b=1957.0, nb=4.0, sigma=0.5, x_beam=3.0, uth=1e-3) -> Workload:
+    """3D3V beam-driven wakefield case (Sec. III(c)), plasma units (w_r = w_p,
+    so n_p = 1 and lambda_p = 2 pi): a 4 lambda_p x 2 lambda_p x 2 lambda_p box
+    of 512 x 192 x 192 cells, electrons and protons (mass 1836) at 8 per cell
+    each, and a 1-GeV drive electron beam (gamma 1957) with a bi-Gaussian
+    density of peak nb = 4 n_p and k_p sigma_x = k_p sigma_r = 0.5, sampled by
+    4 particles per cell within 4 sigma of its centre (x = x_beam lambda_p,
+    on the axis).  The beam's self-fields are those of the ultrarelativistic
+    limit of the rest-frame Poisson solution boosted to the lab: with the
+    line charge Lambda(x) = q nb exp(-(x-x_b)^2/(2 sigma^2)) 2 pi sigma^2 (div E
+    = rho in these units), E_r = Lambda (1 - exp(-r^2/(2 sigma^2))) / (2 pi r),
+    E_x = 0 (order 1/gamma^2), B = beta x^ x E.  Periodic box; `scale`
+    divides the cell counts."""
+    lam_p = 2.0 * math.pi
+    n = (512 // scale, 192 // scale, 192 // scale)
+    d = (4 * lam_p / 512, 2 * lam_p / 192, 2 * lam_p / 192)
+    cfg = Config(dim=3, n=n, d=d, dt=courant_dt(d), order=order, seed=seed, tile=tile,
+                 drift=0 if order == 4 else 1)
+    gen = torch.Generator(device=device).manual_seed(seed)
+    el = plasma(cfg, ppc, lambda ix: torch.ones_like(ix), gen, device, uth=uth)
+    ion = plasma(cfg, ppc, lambda ix: torch.ones_like(ix), gen, device, uth=uth / math.sqrt(1836.0))
+    # beam cells: within 4 sigma of the centre
+    xb = x_beam * lam_p if scale == 1 else 0.75 * n[0] * d[0]
+    yc, zc = 0.5 * n[1] * d[1], 0.5 * n[2] * d[2]
+    reach = 4 * sigma
+    ix = torch.arange(n[0], device=device)
+    iy = torch.arange(n[1], device=device)
+    iz = torch.arange(n[2], device=device)
+    cx = ix[((ix + 0.5) * d[0] - xb).abs() <= reach]
+    cy, cz = torch.meshgrid(iy, iz, indexing="ij")
+    r2 = ((cy + 0.5) * d[1] - yc) ** 2 + ((cz + 0.5) * d[2] - zc) ** 2
+    sel = r2 <= reach ** 2
+    cy, cz, r2 = cy[sel], cz[sel], r2[sel]
+    nt = cy.numel()
+    lin = torch.arange(cx.numel() * nt * beam_ppc, device=device) // beam_ppc
+    bx, tr = cx[lin // nt], lin % nt
+    by, bz = cy[tr], cz[tr]
+    N = lin.numel()
+    off = [torch.rand(N, generator=gen, device=device, dtype=torch.float64) for _ in range(3)]
+    dens = nb * torch.exp(-(((bx + 0.5) * d[0] - xb) ** 2) / (2 * sigma ** 2) - r2[tr].to(torch.float64) / (2 * sigma ** 2))
+    ub = math.sqrt(gamma_b ** 2 - 1.0)
+    u = [torch.full((N,), ub, device=device, dtype=torch.float64), torch.zeros(N, device=device, dtype=torch.float64),
+         torch.zeros(N, device=device, dtype=torch.float64)]
+    beam = RawParticles([bx.to(torch.int64), by.to(torch.int64), bz.to(torch.int64)], off, u,
+                        (dens / beam_ppc).to(torch.float64))
+    # self-fields at each component's Yee location
+    beta = ub / gamma_b
+    shape = (n[2], n[1], n[0])
+    k_i = torch.arange(n[2], device=device, dtype=torch.float64).view(-1, 1, 1)
+    j_i = torch.arange(n[1], device=device, dtype=torch.float64).view(1, -1, 1)
+    i_i = torch.arange(n[0], device=device, dtype=torch.float64).view(1, 1, -1)
+
+    def e_perp(sx, sy, sz):
+        x = (i_i + sx) * d[0]
+        y = (j_i + sy) * d[1] - yc
+        z = (k_i + sz) * d[2] - zc
+        r2_ = y ** 2 + z ** 2
+        lam_x = -1.0 * nb * torch.exp(-((x - xb) ** 2) / (2 * sigma ** 2)) * 2 * math.pi * sigma ** 2
+        er_over_r = lam_x * (1 - torch.exp(-r2_ / (2 * sigma ** 2))) / (2 * math.pi * torch.clamp(r2_, min=1e-30))
+        return (er_over_r * y).expand(shape), (er_over_r * z).expand(shape)
+
+    zero = lambda: torch.zeros(shape, device=device, dtype=torch.float64)  # noqa: E731
+    Ey, _ = e_perp(0, 0.5, 0)
+    _, Ez = e_perp(0, 0, 0.5)
+    _, Ez_at_by = e_perp(0.5, 0, 0.5)
+    Ey_at_bz, _ = e_perp(0.5, 0.5, 0)
+    E = [zero(), Ey.contiguous(), Ez.contiguous()]
+    B = [zero(), (-beta * Ez_at_by).contiguous(), (beta * Ey_at_bz).contiguous()]
+    shape_name = {1: "linear", 2: "quadratic", 4: "quartic"}[order]
+    return Workload(f"beam_wakefield_3d_{n[0]}x{n[1]}x{n[2]}_ppc{ppc}x2+{beam_ppc}_{shape_name}", cfg,
+                    [(-1.0, 1.0, el), (1.0, 1836.0, ion), (-1.0, 1.0, beam)], E, B, steps=0)
+
+
 QED_HBAR_OMEGA = 2.4263e-6  # hbar w_L / (m_e c^2) at lambda = 1 um
 
 

@@ -117,6 +117,14 @@ int orc_shape(int order, double xi, int64_t *i0, double *w) {
  * F[c] points at the plane of component c (E_x..E_z, B_x..B_z); x is the
  * absolute position.  Result in EB[6].
  */
+/* With absorbing x faces, nodes with x index outside [0, n) lie beyond the
+ * faces: no field there, and current deposited there leaves the domain. */
+static int beyond_x(const orc_grid *g, int64_t i) { return g->absorb_x && (i < 0 || i >= g->n[0]); }
+
+static void jadd(const orc_grid *g, double *J, int64_t i, int64_t j, int64_t k, double v) {
+    if (!beyond_x(g, i)) J[idx3(g, i, j, k)] += v;
+}
+
 void orc_gather(const orc_grid *g, const double *const *F, const double *x, double *EB) {
     for (int c = 0; c < 6; ++c) {
         int64_t i0[3] = {0, 0, 0};
@@ -132,8 +140,9 @@ void orc_gather(const orc_grid *g, const double *const *F, const double *x, doub
         for (int kk = 0; kk < nw[2]; ++kk)
             for (int jj = 0; jj < nw[1]; ++jj)
                 for (int ii = 0; ii < nw[0]; ++ii)
-                    acc += w[0][ii] * w[1][jj] * w[2][kk] *
-                           F[c][idx3(g, i0[0] + ii, i0[1] + jj, i0[2] + kk)];
+                    if (!beyond_x(g, i0[0] + ii))
+                        acc += w[0][ii] * w[1][jj] * w[2][kk] *
+                               F[c][idx3(g, i0[0] + ii, i0[1] + jj, i0[2] + kk)];
         EB[c] = acc;
     }
 }
@@ -245,7 +254,7 @@ void orc_deposit(const orc_grid *g, double qw, const double *xh, const double *x
             for (int ii = 0; ii < len - 1; ++ii) {
                 double Wx = DS[0][ii] * (S0[1][jj] + 0.5 * DS[1][jj]);
                 acc -= cx * Wx;
-                J[0][idx3(g, base[0] + ii, base[1] + jj, 0)] += acc;
+                jadd(g, J[0], base[0] + ii, base[1] + jj, 0, acc);
             }
         }
         /* J_y: running sum along y for each x column. */
@@ -254,7 +263,7 @@ void orc_deposit(const orc_grid *g, double qw, const double *xh, const double *x
             for (int jj = 0; jj < len - 1; ++jj) {
                 double Wy = (S0[0][ii] + 0.5 * DS[0][ii]) * DS[1][jj];
                 acc -= cy * Wy;
-                J[1][idx3(g, base[0] + ii, base[1] + jj, 0)] += acc;
+                jadd(g, J[1], base[0] + ii, base[1] + jj, 0, acc);
             }
         }
         /* J_z from the out-of-plane velocity. */
@@ -263,7 +272,7 @@ void orc_deposit(const orc_grid *g, double qw, const double *xh, const double *x
                 double Wz = S0[0][ii] * S0[1][jj] + 0.5 * DS[0][ii] * S0[1][jj] +
                             0.5 * S0[0][ii] * DS[1][jj] +
                             (1.0 / 3.0) * DS[0][ii] * DS[1][jj];
-                J[2][idx3(g, base[0] + ii, base[1] + jj, 0)] += qw * vz * Wz;
+                jadd(g, J[2], base[0] + ii, base[1] + jj, 0, qw * vz * Wz);
             }
         return;
     }
@@ -276,7 +285,7 @@ void orc_deposit(const orc_grid *g, double qw, const double *xh, const double *x
                                          0.5 * S0[1][jj] * DS[2][kk] +
                                          (1.0 / 3.0) * DS[1][jj] * DS[2][kk]);
                 acc -= cx * Wx;
-                J[0][idx3(g, base[0] + ii, base[1] + jj, base[2] + kk)] += acc;
+                jadd(g, J[0], base[0] + ii, base[1] + jj, base[2] + kk, acc);
             }
         }
     for (int kk = 0; kk < len; ++kk)
@@ -287,7 +296,7 @@ void orc_deposit(const orc_grid *g, double qw, const double *xh, const double *x
                                          0.5 * S0[0][ii] * DS[2][kk] +
                                          (1.0 / 3.0) * DS[0][ii] * DS[2][kk]);
                 acc -= cy * Wy;
-                J[1][idx3(g, base[0] + ii, base[1] + jj, base[2] + kk)] += acc;
+                jadd(g, J[1], base[0] + ii, base[1] + jj, base[2] + kk, acc);
             }
         }
     for (int jj = 0; jj < len; ++jj)
@@ -298,7 +307,7 @@ void orc_deposit(const orc_grid *g, double qw, const double *xh, const double *x
                                          0.5 * S0[0][ii] * DS[1][jj] +
                                          (1.0 / 3.0) * DS[0][ii] * DS[1][jj]);
                 acc -= cz * Wz;
-                J[2][idx3(g, base[0] + ii, base[1] + jj, base[2] + kk)] += acc;
+                jadd(g, J[2], base[0] + ii, base[1] + jj, base[2] + kk, acc);
             }
         }
 }
@@ -310,14 +319,16 @@ void orc_deposit(const orc_grid *g, double qw, const double *xh, const double *x
  *   2. gather E, B at xh (Eq. 19)
  *   3. Boris (Eqs. 13-16), or Vay (g->pusher = 1) -> u^{n+1}
  *   4. v = u^{n+1}/gamma^{n+1}; x^{n+1} = xh + dt v / 2; xe = xh + dt v  (Eq. 12)
- *   5. Esirkepov deposit of the move xh -> xe into J; periodic wrap of x.
+ *   5. Esirkepov deposit of the move xh -> xe into J; periodic wrap of x
+ *      (absorbing x faces: nothing is gathered from or deposited beyond
+ *      them, and a particle leaving [0, (n-1) dx] gets weight 0).
  * x[a], u[a]: per-axis arrays of np particles (absolute FP64 positions);
  * w: per-particle weights or NULL (then w0); F: 6 field planes; J: 3 planes,
  * accumulated into.  diag (nullable) += {sum w m (gamma^{n+1}-1) dV,
  * sum q w dV}.
  */
 void orc_push(const orc_grid *g, double q, double m, int64_t np, double *const *x,
-              double *const *u, const double *w, double w0, const double *const *F,
+              double *const *u, double *w, double w0, const double *const *F,
               double *const *J, double *diag) {
     const double qm = q / m, dt = g->dt;
     double dV = g->d[0] * g->d[1] * (g->dim == 3 ? g->d[2] : 1.0);
@@ -341,6 +352,9 @@ void orc_push(const orc_grid *g, double q, double m, int64_t np, double *const *
             xe[a] = xh[a] + dt * v;
         }
         orc_deposit(g, q * wp, xh, xe, up[2] / gn, J);
+        /* absorbing x faces: a particle whose position leaves [0, (n-1) dx]
+         * is absorbed (weight 0; its last move's current inside counted) */
+        if (g->absorb_x && w && (xn[0] < 0.0 || xn[0] >= (double)(g->n[0] - 1) * g->d[0])) w[p] = 0.0;
         for (int a = 0; a < g->dim; ++a) {
             double r = fmod(xn[a], L[a]);
             if (r < 0) r += L[a];

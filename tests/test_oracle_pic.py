@@ -566,3 +566,42 @@ def test_injected_pulse_energy_speed_and_amplitude():
     for _ in range(60):
         O.step(st)
     assert (centroid() - x1) / (st.t - t1) == pytest.approx(1.0, rel=0.02)
+
+
+def _one_particle(g, x, u, w=1.0):
+    return O.Species(-1.0, 1.0, [np.array([x[a]]) for a in range(2)], [np.array([u[a]]) for a in range(3)],
+                     np.array([w]), 1.0)
+
+
+@pytest.mark.parametrize("absorb", [0, 1])
+def test_absorbing_faces_take_particles_and_cut_the_wrap(absorb):
+    """Absorbing x faces: a particle leaving [0, (n-1) dx] gets weight 0, one
+    inside keeps it; a particle next to the far face neither sees the field
+    nor deposits current across the periodic seam, which it does with
+    periodic faces."""
+    n, d = (24, 16), (0.5, 0.5)
+    g = O.Grid(2, n, d, 0.3, 2, absorb_x=absorb)
+    L = n[0] * d[0]
+    F = [np.zeros((1, n[1], n[0])) for _ in range(6)]
+    F[1][0, :, 0:2] = 0.5  # E_y on the first two x nodes only
+    # leaving through the far face, leaving through x = 0, staying inside
+    cases = [((L - 1.05 * d[0], 4.0), (5.0, 0.0, 0.0)), ((0.02, 4.0), (-5.0, 0.0, 0.0)),
+             ((0.5 * L, 4.0), (5.0, 0.0, 0.0))]
+    out = []
+    for x, u in cases:
+        sp = _one_particle(g, x, u)
+        J = [np.zeros((1, n[1], n[0])) for _ in range(3)]
+        O.push(g, sp, F, J)
+        out.append((sp.w[0], J))
+    if absorb:
+        assert out[0][0] == 0.0 and out[1][0] == 0.0 and out[2][0] == 1.0
+    else:
+        assert all(w == 1.0 for w, _ in out)
+    # the far-face particle: E_y on nodes 0, 1 reaches it only across the seam
+    sp = _one_particle(g, (L - 1.4 * d[0], 4.0), (0.0, 0.0, 0.0))
+    EB = O.gather(g, F, [L - 1.4 * d[0] + 0.0, 4.0, 0.0])
+    assert (EB[1] == 0.0) == bool(absorb)
+    # ... and its current reaches x nodes 0, 1 only across the seam
+    J = out[0][1]
+    seam = np.abs(J[0][0, :, 0:2]).sum() + np.abs(J[1][0, :, 0:2]).sum()
+    assert (seam == 0.0) == bool(absorb)

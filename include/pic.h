@@ -69,13 +69,16 @@ typedef enum {
 } pic_status;
 
 enum { PIC_FP32_MIXED = 0, PIC_FP64_PLAIN = 1 };
-/* Boundaries, per axis.  PIC_BC_ABSORB is built for x (bc[0]) and for the
- * fields: the domain is x in [0, (n[0]-1) d[0]], and E_y, E_z on its two faces
- * follow the first-order Mur rule over each half step (the absorbing face of
- * the paper's 1D case, Sec. III; its scheme is not printed), at x = 0 acting
- * on E - E_inc so that a pulse set by pic_set_laser enters.  Particles still
- * wrap periodically along x: keep them the stencil reach plus their travel
- * away from both faces. */
+/* Boundaries, per axis.  PIC_BC_ABSORB is built for x (bc[0]): the domain is
+ * x in [0, (n[0]-1) d[0]] (the absorbing faces of the paper's 1D case,
+ * Sec. III; their scheme is not printed).
+ *   Fields: E_y, E_z on the two faces follow the first-order Mur rule over
+ *   each half step, at x = 0 acting on E - E_inc so that a pulse set by
+ *   pic_set_laser enters; E_x, B_y, B_z half a cell beyond the far face stay 0.
+ *   Particles: nothing is gathered from or deposited to x nodes beyond
+ *   [0, n[0]), and a particle whose new position leaves the domain is
+ *   absorbed: its weight is set to 0 (per-particle weights are required; it
+ *   stays in the arrays, wrapped in x, until the caller drops it). */
 enum { PIC_BC_PERIODIC = 0, PIC_BC_ABSORB = 1 };
 /* Momentum update: Boris (Sec. II.C, Eqs. 13-16) or Vay, which Sec. II.C
  * names for fields whose electric and magnetic forces nearly cancel; Vay

@@ -311,6 +311,8 @@ extern "C" pic_status pic_gather_push_deposit(void *ctx, const pic_species *sp, 
     if (st != PIC_OK) return st;
     for (int a = 0; a < 3; ++a)
         if (!p->u[a]) return fail(c, PIC_E_ARG, "momentum array is NULL");
+    if (c->cfg.bc[0] == PIC_BC_ABSORB && !p->w)
+        return fail(c, PIC_E_ARG, "absorbing x faces need per-particle weights (absorbed particles get w = 0)");
     if (c->cfg.precision == PIC_FP32_MIXED) {
         if (!p->cell || !p->tile_start) return fail(c, PIC_E_ARG, "cell or tile_start is NULL");
         for (int a = 0; a < c->dim; ++a)

@@ -14,7 +14,7 @@ struct PlainArgs {
     int64_t n;
     double *x[3];
     double *u[3];
-    const double *w;
+    double *w;          // written only to absorb particles at absorbing x faces
     double w0;
     float *chi;
     double chi_scale;
@@ -30,6 +30,8 @@ struct PlainArgs {
     double mdV, qdV;    // m dV, q dV for the diagnostics
     double *partials;   // [2 * nblocks]
     uint32_t *status;
+    int absorb_x;       // absorbing x faces: no field from, no current to x nodes beyond
+                        // [0, n), and a particle leaving [0, (n-1) d) is absorbed (weight 0)
 };
 
 template <int DIM>
@@ -42,6 +44,18 @@ __device__ __forceinline__ int64_t gidx(const int *ng, int i, int j, int k) {
     } else {
         return (int64_t)i + (int64_t)ng[0] * j;
     }
+}
+
+template <int DIM>
+__device__ __forceinline__ double fld(const PlainArgs &a, int c, int i, int j, int k) {
+    if (a.absorb_x && (unsigned)i >= (unsigned)a.ng[0]) return 0.0;
+    return a.F[c][gidx<DIM>(a.ng, i, j, k)];
+}
+
+template <int DIM>
+__device__ __forceinline__ void jadd(const PlainArgs &a, int c, int i, int j, int k, double v) {
+    if (a.absorb_x && (unsigned)i >= (unsigned)a.ng[0]) return;
+    atomicAdd(&a.J[c][gidx<DIM>(a.ng, i, j, k)], v);
 }
 
 template <int DIM, int ORDER, int PUSH>
@@ -82,7 +96,7 @@ __global__ void __launch_bounds__(256) gpd_plain_kernel(PlainArgs a) {
                     double r = 0.0;
 #pragma unroll
                     for (int ii = 0; ii < NW; ++ii)
-                        r += wt[sx][0][ii] * a.F[c][gidx<2>(a.ng, i0[sx][0] + ii, i0[sy][1] + jj, 0)];
+                        r += wt[sx][0][ii] * fld<2>(a, c, i0[sx][0] + ii, i0[sy][1] + jj, 0);
                     acc += wt[sy][1][jj] * r;
                 }
             } else {
@@ -95,7 +109,7 @@ __global__ void __launch_bounds__(256) gpd_plain_kernel(PlainArgs a) {
 #pragma unroll
                         for (int ii = 0; ii < NW; ++ii)
                             r += wt[sx][0][ii] *
-                                 a.F[c][gidx<3>(a.ng, i0[sx][0] + ii, i0[sy][1] + jj, i0[sz][2] + kk)];
+                                 fld<3>(a, c, i0[sx][0] + ii, i0[sy][1] + jj, i0[sz][2] + kk);
                         s += wt[sy][1][jj] * r;
                     }
                     acc += wt[sz][2][kk] * s;
@@ -126,7 +140,7 @@ __global__ void __launch_bounds__(256) gpd_plain_kernel(PlainArgs a) {
 #pragma unroll
                 for (int ii = 0; ii < L - 1; ++ii) {
                     acc -= jx * DS[0][ii] * ty;
-                    atomicAdd(&a.J[0][gidx<2>(a.ng, base[0] + ii, base[1] + jj, 0)], acc);
+                    jadd<2>(a, 0, base[0] + ii, base[1] + jj, 0, acc);
                 }
             }
 #pragma unroll
@@ -136,7 +150,7 @@ __global__ void __launch_bounds__(256) gpd_plain_kernel(PlainArgs a) {
 #pragma unroll
                 for (int jj = 0; jj < L - 1; ++jj) {
                     acc -= jy * tx * DS[1][jj];
-                    atomicAdd(&a.J[1][gidx<2>(a.ng, base[0] + ii, base[1] + jj, 0)], acc);
+                    jadd<2>(a, 1, base[0] + ii, base[1] + jj, 0, acc);
                 }
             }
             const double qv = a.q * w * v[2];
@@ -147,7 +161,7 @@ __global__ void __launch_bounds__(256) gpd_plain_kernel(PlainArgs a) {
                     const double wz = S0[0][ii] * S0[1][jj] + 0.5 * DS[0][ii] * S0[1][jj] +
                                       0.5 * S0[0][ii] * DS[1][jj] +
                                       (1.0 / 3.0) * DS[0][ii] * DS[1][jj];
-                    atomicAdd(&a.J[2][gidx<2>(a.ng, base[0] + ii, base[1] + jj, 0)], qv * wz);
+                    jadd<2>(a, 2, base[0] + ii, base[1] + jj, 0, qv * wz);
                 }
         } else {
             const double jz = a.jfac[2] * w;
@@ -162,8 +176,7 @@ __global__ void __launch_bounds__(256) gpd_plain_kernel(PlainArgs a) {
 #pragma unroll
                     for (int ii = 0; ii < L - 1; ++ii) {
                         acc -= jx * DS[0][ii] * t;
-                        atomicAdd(&a.J[0][gidx<3>(a.ng, base[0] + ii, base[1] + jj, base[2] + kk)],
-                                  acc);
+                        jadd<3>(a, 0, base[0] + ii, base[1] + jj, base[2] + kk, acc);
                     }
                 }
 #pragma unroll
@@ -177,8 +190,7 @@ __global__ void __launch_bounds__(256) gpd_plain_kernel(PlainArgs a) {
 #pragma unroll
                     for (int jj = 0; jj < L - 1; ++jj) {
                         acc -= jy * DS[1][jj] * t;
-                        atomicAdd(&a.J[1][gidx<3>(a.ng, base[0] + ii, base[1] + jj, base[2] + kk)],
-                                  acc);
+                        jadd<3>(a, 1, base[0] + ii, base[1] + jj, base[2] + kk, acc);
                     }
                 }
 #pragma unroll
@@ -192,8 +204,7 @@ __global__ void __launch_bounds__(256) gpd_plain_kernel(PlainArgs a) {
 #pragma unroll
                     for (int kk = 0; kk < L - 1; ++kk) {
                         acc -= jz * DS[2][kk] * t;
-                        atomicAdd(&a.J[2][gidx<3>(a.ng, base[0] + ii, base[1] + jj, base[2] + kk)],
-                                  acc);
+                        jadd<3>(a, 2, base[0] + ii, base[1] + jj, base[2] + kk, acc);
                     }
                 }
         }
@@ -202,6 +213,7 @@ __global__ void __launch_bounds__(256) gpd_plain_kernel(PlainArgs a) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             double xn = xh[d] + 0.5 * a.dt * v[d];
+            if (d == 0 && a.absorb_x && (xn < 0.0 || xn >= (double)(a.ng[0] - 1) / a.inv_d[0])) a.w[p] = 0.0;
             if (xn < 0.0) xn += a.L[d];
             else if (xn >= a.L[d]) xn -= a.L[d];
             if (xn >= a.L[d]) xn = 0.0;  // a tiny negative value rounded up to L
@@ -290,7 +302,8 @@ hipError_t launch_gpd_plain(Ctx *c, const pic_species *sp, const pic_particles *
         a.L[d] = (double)cfg.n[d] * cfg.d[d];
         a.jfac[d] = sp->q * cfg.d[d] / cfg.dt;
     }
-    a.w = (const double *)p->w;
+    a.w = (double *)p->w;
+    a.absorb_x = cfg.bc[0] == PIC_BC_ABSORB;
     a.w0 = sp->w0;
     a.chi = cfg.hbar_omega_mc2 > 0.0 ? p->chi : nullptr;
     a.chi_scale = cfg.hbar_omega_mc2;

@@ -47,7 +47,7 @@ struct TiledArgs {
     int32_t *cell;
     float *off[3];
     float *u[3];
-    const float *w;
+    float *w;           // written only to absorb particles at absorbing x faces
     float w0;
     float *chi;
     float chi_scale;
@@ -85,6 +85,9 @@ struct TiledArgs {
     uint32_t *bin_count;   // ntiles
     uint32_t *bin_rank;    // per entry of the straggler list and tail (capacity n)
     int part_off;          // first partial slot (doubles) of the launch
+    int absorb_x;          // absorbing x faces: nothing is gathered from or deposited
+                           // beyond x nodes [0, n), and a particle whose new cell leaves
+                           // [0, n - 1) is absorbed (weight 0)
 };
 
 // Accessor of the LDS window: coordinates local to the window origin.  Fields
@@ -122,6 +125,7 @@ struct GlobAcc {
     float *J[3];
     int ng[3];
     float scale;  // 1: values arrive in physical units
+    int absorb_x;  // no field from, no current to x nodes beyond [0, ng[0])
     __device__ __forceinline__ int64_t idx(int i, int j, int k) const {
         i = wrap_index(i, ng[0]);
         j = wrap_index(j, ng[1]);
@@ -129,9 +133,11 @@ struct GlobAcc {
         return (int64_t)i + (int64_t)ng[0] * ((int64_t)j + (int64_t)ng[1] * k);
     }
     __device__ __forceinline__ float f(int c, int bi, int bj, int bk, int ii, int jj, int kk) const {
+        if (absorb_x && (unsigned)(bi + ii) >= (unsigned)ng[0]) return 0.0f;
         return F[c][idx(bi + ii, bj + jj, bk + kk)];
     }
     __device__ __forceinline__ void add(int c, int bi, int bj, int bk, int ii, int jj, int kk, float v) const {
+        if (absorb_x && (unsigned)(bi + ii) >= (unsigned)ng[0]) return;
         atomicAdd(&J[c][idx(bi + ii, bj + jj, bk + kk)], v);
     }
 };
@@ -403,7 +409,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         offT[d] = a.off[d] + rebase;
         uT[d] = a.u[d] + rebase;
     }
-    const float *wT = a.w ? a.w + rebase : nullptr;
+    float *wT = a.w ? a.w + rebase : nullptr;
     float *chiT = a.chi ? a.chi + rebase : nullptr;
 
     // 1. stage the E/B window, zero the J window (window index decoded once
@@ -417,8 +423,9 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         const int gj = wrap_index(org[1] + j, a.ng[1]);
         const int gk = DIM == 3 ? wrap_index(org[2] + k, a.ng[2]) : 0;
         const int64_t gidx = (int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk);
+        const bool beyond = a.absorb_x && (unsigned)(org[0] + i) >= (unsigned)a.ng[0];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) pic_smem[c * wn + r] = a.F[c][gidx];
+        for (int c = 0; c < 6; ++c) pic_smem[c * wn + r] = beyond ? 0.0f : a.F[c][gidx];
 #pragma unroll
         for (int c = 0; c < 3; ++c) jwin[c * wn + r] = 0ull;
     }
@@ -504,6 +511,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         for (int d = 0; d < DIM; ++d)
             packed |= wrap_index(cc[d] + dc[d], a.ng[d]) << (d == 0 ? 0 : (d == 1 ? a.bx : a.bx + a.by));
         st(cellT, bo, packed);
+        if (a.absorb_x && (unsigned)(cc[0] + dc[0]) >= (unsigned)(a.ng[0] - 1)) st(wT, bo, 0.0f);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) st(offT[d], bo, f[d]);
 #pragma unroll
@@ -525,6 +533,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         const int gj = wrap_index(org[1] + j, a.ng[1]);
         const int gk = DIM == 3 ? wrap_index(org[2] + k, a.ng[2]) : 0;
         const int64_t gidx = (int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk);
+        if (a.absorb_x && (unsigned)(org[0] + ii) >= (unsigned)a.ng[0]) continue;  // beyond a face
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const long long q = (long long)jwin[c * wn + r];
@@ -727,7 +736,7 @@ __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
     double kin = 0.0, chg = 0.0;
     GlobAcc glob{{a.F[0], a.F[1], a.F[2], a.F[3], a.F[4], a.F[5]},
                  {a.J[0], a.J[1], a.J[2]},
-                 {a.ng[0], a.ng[1], a.ng[2]}, 1.0f};
+                 {a.ng[0], a.ng[1], a.ng[2]}, 1.0f, a.absorb_x};
     const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
@@ -757,6 +766,7 @@ __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
             a.off[d][p] = f[d];
         }
         a.cell[p] = packed;
+        if (a.absorb_x && (unsigned)(cc[0] + dc[0]) >= (unsigned)(a.ng[0] - 1)) a.w[p] = 0.0f;
 #pragma unroll
         for (int d = 0; d < 3; ++d) a.u[d][p] = u[d];
         if (a.chi) a.chi[p] = a.chi_scale * chi_of(u_old, u, EB);
@@ -839,7 +849,8 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
         a.dt_d[d] = (float)(cfg.dt / cfg.d[d]);
         a.jfac[d] = (float)(sp->q * cfg.d[d] / cfg.dt);
     }
-    a.w = (const float *)p->w;
+    a.w = (float *)p->w;
+    a.absorb_x = cfg.bc[0] == PIC_BC_ABSORB;
     a.w0 = (float)sp->w0;
     a.chi = cfg.hbar_omega_mc2 > 0.0 ? p->chi : nullptr;
     a.chi_scale = (float)cfg.hbar_omega_mc2;

@@ -450,6 +450,62 @@ def test_absorbing_run_with_injection_matches_oracle(precision):
     assert sim.check()[0] == L.PIC_OK
 
 
+@pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
+def test_particles_leave_through_absorbing_faces(precision):
+    """Two warm slabs drifting out through the x faces (u_x = +-0.6) for ten
+    steps with absorbing faces: the same particles are absorbed (weight 0)
+    as in the oracle, and the fields match it, so nothing was gathered from
+    or deposited across the periodic seam."""
+    print(f"absorbing particles prec={precision}", flush=True)
+    from paper_2104_00642_amd.sim import Simulation
+    from paper_2104_00642_amd.workloads import Workload, concat
+    cfg = make_cfg(2, 2, precision)
+    cfg.bc_x = L.PIC_BC_ABSORB
+    parts = []
+    for seed, (lo, hi), ux in ((21, (38, 47), 0.6), (22, (0, 6), -0.6)):
+        g1 = torch.Generator().manual_seed(seed)
+        cells = [torch.randint(lo, hi, (1500,), generator=g1), torch.randint(0, cfg.n[1], (1500,), generator=g1)]
+        r = random_raw(cfg, 1500, seed=seed + 10, uth=0.1, cells=cells)
+        r.u[0] = r.u[0] + ux
+        parts.append(r)
+    raw = concat(parts)
+    E, B = random_fields(cfg, seed=12, amp=0.02)
+    wl = Workload("leaving", cfg, [(-1.0, 1.0, raw)], E, B)
+    sim = Simulation.from_workload(wl, precision=precision, device=DEV, sort_every=4)
+    st = O.State(oracle_grid(cfg), [e.numpy().copy() for e in E], [b.numpy().copy() for b in B],
+                 [np.zeros(cfg.plane_shape) for _ in range(3)])
+    if precision == L.PIC_FP32_MIXED:
+        st.E = [e.astype(np.float32).astype(np.float64) for e in st.E]
+        st.B = [b.astype(np.float32).astype(np.float64) for b in st.B]
+    st.species.append(oracle_species(cfg, raw, -1.0, 1.0, from_fp32=precision == L.PIC_FP32_MIXED))
+    for _ in range(10):
+        sim.step()
+        O.step(st)
+    torch.cuda.synchronize()
+    gone_g = int((sim.particles[0].w[: raw.n] == 0).sum())
+    gone_o = int((st.species[0].w == 0).sum())
+    print(f"  absorbed: GPU {gone_g}, oracle {gone_o} of {raw.n}")
+    assert gone_o > 200
+    assert abs(gone_g - gone_o) <= (0 if precision == L.PIC_FP64_PLAIN else 2)
+    tol = 1e-10 if precision == L.PIC_FP64_PLAIN else 3e-4
+    for a in range(3):
+        assert rel_l2(np64(sim.fields.E[a]), st.E[a]) < tol
+        assert rel_l2(np64(sim.fields.B[a]), st.B[a]) < tol
+    assert sim.check()[0] == L.PIC_OK
+
+
+def test_absorbing_faces_need_weights():
+    cfg = make_cfg(2, 2, L.PIC_FP64_PLAIN)
+    cfg.bc_x = L.PIC_BC_ABSORB
+    ctx = L.pic_init(cfg)
+    raw = random_raw(cfg, 64, seed=1)
+    p = to_fp64(raw, cfg)
+    p = L.Particles(p.n, [t.to(DEV) for t in p.u], x=[t.to(DEV) for t in p.x])
+    f = L.Fields.zeros(cfg, DEV, torch.float64)
+    with pytest.raises(L.PicError):
+        L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), p, f)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_field_energy_diagnostic(dim):
     cfg = make_cfg(dim, 2, L.PIC_FP64_PLAIN)

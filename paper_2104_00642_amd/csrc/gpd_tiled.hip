@@ -95,7 +95,11 @@ struct TiledArgs {
 // following 3*wn int64 words.  WX, WY, WZ > 0 fix the window shape at compile
 // time (the default tiles), so that every stencil node of a particle is an
 // immediate offset from one base address; 0 takes the shape at run time.
-template <int WX, int WY, int WZ>
+// PAIR (2D): E_x and B_y share the stagger (1/2, 0), E_y and B_x (0, 1/2), so
+// each pair is interleaved node by node (one 8-byte LDS read serves both, and
+// a stencil's nodes lie within the reach of the paired-read offsets); E_z and
+// B_z keep planes of their own.  Otherwise one plane per component.
+template <int WX, int WY, int WZ, bool PAIR>
 struct LdsAcc {
     int wx_, wxy_, wn_;
     float scale;  // S of the fixed-point current
@@ -108,8 +112,55 @@ struct LdsAcc {
     __device__ __forceinline__ int lin(int i, int j, int k) const {
         return i + __mul24(wx(), j) + __mul24(wxy(), k);
     }
+    // float index of component c at window node r
+    __device__ __forceinline__ int slot(int c, int r) const {
+        if constexpr (PAIR) {
+            // c: 0 E_x, 1 E_y, 2 E_z, 3 B_x, 4 B_y, 5 B_z
+            const int plane = c == 0 || c == 4 ? 0 : (c == 1 || c == 3 ? 2 * wn() : (c == 2 ? 4 * wn() : 5 * wn()));
+            const int lane = c == 4 || c == 3 ? 1 : 0;
+            const int step = c == 2 || c == 5 ? 1 : 2;
+            return plane + step * r + lane;
+        } else {
+            return c * wn() + r;
+        }
+    }
     __device__ __forceinline__ float f(int c, int bi, int bj, int bk, int ii, int jj, int kk) const {
-        return pic_smem[c * wn() + lin(bi, bj, bk) + ii + wx() * jj + wxy() * kk];
+        return pic_smem[slot(c, lin(bi, bj, bk) + ii + wx() * jj + wxy() * kk)];
+    }
+    // (PAIR) view of pair p (0: E_x, B_y; 1: E_y, B_x) from stencil base
+    // (bi, bj): both components of node (ii, jj) in one 8-byte read.  The
+    // base address is formed once (the plane offset is too large for the
+    // immediate offsets of paired reads, and would otherwise be re-added per
+    // node); nodes are immediate offsets from it.
+    typedef float vec2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) const vec2 lds_float2;
+    struct PairView {
+        const lds_float2 *p0;
+        int wx;
+        __device__ __forceinline__ float2 operator()(int ii, int jj) const {
+            const vec2 v = p0[ii + wx * jj];
+            return make_float2(v.x, v.y);
+        }
+    };
+    // (PAIR) view of the E_z or B_z plane from stencil base (bi, bj), formed
+    // the same way
+    typedef __attribute__((address_space(3))) const float lds_float;
+    struct PlaneView {
+        const lds_float *p0;
+        int wx;
+        __device__ __forceinline__ float operator()(int ii, int jj) const { return p0[ii + wx * jj]; }
+    };
+    __device__ __forceinline__ PlaneView plane_view(int c, int bi, int bj) const {
+        const lds_float *q = (const lds_float *)(const float *)pic_smem + slot(c, lin(bi, bj, 0));
+        uint32_t addr = (uint32_t)(uintptr_t)q;
+        asm volatile("" : "+v"(addr));
+        return PlaneView{(const lds_float *)(uintptr_t)addr, wx()};
+    }
+    __device__ __forceinline__ PairView pair_view(int p, int bi, int bj) const {
+        const lds_float2 *q = (const lds_float2 *)(const vec2 *)pic_smem + p * wn() + lin(bi, bj, 0);
+        uint32_t addr = (uint32_t)(uintptr_t)q;
+        asm volatile("" : "+v"(addr));  // keep the formed base: no per-node re-addition
+        return PairView{(const lds_float2 *)(uintptr_t)addr, wx()};
     }
     // v is already in fixed-point units (the prefactors carry S), |v| <= 2^30
     __device__ __forceinline__ void add(int c, int bi, int bj, int bk, int ii, int jj, int kk, float v) const {
@@ -136,6 +187,20 @@ struct GlobAcc {
         if (absorb_x && (unsigned)(bi + ii) >= (unsigned)ng[0]) return 0.0f;
         return F[c][idx(bi + ii, bj + jj, bk + kk)];
     }
+    struct PairView {
+        const GlobAcc *g;
+        int p, bi, bj;
+        __device__ __forceinline__ float2 operator()(int ii, int jj) const {
+            return make_float2(g->f(p == 0 ? 0 : 1, bi, bj, 0, ii, jj, 0), g->f(p == 0 ? 4 : 3, bi, bj, 0, ii, jj, 0));
+        }
+    };
+    __device__ __forceinline__ PairView pair_view(int p, int bi, int bj) const { return PairView{this, p, bi, bj}; }
+    struct PlaneView {
+        const GlobAcc *g;
+        int c, bi, bj;
+        __device__ __forceinline__ float operator()(int ii, int jj) const { return g->f(c, bi, bj, 0, ii, jj, 0); }
+    };
+    __device__ __forceinline__ PlaneView plane_view(int c, int bi, int bj) const { return PlaneView{this, c, bi, bj}; }
     __device__ __forceinline__ void add(int c, int bi, int bj, int bk, int ii, int jj, int kk, float v) const {
         if (absorb_x && (unsigned)(bi + ii) >= (unsigned)ng[0]) return;
         atomicAdd(&J[c][idx(bi + ii, bj + jj, bk + kk)], v);
@@ -164,20 +229,49 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
         shape_weights<ORDER>(dh[d], i0[0][d], wt[0][d]);
         shape_weights<ORDER>(dh[d] - 0.5f, i0[1][d], wt[1][d]);
     }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const int sx = stag(c, 0), sy = stag(c, 1), sz = DIM == 3 ? stag(c, 2) : 0;
-        float acc_v = 0.0f;
-        if constexpr (DIM == 2) {
+    if constexpr (DIM == 2) {
+        // (E_x, B_y) share the stagger (1/2, 0) and (E_y, B_x) (0, 1/2): one
+        // node read serves both members of a pair
+        auto gather_pair = [&](int p, int sx, int sy, float &ra, float &rb) {
+            const auto pv = acc.pair_view(p, o[0] + i0[sx][0], o[1] + i0[sy][1]);
+            ra = 0.0f;
+            rb = 0.0f;
 #pragma unroll
             for (int jj = 0; jj < NW; ++jj) {
-                float r = 0.0f;
+                float sa = 0.0f, sb = 0.0f;
 #pragma unroll
-                for (int ii = 0; ii < NW; ++ii)
-                    r += wt[sx][0][ii] * acc.f(c, o[0] + i0[sx][0], o[1] + i0[sy][1], 0, ii, jj, 0);
-                acc_v += wt[sy][1][jj] * r;
+                for (int ii = 0; ii < NW; ++ii) {
+                    const float2 v = pv(ii, jj);
+                    sa += wt[sx][0][ii] * v.x;
+                    sb += wt[sx][0][ii] * v.y;
+                }
+                ra += wt[sy][1][jj] * sa;
+                rb += wt[sy][1][jj] * sb;
             }
-        } else {
+        };
+        gather_pair(0, 1, 0, EB[0], EB[4]);
+        gather_pair(1, 0, 1, EB[1], EB[3]);
+        // E_z at (0, 0), B_z at (1/2, 1/2)
+        auto gather_one = [&](int c, int sx, int sy) {
+            const auto pv = acc.plane_view(c, o[0] + i0[sx][0], o[1] + i0[sy][1]);
+            float r = 0.0f;
+#pragma unroll
+            for (int jj = 0; jj < NW; ++jj) {
+                float t = 0.0f;
+#pragma unroll
+                for (int ii = 0; ii < NW; ++ii) t += wt[sx][0][ii] * pv(ii, jj);
+                r += wt[sy][1][jj] * t;
+            }
+            return r;
+        };
+        EB[2] = gather_one(2, 0, 0);
+        EB[5] = gather_one(5, 1, 1);
+    } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const int sx = stag(c, 0), sy = stag(c, 1), sz = stag(c, 2);
+        float acc_v = 0.0f;
+        {
 #pragma unroll
             for (int kk = 0; kk < NW; ++kk) {
                 float s = 0.0f;
@@ -194,6 +288,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
             }
         }
         EB[c] = acc_v;
+    }
     }
 
     push_u<PUSH, float>(a.qm_h, EB, EB + 3, u);
@@ -388,7 +483,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     constexpr int RLO = ORDER == 4 ? 3 : 2, RHI = ORDER == 4 ? 4 : 3;
     const int g = a.drift + RLO;
     const int org[3] = {tx * a.tile[0] - g, ty * a.tile[1] - g, DIM == 3 ? tz * a.tile[2] - g : 0};
-    LdsAcc<WX, WY, WZ> lds{a.win[0], a.win[0] * a.win[1], a.win[0] * a.win[1] * a.win[2], 0.0f};
+    LdsAcc<WX, WY, WZ, DIM == 2> lds{a.win[0], a.win[0] * a.win[1], a.win[0] * a.win[1] * a.win[2], 0.0f};
     const int wn = lds.wn();
     const int wx = lds.wx(), wxy = lds.wxy();
     unsigned long long *jwin = (unsigned long long *)(pic_smem + 6 * wn);
@@ -425,7 +520,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         const int64_t gidx = (int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk);
         const bool beyond = a.absorb_x && (unsigned)(org[0] + i) >= (unsigned)a.ng[0];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) pic_smem[c * wn + r] = beyond ? 0.0f : a.F[c][gidx];
+        for (int c = 0; c < 6; ++c) pic_smem[lds.slot(c, r)] = beyond ? 0.0f : a.F[c][gidx];
 #pragma unroll
         for (int c = 0; c < 3; ++c) jwin[c * wn + r] = 0ull;
     }
@@ -453,6 +548,12 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
     const int hi[3] = {wx - RHI - 1, (DIM >= 2 ? wxy / wx : 1) - RHI - 1, (DIM == 3 ? wn / wxy : 1) - RHI - 1};
     double kin = 0.0, chg = 0.0;
+    // WRAP: the window crosses the periodic seam (or an absorbing face) along
+    // some axis.  Otherwise a cell's window coordinate is its offset from the
+    // origin, and a pushed particle (it stays within the window's reach)
+    // cannot leave [0, n): neither needs the unwrap.
+    auto particles = [&](auto wrap_c) {
+    constexpr bool WRAP = decltype(wrap_c)::value;
     uint32_t i = threadIdx.x;
     int32_t n_cell = 0;
     float n_f[3] = {0.0f, 0.0f, 0.0f}, n_u[3] = {0.0f, 0.0f, 0.0f}, n_w = a.w0;
@@ -489,7 +590,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         bool inside = DIM == 3 || (cell >> (a.bx + a.by)) == 0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            const int l = wrap_index(cc[d] - org[d], a.ng[d]);
+            const int l = WRAP ? wrap_index(cc[d] - org[d], a.ng[d]) : cc[d] - org[d];
             lc[d] = l;
             inside &= (unsigned)(l - RLO) <= (unsigned)(hi[d] - RLO) && (unsigned)cc[d] < (unsigned)a.ng[d];
             inside &= __float_as_uint(f[d]) < 0x3f800000u;
@@ -509,7 +610,8 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         int packed = 0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
-            packed |= wrap_index(cc[d] + dc[d], a.ng[d]) << (d == 0 ? 0 : (d == 1 ? a.bx : a.bx + a.by));
+            packed |= (WRAP ? wrap_index(cc[d] + dc[d], a.ng[d]) : cc[d] + dc[d])
+                      << (d == 0 ? 0 : (d == 1 ? a.bx : a.bx + a.by));
         st(cellT, bo, packed);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) st(offT[d], bo, f[d]);
@@ -519,6 +621,13 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         kin += (double)w * (double)gm1;
         chg += (double)w;
     }
+    };
+    bool wraps = false;
+    const int wext[3] = {wx, DIM >= 2 ? wxy / wx : 1, DIM == 3 ? wn / wxy : 1};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) wraps |= org[d] < 0 || org[d] + wext[d] > a.ng[d];
+    if (wraps) particles(std::integral_constant<bool, true>{});
+    else particles(std::integral_constant<bool, false>{});
     __syncthreads();
 
     // 3. flush the J window into global J (periodic wrap), skip exact zeros

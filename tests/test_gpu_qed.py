@@ -489,7 +489,7 @@ def test_mlp_gradient_matches_oracle_backward():
     assert loss.item() == pytest.approx(OM.loss(p, X.astype(np.float64), T.astype(np.float64)), rel=2e-2)
 
 
-def trained_network(ctx, iters=30000, n=1 << 20, batch=4096, lr=2e-3):
+def trained_network(ctx, iters=100000, n=1 << 20, batch=16384, lr=2e-3):
     X = torch.empty(n, 4, device=DEV)
     T = torch.empty(n, 2, device=DEV)
     L.pic_qed_training_data(ctx, n, 99, X, T)

@@ -127,13 +127,17 @@ struct LdsAcc {
     __device__ __forceinline__ float f(int c, int bi, int bj, int bk, int ii, int jj, int kk) const {
         return pic_smem[slot(c, lin(bi, bj, bk) + ii + wx() * jj + wxy() * kk)];
     }
-    // (PAIR) view of pair p (0: E_x, B_y; 1: E_y, B_x) from stencil base
-    // (bi, bj): both components of node (ii, jj) in one 8-byte read.  The
-    // base address is formed once (the plane offset is too large for the
-    // immediate offsets of paired reads, and would otherwise be re-added per
-    // node); nodes are immediate offsets from it.
+    // (PAIR) views of the window from a stencil base (bi, bj): the base
+    // address is formed once per particle and plane, and the nodes (ii, jj)
+    // are immediate offsets of paired reads from it.  The empty asm takes the
+    // formed address as an opaque register value, so the compiler cannot fold
+    // the plane offset (too large for a paired read's immediate) back into
+    // every node's address.
     typedef float vec2 __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(3))) const vec2 lds_float2;
+    typedef __attribute__((address_space(3))) const float lds_float;
+    // pair p (0: E_x, B_y; 1: E_y, B_x): both components of a node in one
+    // 8-byte read
     struct PairView {
         const lds_float2 *p0;
         int wx;
@@ -142,9 +146,13 @@ struct LdsAcc {
             return make_float2(v.x, v.y);
         }
     };
-    // (PAIR) view of the E_z or B_z plane from stencil base (bi, bj), formed
-    // the same way
-    typedef __attribute__((address_space(3))) const float lds_float;
+    __device__ __forceinline__ PairView pair_view(int p, int bi, int bj) const {
+        const lds_float2 *q = (const lds_float2 *)(const vec2 *)pic_smem + p * wn() + lin(bi, bj, 0);
+        uint32_t addr = (uint32_t)(uintptr_t)q;
+        asm volatile("" : "+v"(addr));
+        return PairView{(const lds_float2 *)(uintptr_t)addr, wx()};
+    }
+    // the E_z (c = 2) or B_z (c = 5) plane
     struct PlaneView {
         const lds_float *p0;
         int wx;
@@ -155,12 +163,6 @@ struct LdsAcc {
         uint32_t addr = (uint32_t)(uintptr_t)q;
         asm volatile("" : "+v"(addr));
         return PlaneView{(const lds_float *)(uintptr_t)addr, wx()};
-    }
-    __device__ __forceinline__ PairView pair_view(int p, int bi, int bj) const {
-        const lds_float2 *q = (const lds_float2 *)(const vec2 *)pic_smem + p * wn() + lin(bi, bj, 0);
-        uint32_t addr = (uint32_t)(uintptr_t)q;
-        asm volatile("" : "+v"(addr));  // keep the formed base: no per-node re-addition
-        return PairView{(const lds_float2 *)(uintptr_t)addr, wx()};
     }
     // v is already in fixed-point units (the prefactors carry S), |v| <= 2^30
     __device__ __forceinline__ void add(int c, int bi, int bj, int bk, int ii, int jj, int kk, float v) const {

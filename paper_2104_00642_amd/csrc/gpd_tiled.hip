@@ -902,8 +902,10 @@ __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
 
 // window shapes with a compiled kernel: 16x16 tiles with drift 2 in 2D
 // (25 cells wide, 27 for quartic weights), 8x8x4 tiles in 3D with drift 1
-// (drift 0 for quartic weights): 15 x 15 x 11; others use the run-time shape
+// (drift 0 for quartic weights): 15 x 15 x 11, and with drift 0 for
+// quadratic weights: 13 x 13 x 9; others use the run-time shape
 constexpr int W2X = 16 + 2 * 2 + 5, W2X4 = 16 + 2 * 2 + 7, W3X = 8 + 2 * 1 + 5, W3Z = 4 + 2 * 1 + 5;
+constexpr int W3X0 = 8 + 5, W3Z0 = 4 + 5;
 
 // One push of a species:
 //   prep (zero bin counters) -> sorted pass (stragglers listed) -> bin count
@@ -936,10 +938,17 @@ static void launch_tiled(const TiledArgs &a, size_t lds, hipStream_t s) {
         else
             launch_passes<2, ORDER, PUSH, PIC_TILED_THREADS_2D, 0, 0, 0>(a, lds, s);
     } else {
-        if (a.win[0] == W3X && a.win[1] == W3X && a.win[2] == W3Z)
+        if (a.win[0] == W3X && a.win[1] == W3X && a.win[2] == W3Z) {
             launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(a, lds, s);
-        else
-            launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, 0, 0, 0>(a, lds, s);
+            return;
+        }
+        if constexpr (ORDER == 2) {
+            if (a.win[0] == W3X0 && a.win[1] == W3X0 && a.win[2] == W3Z0) {
+                launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, W3X0, W3X0, W3Z0>(a, lds, s);
+                return;
+            }
+        }
+        launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, 0, 0, 0>(a, lds, s);
     }
 }
 
@@ -1048,6 +1057,7 @@ hipError_t set_tiled_lds_limit(size_t bytes) {
     if (e == hipSuccess) e = set_lds<2, 2, PIC_TILED_THREADS_2D, W2X, W2X, 1>(bytes);
     if (e == hipSuccess) e = set_lds<3, 1, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(bytes);
     if (e == hipSuccess) e = set_lds<3, 2, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(bytes);
+    if (e == hipSuccess) e = set_lds<3, 2, PIC_TILED_THREADS_3D, W3X0, W3X0, W3Z0>(bytes);
     return e;
 }
 

@@ -228,6 +228,8 @@ struct PermArgs {
 
 // phases A and D issue the loads of SORT_AHEAD rounds before using them
 constexpr int SORT_AHEAD = 4;
+// entries per thread that phase D keeps in registers for a one-stage tile
+constexpr int PERM_REG = 8;
 
 // Layers of phase C handled per pass: R layers x (cells/64) group counters
 // stay within 16 KB of LDS.
@@ -473,7 +475,35 @@ __global__ void __launch_bounds__(ORDER_THREADS, 8) tile_order_kernel(const uint
         }
     }
     __syncthreads();
-    //    columns through LDS, `seg` final positions at a time
+    //    columns through LDS.  A tile that fits one stage and PERM_REG
+    //    entries per thread keeps its entries' final positions and sources
+    //    in registers across the columns (read once, not once per column);
+    //    larger tiles go `seg` final positions at a time.
+    if (n_t <= (int64_t)seg && n_t <= (int64_t)PERM_REG * ORDER_THREADS) {
+        uint32_t pos[PERM_REG], v[PERM_REG];
+#pragma unroll
+        for (int u = 0; u < PERM_REG; ++u) {
+            const int64_t i = ts + threadIdx.x + (int64_t)u * ORDER_THREADS;
+            pos[u] = i < te ? lrank[i] : 0xFFFFFFFFu;
+            v[u] = i < te ? vals[i] : 0u;
+        }
+        for (int col = 0; col < pa.ncol; ++col) {
+            const uint32_t *src = pa.src[col];
+            const int sd = pa.stride[col];
+            uint32_t x[PERM_REG];
+#pragma unroll
+            for (int u = 0; u < PERM_REG; ++u)
+                if (pos[u] != 0xFFFFFFFFu) x[u] = src[(int64_t)v[u] * sd];
+#pragma unroll
+            for (int u = 0; u < PERM_REG; ++u)
+                if (pos[u] != 0xFFFFFFFFu) stage[pos[u]] = x[u];
+            __syncthreads();
+            uint32_t *d = pa.dst[col] + ts * sd;
+            for (uint32_t j = threadIdx.x; j < (uint32_t)n_t; j += ORDER_THREADS) d[(int64_t)j * sd] = stage[j];
+            __syncthreads();
+        }
+        return;
+    }
     for (int64_t s0 = 0; s0 < n_t; s0 += seg) {
         const uint32_t len = (uint32_t)min((int64_t)seg, n_t - s0);
         for (int col = 0; col < pa.ncol; ++col) {

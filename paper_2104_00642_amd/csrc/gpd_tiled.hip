@@ -510,8 +510,11 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     float *chiT = a.chi ? a.chi + rebase : nullptr;
 
     // 1. stage the E/B window, zero the J window (window index decoded once
-    //    per cell), bound the weights of the tile
-    for (int r = threadIdx.x; r < wn; r += NT) {
+    //    per cell), bound the weights of the tile.  With the window shape
+    //    compiled in, every load of a thread's cells is issued before the
+    //    first store, so the staging waits for one memory latency, not one
+    //    per cell (it matters where one workgroup has the CU to itself).
+    auto cell_src = [&](int r, int64_t &gidx, bool &beyond) {
         const int k = DIM == 3 ? r / wxy : 0;
         const int r2 = r - k * wxy;
         const int j = r2 / wx;
@@ -519,17 +522,55 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         const int gi = wrap_index(org[0] + i, a.ng[0]);
         const int gj = wrap_index(org[1] + j, a.ng[1]);
         const int gk = DIM == 3 ? wrap_index(org[2] + k, a.ng[2]) : 0;
-        const int64_t gidx = (int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk);
-        const bool beyond = a.absorb_x && (unsigned)(org[0] + i) >= (unsigned)a.ng[0];
+        gidx = (int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk);
+        beyond = a.absorb_x && (unsigned)(org[0] + i) >= (unsigned)a.ng[0];
+    };
+    constexpr int SITER = WX > 0 ? (WX * WY * WZ + NT - 1) / NT : 0;
+    if constexpr (SITER > 0 && SITER <= 4) {
+        float v[SITER][6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) pic_smem[lds.slot(c, r)] = beyond ? 0.0f : a.F[c][gidx];
+        for (int s = 0; s < SITER; ++s) {
+            const int r = (int)threadIdx.x + s * NT;
+            if (r < wn) {
+                int64_t gidx;
+                bool beyond;
+                cell_src(r, gidx, beyond);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) jwin[c * wn + r] = 0ull;
+                for (int c = 0; c < 6; ++c) v[s][c] = beyond ? 0.0f : a.F[c][gidx];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < SITER; ++s) {
+            const int r = (int)threadIdx.x + s * NT;
+            if (r < wn) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) pic_smem[lds.slot(c, r)] = v[s][c];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) jwin[c * wn + r] = 0ull;
+            }
+        }
+    } else {
+        for (int r = threadIdx.x; r < wn; r += NT) {
+            int64_t gidx;
+            bool beyond;
+            cell_src(r, gidx, beyond);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) pic_smem[lds.slot(c, r)] = beyond ? 0.0f : a.F[c][gidx];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) jwin[c * wn + r] = 0ull;
+        }
     }
     float wm = fabsf(a.w0);
     if (wT) {
+        // four loads in flight per round
         wm = 0.0f;
-        for (uint32_t i = threadIdx.x; i < np; i += NT) wm = fmaxf(wm, fabsf(ld(wT, poff(i))));
+        for (uint32_t i = threadIdx.x; i < np; i += 4 * NT) {
+            float x[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = i + q * NT < np ? fabsf(ld(wT, poff(i + q * NT))) : 0.0f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) wm = fmaxf(wm, x[q]);
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) wm = fmaxf(wm, __shfl_xor(wm, o));

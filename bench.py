@@ -135,9 +135,13 @@ def fp64_order(raw, cfg, tile, kind, torch):
 # the error the tests enforce at this workload's full size, in this launch
 # configuration (tests/test_gpu_fullsize.py): one step of a 2000-particle
 # sample against the FP64 oracle from the same FP32 state and fields
-PARITY = {"test": "tests/test_gpu_fullsize.py::test_laser_2d_full_size", "sample": 2000,
-          "u_max_rel": 2e-6, "x_max_cells": 2e-6, "sumJx_vs_sum_qwvx_rel": 1e-6,
-          "fp64_plain_u_max_rel": 1e-12}
+# the full-size parity test of each workload and the bars it asserts on a
+# sample of the timed configuration (one step against the oracle)
+_FULL = "tests/test_gpu_fullsize.py::"
+_BARS = {"sample": 2000, "u_max_rel": 2e-6, "x_max_cells": 2e-6, "sumJx_vs_sum_qwvx_rel": 1e-6}
+PARITY = {"laser2d": {"test": _FULL + "test_laser_2d_full_size", **_BARS, "fp64_plain_u_max_rel": 1e-12},
+          "laser3d": {"test": _FULL + "test_laser_3d_full_size", **_BARS},
+          "wake3d": {"test": _FULL + "test_beam_wakefield_3d_full_size", **_BARS}}
 
 MLP_FLOP_PER_SAMPLE = 2 * (4 * 64 + 64 * 64 + 64 * 2)  # the network's multiply-adds
 # executed per 16-sample tile: 4 MFMAs 16x16x16 and 20 MFMAs 16x16x32
@@ -428,7 +432,7 @@ def main():
                      "traffic": measured_traffic(wl.name, r["n"]) if args.scale == 1 else None,
                      "kernel": f"gpd_tiled_kernel<{dim},2> (sorted pass + binned pass; HIP events around the push)",
                      "alg_bytes_per_particle": r["bytes_per_particle"]},
-        "error_vs_oracle": PARITY,
+        "error_vs_oracle": PARITY[args.workload],
     }
     if "fp64" in out:
         f = out["fp64"]

@@ -341,7 +341,7 @@ def cpu_baseline(wl, O, target_s, log):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU domain decomposition is designed, not built)"}))
         sys.exit(2)
     import torch

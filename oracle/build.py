@@ -1,6 +1,6 @@
 """Build the oracle's C sources into ``oracle/liboracle.so`` with gcc.
 
-Test infrastructure only (the oracle judges the HIP library; the library never
+Test infrastructure only (the oracle checks the HIP library; the library never
 loads it).  ``python oracle/build.py`` or ``oracle.build.build()``.
 """
 import os

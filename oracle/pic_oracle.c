@@ -4,7 +4,7 @@
  * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, obviously correct
  * transcription of the method of "YUNIC: A Multi-Dimensional Particle-In-Cell
  * Code for Laser-Plasma Interaction" (Song, Wang, Li; arXiv:2104.00642), used
- * to judge the HIP path.  Only the test-suite, the smoke entry and the
+ * to check the HIP path.  Only the test-suite, the smoke entry and the
  * benchmark's CPU-baseline leg may load it.  It shares no code with the HIP
  * library and never calls it.
  *

@@ -515,7 +515,7 @@ def trained():
 
 def test_mlp_training_learns_the_rates(trained):
     """Training on the library's own tables with the BF16 MFMA kernels; the
-    trained rates of both processes are judged against the oracle's
+    trained rates of both processes are checked against the oracle's
     quadrature over the trained chi range (target: 1e-3 relative)."""
     ctx, net, loss, secs = trained
     errs = {}

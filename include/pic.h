@@ -178,7 +178,8 @@ pic_status pic_get_layout(const void *ctx, int32_t bits[3], int32_t tile[3], int
  * whose packed cell is off the grid is flagged PIC_F_OFFSET and left
  * unchanged; NaN/Inf momenta or offsets are flagged PIC_F_NONFINITE.  The
  * context's straggler list holds up to n entries (4 bytes each, allocated on
- * the first call with a larger n).
+ * the first call with a larger n).  n = 0 is a no-op (the particle arrays
+ * may then be NULL; the fields are still checked).
  * diag (nullable, device double[4]) receives += {sum w m (gamma^{n+1}-1) dV,
  * sum q w dV, -, -} computed in FP64 in a fixed order.  When chi is non-NULL
  * and hbar_omega_mc2 > 0 it receives chi_e of Sec. IV at the fields of x_h

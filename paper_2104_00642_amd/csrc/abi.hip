@@ -309,6 +309,7 @@ extern "C" pic_status pic_gather_push_deposit(void *ctx, const pic_species *sp, 
     if (p->n < 0) return fail(c, PIC_E_ARG, "negative particle count");
     pic_status st = check_fields(c, fields);
     if (st != PIC_OK) return st;
+    if (p->n == 0) return PIC_OK;  // nothing to push; the arrays may be NULL
     for (int a = 0; a < 3; ++a)
         if (!p->u[a]) return fail(c, PIC_E_ARG, "momentum array is NULL");
     if (c->cfg.bc[0] == PIC_BC_ABSORB && !p->w)
@@ -322,7 +323,6 @@ extern "C" pic_status pic_gather_push_deposit(void *ctx, const pic_species *sp, 
         for (int a = 0; a < c->dim; ++a)
             if (!p->x[a]) return fail(c, PIC_E_ARG, "position array is NULL");
     }
-    if (p->n == 0) return PIC_OK;
     hipSetDevice(c->device);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = c->cfg.precision == PIC_FP32_MIXED ? launch_gpd_tiled(c, sp, p, fields, diag, s)

@@ -283,6 +283,70 @@ def test_invalid_particles_are_flagged_and_left_unchanged():
     check_fp32_against_oracle(cfg, p, f, bits, full, J_o, skip=bad)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_dense_tile_sort_and_push_match_oracle(dim):
+    """One tile holds more particles than the sort keeps in registers (8192):
+    14000 particles in the cells of one tile, a few hundred per cell.  The
+    sort takes its staged permutation, the push sums large currents in the
+    fixed-point window; both against the oracle."""
+    print(f"dense tile dim={dim}", flush=True)
+    cfg = make_cfg(dim, 2, L.PIC_FP32_MIXED)
+    ctx0 = L.pic_init(cfg)
+    _, tile, _ = L.pic_get_layout(ctx0)
+    L.pic_destroy(ctx0)
+    g = torch.Generator().manual_seed(700 + dim)
+    n = 14000
+    # the tile one in from the corner along every axis
+    cells = [torch.randint(tile[a], 2 * tile[a], (n,), generator=g) for a in range(dim)]
+    raw = random_raw(cfg, n, seed=710 + dim, uth=0.3, cells=cells)
+    E, B = random_fields(cfg, seed=720 + dim)
+    E = [e.to(torch.float32).to(torch.float64) for e in E]
+    B = [b.to(torch.float32).to(torch.float64) for b in B]
+    ctx, p, f, perm, start, bits = sorted_fp32_state(cfg, raw, E, B)
+    torch.cuda.synchronize()
+    assert np.array_equal(p.tile_start.cpu().numpy(), start)
+    assert int(np.max(np.diff(start))) == n
+    ref_cell = to_fp32(raw, bits).cell.numpy()[perm]
+    assert np.array_equal(p.cell.cpu().numpy(), ref_cell)
+    sp_o, J_o, _ = run_oracle_push(cfg, raw.subset(torch.from_numpy(perm)), E, B, -1.0, 1.0, from_fp32=True)
+    L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), p, f)
+    st, flags, _ = L.pic_check(ctx)
+    assert st == L.PIC_OK and flags == 0
+    check_fp32_against_oracle(cfg, p, f, bits, sp_o, J_o)
+
+
+@pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
+def test_empty_species_is_a_no_op(precision):
+    """A species with no particles: sort and push return without touching J
+    or the diagnostics."""
+    cfg = make_cfg(2, 2, precision)
+    ctx = L.pic_init(cfg)
+    bits, tile, ntiles = L.pic_get_layout(ctx)
+    f32 = torch.float32 if precision == L.PIC_FP32_MIXED else torch.float64
+    z = lambda: torch.zeros(0, dtype=f32, device=DEV)  # noqa: E731
+    if precision == L.PIC_FP32_MIXED:
+        p = L.Particles(0, [z(), z(), z()], cell=torch.zeros(0, dtype=torch.int32, device=DEV), off=[z(), z()],
+                        tile_start=torch.zeros(ntiles + 1, dtype=torch.int64, device=DEV))
+        dst = p.empty_like()
+        dst.tile_start.fill_(-1)
+        L.pic_sort(ctx, p, dst)
+        torch.cuda.synchronize()
+        assert int(dst.tile_start.abs().max().item()) == 0
+        p = dst
+    else:
+        p = L.Particles(0, [z(), z(), z()], x=[z(), z()])
+    J = [torch.full(cfg.plane_shape, 0.5, dtype=f32, device=DEV) for _ in range(3)]
+    f = L.Fields([torch.zeros(cfg.plane_shape, dtype=f32, device=DEV) for _ in range(3)],
+                 [torch.zeros(cfg.plane_shape, dtype=f32, device=DEV) for _ in range(3)], J)
+    diag = torch.zeros(4, dtype=torch.float64, device=DEV)
+    L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), p, f, diag)
+    st, flags, _ = L.pic_check(ctx)
+    assert st == L.PIC_OK and flags == 0
+    for j in J:
+        assert bool((j == 0.5).all())
+    assert np64(diag)[:2].tolist() == [0.0, 0.0]
+
+
 @pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
 def test_vay_keeps_a_force_free_drift(precision):
     """Uniform E_y and B_z with particles at v = E x B / B^2 (gamma 22): no

@@ -315,6 +315,39 @@ def test_dense_tile_sort_and_push_match_oracle(dim):
     check_fp32_against_oracle(cfg, p, f, bits, sp_o, J_o)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_offsets_at_cell_faces_stay_in_range(dim):
+    """Particles on a cell face (offset 0), just below the next face (the
+    largest float below 1), on a half-node tie (0.5), moving by less than an
+    FP32 unit of the offset or by a tenth of a cell, either way, in zero
+    fields: every new
+    offset is in [0, 1), no particle is flagged, and positions and the
+    current match the oracle."""
+    print(f"face offsets dim={dim}", flush=True)
+    cfg = make_cfg(dim, 2, L.PIC_FP32_MIXED)
+    g = torch.Generator().manual_seed(800 + dim)
+    n = 3000
+    raw = random_raw(cfg, n, seed=810 + dim)
+    edge = torch.tensor([0.0, float(np.nextafter(np.float32(1.0), np.float32(0.0))), 0.5], dtype=torch.float64)
+    for a in range(dim):
+        raw.off[a] = edge[torch.randint(0, 3, (n,), generator=g)]
+    # moves of 1e-9, 1e-7 and 0.1 of the smallest cell per step, either sign
+    cells_per_step = torch.tensor([1e-9, 1e-7, 0.1], dtype=torch.float64)
+    for a in range(3):
+        sgn = torch.randint(0, 2, (n,), generator=g).to(torch.float64) * 2 - 1
+        raw.u[a] = sgn * cells_per_step[torch.randint(0, 3, (n,), generator=g)] * min(cfg.d[:dim]) / cfg.dt
+    E, B = random_fields(cfg, seed=820 + dim, amp=0.0)
+    ctx, p, f, perm, start, bits = sorted_fp32_state(cfg, raw, E, B)
+    sp_o, J_o, _ = run_oracle_push(cfg, raw.subset(torch.from_numpy(perm)), E, B, -1.0, 1.0, from_fp32=True)
+    L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), p, f)
+    st, flags, _ = L.pic_check(ctx)
+    assert st == L.PIC_OK and flags == 0
+    for a in range(dim):
+        o = np64(p.off[a])
+        assert o.min() >= 0.0 and o.max() < 1.0
+    check_fp32_against_oracle(cfg, p, f, bits, sp_o, J_o)
+
+
 @pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
 def test_empty_species_is_a_no_op(precision):
     """A species with no particles: sort and push return without touching J

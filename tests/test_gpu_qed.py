@@ -578,3 +578,43 @@ def test_network_mode_spectrum_and_gain(trained, chi):
           f"network {times[1]:.3f} (gain {times[0] / times[1]:.2f}x)")
     assert ks[0] < 0.01
     assert ks[1] < 0.1
+
+
+def test_network_mode_falls_back_to_tables_outside_its_range(trained):
+    """Where the network does not answer (within 0.1 decade of the ends of
+    its chi range, and beyond the range) network mode takes the tables: on
+    the same inputs and random numbers the step's optical depths and events
+    equal table mode's exactly, and the photon energies (the same table
+    lookup, compiled in another source file) to FP32 rounding."""
+    ctx, net, _, _ = trained
+    cfg = qed_cfg()
+    bits, _, _ = L.pic_get_layout(ctx)
+    lcs = np.array([-5.0, -4.0, -3.95, -3.91, 2.91, 2.95, 3.0, 3.5])
+    n = 4000
+    chi = (10.0 ** lcs[np.arange(n) % len(lcs)]).astype(np.float32)
+    ux = np.full(n, math.sqrt(1000.0 ** 2 - 1), dtype=np.float32)
+    out = {}
+    for mode in (L.PIC_QED_TABLE, L.PIC_QED_MLP):
+        # half the leptons fire this step (zero threshold), half accumulate
+        thr = np.where(np.arange(n) % 2 == 0, 0.0, 1e30).astype(np.float32)
+        el = species(n, n, bits, ux, chi, thr)
+        ph = species(0, n, bits, [])
+        f = fields(cfg)
+        L.pic_qed_step(ctx, f, mode=mode, step=3, photon_min_energy=0.0, electrons=el, photons=ph,
+                       mlp=net if mode == L.PIC_QED_MLP else None)
+        torch.cuda.synchronize()
+        m = int(ph.n_dev.item())
+        order = torch.argsort(ph.id[:m]).cpu()
+        out[mode] = (el.tau.cpu().numpy().copy(), el.u[0].cpu().numpy().copy(), m,
+                     ph.u[0][:m].cpu()[order].numpy(), ph.id[:m].cpu()[order].numpy())
+    t, u, m, k, ids = out[L.PIC_QED_TABLE]
+    t2, u2, m2, k2, ids2 = out[L.PIC_QED_MLP]
+    print(f"fallback: {m} photons in both modes" if m == m2 else f"fallback: {m} vs {m2} photons")
+    assert m == m2 and m > 0
+    assert np.array_equal(t, t2) and np.array_equal(ids, ids2)
+    print(f"  photon energy max rel diff {np.max(np.abs(k - k2) / np.abs(k)):.1e}, "
+          f"lepton u max rel diff {np.max(np.abs(u - u2) / np.abs(u)):.1e}")
+    # the recoil u - eps cancels when the photon takes most of the energy:
+    # its difference is bounded by the photon's, relative to u before (1000)
+    assert np.allclose(k, k2, rtol=1e-6, atol=0.0)
+    assert np.max(np.abs(u - u2)) <= 2e-6 * float(ux[0])

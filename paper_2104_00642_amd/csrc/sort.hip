@@ -70,9 +70,25 @@ __global__ void __launch_bounds__(SORT_THREADS) radix_hist_kernel(const uint32_t
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t start = (int64_t)blockIdx.x * SORT_ITEMS;
+    const int lane = threadIdx.x & 63;
     for (int r = 0; r < SORT_ROUNDS; ++r) {
         const int64_t i = start + r * SORT_THREADS + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        const uint32_t d = i < n ? (keys[i] >> shift) & 255u : 0u;
+        bool pending = i < n;
+        // The keys arrive nearly sorted (particles rarely change tiles between
+        // sorts), so a wavefront holds few distinct digits, and LDS atomics on
+        // one address serialize: lanes with equal digits add once per group.
+        // After four groups the remaining lanes add one by one.
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t act = __ballot(pending);
+            if (act == 0) break;
+            const int lead = __ffsll((unsigned long long)act) - 1;
+            const uint32_t d0 = (uint32_t)__shfl((int)d, lead);
+            const uint64_t same = __ballot(pending && d == d0);
+            if (lane == lead) atomicAdd(&h[d0], (uint32_t)__popcll(same));
+            if (d == d0) pending = false;
+        }
+        if (pending) atomicAdd(&h[d], 1u);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];

@@ -561,8 +561,10 @@ void orc_curl_e(const orc_grid *g, const double *const *E, double *const *out) {
  *              0 3 1 2 (2D) or 0 7 1 6 2 5 4 3 (3D), then ordered by
  *              (lz/2, ly/2, lx/2)
  * and particles are ordered by (tile, rank, local) ascending; these triples
- * are unique.  perm[new] = old; tile_start[t] is the first new index of tile
- * t, tile_start[ntiles] = np.
+ * are unique.  A particle whose cell lies off the grid has no tile: such
+ * particles come after every tile, in their source order.  perm[new] = old;
+ * tile_start[t] is the first new index of tile t, and tile_start[ntiles] the
+ * number of particles on the grid (np when every cell is on it).
  */
 static int64_t local_order(int dim, const int64_t *T, int64_t lx, int64_t ly, int64_t lz) {
     static const int order2[4] = {0, 3, 1, 2};
@@ -603,18 +605,26 @@ int orc_sort(const orc_grid *g, const int64_t *tile_size, int64_t np, const int3
         return -1;
     }
     for (int64_t p = 0; p < np; ++p) {
-        int64_t c[3] = {cell[0][p], cell[1][p], g->dim == 3 ? cell[2][p] : 0};
+        int64_t c[3] = {cell[0][p], cell[1][p], cell[2][p]};
+        int on_grid = 1;
+        for (int a = 0; a < 3; ++a) on_grid &= c[a] >= 0 && c[a] < g->n[a];
+        keys[p].old = p;
+        if (!on_grid) {
+            keys[p].tile = ntiles;
+            keys[p].rank = p;
+            keys[p].local = 0;
+            continue;
+        }
         int64_t lin = c[0] + g->n[0] * (c[1] + g->n[1] * c[2]);
         keys[p].tile = c[0] / T[0] + nt[0] * (c[1] / T[1] + nt[1] * (c[2] / T[2]));
         keys[p].local = local_order(g->dim, T, c[0] % T[0], c[1] % T[1], c[2] % T[2]);
         keys[p].rank = seen[lin]++;
-        keys[p].old = p;
     }
     qsort(keys, (size_t)np, sizeof(orc_sort_key), cmp_key);
     for (int64_t t = 0; t <= ntiles; ++t) tile_start[t] = 0;
     for (int64_t p = 0; p < np; ++p) {
         perm[p] = keys[p].old;
-        tile_start[keys[p].tile + 1]++;
+        if (keys[p].tile < ntiles) tile_start[keys[p].tile + 1]++;
     }
     for (int64_t t = 0; t < ntiles; ++t) tile_start[t + 1] += tile_start[t];
     free(seen);

@@ -24,7 +24,9 @@ from __future__ import annotations
 
 import math
 
-from . import compton_bracket, compton_inverse, fpair, frad, pair_bracket, pair_inverse, philox4x32_10, qed_uniforms
+from . import chi as chi_of
+from . import (compton_bracket, compton_inverse, fpair, frad, gather, pair_bracket, pair_inverse,
+               philox4x32_10, qed_uniforms)
 
 ALPHA = 1.0 / 137.035999084
 A_CONST = ALPHA / (math.sqrt(3.0) * math.pi)
@@ -128,6 +130,37 @@ def lepton_step(leptons: dict, seed: int, step: int, dt: float, hbar_w: float, e
             tau = 0.0
             leptons["tau_thr"][p] = -math.log(rt)
         leptons["tau"][p] = tau
+
+
+def photon_move_chi(grid, F, photons: dict, dt: float, hbar_w: float):
+    """The photon part of a step before pair creation (Sec. IV): a photon of
+    momentum k (energy eps = |k|, m c^2 units) moves at the speed of light,
+    x <- x + dt k / eps, and its chi_gamma is taken at the new position,
+    (hbar w_r / m c^2) sqrt((eps E + k x B)^2 - (k . E)^2), with E and B
+    gathered there as for any particle (Eq. 19).  photons: dict of lists
+    x (dim x n, absolute positions), k (3 x n), w; writes chi.  Periodic
+    wrap; with absorbing x faces (grid.absorb_x) a photon whose new position
+    leaves [0, (n_x - 1) d_x] is absorbed (w = 0, chi = 0), like a lepton."""
+    n = len(photons["w"])
+    photons.setdefault("chi", [0.0] * n)
+    L = [grid.n[a] * grid.d[a] for a in range(grid.dim)]
+    for p in range(n):
+        if photons["w"][p] == 0.0:
+            continue
+        k = [photons["k"][a][p] for a in range(3)]
+        eps = math.sqrt(sum(c * c for c in k))
+        if not eps > 0.0:
+            continue
+        xn = [photons["x"][a][p] + dt * k[a] / eps for a in range(grid.dim)]
+        if grid.absorb_x and (xn[0] < 0.0 or xn[0] >= (grid.n[0] - 1) * grid.d[0]):
+            photons["w"][p] = 0.0
+            photons["chi"][p] = 0.0
+        for a in range(grid.dim):
+            photons["x"][a][p] = xn[a] % L[a]
+        if photons["w"][p] == 0.0:
+            continue
+        EB = gather(grid, F, [photons["x"][a][p] for a in range(grid.dim)] + [0.0] * (3 - grid.dim))
+        photons["chi"][p] = chi_of(hbar_w, eps, k, EB[:3], EB[3:])
 
 
 def photon_decay(photons: dict, seed: int, step: int, dt: float, hbar_w: float, rates: Rates,

@@ -501,6 +501,33 @@ def test_sort_wavefront_cells_are_not_neighbours(dim):
                 assert np.all(((cheb >= 2) | (dd.min(axis=2) >= 1))[off])
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sort_puts_off_grid_cells_last(dim):
+    """Particles whose cell is off the grid (any axis below 0 or at or
+    beyond its count) have no tile: they follow every tile in their source
+    order, tile_start[ntiles] counts the others, and the others keep the
+    order the brute force gives them alone."""
+    rng = np.random.default_rng(12)
+    n = (16, 8) if dim == 2 else (8, 8, 4)
+    tile = (4, 4) if dim == 2 else (4, 2, 2)
+    g = O.Grid(dim, n, (1.0,) * dim, 0.1, 2)
+    N = 500
+    cells = [rng.integers(0, n[a], N).astype(np.int32) for a in range(dim)]
+    bad = rng.choice(N, 37, replace=False)
+    for j, p in enumerate(sorted(bad)):
+        a = j % dim
+        cells[a][p] = n[a] + j % 3 if j % 2 else -1 - j % 2
+    perm, start = O.sort(g, tile, cells)
+    good = np.setdiff1d(np.arange(N), bad)
+    ref, tiles = brute_force_order(n, tile, [c[good] for c in cells])
+    assert list(perm[:len(good)]) == [int(good[i]) for i in ref]
+    assert list(perm[len(good):]) == sorted(int(b) for b in bad)
+    ntiles = int(np.prod([n[a] // tile[a] for a in range(dim)]))
+    counts = np.bincount(tiles, minlength=ntiles)
+    assert list(start) == [0] + list(np.cumsum(counts))
+    assert start[-1] == len(good)
+
+
 def test_sort_empty_input():
     g = O.Grid(2, (8, 8), (1.0, 1.0), 0.1, 2)
     perm, start = O.sort(g, (4, 4), [np.zeros(0, np.int32), np.zeros(0, np.int32)])

@@ -157,3 +157,73 @@ def test_method2_reports_saturation():
     W = Q.A_CONST / hbar_w * O.frad(chi) / gamma
     assert not Q.lepton_step_method2(leptons(n, chi, gamma, [1.0] * n), SEED, 1, 0.1 / W, hbar_w, 0.0, None)
     assert Q.lepton_step_method2(leptons(n, chi, gamma, [1.0] * n), SEED, 1, 5.0 / W, hbar_w, 0.0, None)
+
+
+# ------------------------------------------------ photon move and chi_gamma
+
+def _linear_plane(g, comp, a, b):
+    """Plane of component `comp` whose value at its own staggered node is
+    a + b x (x the node's absolute x coordinate)."""
+    sx = {0: 0.5, 1: 0.0, 2: 0.0, 3: 0.0, 4: 0.5, 5: 0.5}[comp]
+    n = list(g.n) + [1] * (3 - len(g.n))
+    x = (np.arange(n[0]) + sx) * g.d[0]
+    return np.broadcast_to(a + b * x, g.shape).copy()
+
+
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 2), (3, 2), (2, 4), (3, 4)])
+def test_photon_chi_in_a_linear_field(dim, order):
+    """A photon moving in the x-y plane across B_z = b0 + b1 x (E = 0) has
+    chi_gamma = (hbar w) eps |B_z| at its new position x + dt k_x / eps: the
+    gather of a linear field is exact on each component's own stagger, so a
+    wrong move, stagger or chi formula shows."""
+    n = (24, 16) if dim == 2 else (24, 12, 10)
+    d = (0.3, 0.25, 0.2)[:dim]
+    g = O.Grid(dim, n, d, 0.1, order)
+    F = [np.zeros(g.shape) for _ in range(6)]
+    b0, b1 = 0.7, 0.31
+    F[5] = _linear_plane(g, 5, b0, b1)
+    rng = np.random.default_rng(4)
+    m, hbar_w = 40, 1e-3
+    th = rng.uniform(0, 2 * np.pi, m)
+    eps = rng.uniform(3.0, 50.0, m)
+    x0 = [rng.uniform(6 * d[0], (n[0] - 6) * d[0], m)] + [rng.uniform(0, n[a] * d[a], m) for a in range(1, dim)]
+    ph = dict(x=[list(v) for v in x0], k=[list(eps * np.cos(th)), list(eps * np.sin(th)), [0.0] * m],
+              w=[1.0] * m)
+    Q.photon_move_chi(g, F, ph, g.dt, hbar_w)
+    xn = x0[0] + g.dt * np.cos(th)
+    assert np.allclose(ph["x"][0], xn, rtol=0, atol=1e-12)
+    yn = (x0[1] + g.dt * np.sin(th)) % (n[1] * d[1])
+    assert np.allclose(ph["x"][1], yn, rtol=0, atol=1e-12)
+    assert np.allclose(ph["chi"], hbar_w * eps * (b0 + b1 * xn), rtol=1e-12)
+
+
+def test_photon_chi_of_plane_waves():
+    """Against a plane wave E_y = B_z = a along x, a photon moving with the
+    wave has chi_gamma = 0 and one moving against it 2 (hbar w) eps a."""
+    g = O.Grid(2, (20, 12), (0.2, 0.2), 0.1, 2)
+    F = [np.zeros(g.shape) for _ in range(6)]
+    a = 0.9
+    F[1][...] = a
+    F[5][...] = a
+    m = 6
+    eps = np.linspace(5.0, 30.0, m)
+    for sign, want in ((1.0, 0.0), (-1.0, 2.0)):
+        ph = dict(x=[[1.0] * m, [1.0] * m], k=[list(sign * eps), [0.0] * m, [0.0] * m], w=[1.0] * m)
+        Q.photon_move_chi(g, F, ph, g.dt, 1e-3)
+        assert np.allclose(ph["chi"], want * 1e-3 * eps * a, rtol=1e-12, atol=1e-15)
+
+
+def test_photon_absorbed_at_x_faces():
+    """With absorbing x faces a photon whose new x leaves [0, (n-1) dx] gets
+    w = 0 and chi = 0; the rest keep their weight; y wraps."""
+    n, d, dt = (16, 8), (0.2, 0.2), 0.1
+    g = O.Grid(2, n, d, dt, 2, absorb_x=1)
+    F = [np.full(g.shape, 0.3) for _ in range(6)]
+    xs = [0.05, 0.05, 2.0, (n[0] - 1) * d[0] - 0.05, (n[0] - 1) * d[0] - 0.05, 1.0]
+    kx = [-1.0, 1.0, -1.0, 1.0, -1.0, 0.0]
+    ky = [0.0, 0.0, 0.0, 0.0, 0.0, 1.0]
+    ph = dict(x=[list(xs), [0.5, 0.5, 0.5, 0.5, 0.5, n[1] * d[1] - 0.01]], k=[kx, ky, [0.0] * 6], w=[1.0] * 6)
+    Q.photon_move_chi(g, F, ph, dt, 1e-3)
+    assert ph["w"] == [0.0, 1.0, 1.0, 0.0, 1.0, 1.0]
+    assert ph["chi"][0] == 0.0 and ph["chi"][3] == 0.0 and ph["chi"][1] > 0.0
+    assert abs(ph["x"][1][5] - (0.09)) < 1e-12

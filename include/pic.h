@@ -38,8 +38,13 @@
  * Positions and momenta are at the same full step n (Sec. II.F).
  *
  * STREAMS.  `stream` is a hipStream_t passed as void* (NULL = default
- * stream).  Calls only enqueue work; they return before it finishes.  Arrays
- * must stay alive until the stream is synchronized.
+ * stream).  Calls only enqueue work; they return before it finishes, and
+ * none of them synchronizes the device.  Arrays must stay alive until the
+ * stream is synchronized.  The context's scratch (straggler lists, sort
+ * buffers, network outputs) is sized by pic_reserve; a call that needs more
+ * allocates it then (hipMalloc, no synchronization) and keeps the outgrown
+ * buffer until the next pic_reserve or pic_destroy.  Calls on different
+ * streams share that scratch and must not overlap.
  *
  * ERRORS.  Argument and configuration errors are found before anything is
  * enqueued and returned as a pic_status with a message in pic_last_error().
@@ -154,6 +159,14 @@ pic_status pic_init(const pic_config *cfg, void **out);
 void pic_destroy(void *ctx);
 const char *pic_last_error(const void *ctx);
 
+/* Size the context's scratch for species of up to `particles` particles
+ * (the push's straggler and bin lists, 12 B per particle; the sort's
+ * buffers, 16 B per particle; with QED, the network outputs, 8 B per
+ * particle), and free scratch outgrown since the last call.  A set-up call:
+ * it synchronizes the device.  Errors: PIC_E_ARG (particles outside
+ * [0, 2^31)), PIC_E_NOMEM. */
+pic_status pic_reserve(void *ctx, int64_t particles);
+
 /* Packed-cell layout and tiling chosen by pic_init: bits[3] per-axis field
  * widths of the packed cell, tile[3] tile size in cells, *ntiles number of
  * tiles (tile_start needs ntiles+1 entries). */
@@ -177,11 +190,13 @@ pic_status pic_get_layout(const void *ctx, int32_t bits[3], int32_t tile[3], int
  * PIC_F_STRAGGLER and counted.  A particle whose offset is outside [0,1) or
  * whose packed cell is off the grid is flagged PIC_F_OFFSET and left
  * unchanged; NaN/Inf momenta or offsets are flagged PIC_F_NONFINITE.  The
- * context's straggler list holds up to n entries (4 bytes each, allocated on
- * the first call with a larger n).  n = 0 is a no-op (the particle arrays
+ * context's straggler and bin lists hold up to n entries each (see
+ * pic_reserve).  n = 0 is a no-op (the particle arrays
  * may then be NULL; the fields are still checked).
  * diag (nullable, device double[4]) receives += {sum w m (gamma^{n+1}-1) dV,
- * sum q w dV, -, -} computed in FP64 in a fixed order.  When chi is non-NULL
+ * sum q w dV} in diag[0..1], computed in FP64 in a fixed order (diag[2] is
+ * the field energy of pic_yee_step, diag[3] the Gauss residual of
+ * pic_gauss_residual).  When chi is non-NULL
  * and hbar_omega_mc2 > 0 it receives chi_e of Sec. IV at the fields of x_h
  * and u^{n+1/2} = (u^n + u^{n+1})/2.
  */
@@ -201,13 +216,20 @@ pic_status pic_yee_step(void *ctx, int32_t half, const pic_fields *fields, doubl
 
 /*
  * Tile binning (FP32 path).  Writes src's particles into dst in the order
- * (tile, rank of the particle among those of its cell in src order, cell
- * within the tile), and dst->tile_start[0..ntiles] (first index of each tile).
- * Tiles are tile[0] x tile[1] (x tile[2]) blocks of cells numbered
- * x-fastest; cells within a tile likewise.  dst arrays must hold src->n
- * elements and may not alias src.  Every non-NULL src array (cell, off, u,
- * w, chi) is permuted into the matching dst array.  Bit-exact and
- * deterministic.
+ * (tile, rank of the particle among those of its cell in src order, key of
+ * the cell within the tile), and dst->tile_start[0..ntiles] (first index of
+ * each tile).  Tiles are tile[0] x tile[1] (x tile[2]) blocks of cells
+ * numbered x-fastest.  Within a tile cells are grouped by the parities of
+ * their tile-local coordinates, classes in the order 00 11 01 10 (2D) or
+ * 000 111 001 110 010 101 100 011 ((x, y, z) parities), each class
+ * z-, y-, x-slowest to fastest on the halved coordinates.  A particle
+ * whose packed cell is off the grid (a field beyond its cell count, any bit
+ * above y in 2D, a negative cell) has no tile: such particles follow the
+ * last tile in src order, and tile_start[ntiles] is the number of particles
+ * on the grid (the push then flags them PIC_F_OFFSET and leaves them
+ * unchanged).  dst arrays must hold src->n elements and may not alias src.
+ * Every non-NULL src array (cell, off, u, w, chi, tau, tau_thr, id) is
+ * permuted into the matching dst array.  Bit-exact and deterministic.
  */
 pic_status pic_sort(void *ctx, const pic_particles *src, const pic_particles *dst, void *stream);
 
@@ -226,9 +248,14 @@ pic_status pic_sort(void *ctx, const pic_particles *src, const pic_particles *ds
  *     recoil u <- u (1 - eps_gamma/|u|) (clamped at 0); the photon is appended
  *     to `photons` when eps_gamma >= photon_min_energy.
  *   Photons (momentum k = eps_gamma k^, chi_gamma computed here at the fields
- *     of `fields` after moving dt at c): above 2 m c^2 an event appends a
- *     positron with x eps_gamma and an electron with (1-x) eps_gamma along k
- *     and sets the photon weight to 0.
+ *     of `fields` after moving dt at c and written to chi when chi is not
+ *     NULL): above 2 m c^2 an event appends a positron with x eps_gamma and
+ *     an electron with (1-x) eps_gamma along k and sets the photon weight to
+ *     0.  Photons need per-particle weights (PIC_E_ARG otherwise), and in
+ *     PIC_QED_MLP mode the chi array, where the network reads this step's
+ *     chi_gamma.  With absorbing x faces a photon whose new position leaves
+ *     [0, (n[0]-1) d[0]] is absorbed (weight 0, chi 0, no pair), and no
+ *     field is gathered from x nodes beyond [0, n[0]).
  * Created particles: identifier Philox(counter (parent_lo, parent_hi, step,
  * 0x80000000 | tag), key seed) (tag 1 photon, 2 positron, 3 electron), tau 0,
  * tau_thr from the counter (id_lo, id_hi, step, 1); parent position and
@@ -265,11 +292,13 @@ pic_status pic_qed_step(void *ctx, const pic_qed_args *args, void *stream);
 /*
  * Surrogate network of the QED module: 4 -> 64 -> 64 -> 2 perceptron,
  * h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 W3 + b3, BF16 weights,
- * FP32 biases, FP32 accumulation (BF16 matrix cores; in the forward pass
- * each activation enters as two BF16 terms, hi and remainder).  Device layout
- * (PIC_MLP_BYTES): W1 bf16[4][64] @0, W2 bf16[64][64] @512, W3 bf16[64][2]
- * @8704, b1 f32[64] @8960, b2 f32[64] @9216, b3 f32[2] @9472 (row-major,
- * input index first).  Inputs x = ((log10 chi - c)/h, 2 rho(r) - 1, [emission],
+ * FP32 biases, FP32 accumulation (BF16 matrix cores).  Each weight is a pair
+ * of BF16 terms, hi = bf16(w) and lo = bf16(w - hi), and in the forward pass
+ * each activation enters as two BF16 terms too (hi and remainder); products
+ * take hi x hi + hi x lo + lo x hi.  Device layout (PIC_MLP_BYTES, row-major,
+ * input index first): hi terms W1 bf16[4][64] @0, W2 bf16[64][64] @512,
+ * W3 bf16[64][2] @8704; b1 f32[64] @8960, b2 f32[64] @9216, b3 f32[2] @9472;
+ * lo terms W1 @9480, W2 @9992, W3 @18184.  Inputs x = ((log10 chi - c)/h, 2 rho(r) - 1, [emission],
  * [pairs]) where log10 chi spans [c-h, c+h] = [-4, 3] (emission) or
  * [-1.7, 3] (pairs) and rho(r) = 1 - sqrt(1-r) (emission) or
  * acos(1-2r)/pi (pairs); outputs y0 = ln(F_rad/chi) or ln F_pair + 8/(3 chi),
@@ -279,13 +308,16 @@ pic_status pic_qed_step(void *ctx, const pic_qed_args *args, void *stream);
  * b2, W3, b3), then the Adam step count.
  */
 #define PIC_MLP_NPARAM 4610
-#define PIC_MLP_BYTES 9480
+#define PIC_MLP_BYTES 18440
 #define PIC_MLP_OFF_W1 0
 #define PIC_MLP_OFF_W2 512
 #define PIC_MLP_OFF_W3 8704
 #define PIC_MLP_OFF_B1 8960
 #define PIC_MLP_OFF_B2 9216
 #define PIC_MLP_OFF_B3 9472
+#define PIC_MLP_OFF_W1_LO 9480
+#define PIC_MLP_OFF_W2_LO 9992
+#define PIC_MLP_OFF_W3_LO 18184
 #define PIC_MLP_STATE_FLOATS (4 * PIC_MLP_NPARAM + 1)
 
 /* y[n][2] = network(x[n][4]) (device arrays). */
@@ -327,6 +359,31 @@ typedef struct {
     int32_t circular;   /* 0: E along y; 1: circular (a0 on E_y and E_z) */
 } pic_laser;
 pic_status pic_set_laser(void *ctx, const pic_laser *laser, double t);
+
+/*
+ * Charge density on the nodes (the integer-node shape weights of Sec. II.D):
+ *   rho(i) += q w prod_a W(i_a - x_a/d_a)
+ * for every particle of the species, at x^n (at_half = 0) or at the half
+ * step x^n + dt u^n / (2 gamma^n) (at_half = 1: the positions of the
+ * push's start point, the time of E after pic_yee_step(half = 1)).  rho is a
+ * device double[n0 n1 n2] in the field layout, ACCUMULATED into (FP64
+ * atomics), periodic on every axis.  Either particle layout.  n = 0 is a
+ * no-op.  Errors: PIC_E_ARG.
+ */
+pic_status pic_deposit_rho(void *ctx, const pic_species *sp, const pic_particles *p, int32_t at_half,
+                           double *rho, void *stream);
+
+/*
+ * Gauss residual (Sec. II.B: with a charge-conserving current, Eq. 5, the
+ * divergence equations, Eqs. 1-2, keep holding as they held initially):
+ *   residual(i) = sum_a (E_a(i) - E_a(i - e_a)) / d_a - rho(i)
+ * on the nodes, in FP64 from the FP32 or FP64 E planes.  residual
+ * (nullable, device double[n0 n1 n2]) receives it; diag (nullable, device
+ * double[4]) receives diag[3] = max(diag[3], max_i |residual(i)|).  rho as
+ * accumulated by pic_deposit_rho over the species.  Errors: PIC_E_ARG.
+ */
+pic_status pic_gauss_residual(void *ctx, const pic_fields *fields, const double *rho, double *residual,
+                              double *diag, void *stream);
 
 /* Synchronize `stream`, return the device status word in *flags (nullable)
  * and the number of straggler particles since the last check in

@@ -6,8 +6,9 @@ Loss = sum over batch rows b and outputs o of w_o (y_bo - t_bo)^2 / (2 B) with
 w = (RATE_WEIGHT, 1): output 0 is the rate, output 1 the sampled fraction.
 Forward and backward are written out with plain matrix products in FP64
 (the paper does not use a network; this is the surrogate of its Monte-Carlo
-rates, Sec. IV Eqs. 23-24).  Weights are passed as given: when checking a
-BF16 GPU kernel the caller passes the BF16-rounded values.
+rates, Sec. IV Eqs. 23-24).  Weights are passed as given: when checking the
+GPU kernels the caller passes the weights the GPU network holds (the sum of
+its hi and lo BF16 terms, or the hi terms alone for its backward pass).
 """
 from __future__ import annotations
 

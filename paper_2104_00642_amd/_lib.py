@@ -29,12 +29,13 @@ PIC_QED_TABLE, PIC_QED_MLP, PIC_QED_METHOD2 = 0, 1, 2
 PIC_PUSH_BORIS, PIC_PUSH_VAY = 0, 1
 PIC_BC_ABSORB = 1
 PIC_MLP_NPARAM = 4610
-PIC_MLP_BYTES = 9480
+PIC_MLP_BYTES = 18440
 PIC_MLP_STATE_FLOATS = 4 * PIC_MLP_NPARAM + 1
 
 EXPORTED = ["pic_init", "pic_destroy", "pic_last_error", "pic_get_layout", "pic_gather_push_deposit",
             "pic_yee_step", "pic_sort", "pic_check", "pic_qed_step", "pic_mlp_forward", "pic_mlp_grad",
-            "pic_mlp_train", "pic_qed_training_data", "pic_qed_table_lookup", "pic_set_laser"]
+            "pic_mlp_train", "pic_qed_training_data", "pic_qed_table_lookup", "pic_set_laser", "pic_reserve",
+            "pic_deposit_rho", "pic_gauss_residual"]
 
 
 class PicError(RuntimeError):
@@ -125,6 +126,14 @@ def lib():
         L.pic_qed_table_lookup.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                            C.c_int64, C.c_void_p, C.c_void_p]
         L.pic_qed_table_lookup.restype = C.c_int
+        L.pic_reserve.argtypes = [C.c_void_p, C.c_int64]
+        L.pic_reserve.restype = C.c_int
+        L.pic_deposit_rho.argtypes = [C.c_void_p, C.POINTER(pic_species), C.POINTER(pic_particles), C.c_int32,
+                                      C.c_void_p, C.c_void_p]
+        L.pic_deposit_rho.restype = C.c_int
+        L.pic_gauss_residual.argtypes = [C.c_void_p, C.POINTER(pic_fields), C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]
+        L.pic_gauss_residual.restype = C.c_int
         _lib = L
     return _lib
 
@@ -389,3 +398,23 @@ def pic_qed_training_data(ctx: Context, n: int, seed: int, x, t, stream=None):
 def pic_qed_table_lookup(ctx: Context, proc: int, what: int, chi, r, out, stream=None):
     _check(lib().pic_qed_table_lookup(C.c_void_p(ctx.handle), int(proc), int(what), _ptr(chi), _ptr(r),
                                       chi.shape[0], _ptr(out), _stream(stream)), C.c_void_p(ctx.handle))
+
+
+def pic_reserve(ctx: Context, particles: int):
+    _check(lib().pic_reserve(C.c_void_p(ctx.handle), int(particles)), C.c_void_p(ctx.handle))
+
+
+def pic_deposit_rho(ctx: Context, sp: Species, p: Particles, rho: torch.Tensor, at_half: bool = True,
+                    stream=None):
+    assert rho.dtype == torch.float64
+    sc, pc = sp.c(), p.c()
+    _check(lib().pic_deposit_rho(C.c_void_p(ctx.handle), C.byref(sc), C.byref(pc), int(bool(at_half)), _ptr(rho),
+                                 _stream(stream)), C.c_void_p(ctx.handle))
+
+
+def pic_gauss_residual(ctx: Context, f: Fields, rho: torch.Tensor, residual: Optional[torch.Tensor] = None,
+                       diag: Optional[torch.Tensor] = None, stream=None):
+    assert rho.dtype == torch.float64 and (residual is None or residual.dtype == torch.float64)
+    fc = f.c()
+    _check(lib().pic_gauss_residual(C.c_void_p(ctx.handle), C.byref(fc), _ptr(rho), _ptr(residual), _ptr(diag),
+                                    _stream(stream)), C.c_void_p(ctx.handle))

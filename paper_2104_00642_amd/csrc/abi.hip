@@ -23,15 +23,26 @@ static pic_status hip_fail(Ctx *c, hipError_t e, const char *what) {
     return fail(c, PIC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Scratch that an enqueueing call outgrows is not freed there: work already
+// queued (on any stream) may still use it, and a free would have to wait for
+// the whole device.  The old buffer is retired and released by the next
+// pic_reserve or by pic_destroy, which synchronize anyway.
+static void retire(Ctx *c, void *p) {
+    if (p) c->retired.push_back(p);
+}
+
+static void release_retired(Ctx *c) {
+    if (c->retired.empty()) return;
+    hipDeviceSynchronize();
+    for (void *p : c->retired) hipFree(p);
+    c->retired.clear();
+}
+
 pic_status ensure_partials(Ctx *c, size_t n) {
     if (n <= c->partials_cap) return PIC_OK;
-    // work already queued may still read the old buffer
-    if (c->partials) {
-        hipDeviceSynchronize();
-        hipFree(c->partials);
-        c->partials = nullptr;
-        c->partials_cap = 0;
-    }
+    retire(c, c->partials);
+    c->partials = nullptr;
+    c->partials_cap = 0;
     size_t cap = n + n / 4 + 64;
     if (hipMalloc(&c->partials, cap * sizeof(double)) != hipSuccess) {
         c->partials = nullptr;
@@ -49,16 +60,12 @@ pic_status ensure_strag_list(Ctx *c, int64_t n) {
             return fail(c, PIC_E_NOMEM, "cannot allocate the tile bins");
     }
     if ((size_t)n <= c->strag_cap) return PIC_OK;
-    if (c->strag_list) {
-        // work already queued may still use the old buffers
-        hipDeviceSynchronize();
-        hipFree(c->strag_list);
-        hipFree(c->bin_list);
-        hipFree(c->bin_rank);
-        c->strag_list = c->bin_list = nullptr;
-        c->bin_rank = nullptr;
-        c->strag_cap = 0;
-    }
+    retire(c, c->strag_list);
+    retire(c, c->bin_list);
+    retire(c, c->bin_rank);
+    c->strag_list = c->bin_list = nullptr;
+    c->bin_rank = nullptr;
+    c->strag_cap = 0;
     const size_t cap = (size_t)n + (size_t)n / 8 + 1024;
     if (hipMalloc(&c->strag_list, cap * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&c->bin_list, cap * sizeof(int32_t)) != hipSuccess ||
@@ -73,14 +80,13 @@ pic_status ensure_sort_scratch(Ctx *c, int64_t n) {
     const int64_t nblocks = (n + items - 1) / items;
     const size_t hist_need = (size_t)(256 * nblocks + (256 * nblocks + items - 1) / items + 16);
     if ((size_t)n <= c->sort_cap && hist_need <= c->hist_cap) return PIC_OK;
-    hipDeviceSynchronize();
     for (int b = 0; b < 2; ++b) {
-        hipFree(c->keys[b]);
-        hipFree(c->vals[b]);
+        retire(c, c->keys[b]);
+        retire(c, c->vals[b]);
         c->keys[b] = c->vals[b] = nullptr;
     }
-    hipFree(c->hist);
-    hipFree(c->final_perm);
+    retire(c, c->hist);
+    retire(c, c->final_perm);
     c->hist = c->final_perm = nullptr;
     c->sort_cap = c->hist_cap = 0;
     size_t cap = (size_t)n + (size_t)n / 8 + 1024;
@@ -96,6 +102,28 @@ pic_status ensure_sort_scratch(Ctx *c, int64_t n) {
     c->sort_cap = cap;
     c->hist_cap = hcap;
     return PIC_OK;
+}
+
+pic_status ensure_mlp_scratch(Ctx *c, int64_t nmax) {
+    if ((size_t)(2 * nmax) <= c->mlp_scratch_cap) return PIC_OK;
+    retire(c, c->mlp_scratch);
+    c->mlp_scratch = nullptr;
+    c->mlp_scratch_cap = 0;
+    const size_t cap = (size_t)(2 * nmax) + (size_t)nmax / 2 + 1024;
+    if (hipMalloc(&c->mlp_scratch, cap * sizeof(float)) != hipSuccess) {
+        c->mlp_scratch = nullptr;
+        return fail(c, PIC_E_NOMEM, "cannot allocate network outputs");
+    }
+    c->mlp_scratch_cap = cap;
+    return PIC_OK;
+}
+
+pic_status reserve(Ctx *c, int64_t n) {
+    pic_status st = ensure_strag_list(c, n);
+    if (st == PIC_OK && c->cfg.precision == PIC_FP32_MIXED) st = ensure_sort_scratch(c, n);
+    if (st == PIC_OK && c->qed.dev) st = ensure_mlp_scratch(c, n);
+    release_retired(c);
+    return st;
 }
 
 hipError_t set_tiled_lds_limit(size_t bytes);
@@ -221,6 +249,10 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
         pic_destroy(c);
         return st;
     }
+    if (hipMalloc(&c->gauss_part, sizeof(double) * GAUSS_PART) != hipSuccess) {
+        pic_destroy(c);
+        return fail(nullptr, PIC_E_NOMEM, "cannot allocate the residual partials");
+    }
     if (ensure_partials(c, 2 * (size_t)c->ntiles + 1024) != PIC_OK) {
         g_init_error = c->err;
         pic_destroy(c);
@@ -260,7 +292,17 @@ extern "C" void pic_destroy(void *ctx) {
     hipFree(c->qed.dev);
     hipFree(c->mlp_scratch);
     hipFree(c->mur_old);
+    hipFree(c->gauss_part);
+    for (void *p : c->retired) hipFree(p);
     delete c;
+}
+
+extern "C" pic_status pic_reserve(void *ctx, int64_t particles) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (particles < 0 || particles >= ((int64_t)1 << 31)) return fail(c, PIC_E_ARG, "particles must be in [0, 2^31)");
+    hipSetDevice(c->device);
+    return reserve(c, particles);
 }
 
 extern "C" pic_status pic_set_laser(void *ctx, const pic_laser *laser, double t) {
@@ -299,10 +341,9 @@ static pic_status check_fields(Ctx *c, const pic_fields *f) {
     return PIC_OK;
 }
 
-extern "C" pic_status pic_gather_push_deposit(void *ctx, const pic_species *sp, const pic_particles *p,
-                                              const pic_fields *fields, double *diag, void *stream) {
-    Ctx *c = (Ctx *)ctx;
-    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+// checks shared by the push entry points; PIC_OK with p->n == 0 means a no-op
+pic_status pic::validate_push_args(Ctx *c, const pic_species *sp, const pic_particles *p,
+                                   const pic_fields *fields) {
     if (!sp || !p) return fail(c, PIC_E_ARG, "species or particles is NULL");
     if (!(sp->m > 0.0) || !isfinite(sp->q) || !isfinite(sp->w0))
         return fail(c, PIC_E_ARG, "species mass must be > 0 and charge/weight finite");
@@ -323,6 +364,15 @@ extern "C" pic_status pic_gather_push_deposit(void *ctx, const pic_species *sp, 
         for (int a = 0; a < c->dim; ++a)
             if (!p->x[a]) return fail(c, PIC_E_ARG, "position array is NULL");
     }
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_gather_push_deposit(void *ctx, const pic_species *sp, const pic_particles *p,
+                                              const pic_fields *fields, double *diag, void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    pic_status st = validate_push_args(c, sp, p, fields);
+    if (st != PIC_OK || p->n == 0) return st;
     hipSetDevice(c->device);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = c->cfg.precision == PIC_FP32_MIXED ? launch_gpd_tiled(c, sp, p, fields, diag, s)
@@ -341,6 +391,50 @@ extern "C" pic_status pic_yee_step(void *ctx, int32_t half, const pic_fields *fi
     hipSetDevice(c->device);
     hipError_t e = launch_yee(c, half, fields, diag, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "pic_yee_step");
+    return PIC_OK;
+}
+
+static pic_status check_particles_layout(Ctx *c, const pic_particles *p) {
+    for (int a = 0; a < 3; ++a)
+        if (!p->u[a]) return fail(c, PIC_E_ARG, "momentum array is NULL");
+    if (c->cfg.precision == PIC_FP32_MIXED) {
+        if (!p->cell) return fail(c, PIC_E_ARG, "cell array is NULL");
+        for (int a = 0; a < c->dim; ++a)
+            if (!p->off[a]) return fail(c, PIC_E_ARG, "offset array is NULL");
+    } else {
+        for (int a = 0; a < c->dim; ++a)
+            if (!p->x[a]) return fail(c, PIC_E_ARG, "position array is NULL");
+    }
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_deposit_rho(void *ctx, const pic_species *sp, const pic_particles *p, int32_t at_half,
+                                      double *rho, void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (!sp || !p || !rho) return fail(c, PIC_E_ARG, "species, particles or rho is NULL");
+    if (!isfinite(sp->q) || !isfinite(sp->w0)) return fail(c, PIC_E_ARG, "charge and weight must be finite");
+    if (at_half != 0 && at_half != 1) return fail(c, PIC_E_ARG, "at_half must be 0 or 1");
+    if (p->n < 0) return fail(c, PIC_E_ARG, "negative particle count");
+    if (p->n == 0) return PIC_OK;
+    pic_status st = check_particles_layout(c, p);
+    if (st != PIC_OK) return st;
+    hipSetDevice(c->device);
+    hipError_t e = launch_rho(c, sp, p, at_half, rho, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_deposit_rho");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_gauss_residual(void *ctx, const pic_fields *fields, const double *rho,
+                                         double *residual, double *diag, void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (!fields || !rho) return fail(c, PIC_E_ARG, "fields or rho is NULL");
+    for (int a = 0; a < c->dim; ++a)
+        if (!fields->E[a]) return fail(c, PIC_E_ARG, "an E plane is NULL");
+    hipSetDevice(c->device);
+    hipError_t e = launch_gauss(c, fields, rho, residual, diag, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_gauss_residual");
     return PIC_OK;
 }
 
@@ -427,18 +521,18 @@ extern "C" pic_status pic_qed_step(void *ctx, const pic_qed_args *qa, void *stre
         if (st != PIC_OK) return st;
         if (sp[k] && k < 2 && sp[k]->n > 0 && !sp[k]->chi)
             return fail(c, PIC_E_ARG, "leptons need the chi array written by the push");
+        // a decayed photon is removed through its weight
+        if (sp[k] && k == 2 && (sp[k]->n > 0 || sp[k]->capacity > 0) && !sp[k]->w)
+            return fail(c, PIC_E_ARG, "photons need per-particle weights (a decayed photon gets w = 0)");
+        // the network reads chi_gamma, which the photon step writes there first
+        if (sp[k] && k == 2 && sp[k]->n > 0 && qa->mode == PIC_QED_MLP && !sp[k]->chi)
+            return fail(c, PIC_E_ARG, "PIC_QED_MLP needs the photons' chi array");
         if (sp[k] && sp[k]->n > nmax) nmax = sp[k]->n;
     }
     hipSetDevice(c->device);
-    if (qa->mode == PIC_QED_MLP && (size_t)(2 * nmax) > c->mlp_scratch_cap) {
-        hipDeviceSynchronize();
-        hipFree(c->mlp_scratch);
-        c->mlp_scratch = nullptr;
-        c->mlp_scratch_cap = 0;
-        const size_t cap = (size_t)(2 * nmax) + (size_t)nmax / 2 + 1024;
-        if (hipMalloc(&c->mlp_scratch, cap * sizeof(float)) != hipSuccess)
-            return fail(c, PIC_E_NOMEM, "cannot allocate network outputs");
-        c->mlp_scratch_cap = cap;
+    if (qa->mode == PIC_QED_MLP) {
+        st = ensure_mlp_scratch(c, nmax);
+        if (st != PIC_OK) return st;
     }
     hipError_t e = launch_qed(c, qa, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "pic_qed_step");

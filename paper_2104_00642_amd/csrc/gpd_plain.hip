@@ -286,8 +286,10 @@ hipError_t launch_finalize(const double *partials, int64_t nblocks, int nval, do
     return hipGetLastError();
 }
 
+size_t push_partials_plain(int64_t n) { return 2 * (size_t)((n + 255) / 256); }
+
 hipError_t launch_gpd_plain(Ctx *c, const pic_species *sp, const pic_particles *p,
-                            const pic_fields *f, double *diag, hipStream_t s) {
+                            const pic_fields *f, double *diag, hipStream_t s, const PushScratch *ps) {
     const pic_config &cfg = c->cfg;
     PlainArgs a{};
     a.n = p->n;
@@ -316,8 +318,12 @@ hipError_t launch_gpd_plain(Ctx *c, const pic_species *sp, const pic_particles *
     a.status = c->status;
     const int64_t nblocks = (p->n + 255) / 256;
     if (nblocks == 0) return hipSuccess;
-    if (ensure_partials(c, 2 * (size_t)nblocks) != PIC_OK) return hipErrorOutOfMemory;
-    a.partials = c->partials;
+    if (ps) {
+        a.partials = ps->partials;
+    } else {
+        if (ensure_partials(c, push_partials_plain(p->n)) != PIC_OK) return hipErrorOutOfMemory;
+        a.partials = c->partials;
+    }
     dim3 grid((unsigned)nblocks), block(256);
     const int key = c->dim * 10 + cfg.order;
     switch (key) {
@@ -331,7 +337,7 @@ hipError_t launch_gpd_plain(Ctx *c, const pic_species *sp, const pic_particles *
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !diag) return e;
-    return launch_finalize(c->partials, nblocks, 2, diag, 0, 1.0, s);
+    return launch_finalize(a.partials, nblocks, 2, diag, 0, 1.0, s);
 }
 
 }  // namespace pic

@@ -999,8 +999,10 @@ static void launch_pusher(const TiledArgs &a, int pusher, size_t lds, hipStream_
     else launch_tiled<DIM, ORDER, PIC_PUSH_BORIS>(a, lds, s);
 }
 
+size_t push_partials_tiled(int64_t ntiles) { return 2 * (2 * (size_t)ntiles + GLOBAL_BLOCKS); }
+
 hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *p,
-                            const pic_fields *f, double *diag, hipStream_t s) {
+                            const pic_fields *f, double *diag, hipStream_t s, const PushScratch *ps) {
     const pic_config &cfg = c->cfg;
     TiledArgs a{};
     a.cell = p->cell;
@@ -1042,15 +1044,26 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
     a.stragglers = (unsigned long long *)(c->status + 2);
     a.strag_count = c->status + 4;
     const size_t nblocks = 2 * (size_t)c->ntiles + GLOBAL_BLOCKS;
-    if (ensure_partials(c, 2 * nblocks) != PIC_OK) return hipErrorOutOfMemory;
-    if (ensure_strag_list(c, p->n) != PIC_OK) return hipErrorOutOfMemory;
-    a.partials = c->partials;
-    a.strag_list = c->strag_list;
-    a.strag_tile = c->strag_tile;
-    a.bin_list = c->bin_list;
-    a.bin_rank = c->bin_rank;
-    a.bin_start = c->bin_start;
-    a.bin_count = c->bin_count;
+    PushScratch own;
+    if (!ps) {
+        if (ensure_partials(c, push_partials_tiled(c->ntiles)) != PIC_OK) return hipErrorOutOfMemory;
+        if (ensure_strag_list(c, p->n) != PIC_OK) return hipErrorOutOfMemory;
+        own.partials = c->partials;
+        own.strag_list = c->strag_list;
+        own.strag_tile = c->strag_tile;
+        own.bin_list = c->bin_list;
+        own.bin_rank = c->bin_rank;
+        own.bin_start = c->bin_start;
+        own.bin_count = c->bin_count;
+        ps = &own;
+    }
+    a.partials = ps->partials;
+    a.strag_list = ps->strag_list;
+    a.strag_tile = ps->strag_tile;
+    a.bin_list = ps->bin_list;
+    a.bin_rank = ps->bin_rank;
+    a.bin_start = ps->bin_start;
+    a.bin_count = ps->bin_count;
     const size_t lds = c->lds_bytes;
     switch (c->dim * 10 + cfg.order) {
         case 21: launch_pusher<2, 1>(a, cfg.pusher, lds, s); break;
@@ -1066,7 +1079,7 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
                                                                          a.ng[0] - 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !diag) return e;
-    return launch_finalize(c->partials, (int64_t)nblocks, 2, diag, 0, 1.0, s);
+    return launch_finalize(a.partials, (int64_t)nblocks, 2, diag, 0, 1.0, s);
 }
 
 template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ>

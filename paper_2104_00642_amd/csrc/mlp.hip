@@ -4,10 +4,14 @@
 // on gfx950.
 //
 // Network: h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 W3 + b3.
-// Weights are BF16, biases FP32.  In the forward pass every activation enters
-// the MFMAs as two BF16 terms (hi = bf16(a), lo = bf16(a - hi): about 16
-// significant bits, two MFMAs per tile), so the rates are not limited by an
-// 8-bit activation mantissa; the backward pass uses single BF16 terms.
+// Weights are BF16 pairs, biases FP32.  Each weight is stored as two BF16
+// terms, hi = bf16(w) and lo = bf16(w - hi) (about 16 significant bits), and
+// in the forward pass every activation enters the MFMAs as two BF16 terms
+// too; a product takes w_hi a_hi + w_hi a_lo + w_lo a_hi (the lo x lo term
+// is below 2^-16 of it).  With single BF16 weights the rates stalled near
+// 1e-3 relative error: gradient steps below half a BF16 unit do not change
+// the rounded weights, so training cannot polish them.  The backward pass
+// uses single BF16 terms (hi only).
 // Training objective: sum over rows and outputs of w_o (y_o - t_o)^2 / (2 n)
 // with w = (MLP_RATE_WEIGHT, 1): the rate output carries the 1e-3 accuracy
 // target, the sampled fraction only enters a Monte-Carlo draw.
@@ -75,6 +79,29 @@ __device__ __forceinline__ f32x4 tile_mma_split(FA A, FB B, int K, f32x4 acc) {
     return acc;
 }
 
+// acc += A B for one 16x16 tile, A split into hi + lo BF16 terms and B given
+// as its hi and lo BF16 terms: A_hi B_hi + A_lo B_hi + A_hi B_lo
+template <class FA, class FB, class FBL>
+__device__ __forceinline__ f32x4 tile_mma_split2(FA A, FB Bh, FBL Bl, int K, f32x4 acc) {
+    const int l = threadIdx.x & 63;
+    const int rc = l & 15, kq = 4 * (l >> 4);
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x4 ah, al, bh, bl;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float x = A(rc, k0 + kq + i);
+            ah[i] = f2bf(x);
+            al[i] = f2bf(x - bf2f(ah[i]));
+            bh[i] = Bh(k0 + kq + i, rc);
+            bl[i] = Bl(k0 + kq + i, rc);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
 constexpr float MLP_RATE_WEIGHT = 10.0f;
 
 // tanh from the hardware exponential and reciprocal: 1 - 2 / (1 + 2^{2x log2 e})
@@ -84,15 +111,24 @@ __device__ __forceinline__ float tanh_f(float x) {
 }
 
 struct MlpView {
-    const short *W1, *W2, *W3;  // [4][64], [64][64], [64][2] BF16
+    const short *W1, *W2, *W3;  // [4][64], [64][64], [64][2] BF16 hi terms
     const float *b1, *b2, *b3;
+    const short *L1, *L2, *L3;  // their BF16 lo terms
 };
 
 __device__ __forceinline__ MlpView mlp_view(const void *m) {
     const char *p = (const char *)m;
     return MlpView{(const short *)(p + PIC_MLP_OFF_W1), (const short *)(p + PIC_MLP_OFF_W2),
                    (const short *)(p + PIC_MLP_OFF_W3), (const float *)(p + PIC_MLP_OFF_B1),
-                   (const float *)(p + PIC_MLP_OFF_B2), (const float *)(p + PIC_MLP_OFF_B3)};
+                   (const float *)(p + PIC_MLP_OFF_B2), (const float *)(p + PIC_MLP_OFF_B3),
+                   (const short *)(p + PIC_MLP_OFF_W1_LO), (const short *)(p + PIC_MLP_OFF_W2_LO),
+                   (const short *)(p + PIC_MLP_OFF_W3_LO)};
+}
+
+// a weight's hi and lo BF16 terms
+__device__ __forceinline__ void bf_split(float p, short &hi, short &lo) {
+    hi = f2bf(p);
+    lo = f2bf(p - bf2f(hi));
 }
 
 struct WaveLds {
@@ -109,24 +145,27 @@ __device__ void mlp_forward16(const MlpView &w, WaveLds &L) {
     const int col = l & 15, r4 = 4 * (l >> 4);
     for (int nt = 0; nt < 4; ++nt) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = tile_mma_split([&](int m, int k) { return k < 4 ? L.X[m][k] : 0.0f; },
-                       [&](int k, int n) { return k < 4 ? bf2f(w.W1[k * 64 + 16 * nt + n]) : 0.0f; }, 16, acc);
+        acc = tile_mma_split2([&](int m, int k) { return k < 4 ? L.X[m][k] : 0.0f; },
+                              [&](int k, int n) { return k < 4 ? w.W1[k * 64 + 16 * nt + n] : (short)0; },
+                              [&](int k, int n) { return k < 4 ? w.L1[k * 64 + 16 * nt + n] : (short)0; }, 16, acc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) L.H1[r4 + i][16 * nt + col] = tanh_f(acc[i] + w.b1[16 * nt + col]);
     }
     __syncthreads();
     for (int nt = 0; nt < 4; ++nt) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = tile_mma_split([&](int m, int k) { return L.H1[m][k]; },
-                       [&](int k, int n) { return bf2f(w.W2[k * 64 + 16 * nt + n]); }, 64, acc);
+        acc = tile_mma_split2([&](int m, int k) { return L.H1[m][k]; },
+                              [&](int k, int n) { return w.W2[k * 64 + 16 * nt + n]; },
+                              [&](int k, int n) { return w.L2[k * 64 + 16 * nt + n]; }, 64, acc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) L.H2[r4 + i][16 * nt + col] = tanh_f(acc[i] + w.b2[16 * nt + col]);
     }
     __syncthreads();
     {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = tile_mma_split([&](int m, int k) { return L.H2[m][k]; },
-                       [&](int k, int n) { return n < 2 ? bf2f(w.W3[k * 2 + n]) : 0.0f; }, 64, acc);
+        acc = tile_mma_split2([&](int m, int k) { return L.H2[m][k]; },
+                              [&](int k, int n) { return n < 2 ? w.W3[k * 2 + n] : (short)0; },
+                              [&](int k, int n) { return n < 2 ? w.L3[k * 2 + n] : (short)0; }, 64, acc);
         if (col < 2) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) L.Y[r4 + i][col] = acc[i] + w.b3[col];
@@ -175,16 +214,21 @@ __device__ __forceinline__ void mlp_decode(int proc, float chi, const float *y, 
 // i = 0..7: the lane's values of output blocks 2j and 2j+1.  Any order of
 // the contraction is the same sum, provided the weights' A fragments use it
 // too.  Layer 1 (v_mfma_f32_16x16x16_bf16, k = 4 g + i) takes the inputs'
-// hi terms in g = 0, their lo terms in g = 1 and the bias as three BF16
-// terms against constant ones in g = 2.  Per 16-sample tile: 4 + 16 + 4
-// MFMAs, 32 tanh and 32 hi/lo splits per lane.
+// hi terms against W1's hi terms in g = 0, their lo terms against W1's hi
+// terms in g = 1, the bias as three BF16 terms against constant ones in
+// g = 2 and the inputs' hi terms against W1's lo terms in g = 3.  Layers 2
+// and 3 add a third MFMA per k-step, the weights' lo terms against the hi
+// activations.  Per 16-sample tile: 4 + 24 + 6 MFMAs, 32 tanh and 32 hi/lo
+// splits per lane.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16v4 __attribute__((ext_vector_type(4)));
 
 struct MlpFrags {
     bf16x4 w1[4];     // [output block]
-    bf16x8 w2[4][2];  // [output block][k-step]
-    bf16x8 w3[2];     // [k-step]; rows 0, 1 are the two outputs
+    bf16x8 w2[4][2];  // [output block][k-step], hi terms
+    bf16x8 l2[4][2];  // lo terms
+    bf16x8 w3[2];     // [k-step]; rows 0, 1 are the two outputs; hi terms
+    bf16x8 l3[2];     // lo terms
     f32x4 b2[4];      // bias of rows 4g+i of each output block
     f32x4 b3;
 };
@@ -207,20 +251,25 @@ __device__ __forceinline__ void mlp_load_frags(const MlpView &w, MlpFrags &F) {
             short v = 0;
             if (g < 2) v = w.W1[i * 64 + o];
             else if (g == 2) v = bf_bits(i == 0 ? t0 : i == 1 ? t1 : i == 2 ? t2 : 0.0f);
+            else v = w.L1[i * 64 + o];
             F.w1[nt][i] = v;
             F.b2[nt][i] = w.b2[16 * nt + 4 * g + i];
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
+            for (int i = 0; i < 8; ++i) {
                 F.w2[nt][j][i] = __builtin_bit_cast(__bf16, w.W2[mlp_slot_feature(j, g, i) * 64 + o]);
+                F.l2[nt][j][i] = __builtin_bit_cast(__bf16, w.L2[mlp_slot_feature(j, g, i) * 64 + o]);
+            }
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < 8; ++i) {
             F.w3[j][i] = __builtin_bit_cast(__bf16, m < 2 ? w.W3[mlp_slot_feature(j, g, i) * 2 + m] : (short)0);
+            F.l3[j][i] = __builtin_bit_cast(__bf16, m < 2 ? w.L3[mlp_slot_feature(j, g, i) * 2 + m] : (short)0);
+        }
 #pragma unroll
     for (int i = 0; i < 4; ++i) F.b3[i] = g == 0 && i < 2 ? w.b3[i] : 0.0f;
 }
@@ -266,12 +315,13 @@ __device__ __forceinline__ void mlp_infer_tile(const MlpFrags &F, InferLds &L, i
     const int l = threadIdx.x & 63;
     const int g = l >> 4, s = 16 * t + (l & 15);
     const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-    // lane group g: 0 hi terms, 1 lo terms, 2 the ones against the bias terms
+    // lane group g: 0 hi terms, 1 lo terms, 2 the ones against the bias
+    // terms, 3 hi terms against the weights' lo terms
     const f32x4 x = *(const f32x4 *)L.X[s];
     const bf16v4 xh = __builtin_convertvector(x, bf16v4);
     const bf16v4 xl = __builtin_convertvector(x - __builtin_convertvector(xh, f32x4), bf16v4);
-    const bf16v4 one = {(__bf16)1.0f, (__bf16)1.0f, (__bf16)1.0f, (__bf16)0.0f}, zero = {};
-    const bf16x4 xb = __builtin_bit_cast(bf16x4, g == 0 ? xh : g == 1 ? xl : g == 2 ? one : zero);
+    const bf16v4 one = {(__bf16)1.0f, (__bf16)1.0f, (__bf16)1.0f, (__bf16)0.0f};
+    const bf16x4 xb = __builtin_bit_cast(bf16x4, g == 1 ? xl : g == 2 ? one : xh);
     f32x4 c1[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) c1[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(F.w1[nt], xb, z, 0, 0, 0);
@@ -286,6 +336,7 @@ __device__ __forceinline__ void mlp_infer_tile(const MlpFrags &F, InferLds &L, i
         for (int j = 0; j < 2; ++j) {
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w2[nt][j], hh[j], acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w2[nt][j], hl[j], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.l2[nt][j], hh[j], acc, 0, 0, 0);
         }
         c2[nt] = acc;
     }
@@ -296,6 +347,7 @@ __device__ __forceinline__ void mlp_infer_tile(const MlpFrags &F, InferLds &L, i
     for (int j = 0; j < 2; ++j) {
         c3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w3[j], hh[j], c3, 0, 0, 0);
         c3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w3[j], hl[j], c3, 0, 0, 0);
+        c3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.l3[j], hh[j], c3, 0, 0, 0);
     }
     if (g == 0) {
         L.Y[s][0] = c3[0];
@@ -508,6 +560,28 @@ __global__ void __launch_bounds__(64) mlp_grad_kernel(const void *mlp, const flo
     }
 }
 
+// parameter i (flat order) into the network: weights as hi and lo BF16 terms
+__device__ __forceinline__ void mlp_store_param(char *net, int i, float p) {
+    short hi, lo;
+    bf_split(p, hi, lo);
+    if (i < P_B1) {
+        ((short *)(net + PIC_MLP_OFF_W1))[i - P_W1] = hi;
+        ((short *)(net + PIC_MLP_OFF_W1_LO))[i - P_W1] = lo;
+    } else if (i < P_W2) {
+        ((float *)(net + PIC_MLP_OFF_B1))[i - P_B1] = p;
+    } else if (i < P_B2) {
+        ((short *)(net + PIC_MLP_OFF_W2))[i - P_W2] = hi;
+        ((short *)(net + PIC_MLP_OFF_W2_LO))[i - P_W2] = lo;
+    } else if (i < P_W3) {
+        ((float *)(net + PIC_MLP_OFF_B2))[i - P_B2] = p;
+    } else if (i < P_B3) {
+        ((short *)(net + PIC_MLP_OFF_W3))[i - P_W3] = hi;
+        ((short *)(net + PIC_MLP_OFF_W3_LO))[i - P_W3] = lo;
+    } else {
+        ((float *)(net + PIC_MLP_OFF_B3))[i - P_B3] = p;
+    }
+}
+
 // Adam step on the FP32 master parameters, then the BF16/FP32 network copy;
 // clears the gradient.  state: [params | m | v | grad] floats, then step count.
 __global__ void __launch_bounds__(256) mlp_adam_kernel(float *state, float lr, void *mlp) {
@@ -525,12 +599,7 @@ __global__ void __launch_bounds__(256) mlp_adam_kernel(float *state, float lr, v
         prm[i] -= lr * (m[i] / c1) / (sqrtf(v[i] / c2) + 1e-8f);
         g[i] = 0.0f;
         const float p = prm[i];
-        if (i < P_B1) ((short *)(net + PIC_MLP_OFF_W1))[i - P_W1] = f2bf(p);
-        else if (i < P_W2) ((float *)(net + PIC_MLP_OFF_B1))[i - P_B1] = p;
-        else if (i < P_B2) ((short *)(net + PIC_MLP_OFF_W2))[i - P_W2] = f2bf(p);
-        else if (i < P_W3) ((float *)(net + PIC_MLP_OFF_B2))[i - P_B2] = p;
-        else if (i < P_B3) ((short *)(net + PIC_MLP_OFF_W3))[i - P_W3] = f2bf(p);
-        else ((float *)(net + PIC_MLP_OFF_B3))[i - P_B3] = p;
+        mlp_store_param(net, i, p);
     }
     __syncthreads();
     if (threadIdx.x == 0) tstep[0] = t;
@@ -541,12 +610,7 @@ __global__ void mlp_export_kernel(const float *prm, void *mlp) {
     char *net = (char *)mlp;
     for (int i = threadIdx.x; i < PIC_MLP_NPARAM; i += blockDim.x) {
         const float p = prm[i];
-        if (i < P_B1) ((short *)(net + PIC_MLP_OFF_W1))[i - P_W1] = f2bf(p);
-        else if (i < P_W2) ((float *)(net + PIC_MLP_OFF_B1))[i - P_B1] = p;
-        else if (i < P_B2) ((short *)(net + PIC_MLP_OFF_W2))[i - P_W2] = f2bf(p);
-        else if (i < P_W3) ((float *)(net + PIC_MLP_OFF_B2))[i - P_B2] = p;
-        else if (i < P_B3) ((short *)(net + PIC_MLP_OFF_W3))[i - P_W3] = f2bf(p);
-        else ((float *)(net + PIC_MLP_OFF_B3))[i - P_B3] = p;
+        mlp_store_param(net, i, p);
     }
 }
 

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/pic.h"
 #include "qed_internal.h"
@@ -53,6 +54,10 @@ struct Ctx {
     void *mur_old = nullptr;
     pic_laser laser{};
     double time = 0.0;
+    // block maxima of the Gauss residual (GAUSS_PART doubles)
+    double *gauss_part = nullptr;
+    // scratch outgrown by an enqueueing call, freed by pic_reserve / pic_destroy
+    std::vector<void *> retired;
     std::string err;
 };
 
@@ -60,12 +65,32 @@ struct Ctx {
 pic_status fail(Ctx *c, pic_status s, const std::string &msg);
 pic_status ensure_partials(Ctx *c, size_t n);
 pic_status ensure_strag_list(Ctx *c, int64_t n);
+pic_status ensure_sort_scratch(Ctx *c, int64_t n);
+pic_status ensure_mlp_scratch(Ctx *c, int64_t nmax);
 
-// launchers (return hipError_t of the launch)
+// Scratch of one push: FP64 block partials of the diagnostics, the straggler
+// list, the bin list and ranks (n entries each), per-tile counters and bin
+// starts.  The context's own buffers, or carved from a caller's region.
+struct PushScratch {
+    double *partials = nullptr;
+    int32_t *strag_list = nullptr;
+    int32_t *bin_list = nullptr;
+    uint32_t *bin_rank = nullptr;
+    uint32_t *bin_count = nullptr;   // ntiles
+    uint32_t *strag_tile = nullptr;  // ntiles
+    int64_t *bin_start = nullptr;    // ntiles + 1
+};
+// doubles of FP64 partials one push writes (FP32 tiled path, FP64 plain path)
+size_t push_partials_tiled(int64_t ntiles);
+size_t push_partials_plain(int64_t n);
+
+// launchers (return hipError_t of the launch); ps = nullptr: the context's
+// scratch, grown as needed
 hipError_t launch_gpd_plain(Ctx *c, const pic_species *sp, const pic_particles *p,
-                            const pic_fields *f, double *diag, hipStream_t s);
+                            const pic_fields *f, double *diag, hipStream_t s, const PushScratch *ps = nullptr);
 hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *p,
-                            const pic_fields *f, double *diag, hipStream_t s);
+                            const pic_fields *f, double *diag, hipStream_t s, const PushScratch *ps = nullptr);
+pic_status validate_push_args(Ctx *c, const pic_species *sp, const pic_particles *p, const pic_fields *fields);
 hipError_t launch_yee(Ctx *c, int half, const pic_fields *f, double *diag, hipStream_t s);
 hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *dst,
                        hipStream_t s);
@@ -78,6 +103,11 @@ hipError_t launch_mlp_grad(const void *mlp, const float *x, const float *t, int6
 hipError_t launch_mlp_train(float *state, void *mlp, const float *x, const float *t, int64_t n, int batch,
                             int iters, float lr, float *loss, hipStream_t s);
 hipError_t launch_mlp_data(Ctx *c, int64_t n, uint64_t seed, float *x, float *t, hipStream_t s);
+hipError_t launch_rho(Ctx *c, const pic_species *sp, const pic_particles *p, int at_half, double *rho,
+                      hipStream_t s);
+hipError_t launch_gauss(Ctx *c, const pic_fields *f, const double *rho, double *res, double *diag,
+                        hipStream_t s);
+constexpr int GAUSS_PART = 1024;
 size_t sort_lds_bytes(int cells_per_tile);
 hipError_t launch_finalize(const double *partials, int64_t nblocks, int nval, double *diag,
                            int diag_offset, double scale, hipStream_t s);

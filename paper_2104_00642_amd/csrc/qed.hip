@@ -55,6 +55,7 @@ struct QedArgs {
     uint64_t seed;
     uint32_t step;
     int method2;
+    int absorb_x;          // absorbing x faces (photons leave through them)
     uint32_t *status;
 };
 
@@ -181,8 +182,17 @@ __global__ void __launch_bounds__(QED_THREADS) qed_lepton_kernel(QedArgs a, int 
     }
 }
 
-// photons: ballistic move, chi_gamma at the new position, pair creation
-template <int DIM, int ORDER>
+// Photon step phases.  The tables (and Method II) take every step of a photon
+// in one pass; the network needs chi_gamma at the moved photon before it can
+// answer, so network mode runs the move and chi_gamma first (PH_MOVE, which
+// writes chi), then the network on those chi, then the decays (PH_DECAY).
+enum { PH_ALL = 0, PH_MOVE = 1, PH_DECAY = 2 };
+
+// photons: ballistic move, chi_gamma at the new position, pair creation.
+// With absorbing x faces a photon whose new position leaves [0, (n-1) dx]
+// is absorbed (weight 0, chi 0, no decay), and no field is gathered from x
+// nodes beyond [0, n).
+template <int DIM, int ORDER, int PHASE>
 __global__ void __launch_bounds__(QED_PHOTON_THREADS) qed_photon_kernel(QedArgs a) {
     const QedSpecies &P = a.sp[2];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -192,73 +202,96 @@ __global__ void __launch_bounds__(QED_PHOTON_THREADS) qed_photon_kernel(QedArgs 
     uint64_t id = 0;
     do {  // every thread reaches the appends below
     if (p >= P.n) break;
-    w = P.w ? P.w[p] : 1.0f;
+    w = P.w[p];
     if (w == 0.0f) break;
     k[0] = P.u[0][p];
     k[1] = P.u[1][p];
     k[2] = P.u[2][p];
     eps = sqrtf(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
     if (!(eps > 0.0f)) break;
-    const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
-    const int32_t cell = P.cell[p];
-    int cc[3] = {cell & mx, (cell >> a.bx) & my, DIM == 3 ? (cell >> (a.bx + a.by)) : 0};
-    f[0] = P.off[0][p];
-    f[1] = P.off[1][p];
-    f[2] = DIM == 3 ? P.off[2][p] : 0.0f;
-    // move at c along k
+    float chi;
+    if constexpr (PHASE == PH_DECAY) {
+        // moved, and chi_gamma written, by the PH_MOVE pass
+        packed = P.cell[p];
+        f[0] = P.off[0][p];
+        f[1] = P.off[1][p];
+        f[2] = DIM == 3 ? P.off[2][p] : 0.0f;
+        chi = P.chi[p];
+    } else {
+        const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
+        const int32_t cell = P.cell[p];
+        int cc[3] = {cell & mx, (cell >> a.bx) & my, DIM == 3 ? (cell >> (a.bx + a.by)) : 0};
+        f[0] = P.off[0][p];
+        f[1] = P.off[1][p];
+        f[2] = DIM == 3 ? P.off[2][p] : 0.0f;
+        bool gone = false;
+        // move at c along k
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        const float xn = f[d] + a.dt * a.inv_d[d] * k[d] / eps;
-        const float fl = floorf(xn);
-        float fr = xn - fl;
-        int di = (int)fl;
-        if (fr >= 1.0f) {
-            fr = 0.0f;
-            ++di;
+        for (int d = 0; d < DIM; ++d) {
+            const float xn = f[d] + a.dt * a.inv_d[d] * k[d] / eps;
+            const float fl = floorf(xn);
+            float fr = xn - fl;
+            int di = (int)fl;
+            if (fr >= 1.0f) {
+                fr = 0.0f;
+                ++di;
+            }
+            int nc = cc[d] + di;
+            // x nodes of the domain are [0, n-1]: a new cell outside [0, n-2]
+            // (before the wrap) is a position beyond a face
+            if (d == 0 && a.absorb_x) gone = nc < 0 || nc >= a.ng[0] - 1;
+            nc = ((nc % a.ng[d]) + a.ng[d]) % a.ng[d];
+            cc[d] = nc;
+            f[d] = fr;
+            P.off[d][p] = fr;
+            packed |= nc << (d == 0 ? 0 : (d == 1 ? a.bx : a.bx + a.by));
         }
-        int nc = cc[d] + di;
-        nc = ((nc % a.ng[d]) + a.ng[d]) % a.ng[d];
-        cc[d] = nc;
-        f[d] = fr;
-        P.off[d][p] = fr;
-        packed |= nc << (d == 0 ? 0 : (d == 1 ? a.bx : a.bx + a.by));
+        P.cell[p] = packed;
+        if (gone) {
+            P.w[p] = 0.0f;
+            if (P.chi) P.chi[p] = 0.0f;
+            w = 0.0f;
+            break;
+        }
+        // fields at the photon (Eq. 19 with the push's weights)
+        constexpr int NW = ORDER + 1;
+        int i0[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        float wt[2][3][NW];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            shape_weights<ORDER>(f[d], i0[0][d], wt[0][d]);
+            shape_weights<ORDER>(f[d] - 0.5f, i0[1][d], wt[1][d]);
+        }
+        float EB[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const int sx = stag(c, 0), sy = stag(c, 1), sz = DIM == 3 ? stag(c, 2) : 0;
+            float acc = 0.0f;
+#pragma unroll
+            for (int kk = 0; kk < (DIM == 3 ? NW : 1); ++kk)
+#pragma unroll
+                for (int jj = 0; jj < NW; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < NW; ++ii) {
+                        const int ui = cc[0] + i0[sx][0] + ii;
+                        if (a.absorb_x && (unsigned)ui >= (unsigned)a.ng[0]) continue;  // beyond a face
+                        const int gi = wrap_index(ui, a.ng[0]);
+                        const int gj = wrap_index(cc[1] + i0[sy][1] + jj, a.ng[1]);
+                        const int gk = DIM == 3 ? wrap_index(cc[2] + i0[sz][2] + kk, a.ng[2]) : 0;
+                        const float wk = DIM == 3 ? wt[sz][2][kk] : 1.0f;
+                        acc += wt[sx][0][ii] * wt[sy][1][jj] * wk *
+                               a.F[c][(int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk)];
+                    }
+            EB[c] = acc;
+        }
+        const float f0 = eps * EB[0] + k[1] * EB[5] - k[2] * EB[4];
+        const float f1 = eps * EB[1] + k[2] * EB[3] - k[0] * EB[5];
+        const float f2 = eps * EB[2] + k[0] * EB[4] - k[1] * EB[3];
+        const float ke = k[0] * EB[0] + k[1] * EB[1] + k[2] * EB[2];
+        chi = a.hbar_w * sqrtf(fmaxf(f0 * f0 + f1 * f1 + f2 * f2 - ke * ke, 0.0f));
+        if (P.chi) P.chi[p] = chi;
+        if constexpr (PHASE == PH_MOVE) break;
     }
-    P.cell[p] = packed;
-    // fields at the photon (Eq. 19 with the push's weights)
-    constexpr int NW = ORDER + 1;
-    int i0[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    float wt[2][3][NW];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        shape_weights<ORDER>(f[d], i0[0][d], wt[0][d]);
-        shape_weights<ORDER>(f[d] - 0.5f, i0[1][d], wt[1][d]);
-    }
-    float EB[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const int sx = stag(c, 0), sy = stag(c, 1), sz = DIM == 3 ? stag(c, 2) : 0;
-        float acc = 0.0f;
-#pragma unroll
-        for (int kk = 0; kk < (DIM == 3 ? NW : 1); ++kk)
-#pragma unroll
-            for (int jj = 0; jj < NW; ++jj)
-#pragma unroll
-                for (int ii = 0; ii < NW; ++ii) {
-                    const int gi = wrap_index(cc[0] + i0[sx][0] + ii, a.ng[0]);
-                    const int gj = wrap_index(cc[1] + i0[sy][1] + jj, a.ng[1]);
-                    const int gk = DIM == 3 ? wrap_index(cc[2] + i0[sz][2] + kk, a.ng[2]) : 0;
-                    const float wk = DIM == 3 ? wt[sz][2][kk] : 1.0f;
-                    acc += wt[sx][0][ii] * wt[sy][1][jj] * wk *
-                           a.F[c][(int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk)];
-                }
-        EB[c] = acc;
-    }
-    const float f0 = eps * EB[0] + k[1] * EB[5] - k[2] * EB[4];
-    const float f1 = eps * EB[1] + k[2] * EB[3] - k[0] * EB[5];
-    const float f2 = eps * EB[2] + k[0] * EB[4] - k[1] * EB[3];
-    const float ke = k[0] * EB[0] + k[1] * EB[1] + k[2] * EB[2];
-    const float chi = a.hbar_w * sqrtf(fmaxf(f0 * f0 + f1 * f1 + f2 * f2 - ke * ke, 0.0f));
-    if (P.chi) P.chi[p] = chi;
     double tau = 0.0;
     id = P.id[p];
     if (a.method2) {
@@ -280,9 +313,10 @@ __global__ void __launch_bounds__(QED_PHOTON_THREADS) qed_photon_kernel(QedArgs 
             tau = 0.0;
         }
     }
-    if (x >= 0.0f && P.w) P.w[p] = 0.0f;  // the photon is gone
+    if (x >= 0.0f) P.w[p] = 0.0f;  // the photon is gone
     if (!a.method2) P.tau[p] = tau;
     } while (false);
+    if constexpr (PHASE == PH_MOVE) return;  // uniform: no appends in this pass
     const bool decay = x >= 0.0f;
     const float xs = fminf(fmaxf(x, 0.0f), 1.0f);
     const float ep = xs * eps, em = (1.0f - xs) * eps;
@@ -296,6 +330,18 @@ __global__ void __launch_bounds__(QED_PHOTON_THREADS) qed_photon_kernel(QedArgs 
         const int64_t slot = group_reserve(decay, a.sp[0].n_dev, a.sp[0].capacity, a.status);
         const float um[3] = {nm * k[0], nm * k[1], nm * k[2]};
         if (slot >= 0) qed_write(a, 0, slot, packed, f, um, w, qed_child_id(a.seed, id, a.step, 3u));
+    }
+}
+
+template <int PHASE>
+static void launch_photons(const QedArgs &ap, int key, unsigned nb, hipStream_t s) {
+    switch (key) {
+        case 21: qed_photon_kernel<2, 1, PHASE><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
+        case 22: qed_photon_kernel<2, 2, PHASE><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
+        case 31: qed_photon_kernel<3, 1, PHASE><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
+        case 32: qed_photon_kernel<3, 2, PHASE><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
+        case 24: qed_photon_kernel<2, 4, PHASE><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
+        case 34: qed_photon_kernel<3, 4, PHASE><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
     }
 }
 
@@ -347,26 +393,26 @@ hipError_t launch_qed(Ctx *c, const pic_qed_args *qa, hipStream_t s) {
     a.seed = cfg.seed;
     a.step = qa->step;
     a.method2 = qa->mode == PIC_QED_METHOD2;
+    a.absorb_x = cfg.bc[0] == PIC_BC_ABSORB;
     a.status = c->status;
     // photons first (their pairs are created from this step's photons only),
     // then the leptons that existed at the start of the step
     if (sp[2] && sp[2]->n > 0) {
         QedArgs ap = a;
-        if (qa->mode == PIC_QED_MLP) {
-            QedSpeciesView v{sp[2]->chi, sp[2]->id, (const float *)sp[2]->w, sp[2]->n, cfg.seed, qa->step};
-            hipError_t e = launch_mlp_for_qed(c, qa->mlp, v, QED_PAIR, c->mlp_scratch, s);
-            if (e != hipSuccess) return e;
-            ap.mlp_out = c->mlp_scratch;
-        }
         const unsigned nb = (unsigned)((sp[2]->n + QED_PHOTON_THREADS - 1) / QED_PHOTON_THREADS);
         const int key = c->dim * 10 + cfg.order;
-        switch (key) {
-            case 21: qed_photon_kernel<2, 1><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
-            case 22: qed_photon_kernel<2, 2><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
-            case 31: qed_photon_kernel<3, 1><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
-            case 32: qed_photon_kernel<3, 2><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
-            case 24: qed_photon_kernel<2, 4><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
-            case 34: qed_photon_kernel<3, 4><<<nb, QED_PHOTON_THREADS, 0, s>>>(ap); break;
+        if (qa->mode == PIC_QED_MLP) {
+            // move and chi_gamma first: the network answers at this step's chi
+            launch_photons<PH_MOVE>(ap, key, nb, s);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            QedSpeciesView v{sp[2]->chi, sp[2]->id, (const float *)sp[2]->w, sp[2]->n, cfg.seed, qa->step};
+            e = launch_mlp_for_qed(c, qa->mlp, v, QED_PAIR, c->mlp_scratch, s);
+            if (e != hipSuccess) return e;
+            ap.mlp_out = c->mlp_scratch;
+            launch_photons<PH_DECAY>(ap, key, nb, s);
+        } else {
+            launch_photons<PH_ALL>(ap, key, nb, s);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

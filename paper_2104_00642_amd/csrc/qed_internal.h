@@ -9,9 +9,9 @@ namespace pic {
 
 enum { QED_COMPTON = 0, QED_PAIR = 1 };
 
-constexpr int QED_NCHI = 128;   // chi points (log-uniform)
-constexpr int QED_NR = 512;     // inverse-CDF points in the transformed level rho
-constexpr int QED_NV = 4096;    // quadrature nodes of the table build
+constexpr int QED_NCHI = 256;   // chi points (log-uniform)
+constexpr int QED_NR = 1024;    // inverse-CDF points in the transformed level rho
+constexpr int QED_NV = 16384;   // quadrature nodes of the table build
 constexpr double QED_LOG_CHI_MIN_C = -4.0;
 constexpr double QED_LOG_CHI_MIN_P = -1.7;  // W_pair ~ exp(-8/(3 chi)) is below 1e-50 under chi = 0.02
 constexpr double QED_LOG_CHI_MAX = 3.0;
@@ -94,21 +94,27 @@ __device__ inline float qed_rate_F(const float *tab, int proc, float chi) {
 }
 
 // Inverse CDF: photon energy fraction u (Compton) or positron fraction x
-// (pairs) at level r, bilinear in (log10 chi, rho); chi clamped to the table.
+// (pairs) at level r: linear in rho, Catmull-Rom in log10 chi (at small chi
+// the fractions scale as powers of chi, u^(1/3) ~ chi^(1/3) and
+// x - 1/2 ~ chi^(1/2), curved in log chi enough that linear interpolation
+// would move the level by a few 1e-5); chi clamped to the table.
 __device__ inline float qed_inverse(const float *tab, int proc, float chi, float r) {
     const float lmin = qed_log_chi_min(proc), lmax = (float)QED_LOG_CHI_MAX;
     float x = (log10f(fmaxf(chi, 1e-30f)) - lmin) / (lmax - lmin) * (QED_NCHI - 1);
     x = fminf(fmaxf(x, 0.0f), (float)(QED_NCHI - 1) - 1e-3f);
     const int i = (int)x;
-    const float tx = x - i;
+    const float t = x - i;
     float y = qed_rho_of_r(proc, r) * (QED_NR - 1);
     y = fminf(fmaxf(y, 0.0f), (float)(QED_NR - 1) - 1e-3f);
     const int k = (int)y;
     const float ty = y - k;
     const float *T = tab + (proc == QED_COMPTON ? QED_OFF_INV_C : QED_OFF_INV_P);
-    const float a = T[i * QED_NR + k] * (1.0f - ty) + T[i * QED_NR + k + 1] * ty;
-    const float b = T[(i + 1) * QED_NR + k] * (1.0f - ty) + T[(i + 1) * QED_NR + k + 1] * ty;
-    const float v = a * (1.0f - tx) + b * tx;
+    auto row = [&](int ii) { return T[ii * QED_NR + k] * (1.0f - ty) + T[ii * QED_NR + k + 1] * ty; };
+    const float p1 = row(i), p2 = row(i + 1);
+    const float p0 = i > 0 ? row(i - 1) : 2.0f * p1 - p2;
+    const float p3 = i + 2 < QED_NCHI ? row(i + 2) : 2.0f * p2 - p1;
+    const float v = p1 + 0.5f * t * (p2 - p0 + t * (2.0f * p0 - 5.0f * p1 + 4.0f * p2 - p3 +
+                                                    t * (3.0f * (p1 - p2) + p3 - p0)));
     return proc == QED_COMPTON ? v * v * v : v;
 }
 

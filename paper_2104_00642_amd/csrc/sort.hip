@@ -53,14 +53,24 @@ __device__ __forceinline__ void decode_cell(int32_t c, const SortGeom &g, int &i
     iz = g.dim == 3 ? (c >> (g.bx + g.by)) : 0;
 }
 
+// A packed cell off the grid (x or y field beyond the cell count, or bits
+// above y that are not a z inside the grid: any in 2D, a negative cell) gets
+// the key ntiles: such particles follow the last tile in source order, where
+// the push flags them and leaves them unchanged.
 __global__ void __launch_bounds__(256) sort_keys_kernel(const int32_t *cell, int64_t n, SortGeom g,
                                                         uint32_t *keys) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
+    const int32_t c = cell[p];
     int ix, iy, iz;
-    decode_cell(cell[p], g, ix, iy, iz);
-    const int tx = ix / g.tile[0], ty = iy / g.tile[1], tz = iz / g.tile[2];
-    keys[p] = (uint32_t)(tx + g.ntile_axis[0] * (ty + g.ntile_axis[1] * tz));
+    decode_cell(c, g, ix, iy, iz);
+    const uint32_t above = (uint32_t)(c >> (g.bx + g.by));
+    const bool ok = (unsigned)ix < (unsigned)(g.tile[0] * g.ntile_axis[0]) &&
+                    (unsigned)iy < (unsigned)(g.tile[1] * g.ntile_axis[1]) &&
+                    above < (uint32_t)(g.dim == 3 ? g.tile[2] * g.ntile_axis[2] : 1);
+    const int tx = ix / g.tile[0], ty = iy / g.tile[1], tz = g.dim == 3 ? (int)above / g.tile[2] : 0;
+    keys[p] = ok ? (uint32_t)(tx + g.ntile_axis[0] * (ty + g.ntile_axis[1] * tz))
+                 : (uint32_t)(g.ntile_axis[0] * g.ntile_axis[1] * g.ntile_axis[2]);
 }
 
 __global__ void __launch_bounds__(SORT_THREADS) radix_hist_kernel(const uint32_t *keys, int64_t n,
@@ -224,8 +234,10 @@ __global__ void __launch_bounds__(256) tile_bounds_kernel(const uint32_t *keys, 
                                                           int64_t ntiles, int64_t *tile_start) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > n) return;
-    const int64_t tprev = i == 0 ? -1 : (int64_t)keys[i - 1];
-    const int64_t tcur = i == n ? ntiles : (int64_t)keys[i];
+    // keys are at most ntiles (off-grid particles); the clamps keep every
+    // write inside the ntiles + 1 entries whatever the keys hold
+    const int64_t tprev = i == 0 ? -1 : min((int64_t)keys[i - 1], ntiles);
+    const int64_t tcur = i == n ? ntiles : min((int64_t)keys[i], ntiles);
     for (int64_t t = tprev + 1; t <= tcur; ++t) tile_start[t] = i;
 }
 
@@ -241,6 +253,22 @@ struct PermArgs {
     int stride[SORT_MAX_COLS];
     int ncol;
 };
+
+// Off-grid particles [tile_start[ntiles], n) (key ntiles): copied in the
+// order of the sorted keys, which the stable radix sort left in source order
+// (vals: source indices).  Normally there are none.
+__global__ void __launch_bounds__(256) tail_copy_kernel(const uint32_t *vals, const int64_t *tile_start,
+                                                        int64_t ntiles, int64_t n, PermArgs pa) {
+    const int64_t first = min(tile_start[ntiles], n);
+    for (int64_t i = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = vals[i];
+        for (int col = 0; col < pa.ncol; ++col) {
+            const int sd = pa.stride[col];
+            pa.dst[col][i * sd] = pa.src[col][v * sd];
+        }
+    }
+}
 
 // phases A and D issue the loads of SORT_AHEAD rounds before using them
 constexpr int SORT_AHEAD = 4;
@@ -582,8 +610,9 @@ hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *ds
         return hipGetLastError();
     }
     sort_keys_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src->cell, n, g, c->keys[0]);
+    // keys run up to ntiles (the off-grid key)
     int bits = 0;
-    while ((1ll << bits) < c->ntiles) ++bits;
+    while ((1ll << bits) <= c->ntiles) ++bits;
     const int passes = bits == 0 ? 1 : (bits + 7) / 8;
     const int64_t nblocks = (n + SORT_ITEMS - 1) / SORT_ITEMS;
     int cur = 0;
@@ -632,6 +661,7 @@ hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *ds
     tile_order_kernel<<<(unsigned)c->ntiles, ORDER_THREADS, sort_lds_bytes(g.ct), s>>>(
         c->vals[cur], dst->tile_start, g, lbits, sort_stage_len(g.ct), c->keys[cur ^ 1], c->vals[cur ^ 1],
         c->final_perm, pa);
+    tail_copy_kernel<<<64, 256, 0, s>>>(c->vals[cur], dst->tile_start, c->ntiles, n, pa);
     return hipGetLastError();
 }
 

@@ -38,6 +38,8 @@ class Simulation:
                     p.tile_start = torch.zeros(self.ntiles + 1, dtype=torch.int64, device=device)
                 self.spare.append(p.empty_like())
         self.diag = torch.zeros(4, dtype=torch.float64, device=device)
+        # scratch for the largest species up front: no call grows it later
+        L.pic_reserve(self.ctx, max([p.capacity or p.n for p in particles] + [0]))
         self.step_index = 0
         self.sorted_at = -1
 
@@ -72,13 +74,22 @@ class Simulation:
             self.particles[k], self.spare[k] = dst, p
         self.sorted_at = self.step_index
 
-    def step(self, with_diag: bool = False, events=None):
+    def step(self, with_diag: bool = False, events=None, gauss=None):
         """One step; `events` = (start, end) torch events recorded on the
-        current stream around the gather-push-deposit launches."""
+        current stream around the gather-push-deposit launches; `gauss` =
+        (rho, residual) FP64 planes that receive the charge density at the
+        half step and div E - rho after the first half field update (the
+        residual's maximum goes to diag[3] when with_diag)."""
         if self.fp32 and (self.sorted_at < 0 or self.step_index - self.sorted_at >= self.sort_every):
             self.sort()
         diag = self.diag if with_diag else None
         L.pic_yee_step(self.ctx, 1, self.fields)
+        if gauss is not None:
+            rho, res = gauss
+            rho.zero_()
+            for sp, p in zip(self.species, self.particles):
+                L.pic_deposit_rho(self.ctx, sp, p, rho, at_half=True)
+            L.pic_gauss_residual(self.ctx, self.fields, rho, res, diag)
         for j in self.fields.J:
             j.zero_()
         if events is not None:

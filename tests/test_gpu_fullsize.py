@@ -142,8 +142,8 @@ def test_laser_3d_full_size():
 
 
 # the trained surrogate's rate error over its chi range (its training test
-# bounds the maximum at 3e-3); outside the range the tables answer
-NET_RATE_REL = 3e-3
+# bounds the maximum at 1e-3); outside the range the tables answer
+NET_RATE_REL = 1e-3
 
 
 def network(ctx):

@@ -696,3 +696,160 @@ def test_multistep_run_matches_oracle(precision):
         assert rel_l2(np64(sim.fields.E[a]), st.E[a]) < tol
         assert rel_l2(np64(sim.fields.B[a]), st.B[a]) < tol
     assert sim.check()[0] == L.PIC_OK
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sort_puts_off_grid_cells_last(dim):
+    """Packed cells off the grid (a field beyond its cell count, bits above
+    y in 2D, a negative cell, z beyond its count in 3D) get no tile: they
+    follow the last tile in source order with every array intact, and
+    tile_start[ntiles] counts the others, as in the oracle's order; the push
+    then flags them and leaves them unchanged."""
+    cfg = make_cfg(dim, 2, L.PIC_FP32_MIXED)
+    n = 20011
+    raw = random_raw(cfg, n, seed=61 + dim)
+    ctx = L.pic_init(cfg)
+    bits, tile, ntiles = L.pic_get_layout(ctx)
+    p = to_fp32(raw, bits, with_chi=True)
+    p.chi = torch.arange(n, dtype=torch.float32)  # source index through the sort
+    cells = [c.numpy().astype(np.int64).copy() for c in raw.cell] + ([np.zeros(n, np.int64)] if dim == 2 else [])
+    rng = np.random.default_rng(3)
+    bad = np.sort(rng.choice(n, 53, replace=False))
+    packed = p.cell.numpy().astype(np.int64)
+    for j, q in enumerate(bad):
+        kind = j % 4
+        if kind == 0:    # x field beyond the cell count (48 or 24 cells in 6 or 5 bits)
+            packed[q] = (packed[q] & ~((1 << bits[0]) - 1)) | cfg.n[0] + 1
+            cells[0][q] = cfg.n[0] + 1
+        elif kind == 1:  # y field beyond its count
+            packed[q] = (packed[q] & ~(((1 << bits[1]) - 1) << bits[0])) | ((cfg.n[1] + 2) << bits[0])
+            cells[1][q] = cfg.n[1] + 2
+        elif kind == 2:  # negative cell
+            packed[q] = -5
+            cells[0][q] = -1
+        else:            # 2D: a bit above y; 3D: z beyond its count
+            if dim == 2:
+                packed[q] |= 1 << (bits[0] + bits[1])
+                cells[2][q] = 1
+            else:
+                packed[q] = (packed[q] & ((1 << (bits[0] + bits[1])) - 1)) | ((cfg.n[2] + 1) << (bits[0] + bits[1]))
+                cells[2][q] = cfg.n[2] + 1
+    p.cell = torch.from_numpy(packed.astype(np.int32))
+    p = L.Particles(n, [t.to(DEV) for t in p.u], cell=p.cell.to(DEV), off=[t.to(DEV) for t in p.off],
+                    w=p.w.to(DEV), chi=p.chi.to(DEV),
+                    tile_start=torch.zeros(ntiles + 1, dtype=torch.int64, device=DEV))
+    dst = p.empty_like()
+    dst.tile_start.fill_(-7)
+    L.pic_sort(ctx, p, dst)
+    torch.cuda.synchronize()
+    perm, start = O.sort(oracle_grid(cfg), tile[:dim], [c.astype(np.int32) for c in cells[:3]])
+    assert int(start[-1]) == n - len(bad)
+    assert np.array_equal(dst.tile_start.cpu().numpy(), start)
+    assert np.array_equal(dst.chi.cpu().numpy().astype(np.int64), perm)
+    assert np.array_equal(dst.cell.cpu().numpy(), packed.astype(np.int32)[perm])
+    for a in range(dim):
+        assert np.array_equal(dst.off[a].cpu().numpy(), p.off[a].cpu().numpy()[perm])
+    for a in range(3):
+        assert np.array_equal(dst.u[a].cpu().numpy(), p.u[a].cpu().numpy()[perm])
+    # the push leaves them alone and flags them
+    tail = slice(n - len(bad), n)
+    before = [t[tail].clone() for t in [dst.cell, *dst.off, *dst.u]]
+    f = L.Fields.zeros(cfg, DEV, torch.float32)
+    L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), dst, f)
+    st, flags, _ = L.pic_check(ctx)
+    assert st == L.PIC_E_STATE and flags & L.PIC_F_OFFSET
+    for t0, t1 in zip(before, [dst.cell, *dst.off, *dst.u]):
+        assert torch.equal(t0, t1[tail])
+
+
+# ------------------------------------------------- charge and Gauss's law
+
+@pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
+@pytest.mark.parametrize("dim,order", CASES)
+def test_rho_and_gauss_residual_match_oracle(dim, order, precision):
+    """rho on the nodes at the half-step positions and the Gauss residual
+    div E - rho, element by element against the oracle's rho and div."""
+    print(f"rho/gauss dim={dim} order={order} prec={precision}", flush=True)
+    cfg = make_cfg(dim, order, precision)
+    raw = random_raw(cfg, 3001, seed=70 + 10 * dim + order)
+    E, B = random_fields(cfg, seed=3 + dim, amp=0.3)
+    fp32 = precision == L.PIC_FP32_MIXED
+    if fp32:
+        E = [e.to(torch.float32).to(torch.float64) for e in E]
+    ctx = L.pic_init(cfg)
+    bits, _, ntiles = L.pic_get_layout(ctx)
+    q = -1.0
+    if fp32:
+        p = to_fp32(raw, bits)
+        p = L.Particles(p.n, [t.to(DEV) for t in p.u], cell=p.cell.to(DEV), off=[t.to(DEV) for t in p.off],
+                        w=p.w.to(DEV))
+        dtype = torch.float32
+    else:
+        p = to_fp64(raw, cfg)
+        p = L.Particles(p.n, [t.to(DEV) for t in p.u], x=[t.to(DEV) for t in p.x], w=p.w.to(DEV))
+        dtype = torch.float64
+    f = L.Fields([e.to(DEV, dtype) for e in E], [b.to(DEV, dtype) for b in B],
+                 [torch.zeros(cfg.plane_shape, device=DEV, dtype=dtype) for _ in range(3)])
+    rho = torch.zeros(cfg.plane_shape, dtype=torch.float64, device=DEV)
+    res = torch.zeros_like(rho)
+    diag = torch.zeros(4, dtype=torch.float64, device=DEV)
+    L.pic_deposit_rho(ctx, L.Species(q, 1.0, 1.0), p, rho, at_half=True)
+    L.pic_gauss_residual(ctx, f, rho, res, diag)
+    torch.cuda.synchronize()
+    g = oracle_grid(cfg)
+    sp = oracle_species(cfg, raw, q, 1.0, from_fp32=fp32)
+    gam = np.sqrt(1 + sp.u[0] ** 2 + sp.u[1] ** 2 + sp.u[2] ** 2)
+    xh = [sp.x[a] + 0.5 * cfg.dt * sp.u[a] / gam for a in range(dim)]
+    rho_o = O.rho(g, q, xh, sp.w)
+    res_o = O.div(g, [e.numpy() for e in E]) - rho_o
+    e_rho = rel_l2(np64(rho), rho_o)
+    e_res = np.abs(np64(res) - res_o).max() / np.abs(res_o).max()
+    print(f"  rho rel L2 {e_rho:.1e}, residual max rel {e_res:.1e}", flush=True)
+    assert e_rho < 1e-12 and e_res < 1e-12
+    assert float(diag[3]) == pytest.approx(np.abs(res_o).max(), rel=1e-12)
+    assert float(diag[0]) == 0.0 and float(diag[1]) == 0.0 and float(diag[2]) == 0.0
+
+
+@pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gauss_residual_stays_constant(dim, precision):
+    """Sec. II.B: with the charge-conserving deposit (Eq. 5) div E - rho at
+    the half steps keeps its initial value (Eqs. 1, 3) over 200 steps of a
+    warm plasma, on the GPU: to round-off in FP64; in FP32 within the
+    rounding that the field updates and the current add each step."""
+    print(f"gauss constant dim={dim} prec={precision}", flush=True)
+    from paper_2104_00642_amd.sim import Simulation
+    from paper_2104_00642_amd.workloads import Workload
+    cfg = make_cfg(dim, 2, precision)
+    raw = random_raw(cfg, 6000 if dim == 2 else 12000, seed=90 + dim, uth=0.2)
+    E, B = random_fields(cfg, seed=11, amp=0.05)
+    wl = Workload("gauss", cfg, [(-1.0, 1.0, raw)], E, B)
+    sim = Simulation.from_workload(wl, precision=precision, device=DEV, sort_every=4, drift=cfg.drift)
+    rho = torch.zeros(cfg.plane_shape, dtype=torch.float64, device=DEV)
+    res = torch.zeros_like(rho)
+    first, drift = None, 0.0
+    steps = 200
+    for it in range(steps):
+        sim.step(gauss=(rho, res))
+        r = np64(res)
+        if first is None:
+            first = r.copy()
+            scale = np.abs(first).max()
+        drift = max(drift, np.abs(r - first).max())
+    eps = 1.2e-16 if precision == L.PIC_FP64_PLAIN else 6e-8
+    emax = max(float(e.abs().max()) for e in sim.fields.E)
+    rmax = float(rho.abs().max())
+    # rounding walks over the run: each half update of E rounds every
+    # component once (the divergence takes two neighbours over d), and each
+    # stored position rounds once per step, which moves a node's rho by up
+    # to twice that relative to its size (the weights' slope is at most 2
+    # per cell); an absolute FP64 position rounds to eps of the box length,
+    # n cells, an FP32 in-cell offset to eps of one cell.  A factor 8 over
+    # both random walks
+    field_walk = math.sqrt(2 * steps) * eps * emax * sum(2 / cfg.d[a] for a in range(dim))
+    pos_eps = eps * (max(cfg.n[:dim]) if precision == L.PIC_FP64_PLAIN else 1)
+    position_walk = math.sqrt(steps) * pos_eps * 2 * rmax
+    bound = 8 * (field_walk + position_walk)
+    print(f"  residual {scale:.2e}, largest change over {steps} steps {drift:.2e} (bound {bound:.2e})", flush=True)
+    assert drift <= bound
+    assert sim.check()[0] == L.PIC_OK

@@ -18,6 +18,10 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 HBAR_W = 2.4263e-6
 SEED = 2104
+# inverse-spectrum bar in CDF units: the tables' inverse error (worst of
+# 150 random (chi, r) per process measured 7.4e-6, at chi = 1e-4 where the
+# photon spectrum is narrowest) with a margin of about 3
+CDF_TOL = 2e-5
 
 
 def qed_cfg():
@@ -64,7 +68,10 @@ def lookup(ctx, proc, what, chi, r=None):
 
 
 def test_rate_tables_match_oracle_quadrature():
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     ctx = L.pic_init(qed_cfg())
+    print(f"pic_init with the QED tables: {time.perf_counter() - t0:.2f} s")
     chis = np.logspace(-4, 3, 29)
     got = lookup(ctx, 0, 0, chis)
     ref = np.array([O.frad(c) for c in chis])
@@ -74,25 +81,34 @@ def test_rate_tables_match_oracle_quadrature():
     ref_p = np.array([O.fpair(c) for c in chis_p])
     err_p = np.max(np.abs(got_p / ref_p - 1))
     print(f"table rate max rel error: emission {err_c:.2e}, pairs {err_p:.2e}")
-    assert err_c < 1e-4 and err_p < 1e-4
+    # measured 5.7e-7: the bar keeps a margin of about 10
+    assert err_c < 5e-6 and err_p < 5e-6
     # below the table: classical limit; pairs vanish
     assert lookup(ctx, 0, 0, [1e-6])[0] == pytest.approx(2.5 * math.pi * 1e-6, rel=1e-5)
     assert lookup(ctx, 1, 0, [1e-3])[0] == 0.0
 
 
 def test_inverse_tables_match_oracle_cdf():
+    """The tabulated inverse spectra at random (chi, r) over the whole table:
+    the oracle's cumulative spectrum at the returned fraction equals r
+    within CDF_TOL (the worst case is reported)."""
     ctx = L.pic_init(qed_cfg())
     rng = np.random.default_rng(3)
-    for proc, lo in ((0, -3.5), (1, -1.0)):
-        chis = 10 ** rng.uniform(lo, 2.8, 12)
-        rs = rng.uniform(0.001, 0.999, 12)
+    for proc, lo in ((0, -4.0), (1, -1.7)):
+        chis = 10 ** rng.uniform(lo, 3.0, 150)
+        rs = rng.uniform(0.0005, 0.9995, 150)
         got = lookup(ctx, proc, 1, chis, rs)
+        worst = (0.0, None)
+        F = {}
         for chi, r, v in zip(chis, rs, got):
             if proc == 0:
                 c = O.compton_cum(chi, v) / O.frad(chi)
             else:
                 c = O.pair_cum(chi, v) / O.fpair(chi)
-            assert abs(c - r) < 2e-3, (proc, chi, r, v, c)
+            if abs(c - r) > worst[0]:
+                worst = (abs(c - r), (chi, r, v))
+        print(f"inverse table {proc}: worst CDF distance {worst[0]:.2e} at (chi, r, v) = {worst[1]}")
+        assert worst[0] < CDF_TOL
 
 
 def run_qed(ctx, cfg, f, mode=L.PIC_QED_TABLE, step=1, **sp):
@@ -112,7 +128,8 @@ def test_lepton_events_match_oracle():
     ux = np.sqrt(gam ** 2 - 1).astype(np.float32)
     chi = rng.choice([0.49, 4.9, 49.0], n).astype(np.float32)
     thr = np.array([Q.first_threshold(SEED, i + 1, 0) for i in range(n)], dtype=np.float32)
-    rates = Q.Rates(nodes=1024)
+    # the oracle's exact inverse spectrum (bisection on its quadrature)
+    rates = Q.Rates(nodes=0)
     dt = float(np.float32(cfg.dt))  # the kernels take dt in FP32
     el = species(n, n, bits, ux, chi, thr)
     ph = species(0, 4 * n, bits, [], None, None)
@@ -133,13 +150,34 @@ def test_lepton_events_match_oracle():
     near_children = {Q.child_id(SEED, i + 1, 1, 1) for i in np.nonzero(near)[0]}
     assert ({int(v) & 0xFFFFFFFFFFFFFFFF for v in ids_g} - near_children ==
             {o["id"] for o in out} - near_children)
-    # recoil and photon energies (table inverse vs oracle quadrature)
+    # photon energies: the GPU's fraction u_g = eps_g / gamma must sit where
+    # the oracle's cumulative spectrum reaches the event's uniform r, within
+    # the tables' inverse error (measured 1.6e-6 in CDF units; bar CDF_TOL);
+    # in u that is CDF_TOL / pdf(u) plus FP32 rounding
     ux_g = el.u[0].cpu().numpy()[:n].astype(np.float64)
-    assert np.allclose(ux_g[fired_o & ~near], np.array(L_o["u"][0])[fired_o & ~near], rtol=5e-3)
     eps_g = {int(i) & 0xFFFFFFFFFFFFFFFF: float(k) for i, k in zip(ids_g, ph.u[0].cpu().numpy()[:nph])}
-    for o in out:
-        if o["id"] in eps_g:
-            assert eps_g[o["id"]] == pytest.approx(o["k"][0], rel=5e-3)
+    pos_of = {o["id"]: o for o in out}
+    worst_cdf, worst_u, checked = 0.0, 0.0, 0
+    for p in np.nonzero(fired_o & ~near)[0]:
+        cid = Q.child_id(SEED, int(p) + 1, 1, 1)
+        o = pos_of[cid]
+        g = math.sqrt(1.0 + float(ux[p]) ** 2)
+        uf_g = eps_g[cid] / g
+        uf_o = o["k"][0] / g
+        ru, _ = O.qed_uniforms(SEED, int(p) + 1, 1, 0)
+        c = float(chi[p])
+        Fr = O.frad(c)
+        dcdf = abs(O.compton_cum(c, uf_g) / Fr - ru)
+        pdf = O.compton_bracket(uf_o, c) / Fr
+        du = abs(uf_g - uf_o) / (CDF_TOL / pdf + 1e-6 * uf_o)
+        worst_cdf, worst_u = max(worst_cdf, dcdf), max(worst_u, du)
+        # recoil u (1 - eps/|u|) from the GPU's own photon energy, FP32 rounding
+        f = max(0.0, 1.0 - eps_g[cid] / float(ux[p]))
+        assert abs(ux_g[p] - float(ux[p]) * f) <= 1e-6 * float(ux[p])
+        checked += 1
+    print(f"events: {checked} photon energies, worst CDF distance {worst_cdf:.2e}, "
+          f"worst u error {worst_u:.2f} of its allowance")
+    assert checked > 20 and worst_cdf < CDF_TOL and worst_u <= 1.0
     # taus of the quiet leptons: W dt in FP64
     quiet = ~fired_o & ~near
     assert np.allclose(tau_g[quiet], np.array(L_o["tau"])[quiet], rtol=1e-5)
@@ -420,28 +458,43 @@ def bf16(a):
 
 
 def pack_mlp(p):
-    """Network bytes in the documented layout from a dict of FP64 arrays."""
+    """Network bytes in the documented layout from a dict of FP64 arrays:
+    weights as their hi and lo BF16 terms (hi = bf16(w), lo = bf16(w - hi)),
+    biases as FP32.  Returns the device bytes; the weights the network then
+    holds are hi + lo (see split_weights)."""
     buf = torch.zeros(L.PIC_MLP_BYTES, dtype=torch.uint8)
 
     def put(off, arr, dt):
         t = torch.as_tensor(np.ascontiguousarray(arr), dtype=torch.float32).to(dt).contiguous()
         b = t.view(torch.uint8).reshape(-1)
         buf[off:off + b.numel()] = b
-    put(0, p["W1"], torch.bfloat16)
-    put(512, p["W2"], torch.bfloat16)
-    put(8704, p["W3"], torch.bfloat16)
+    for k, off, off_lo in (("W1", 0, 9480), ("W2", 512, 9992), ("W3", 8704, 18184)):
+        hi = bf16(p[k])
+        put(off, hi, torch.bfloat16)
+        put(off_lo, bf16(p[k] - hi), torch.bfloat16)
     put(8960, p["b1"], torch.float32)
     put(9216, p["b2"], torch.float32)
     put(9472, p["b3"], torch.float32)
     return buf.to(DEV)
 
 
+def split_weights(p):
+    """The weights pack_mlp stores, as FP64: hi + lo of each."""
+    q = dict(p)
+    for k in ("W1", "W2", "W3"):
+        hi = bf16(p[k])
+        q[k] = hi + bf16(p[k] - hi)
+    return q
+
+
 def random_net(seed=0):
+    """Random parameters (FP32-representable biases); the network holds
+    split_weights(p)."""
     rng = np.random.default_rng(seed)
     p = OM.init_params(rng)
     for k in p:
         p[k] = p[k] + 0.2 * rng.standard_normal(p[k].shape)
-        p[k] = bf16(p[k]) if k.startswith("W") else np.float32(p[k]).astype(np.float64)
+        p[k] = np.float32(p[k]).astype(np.float64)
     return p
 
 
@@ -454,13 +507,14 @@ def test_mlp_forward_matches_oracle():
     y = torch.empty(1000, 2, device=DEV)
     L.pic_mlp_forward(ctx, net, torch.from_numpy(X).to(DEV), y)
     torch.cuda.synchronize()
-    ref, _ = OM.forward(p, X.astype(np.float64))
+    ref, _ = OM.forward(split_weights(p), X.astype(np.float64))
     got = y.cpu().numpy()
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     print(f"network forward relative L2 vs FP64: {err:.2e}")
-    # same BF16 weights; activations enter the matrix cores as hi + lo BF16
-    # terms (about 16 significant bits)
-    assert err < 2e-4
+    # the weights the network holds (hi + lo BF16 terms); activations enter
+    # the matrix cores as hi + lo BF16 terms, the lo x lo products are left
+    # out: about 2^-16 of each product
+    assert err < 2e-5
 
 
 def test_mlp_gradient_matches_oracle_backward():
@@ -476,7 +530,9 @@ def test_mlp_gradient_matches_oracle_backward():
     L.pic_mlp_grad(ctx, net, torch.from_numpy(X).to(DEV), torch.from_numpy(T).to(DEV), grad, loss)
     torch.cuda.synchronize()
     g = grad.cpu().numpy()
-    ref = OM.backward(p, X.astype(np.float64), T.astype(np.float64))
+    # the backward pass takes the weights' hi terms only
+    ph = {k: (bf16(v) if k.startswith("W") else v) for k, v in p.items()}
+    ref = OM.backward(ph, X.astype(np.float64), T.astype(np.float64))
     off = 0
     for k, shape in (("W1", (4, 64)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (64, 2)),
                      ("b3", (2,))):
@@ -486,7 +542,8 @@ def test_mlp_gradient_matches_oracle_backward():
         err = np.linalg.norm(gk - ref[k]) / np.linalg.norm(ref[k])
         print(f"grad {k}: relative L2 {err:.2e}")
         assert err < 5e-2, k
-    assert loss.item() == pytest.approx(OM.loss(p, X.astype(np.float64), T.astype(np.float64)), rel=2e-2)
+    assert loss.item() == pytest.approx(OM.loss(split_weights(p), X.astype(np.float64), T.astype(np.float64)),
+                                        rel=2e-2)
 
 
 def trained_network(ctx, iters=100000, n=1 << 20, batch=16384, lr=2e-3):
@@ -538,8 +595,8 @@ def test_mlp_training_learns_the_rates(trained):
           f"max {errs[1].max():.2e}")
     assert loss < 1e-3
     for proc in (0, 1):
-        assert np.median(errs[proc]) < 1e-3
-        assert errs[proc].max() < 3e-3
+        assert np.median(errs[proc]) < 3e-4
+        assert errs[proc].max() < 1e-3
 
 
 @pytest.mark.parametrize("chi", [0.49, 4.9, 49.0])
@@ -576,8 +633,9 @@ def test_network_mode_spectrum_and_gain(trained, chi):
         times[mode] = e0.elapsed_time(e1) / 10
     print(f"chi={chi}: KS table {ks[0]:.4f} network {ks[1]:.4f}; step ms table {times[0]:.3f} "
           f"network {times[1]:.3f} (gain {times[0] / times[1]:.2f}x)")
-    assert ks[0] < 0.01
-    assert ks[1] < 0.1
+    # measured: tables 0.0027, network 0.0029-0.0038 (1e5 photons)
+    assert ks[0] < 0.006
+    assert ks[1] < 0.008
 
 
 def test_network_mode_falls_back_to_tables_outside_its_range(trained):
@@ -614,7 +672,184 @@ def test_network_mode_falls_back_to_tables_outside_its_range(trained):
     assert np.array_equal(t, t2) and np.array_equal(ids, ids2)
     print(f"  photon energy max rel diff {np.max(np.abs(k - k2) / np.abs(k)):.1e}, "
           f"lepton u max rel diff {np.max(np.abs(u - u2) / np.abs(u)):.1e}")
-    # the recoil u - eps cancels when the photon takes most of the energy:
-    # its difference is bounded by the photon's, relative to u before (1000)
-    assert np.allclose(k, k2, rtol=1e-6, atol=0.0)
-    assert np.max(np.abs(u - u2)) <= 2e-6 * float(ux[0])
+    # the same table lookup compiled in two source files rounds apart by a
+    # few FP32 units of v = u^(1/3), three times that in u; the recoil u - eps
+    # cancels when the photon takes most of the energy: its difference is
+    # bounded by the photon's, relative to u before (1000)
+    assert np.allclose(k, k2, rtol=4e-6, atol=0.0)
+    assert np.max(np.abs(u - u2)) <= 4e-6 * float(ux[0])
+
+
+# ------------------------------------------- photons in non-uniform fields
+
+def photon_cfg(dim, order, absorb=False):
+    if dim == 2:
+        n, d, tile = (48, 40), (0.3, 0.25), (16, 8)
+    else:
+        n, d, tile = (24, 20, 18), (0.3, 0.25, 0.2), (8, 4, 6)
+    return L.Config(dim=dim, n=n, d=d, dt=courant_dt(d, 0.9), order=order, tile=tile, seed=SEED,
+                    hbar_omega_mc2=HBAR_W, drift=0 if dim == 3 else 2,
+                    bc_x=L.PIC_BC_ABSORB if absorb else L.PIC_BC_PERIODIC)
+
+
+def photon_state(cfg, bits, n, seed, eps_range=(3.0, 3000.0), near_faces=False, in_plane=False):
+    """Photons at random cells and offsets with random directions (in the
+    x-y plane with in_plane): device species (FP32 layout) and the oracle's
+    dict (FP64 copies of the same FP32 values)."""
+    rng = np.random.default_rng(seed)
+    dim = cfg.dim
+    cells = [rng.integers(0, cfg.n[a], n) for a in range(dim)]
+    if near_faces:  # a fifth of them in the x cells next to the faces
+        k = n // 5
+        cells[0][:k] = rng.choice([0, 1, cfg.n[0] - 2, cfg.n[0] - 1], k)
+    off = [rng.uniform(0, 1, n).astype(np.float32) for _ in range(dim)]
+    v = rng.standard_normal((3, n))
+    if in_plane:
+        v[2] = 0.0
+    v /= np.linalg.norm(v, axis=0)
+    eps = np.exp(rng.uniform(np.log(eps_range[0]), np.log(eps_range[1]), n))
+    k = (v * eps).astype(np.float32)
+    packed = np.zeros(n, dtype=np.int64)
+    shift = 0
+    for a in range(dim):
+        packed |= cells[a] << shift
+        shift += bits[a]
+    f32 = dict(device=DEV, dtype=torch.float32)
+    ph = L.Particles(n, [torch.from_numpy(k[a]).to(DEV) for a in range(3)],
+                     cell=torch.from_numpy(packed.astype(np.int32)).to(DEV),
+                     off=[torch.from_numpy(o).to(DEV) for o in off], w=torch.ones(n, **f32),
+                     chi=torch.zeros(n, **f32), tau=torch.zeros(n, device=DEV, dtype=torch.float64),
+                     tau_thr=torch.full((n,), 1e30, **f32),
+                     id=torch.arange(1, n + 1, device=DEV, dtype=torch.int64), capacity=n,
+                     n_dev=torch.tensor([n], dtype=torch.int64, device=DEV))
+    orc = dict(x=[list((cells[a] + off[a].astype(np.float64)) * cfg.d[a]) for a in range(dim)],
+               k=[list(k[a].astype(np.float64)) for a in range(3)], w=[1.0] * n)
+    return ph, orc
+
+
+@pytest.mark.parametrize("absorb", [False, True])
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 2), (2, 4), (3, 1), (3, 2), (3, 4)])
+def test_photon_move_and_chi_match_oracle(dim, order, absorb):
+    """The photon step's own move and gather in seeded random E and B (every
+    component non-uniform, several tiles): new cell and offset and chi_gamma
+    against the oracle's move plus gather (Eq. 19) plus chi_gamma (Sec. IV),
+    photon by photon; with absorbing x faces the absorbed photons too."""
+    print(f"photon chi dim={dim} order={order} absorb={absorb}", flush=True)
+    from _helpers import host_fields, oracle_grid, periodic_dx, random_fields
+    cfg = photon_cfg(dim, order, absorb)
+    ctx = L.pic_init(cfg)
+    bits, _, _ = L.pic_get_layout(ctx)
+    E, B = random_fields(cfg, seed=40 + 10 * dim + order, amp=0.4)
+    f = L.Fields([e.to(DEV, torch.float32) for e in E], [b.to(DEV, torch.float32) for b in B],
+                 [torch.zeros(cfg.plane_shape, device=DEV) for _ in range(3)])
+    n = 3001
+    ph, orc = photon_state(cfg, bits, n, seed=7 * dim + order, near_faces=absorb)
+    L.pic_qed_step(ctx, f, photons=ph, step=1, photon_min_energy=0.0)
+    torch.cuda.synchronize()
+    assert L.pic_check(ctx)[0] == L.PIC_OK
+    F = host_fields(f)
+    dt32 = float(np.float32(cfg.dt))
+    Q.photon_move_chi(oracle_grid(cfg), F, orc, dt32, HBAR_W)
+    w_g = ph.w.cpu().numpy().astype(np.float64)
+    assert np.array_equal(w_g, np.array(orc["w"]))
+    live = w_g != 0.0
+    if absorb:
+        print(f"  {n - live.sum()} of {n} photons absorbed", flush=True)
+        assert 50 < (~live).sum() < n // 5
+    cell = ph.cell.cpu().numpy().astype(np.int64)
+    shift, dx = 0, 0.0
+    for a in range(dim):
+        c = (cell >> shift) & ((1 << bits[a]) - 1)
+        shift += bits[a]
+        xg = (c + ph.off[a].cpu().numpy().astype(np.float64)) * cfg.d[a]
+        L_a = cfg.n[a] * cfg.d[a]
+        dx = max(dx, float(np.abs(periodic_dx(xg, np.array(orc["x"][a]), L_a)).max()) / cfg.d[a])
+    chi_g = ph.chi.cpu().numpy().astype(np.float64)
+    chi_o = np.array(orc["chi"])
+    eps = np.linalg.norm(np.array(orc["k"]), axis=0)
+    # chi^2 = (hbar w)^2 ((eps E + k x B)^2 - (k.E)^2) cancels terms of size
+    # scale^2, scale = hbar w eps (|E| + |B|): an FP32 gather of up to 125
+    # nodes rounds at about 1e-7 of the largest field, so chi^2 is compared
+    # at 5e-7 of scale^2 (near chi = 0 the square root magnifies it)
+    scale = HBAR_W * eps * (np.linalg.norm(np.array(F[:3]).reshape(3, -1), axis=0).max() +
+                            np.linalg.norm(np.array(F[3:]).reshape(3, -1), axis=0).max())
+    ratio = np.abs(chi_g ** 2 - chi_o ** 2) / (5e-7 * scale ** 2)
+    print(f"  position max error {dx:.2e} cells, chi max error {ratio.max():.2f} of its allowance "
+          f"(chi median {np.median(chi_o[live]):.2e})", flush=True)
+    assert dx < 2e-6
+    assert ratio.max() <= 1.0
+    assert np.all(chi_g[~live] == 0.0)
+
+
+def test_network_mode_photon_pairs_equal_table_mode():
+    """Network mode on photons whose chi_gamma (this step's, from the move
+    and gather; the chi array starts at 0) lies beyond the network's range:
+    the tables answer, so the pair events, their products and every photon
+    array equal table mode's exactly, in a non-uniform field."""
+    from _helpers import random_fields
+    cfg = photon_cfg(2, 2)
+    ctx = L.pic_init(cfg)
+    bits, _, _ = L.pic_get_layout(ctx)
+    E, B = random_fields(cfg, seed=77, amp=1.0)
+    n = 4000
+    out = {}
+    for mode in (L.PIC_QED_TABLE, L.PIC_QED_MLP):
+        # B_z 5e4 (+-10%) and eps 2e4: chi_gamma about 2.4e3, beyond the range the network answers
+        # (up to 10^2.9)
+        f = L.Fields([(e * 100.0).to(DEV, torch.float32) for e in E],
+                     [(b * 5e3 + (5e4 if a == 2 else 0.0)).to(DEV, torch.float32) for a, b in enumerate(B)],
+                     [torch.zeros(cfg.plane_shape, device=DEV) for _ in range(3)])
+        ph, _ = photon_state(cfg, bits, n, seed=5, eps_range=(2e4, 2e4 + 1), in_plane=True)  # across B_z
+        ph.tau_thr[: n // 2] = 0.0
+        po = qed_species_2d(n)
+        el = qed_species_2d(n)
+        net = pack_mlp(random_net(9))
+        L.pic_qed_step(ctx, f, photons=ph, positrons=po, electrons=el, mode=mode, step=4, photon_min_energy=0.0,
+                       mlp=net if mode == L.PIC_QED_MLP else None)
+        torch.cuda.synchronize()
+        assert L.pic_check(ctx)[0] == L.PIC_OK
+        m = int(po.n_dev.item())
+        order = torch.argsort(po.id[:m])
+        out[mode] = dict(w=ph.w.cpu(), chi=ph.chi.cpu(), tau=ph.tau.cpu(), cell=ph.cell.cpu(), off=ph.off[0].cpu(),
+                         pos=po.u[0][:m][order].cpu(), pid=po.id[:m][order].cpu(), m=m, ne=int(el.n_dev.item()))
+    a, b = out[L.PIC_QED_TABLE], out[L.PIC_QED_MLP]
+    lc = np.log10(a["chi"].numpy().astype(np.float64))  # every photon was moved and got its chi_gamma
+    print(f"network-mode photons: {a['m']} pairs; log10 chi_gamma in [{lc.min():.2f}, {lc.max():.2f}]")
+    assert a["m"] > 100 and a["m"] == b["m"] and a["ne"] == b["ne"] == a["m"]
+    assert lc.min() > 2.95
+    # the same events and products; values that pass through the table
+    # lookups (compiled in two source files) agree to FP32 rounding
+    for key in ("w", "cell", "pid"):
+        assert torch.equal(a[key], b[key]), key
+    for key in ("chi", "tau", "off", "pos"):
+        assert torch.allclose(a[key], b[key], rtol=1e-6, atol=0.0), key
+
+
+def qed_species_2d(capacity):
+    f32 = dict(device=DEV, dtype=torch.float32)
+    return L.Particles(0, [torch.zeros(capacity, **f32) for _ in range(3)],
+                       cell=torch.zeros(capacity, device=DEV, dtype=torch.int32),
+                       off=[torch.zeros(capacity, **f32) for _ in range(2)], w=torch.zeros(capacity, **f32),
+                       chi=torch.zeros(capacity, **f32), tau=torch.zeros(capacity, device=DEV, dtype=torch.float64),
+                       tau_thr=torch.zeros(capacity, **f32), id=torch.zeros(capacity, device=DEV, dtype=torch.int64),
+                       capacity=capacity, n_dev=torch.tensor([0], device=DEV, dtype=torch.int64))
+
+
+def test_photon_species_needs_weights_and_network_chi():
+    """A decayed photon is removed through its weight: a photon species
+    without w is refused; network mode also needs the photons' chi array."""
+    cfg = qed_cfg()
+    ctx = L.pic_init(cfg)
+    bits, _, _ = L.pic_get_layout(ctx)
+    ph = species(10, 10, bits, np.full(10, 100.0, dtype=np.float32))
+    ph.w = None
+    with pytest.raises(L.PicError) as e:
+        L.pic_qed_step(ctx, fields(cfg), photons=ph, step=1)
+    assert e.value.status == L.PIC_E_ARG
+    ph = species(10, 10, bits, np.full(10, 100.0, dtype=np.float32))
+    ph.chi = None
+    with pytest.raises(L.PicError) as e:
+        L.pic_qed_step(ctx, fields(cfg), photons=ph, step=1, mode=L.PIC_QED_MLP, mlp=pack_mlp(random_net(1)))
+    assert e.value.status == L.PIC_E_ARG
+    L.pic_qed_step(ctx, fields(cfg), photons=ph, step=1)  # tables: chi is optional
+    torch.cuda.synchronize()

@@ -204,6 +204,26 @@ pic_status pic_gather_push_deposit(void *ctx, const pic_species *sp, const pic_p
                                    const pic_fields *fields, double *diag, void *stream);
 
 /*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): pic_gather_push_deposit
+ * with the same arguments, results and errors, but every scratch buffer of
+ * the push (FP64 partials, straggler and bin lists, tile counters) taken
+ * from a static device array of PIC_NOALLOC_SCRATCH_BYTES that each GPU the
+ * library runs on holds until the process ends; the call allocates nothing
+ * and frees nothing.  Scratch per push (each part rounded up to 256 bytes):
+ * FP32 path 12 B per particle, 48 B per tile and 4 KB; FP64 path 16 B per
+ * 256 particles.  A push needing more returns PIC_E_ARG before anything is
+ * enqueued (with 4096 tiles the FP32 path takes up to about 5.5e6
+ * particles).  Every call on one GPU shares its array
+ * and leaves its contents behind (what must start at zero is cleared by the
+ * push's own kernels): calls that overlap in time on one GPU (other streams,
+ * other threads, other contexts) race.
+ */
+#define PIC_NOALLOC_SCRATCH_BYTES (64ll << 20)
+pic_status pic_gather_push_deposit_noalloc(void *ctx, const pic_species *sp, const pic_particles *p,
+                                           const pic_fields *fields, double *diag, void *stream);
+
+/*
  * Half field update (Sec. II.B Eqs. 9-10 split as in Sec. II.F):
  *   half = 1:  E += (dt/2)(curl B - J);  B -= (dt/2) curl E
  *   half = 2:  B -= (dt/2) curl E;       E += (dt/2)(curl B - J)

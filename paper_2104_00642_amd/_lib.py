@@ -35,7 +35,7 @@ PIC_MLP_STATE_FLOATS = 4 * PIC_MLP_NPARAM + 1
 EXPORTED = ["pic_init", "pic_destroy", "pic_last_error", "pic_get_layout", "pic_gather_push_deposit",
             "pic_yee_step", "pic_sort", "pic_check", "pic_qed_step", "pic_mlp_forward", "pic_mlp_grad",
             "pic_mlp_train", "pic_qed_training_data", "pic_qed_table_lookup", "pic_set_laser", "pic_reserve",
-            "pic_deposit_rho", "pic_gauss_residual"]
+            "pic_deposit_rho", "pic_gauss_residual", "pic_gather_push_deposit_noalloc"]
 
 
 class PicError(RuntimeError):
@@ -126,6 +126,10 @@ def lib():
         L.pic_qed_table_lookup.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                            C.c_int64, C.c_void_p, C.c_void_p]
         L.pic_qed_table_lookup.restype = C.c_int
+        L.pic_gather_push_deposit_noalloc.argtypes = [C.c_void_p, C.POINTER(pic_species),
+                                                      C.POINTER(pic_particles), C.POINTER(pic_fields), C.c_void_p,
+                                                      C.c_void_p]
+        L.pic_gather_push_deposit_noalloc.restype = C.c_int
         L.pic_reserve.argtypes = [C.c_void_p, C.c_int64]
         L.pic_reserve.restype = C.c_int
         L.pic_deposit_rho.argtypes = [C.c_void_p, C.POINTER(pic_species), C.POINTER(pic_particles), C.c_int32,
@@ -325,6 +329,14 @@ def pic_gather_push_deposit(ctx: Context, sp: Species, p: Particles, f: Fields,
     sc, pc, fc = sp.c(), p.c(), f.c()
     st = lib().pic_gather_push_deposit(C.c_void_p(ctx.handle), C.byref(sc), C.byref(pc), C.byref(fc),
                                        _ptr(diag), _stream(stream))
+    _check(st, C.c_void_p(ctx.handle))
+
+
+def pic_gather_push_deposit_noalloc(ctx: Context, sp: Species, p: Particles, f: Fields,
+                                    diag: Optional[torch.Tensor] = None, stream=None):
+    sc, pc, fc = sp.c(), p.c(), f.c()
+    st = lib().pic_gather_push_deposit_noalloc(C.c_void_p(ctx.handle), C.byref(sc), C.byref(pc), C.byref(fc),
+                                               _ptr(diag), _stream(stream))
     _check(st, C.c_void_p(ctx.handle))
 
 

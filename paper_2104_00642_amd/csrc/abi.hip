@@ -253,6 +253,14 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
         pic_destroy(c);
         return fail(nullptr, PIC_E_NOMEM, "cannot allocate the residual partials");
     }
+    // device address of the static scratch of pic_gather_push_deposit_noalloc
+    // on this device (looked up once per device)
+    e = noalloc_scratch_init(&c->noalloc_scratch);
+    if (e != hipSuccess) {
+        pic_status st = hip_fail(nullptr, e, "pic_init: no-allocation scratch address");
+        pic_destroy(c);
+        return st;
+    }
     if (ensure_partials(c, 2 * (size_t)c->ntiles + 1024) != PIC_OK) {
         g_init_error = c->err;
         pic_destroy(c);

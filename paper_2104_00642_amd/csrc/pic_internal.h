@@ -56,6 +56,9 @@ struct Ctx {
     double time = 0.0;
     // block maxima of the Gauss residual (GAUSS_PART doubles)
     double *gauss_part = nullptr;
+    // device address of the library's static no-allocation scratch on this
+    // context's device
+    void *noalloc_scratch = nullptr;
     // scratch outgrown by an enqueueing call, freed by pic_reserve / pic_destroy
     std::vector<void *> retired;
     std::string err;
@@ -91,6 +94,7 @@ hipError_t launch_gpd_plain(Ctx *c, const pic_species *sp, const pic_particles *
 hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *p,
                             const pic_fields *f, double *diag, hipStream_t s, const PushScratch *ps = nullptr);
 pic_status validate_push_args(Ctx *c, const pic_species *sp, const pic_particles *p, const pic_fields *fields);
+hipError_t noalloc_scratch_init(void **ptr);
 hipError_t launch_yee(Ctx *c, int half, const pic_fields *f, double *diag, hipStream_t s);
 hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *dst,
                        hipStream_t s);

@@ -29,6 +29,8 @@
 // tile.  The tile kernel therefore holds only the LDS path.
 // Blocks are remapped so that each XCD (own L2) works on a contiguous run of
 // tiles: neighbouring tiles share guard rows in the same L2.
+#include <type_traits>
+
 #include "device_common.h"
 #include "pic_internal.h"
 
@@ -170,6 +172,119 @@ struct LdsAcc {
         atomicAdd(&jw[c * wn() + lin(bi, bj, bk) + ii + wx() * jj + wxy() * kk],
                   (unsigned long long)(long long)(int)v);
     }
+    // the int64 current window: its first float of the dynamic LDS, its
+    // length, and the entry of component c at window node r
+    __device__ __forceinline__ int jbase() const { return 6 * wn(); }
+    __device__ __forceinline__ int jcount() const { return 3 * wn(); }
+    __device__ __forceinline__ int jslot(int c, int r) const { return c * wn() + r; }
+    // (2D) current view from an Esirkepov stencil base: node (ii, jj) of
+    // component c at base + c wn + ii + jj wx
+    struct JView {
+        unsigned long long *jw;
+        int base, wx, wn;
+        __device__ __forceinline__ void add(int c, int ii, int jj, float v) const {
+            atomicAdd(&jw[c * wn + base + ii + wx * jj], (unsigned long long)(long long)(int)v);
+        }
+    };
+    __device__ __forceinline__ JView jview(int bi, int bj) const {
+        return JView{(unsigned long long *)(pic_smem + 6 * wn()), lin(bi, bj, 0), wx(), wn()};
+    }
+};
+
+// 2D window in x-parity planes.  Consecutive lanes of a wavefront push
+// particles in cells two apart along x (one parity class of the tile per
+// wavefront), so with nodes stored row by row their addresses all have one
+// parity and use half the LDS banks.  Here the nodes of even x and of odd x
+// sit in separate planes: node (x, y) is at (x & 1) P + (x >> 1) + WP y, the
+// lanes of a row of cells hit consecutive words, and the row stride WP
+// (12 = 4 mod 8 in 8-byte words) puts the four rows of cells of a
+// half-wavefront on four disjoint groups of eight banks.  P (the odd plane's
+// start, 289 = 1 mod 32) was chosen by a model of the bank conflicts of
+// random stencil shifts.  A stencil that starts at x = b has its even-offset
+// nodes in b's plane at columns (b >> 1) + ii/2 and its odd-offset nodes in
+// the other plane, so a view keeps two base addresses and every node is an
+// immediate offset from one of them.  Plane groups of GS = 2P elements:
+// (E_x, B_y) and (E_y, B_x) interleaved node by node (8-byte elements),
+// E_z, B_z (4 bytes), then the int64 current window, three groups.  Built
+// for the 23 x 23 window (16 x 16 tiles, drift 1, reach [c-2, c+3]).
+template <int WX, int WY>
+struct LdsSplit2 {
+    static_assert(WX == 23 && WY == 23, "x-parity layout built for the 23 x 23 window");
+    static constexpr int WP = 12, P = 289, GS = 2 * P;
+    float scale;
+    __device__ __forceinline__ int wx() const { return WX; }
+    __device__ __forceinline__ int wxy() const { return WX * WY; }
+    __device__ __forceinline__ int wn() const { return WX * WY; }
+    static __device__ __forceinline__ int idx(int x, int y) { return (x & 1) * P + (x >> 1) + WP * y; }
+    // index in a plane group of window node r (row-major r = x + WX y)
+    static __device__ __forceinline__ int idx_r(int r) {
+        const int y = r / WX;
+        return idx(r - WX * y, y);
+    }
+    __device__ __forceinline__ int slot(int c, int r) const {
+        const int n = idx_r(r);
+        const int grp = c == 0 || c == 4 ? 0 : (c == 1 || c == 3 ? 2 * GS : (c == 2 ? 4 * GS : 5 * GS));
+        const int lane = c == 4 || c == 3 ? 1 : 0;
+        const int step = c == 2 || c == 5 ? 1 : 2;
+        return grp + step * n + lane;
+    }
+    __device__ __forceinline__ int jbase() const { return 6 * GS; }
+    __device__ __forceinline__ int jcount() const { return 3 * GS; }
+    __device__ __forceinline__ int jslot(int c, int r) const { return c * GS + idx_r(r); }
+    // the two base addresses of a stencil starting at window node (bi, bj):
+    // first = its own node, second = node (bi + 1, bj)
+    static __device__ __forceinline__ void bases(int bi, int bj, int &first, int &second) {
+        const int e = bi & 1;
+        first = (bi >> 1) + WP * bj + (e ? P : 0);
+        second = first + (e ? 1 - P : P);
+    }
+    typedef float vec2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) const vec2 lds_float2;
+    typedef __attribute__((address_space(3))) const float lds_float;
+    template <typename T>
+    static __device__ __forceinline__ const T *opaque(const T *q) {
+        uint32_t addr = (uint32_t)(uintptr_t)q;
+        asm volatile("" : "+v"(addr));
+        return (const T *)(uintptr_t)addr;
+    }
+    struct PairView {
+        const lds_float2 *p0, *p1;
+        __device__ __forceinline__ float2 operator()(int ii, int jj) const {
+            const vec2 v = (ii & 1 ? p1 : p0)[(ii >> 1) + WP * jj];
+            return make_float2(v.x, v.y);
+        }
+    };
+    __device__ __forceinline__ PairView pair_view(int p, int bi, int bj) const {
+        int f, g;
+        bases(bi, bj, f, g);
+        const lds_float2 *q = (const lds_float2 *)(const vec2 *)pic_smem + p * GS;
+        return PairView{opaque(q + f), opaque(q + g)};
+    }
+    struct PlaneView {
+        const lds_float *p0, *p1;
+        __device__ __forceinline__ float operator()(int ii, int jj) const {
+            return (ii & 1 ? p1 : p0)[(ii >> 1) + WP * jj];
+        }
+    };
+    __device__ __forceinline__ PlaneView plane_view(int c, int bi, int bj) const {
+        int f, g;
+        bases(bi, bj, f, g);
+        const lds_float *q = (const lds_float *)(const float *)pic_smem + (c == 2 ? 4 * GS : 5 * GS);
+        return PlaneView{opaque(q + f), opaque(q + g)};
+    }
+    struct JView {
+        unsigned long long *j0, *j1;
+        __device__ __forceinline__ void add(int c, int ii, int jj, float v) const {
+            atomicAdd(&(ii & 1 ? j1 : j0)[c * GS + (ii >> 1) + WP * jj], (unsigned long long)(long long)(int)v);
+        }
+    };
+    __device__ __forceinline__ JView jview(int bi, int bj) const {
+        int f, g;
+        bases(bi, bj, f, g);
+        unsigned long long *jw = (unsigned long long *)(pic_smem + 6 * GS);
+        return JView{jw + f, jw + g};
+    }
+    static constexpr size_t bytes() { return (size_t)GS * (6 * sizeof(float) + 3 * sizeof(int64_t)); }
 };
 
 // Accessor of global memory: absolute cell coordinates, periodic wrap.
@@ -207,6 +322,12 @@ struct GlobAcc {
         if (absorb_x && (unsigned)(bi + ii) >= (unsigned)ng[0]) return;
         atomicAdd(&J[c][idx(bi + ii, bj + jj, bk + kk)], v);
     }
+    struct JView {
+        const GlobAcc *g;
+        int bi, bj;
+        __device__ __forceinline__ void add(int c, int ii, int jj, float v) const { g->add(c, bi, bj, 0, ii, jj, 0, v); }
+    };
+    __device__ __forceinline__ JView jview(int bi, int bj) const { return JView{this, bi, bj}; }
 };
 
 // Push one particle whose cell origin is at o[] in the accessor's coordinates.
@@ -316,6 +437,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
     const float ws = w * acc.scale;  // fixed-point units in the LDS window
     const float jx = a.jfac[0] * ws, jy = a.jfac[1] * ws;
     if constexpr (DIM == 2) {
+        const auto jv = acc.jview(b0, b1);
 #pragma unroll
         for (int jj = 0; jj < L; ++jj) {
             const float ty = jx * (S0[1][jj] + 0.5f * DS[1][jj]);
@@ -323,7 +445,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
 #pragma unroll
             for (int ii = 0; ii < L - 1; ++ii) {
                 run -= DS[0][ii] * ty;
-                if (rnode(0, ii) && wnode(1, jj)) acc.add(0, b0, b1, 0, ii, jj, 0, run);
+                if (rnode(0, ii) && wnode(1, jj)) jv.add(0, ii, jj, run);
             }
         }
 #pragma unroll
@@ -333,7 +455,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
 #pragma unroll
             for (int jj = 0; jj < L - 1; ++jj) {
                 run -= DS[1][jj] * tx;
-                if (rnode(1, jj) && wnode(0, ii)) acc.add(1, b0, b1, 0, ii, jj, 0, run);
+                if (rnode(1, jj) && wnode(0, ii)) jv.add(1, ii, jj, run);
             }
         }
         const float qv = a.q * ws * v[2];
@@ -343,7 +465,7 @@ __device__ __forceinline__ void push_one(const Acc &acc, const TiledArgs &a, con
             const float a1 = qv * (0.5f * S0[1][jj] + (1.0f / 3.0f) * DS[1][jj]);
 #pragma unroll
             for (int ii = 0; ii < L; ++ii)
-                if (wnode(0, ii) && wnode(1, jj)) acc.add(2, b0, b1, 0, ii, jj, 0, S0[0][ii] * a0 + DS[0][ii] * a1);
+                if (wnode(0, ii) && wnode(1, jj)) jv.add(2, ii, jj, S0[0][ii] * a0 + DS[0][ii] * a1);
         }
     } else {
         const int b2 = o[2] + base[2];
@@ -442,6 +564,15 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return t;
 }
 
+template <class Lds>
+__device__ __forceinline__ Lds make_lds(const TiledArgs &a) {
+    if constexpr (std::is_same<Lds, LdsSplit2<23, 23>>::value) {
+        return Lds{0.0f};
+    } else {
+        return Lds{a.win[0], a.win[0] * a.win[1], a.win[0] * a.win[1] * a.win[2], 0.0f};
+    }
+}
+
 // Byte offset of a particle's elements: 32-bit against per-tile bases in the
 // sorted (contiguous) pass, 64-bit against the array bases in the binned pass.
 template <bool LIST>
@@ -457,7 +588,7 @@ struct POff<true> {
 // the sorted arrays.  LIST = true: they are bin_list[bin_start[t] ..
 // bin_start[t+1]) (the stragglers and appended particles binned by the tile
 // that holds them now).
-template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ, bool LIST>
+template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ, bool LIST, bool SPLIT = false>
 __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     typedef typename POff<LIST>::type off_t;
     const int b = blockIdx.x;
@@ -485,10 +616,11 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     constexpr int RLO = ORDER == 4 ? 3 : 2, RHI = ORDER == 4 ? 4 : 3;
     const int g = a.drift + RLO;
     const int org[3] = {tx * a.tile[0] - g, ty * a.tile[1] - g, DIM == 3 ? tz * a.tile[2] - g : 0};
-    LdsAcc<WX, WY, WZ, DIM == 2> lds{a.win[0], a.win[0] * a.win[1], a.win[0] * a.win[1] * a.win[2], 0.0f};
+    typedef typename std::conditional<SPLIT, LdsSplit2<WX, WY>, LdsAcc<WX, WY, WZ, DIM == 2>>::type Lds;
+    Lds lds = make_lds<Lds>(a);
     const int wn = lds.wn();
     const int wx = lds.wx(), wxy = lds.wxy();
-    unsigned long long *jwin = (unsigned long long *)(pic_smem + 6 * wn);
+    unsigned long long *jwin = (unsigned long long *)(pic_smem + lds.jbase());
     const uint32_t np = (uint32_t)(pend - pbeg);
     // element offsets: sorted pass, bases moved to the tile's first particle
     // and one 32-bit offset per particle; binned pass, offsets of the listed
@@ -545,8 +677,6 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
             if (r < wn) {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) pic_smem[lds.slot(c, r)] = v[s][c];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) jwin[c * wn + r] = 0ull;
             }
         }
     } else {
@@ -556,10 +686,9 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
             cell_src(r, gidx, beyond);
 #pragma unroll
             for (int c = 0; c < 6; ++c) pic_smem[lds.slot(c, r)] = beyond ? 0.0f : a.F[c][gidx];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) jwin[c * wn + r] = 0ull;
         }
     }
+    for (int r = threadIdx.x; r < lds.jcount(); r += NT) jwin[r] = 0ull;
     float wm = fabsf(a.w0);
     if (wT) {
         // four loads in flight per round
@@ -687,7 +816,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         if (a.absorb_x && (unsigned)(org[0] + ii) >= (unsigned)a.ng[0]) continue;  // beyond a face
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const long long q = (long long)jwin[c * wn + r];
+            const long long q = (long long)jwin[lds.jslot(c, r)];
             if (q != 0) atomicAdd(&a.J[c][gidx], (float)((double)q * inv_scale));
         }
     }
@@ -942,10 +1071,16 @@ __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
 }
 
 // window shapes with a compiled kernel: 16x16 tiles with drift 2 in 2D
-// (25 cells wide, 27 for quartic weights), 8x8x4 tiles in 3D with drift 1
+// (25 cells wide, 27 for quartic weights) and with drift 1 (23 wide, in the
+// x-parity layout: measured 7% faster than drift 2's row-major window right
+// after a sort, but at 24 steps between sorts drift 1 leaves three times the
+// stragglers of drift 2, so 2D runs default to drift 2; the same layout at
+// 25 x 25 needs a row stride of 20 and costs two workgroups per CU, which
+// measured no faster), 8x8x4 tiles in 3D with drift 1
 // (drift 0 for quartic weights): 15 x 15 x 11, and with drift 0 for
 // quadratic weights: 13 x 13 x 9; others use the run-time shape
 constexpr int W2X = 16 + 2 * 2 + 5, W2X4 = 16 + 2 * 2 + 7, W3X = 8 + 2 * 1 + 5, W3Z = 4 + 2 * 1 + 5;
+constexpr int W2S = 16 + 2 * 1 + 5;
 constexpr int W3X0 = 8 + 5, W3Z0 = 4 + 5;
 
 // One push of a species:
@@ -953,19 +1088,19 @@ constexpr int W3X0 = 8 + 5, W3Z0 = 4 + 5;
 //   -> bin scan -> bin scatter -> reset of the list -> binned pass -> global
 //   pass over whatever the binned pass listed.
 // Partials: [sorted pass: 2 ntiles][binned pass: 2 ntiles][global: 2 x 256].
-template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ>
+template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ, bool SPLIT = false>
 static void launch_passes(TiledArgs a, size_t lds, hipStream_t s) {
     const dim3 tiles((unsigned)(8 * a.chunk)), block(NT), gb(GLOBAL_BLOCKS), b256(256);
     gpd_prep_kernel<<<(unsigned)((a.ntiles + 255) / 256), 256, 0, s>>>(a.bin_count, a.ntiles, a.strag_count);
     a.part_off = 0;
-    gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, false><<<tiles, block, lds, s>>>(a);
+    gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, false, SPLIT><<<tiles, block, lds, s>>>(a);
     const dim3 bins((unsigned)(a.ntiles + TAIL_BLOCKS));
     gpd_bin_count_kernel<DIM><<<bins, b256, 0, s>>>(a);
     gpd_bin_scan_kernel<<<1, 1024, 0, s>>>(a.bin_count, a.ntiles, a.bin_start);
     gpd_bin_scatter_kernel<DIM><<<bins, b256, 0, s>>>(a);
     gpd_reset_kernel<<<1, 1, 0, s>>>(a.strag_count);
     a.part_off = 2 * a.ntiles;
-    gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, true><<<tiles, block, lds, s>>>(a);
+    gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, true, SPLIT><<<tiles, block, lds, s>>>(a);
     a.part_off = 4 * a.ntiles;
     gpd_global_kernel<DIM, ORDER, PUSH><<<gb, b256, 0, s>>>(a);
 }
@@ -973,6 +1108,14 @@ static void launch_passes(TiledArgs a, size_t lds, hipStream_t s) {
 template <int DIM, int ORDER, int PUSH>
 static void launch_tiled(const TiledArgs &a, size_t lds, hipStream_t s) {
     if constexpr (DIM == 2) {
+        if constexpr (ORDER != 4) {
+            // 16 x 16 tiles with drift 1: the x-parity window layout
+            if (a.win[0] == W2S && a.win[1] == W2S) {
+                launch_passes<2, ORDER, PUSH, PIC_TILED_THREADS_2D, W2S, W2S, 1, true>(a, LdsSplit2<W2S, W2S>::bytes(),
+                                                                                     s);
+                return;
+            }
+        }
         constexpr int WX = ORDER == 4 ? W2X4 : W2X;
         if (a.win[0] == WX && a.win[1] == WX)
             launch_passes<2, ORDER, PUSH, PIC_TILED_THREADS_2D, WX, WX, 1>(a, lds, s);

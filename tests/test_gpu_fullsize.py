@@ -21,7 +21,8 @@ from paper_2104_00642_amd import _lib as L
 from paper_2104_00642_amd import workloads as W
 from paper_2104_00642_amd.sim import Simulation
 
-from _helpers import DEV, host_fields, np64, oracle_grid, oracle_sample, push_errors, sampled_push
+from _helpers import (DEV, host_fields, np64, oracle_grid, oracle_sample, positions_fp32, push_errors, rel_l2,
+                      sampled_push)
 
 pytestmark = pytest.mark.gpu
 
@@ -64,7 +65,60 @@ def current_consistency(fields: L.Fields, sp: L.Species, p: L.Particles, cfg):
     return abs(jx - float(qwv.sum().item())) / max(float(qwv.abs().sum().item()), 1e-300)
 
 
-def laser_case(wl, tile, drift, nsample=2000):
+def window_snapshot(sim, lo, size, margin=4):
+    """Every particle whose deposit can reach the cells [lo, lo + size) (a
+    particle in cell c deposits on nodes [c - 2, c + 3]; the margin covers
+    that with room), periodic, per species: FP64 positions, momenta and
+    weights before the push."""
+    out = []
+    for p in sim.particles:
+        cell = p.cell[: p.n].to(torch.int64)
+        keep = torch.ones(p.n, dtype=torch.bool, device=cell.device)
+        shift = 0
+        for a in range(sim.cfg.dim):
+            c = (cell >> shift) & ((1 << sim.bits[a]) - 1)
+            shift += sim.bits[a]
+            keep &= torch.remainder(c - (lo[a] - margin), sim.cfg.n[a]) < size[a] + 2 * margin
+        del cell
+        idx = torch.nonzero(keep).flatten()
+        out.append(dict(idx=idx, x0=positions_fp32(p, sim.bits, sim.cfg, idx), u0=[np64(t[idx]) for t in p.u],
+                        w0=np64(p.w[idx])))
+    return out
+
+
+def window_current(sim, snaps, F, lo, size):
+    """The oracle's current of the snapshot particles (same FP32 state and
+    fields), on the window cells; with the GPU's."""
+    g = oracle_grid(sim.cfg)
+    J = [np.zeros(F[0].shape) for _ in range(3)]
+    for sp, snap in zip(sim.species, snaps):
+        osp = O.Species(sp.q, sp.m, [a.copy() for a in snap["x0"]], [a.copy() for a in snap["u0"]],
+                        snap["w0"].copy(), sp.w0)
+        O.push(g, osp, F, J)
+    dim = sim.cfg.dim
+    ix = [np.arange(lo[a], lo[a] + size[a]) % sim.cfg.n[a] for a in range(dim)]
+    sel = np.ix_(*([ix[2]] if dim == 3 else [[0]]), ix[1], ix[0])
+    got = [np64(j)[sel] for j in sim.fields.J]
+    return [Jc[sel] for Jc in J], got
+
+
+def check_windows(sim, windows, snaps, F):
+    """Element-wise current on each window: relative L2 within 1e-5 (the
+    per-step field bar) and every node within 1e-5 of the window's largest
+    |J| component."""
+    for (lo, size), snap in zip(windows, snaps):
+        ref, got = window_current(sim, snap, F, lo, size)
+        rel = [rel_l2(g, r) for g, r in zip(got, ref)]
+        jmax = max(float(np.abs(r).max()) for r in ref)
+        mabs = max(float(np.abs(g - r).max()) for g, r in zip(got, ref)) / max(jmax, 1e-300)
+        npart = sum(len(s["w0"]) for s in snap)
+        print(f"  J window at {lo} size {size}: {npart} particles, rel L2 {max(rel):.2e}, "
+              f"max |dJ| / max |J| {mabs:.2e} (max |J| {jmax:.3e})", flush=True)
+        assert jmax > 0.0
+        assert max(rel) < 1e-5 and mabs < 1e-5
+
+
+def laser_case(wl, tile, drift, nsample=2000, windows=()):
     sim = Simulation.from_workload(wl, precision=L.PIC_FP32_MIXED, device=DEV, sort_every=1 << 30,
                                    tile=tile, drift=drift)
     sim.sort()
@@ -76,6 +130,7 @@ def laser_case(wl, tile, drift, nsample=2000):
         j.zero_()
     torch.cuda.synchronize()
     F = host_fields(sim.fields)
+    snaps = [window_snapshot(sim, lo, size) for lo, size in windows]
     worst = []
     for k, (sp, p) in enumerate(zip(sim.species, sim.particles)):
         jx_before = float(sim.fields.J[0].double().sum().item())
@@ -93,6 +148,7 @@ def laser_case(wl, tile, drift, nsample=2000):
         print(f"  species {k}: {p.n} particles, sample {nsample}: du {du:.2e}, dx {dx:.2e} cells, "
               f"sum J_x vs sum q w v_x {jrel:.2e}", flush=True)
         worst.append((du, dx, jrel))
+    check_windows(sim, windows, snaps, F)
     return sim, worst
 
 
@@ -101,7 +157,9 @@ def test_laser_2d_full_size():
     16 x 16, drift 2: the benchmark's case and launch configuration."""
     print("full size: 2D laser-plasma 4096x2048, 32 ppc, FP32", flush=True)
     wl = W.laser_plasma_2d(device=DEV)
-    sim, worst = laser_case(wl, (16, 16), 2)
+    # element-wise current on two 64 x 64 windows in the pulse: one on the
+    # axis, one across the periodic y seam; both span several tile windows
+    sim, worst = laser_case(wl, (16, 16), 2, windows=[((300, 992), (64, 64)), ((300, 2016), (64, 64))])
     for du, dx, jrel in worst:
         assert du < U_TOL and dx < X_TOL and jrel < J_TOL
     del sim
@@ -136,7 +194,10 @@ def test_laser_3d_full_size():
     (4.95e8), quadratic, tile 8 x 8 x 4, drift 1."""
     print("full size: 3D laser-plasma 512x256x256, 8+8 ppc, FP32", flush=True)
     wl = W.laser_plasma_3d(device=DEV, tile=(8, 8, 4))
-    sim, worst = laser_case(wl, (8, 8, 4), 1)
+    # element-wise current on two 32^3 windows in the pulse: one on the
+    # axis, one across the periodic y and z seams
+    sim, worst = laser_case(wl, (8, 8, 4), 1, windows=[((60, 112, 112), (32, 32, 32)),
+                                                      ((60, 240, 240), (32, 32, 32))])
     for du, dx, jrel in worst:
         assert du < U_TOL and dx < X_TOL and jrel < J_TOL
 

@@ -142,7 +142,8 @@ def test_sort_then_fp32_push_matches_oracle(dim, order, pusher):
     assert np64(diag)[:2] == pytest.approx(diag_o, rel=1e-5)
 
 
-@pytest.mark.parametrize("dim,order,drift", [(2, 1, 2), (2, 2, 2), (2, 4, 2), (3, 2, 1), (3, 2, 0), (3, 4, 0)])
+@pytest.mark.parametrize("dim,order,drift", [(2, 1, 2), (2, 2, 2), (2, 4, 2), (2, 1, 1), (2, 2, 1), (3, 2, 1),
+                                             (3, 2, 0), (3, 4, 0)])
 def test_default_tiles_fp32_push_matches_oracle(dim, order, drift):
     """The default tiles (16x16 with drift 2 in 2D; 8x8x4 with drift 1 or 0
     in 3D) run the kernels compiled for their window shape; sort and push
@@ -176,7 +177,38 @@ def test_stragglers_take_the_global_path(dim, order):
     still pushed exactly like the oracle and are counted."""
     print(f"stragglers dim={dim}", flush=True)
     cfg = make_cfg(dim, order, L.PIC_FP32_MIXED, drift=0)
-    raw = random_raw(cfg, 2001, seed=77 + dim)
+    stragglers_case(cfg)
+
+
+@pytest.mark.parametrize("pusher", PUSHERS)
+@pytest.mark.parametrize("order", [1, 2])
+def test_x_parity_window_layout(order, pusher):
+    """16 x 16 tiles with drift 1 take the x-parity LDS window layout: a grid
+    of 5 x 4 tiles (inner windows off the periodic seam, outer ones across
+    it) pushed after a sort, then with particles moved out of their windows
+    (binned pass through the same layout), against the oracle."""
+    print(f"x-parity layout order={order} pusher={pusher}", flush=True)
+    d = (0.3, 0.25)
+    cfg = L.Config(dim=2, n=(80, 64), d=d, dt=courant_dt(d, 0.9), order=order, precision=L.PIC_FP32_MIXED,
+                   tile=(16, 16), drift=1, pusher=pusher, hbar_omega_mc2=2.4263e-6)
+    raw = random_raw(cfg, 30011, seed=90 + order)
+    E, B = random_fields(cfg, seed=91 + order)
+    E = [e.to(torch.float32).to(torch.float64) for e in E]
+    B = [b.to(torch.float32).to(torch.float64) for b in B]
+    ctx, p, f, perm, start, bits = sorted_fp32_state(cfg, raw, E, B)
+    sp_o, J_o, diag_o = run_oracle_push(cfg, raw.subset(torch.from_numpy(perm)), E, B, -1.0, 1.0, from_fp32=True)
+    diag = torch.zeros(4, dtype=torch.float64, device=DEV)
+    L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), p, f, diag)
+    st, flags, nstray = L.pic_check(ctx)
+    assert st == L.PIC_OK and flags == 0 and nstray == 0
+    check_fp32_against_oracle(cfg, p, f, bits, sp_o, J_o)
+    assert np64(diag)[:2] == pytest.approx(diag_o, rel=1e-5)
+    stragglers_case(cfg, seed=95 + order)
+
+
+def stragglers_case(cfg, seed=None):
+    dim = cfg.dim
+    raw = random_raw(cfg, 2001, seed=77 + dim if seed is None else seed)
     E, B = random_fields(cfg, seed=9)
     E = [e.to(torch.float32).to(torch.float64) for e in E]
     B = [b.to(torch.float32).to(torch.float64) for b in B]

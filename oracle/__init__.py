@@ -285,6 +285,32 @@ def push(grid: Grid, sp: Species, F, J, diag=None):
                    _pp(J), dg)
 
 
+_omp = None
+
+
+def push_parallel(grid: Grid, sp: Species, F, J) -> int:
+    """`push` on every host thread (the benchmark's CPU baseline): one chunk
+    of particles per thread, thread-private current planes summed into J.
+    Returns the number of threads that ran."""
+    global _omp
+    if _omp is None:
+        if not os.path.exists(_build.OMP_LIB):
+            _build.build_omp()
+        _omp = C.CDLL(_build.OMP_LIB)
+        _omp.orc_push_omp.argtypes = [_GP, C.c_double, C.c_double, C.c_int64, _PP, _PP, _D, C.c_double, _PP, _PP,
+                                      C.POINTER(C.c_int)]
+        _omp.orc_push_omp.restype = C.c_int
+    xs = list(sp.x)
+    if grid.dim == 2:
+        xs = xs[:2] + [np.zeros(sp.n)]
+    wp = _dp(sp.w) if sp.w is not None else None
+    used = C.c_int(0)
+    rc = _omp.orc_push_omp(C.byref(grid.c()), sp.q, sp.m, sp.n, _pp(xs), _pp(sp.u), wp, sp.w0, _pp(F), _pp(J),
+                           C.byref(used))
+    assert rc == 0, "cannot allocate the per-thread current planes"
+    return used.value
+
+
 def step(st: State, diag=None):
     """One full step in the half-step arrangement of Sec. II.F:
     E += dt/2 (curl B - J^n); B -= dt/2 curl E; particles (J^{n+1} from zero);

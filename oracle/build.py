@@ -11,6 +11,25 @@ SOURCES = ["pic_oracle.c", "qed_oracle.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
+OMP_SOURCES = ["pic_oracle.c", "omp_push.c"]
+OMP_LIB = os.path.join(HERE, "liboracle_omp.so")
+
+
+def build_omp(verbose: bool = False) -> str:
+    """The parallel driver of the benchmark's CPU baseline (the oracle's own
+    particle step on every host thread, -O3 -fopenmp, same IEEE arithmetic:
+    no contraction, no fast-math)."""
+    srcs = [os.path.join(HERE, s) for s in OMP_SOURCES]
+    tmp = OMP_LIB + ".tmp"
+    cmd = ["gcc", "-std=c11", "-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-Wall", "-Wextra", "-o", tmp] + srcs + ["-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, OMP_LIB)
+    return OMP_LIB
+
+
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(HERE, s) for s in SOURCES]
     tmp = LIB + ".tmp"
@@ -20,6 +39,7 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_omp(verbose)
     return LIB
 
 

@@ -510,7 +510,7 @@ void orc_rho(const orc_grid *g, double q, int64_t np, const double *const *x, co
              double w0, double *rho) {
     for (int64_t p = 0; p < np; ++p) {
         int64_t i0[3] = {0, 0, 0};
-        double wt[3][5];
+        double wt[3][5] = {{0.0}};
         int nw[3] = {1, 1, 1};
         wt[2][0] = 1.0;
         for (int a = 0; a < g->dim; ++a) nw[a] = orc_shape(g->order, x[a][p] / g->d[a], &i0[a], wt[a]);

@@ -668,3 +668,28 @@ def test_beam_self_fields_satisfy_gauss_law():
     # B_y at (1/2, 0, 1/2) and B_z at (1/2, 1/2, 0): -beta E_z and beta E_y half a cell on in x
     assert np.abs(B[1]).max() == pytest.approx(beta * np.abs(E[2]).max(), rel=2e-2)
     assert np.abs(B[2]).max() == pytest.approx(beta * np.abs(E[1]).max(), rel=2e-2)
+
+
+def test_parallel_driver_equals_the_serial_push():
+    """The benchmark's CPU baseline runs the oracle's particle step on every
+    host thread with thread-private current planes: particles bit for bit,
+    the current up to the order of the final sum."""
+    g = O.Grid(2, (64, 48), (0.3, 0.25), 0.15, 2)
+    rng = np.random.default_rng(1)
+    n = 20000
+    x = [rng.uniform(0, 64 * 0.3, n), rng.uniform(0, 48 * 0.25, n)]
+    u = [rng.normal(0, 0.5, n) for _ in range(3)]
+    w = rng.uniform(0.5, 1.5, n)
+    F = [rng.normal(0, 0.3, g.shape) for _ in range(6)]
+    a = O.Species(-1.0, 1.0, [c.copy() for c in x], [c.copy() for c in u], w.copy())
+    b = O.Species(-1.0, 1.0, [c.copy() for c in x], [c.copy() for c in u], w.copy())
+    Ja = [np.zeros(g.shape) for _ in range(3)]
+    Jb = [np.zeros(g.shape) for _ in range(3)]
+    O.push(g, a, F, Ja)
+    threads = O.push_parallel(g, b, F, Jb)
+    assert threads >= 1
+    for k in range(3):
+        assert np.array_equal(a.u[k], b.u[k])
+        assert np.abs(Ja[k] - Jb[k]).max() <= 1e-13 * np.abs(Ja[k]).max()
+    for k in range(2):
+        assert np.array_equal(a.x[k], b.x[k])

@@ -275,3 +275,84 @@ def photon_decay_method2(photons: dict, seed: int, step: int, dt: float, hbar_w:
                             tau_thr=first_threshold(seed, cid, step)))
         photons["w"][p] = 0.0
     return saturated
+
+
+# ------------------------------------------------ cascade in a uniform field
+
+def cascade_uniform_b(b0: float, gamma0: float, n_el: int, steps: int, dt: float, hbar_w: float, seed: int,
+                      ids=None, emin: float = 0.0, first_step: int = 0):
+    """Electron-positron cascade of the Fig. 9 setup (Sec. IV): electrons of
+    Lorentz factor gamma0 moving along x across a uniform magnetic field
+    B = b0 z^ (E = 0), photon emission and pair creation by Method II only,
+    with the field left external (no current feedback: the test particles of
+    the setup).  Each step, in the order of the library's step: every lepton
+    that exists at the start of the step is pushed by Boris (Eqs. 13-16) and
+    takes chi_e at u^{n+1/2} = (u^n + u^{n+1})/2; the photons that exist at
+    the start of the step take chi_gamma and may decay into a pair (Eq. 24);
+    then the leptons of the start of the step may emit (Eq. 23), the photon
+    going along u with recoil.  Particles created in a step act from the next
+    step on.  Positions do not enter (the field is uniform).  Returns the
+    containers: electrons and positrons (dicts of u, chi, w, id, pos, q) and
+    photons (k, chi, w, id, pos), and the saturation flag of Method II."""
+    from . import boris
+    u0 = math.sqrt(gamma0 * gamma0 - 1.0)
+    ids = list(range(1, n_el + 1)) if ids is None else list(ids)
+    el = dict(u=[[u0] * n_el, [0.0] * n_el, [0.0] * n_el], chi=[0.0] * n_el, tau=[0.0] * n_el, tau_thr=[0.0] * n_el,
+              id=ids, w=[1.0] * n_el, pos=list(range(n_el)), q=-1.0)
+    po = dict(u=[[], [], []], chi=[], tau=[], tau_thr=[], id=[], w=[], pos=[], q=1.0)
+    ph = dict(k=[[], [], []], chi=[], tau=[], tau_thr=[], id=[], w=[], pos=[])
+    E0 = [0.0, 0.0, 0.0]
+    B0 = [0.0, 0.0, b0]
+    saturated = False
+
+    def append_lepton(L, p):
+        for a in range(3):
+            L["u"][a].append(p["u"][a])
+        L["chi"].append(0.0)
+        L["tau"].append(0.0)
+        L["tau_thr"].append(p["tau_thr"])
+        L["id"].append(p["id"])
+        L["w"].append(p["w"])
+        L["pos"].append(p["pos"])
+
+    for s in range(first_step, first_step + steps):
+        for L in (el, po):
+            for p in range(len(L["w"])):
+                u = [L["u"][a][p] for a in range(3)]
+                un = boris(L["q"], dt, E0, B0, u)
+                uh = [0.5 * (u[a] + un[a]) for a in range(3)]
+                gh = math.sqrt(1.0 + sum(c * c for c in uh))
+                L["chi"][p] = chi_of(hbar_w, gh, uh, E0, B0)
+                for a in range(3):
+                    L["u"][a][p] = float(un[a])
+        nph = len(ph["w"])
+        for p in range(nph):
+            k = [ph["k"][a][p] for a in range(3)]
+            eps = math.sqrt(sum(c * c for c in k))
+            ph["chi"][p] = chi_of(hbar_w, eps, k, E0, B0) if eps > 0 else 0.0
+        view = {key: (val[:nph] if key != "k" else [v[:nph] for v in val]) for key, val in ph.items()}
+        pos_out, ele_out = [], []
+        saturated |= photon_decay_method2(view, seed, s, dt, hbar_w, pos_out, ele_out)
+        ph["w"][:nph] = view["w"]
+        n0 = (len(el["w"]), len(po["w"]))
+        ph_out = []
+        for L, n in zip((el, po), n0):
+            sub = {key: (val[:n] if key not in ("u", "q") else ([v[:n] for v in val] if key == "u" else val))
+                   for key, val in L.items()}
+            saturated |= lepton_step_method2(sub, seed, s, dt, hbar_w, emin, ph_out)
+            for a in range(3):
+                L["u"][a][:n] = sub["u"][a]
+        for p in pos_out:
+            append_lepton(po, p)
+        for p in ele_out:
+            append_lepton(el, p)
+        for p in ph_out:
+            for a in range(3):
+                ph["k"][a].append(p["k"][a])
+            ph["chi"].append(0.0)
+            ph["tau"].append(0.0)
+            ph["tau_thr"].append(p["tau_thr"])
+            ph["id"].append(p["id"])
+            ph["w"].append(p["w"])
+            ph["pos"].append(p["pos"])
+    return el, po, ph, saturated

@@ -227,3 +227,41 @@ def test_photon_absorbed_at_x_faces():
     assert ph["w"] == [0.0, 1.0, 1.0, 0.0, 1.0, 1.0]
     assert ph["chi"][0] == 0.0 and ph["chi"][3] == 0.0 and ph["chi"][1] > 0.0
     assert abs(ph["x"][1][5] - (0.09)) < 1e-12
+
+
+def test_cascade_bookkeeping():
+    """The oracle's Fig. 9 cascade run: every pair adds one positron and
+    one electron and removes its photon; the field does no work; pair
+    members carry the photon's energy (a member whose share x eps is below
+    m c^2 is left at rest, so a pair may add up to 2 m c^2) and an emission's
+    recoil loses up to one m c^2 beyond the photon's energy: the total energy
+    stays within [start - emissions, start + 2 pairs]."""
+    hb = 2.4263e-6
+    b0 = 0.009 / hb
+    n = 60
+    el, po, ph, sat = Q.cascade_uniform_b(b0, 1000.0, n, 12, 0.02, hb, SEED)
+    assert not sat
+    decayed = sum(1 for w in ph["w"] if w == 0.0)
+    assert len(po["w"]) == decayed and len(el["w"]) == n + decayed
+    assert decayed > 0 and len(ph["w"]) > 3 * n
+    gam = lambda L: sum(math.sqrt(1 + sum(L["u"][a][p] ** 2 for a in range(3))) for p in range(len(L["w"])))  # noqa
+    eps = sum(math.sqrt(sum(ph["k"][a][p] ** 2 for a in range(3))) for p in range(len(ph["w"])) if ph["w"][p] != 0)
+    total, start = gam(el) + gam(po) + eps, n * 1000.0
+    assert start - len(ph["w"]) <= total <= start + 2 * decayed + 1e-9 * start
+
+
+def test_cascade_electrons_gyrate_between_emissions():
+    """Between emissions the uniform magnetic field turns u without changing
+    |u| (Boris), by the angle 2 atan(Omega dt / 2) per step."""
+    hb = 2.4263e-6
+    b0 = 0.001 / hb
+    el, _, ph, _ = Q.cascade_uniform_b(b0, 1000.0, 40, 1, 0.1, hb, SEED)
+    emitted = {Q.child_id(SEED, i, 0, 1) for i in range(1, 41)} & set(ph["id"])
+    quiet = [p for p in range(40) if Q.child_id(SEED, p + 1, 0, 1) not in emitted]
+    assert quiet
+    u0 = math.sqrt(1000.0 ** 2 - 1)
+    for p in quiet:
+        u = [el["u"][a][p] for a in range(3)]
+        assert math.sqrt(sum(c * c for c in u)) == pytest.approx(u0, rel=1e-14)
+        ang = math.atan2(u[1], u[0])
+        assert abs(ang) == pytest.approx(2 * math.atan(b0 / 1000.0 * 0.1 / 2), rel=1e-12)

@@ -93,6 +93,9 @@ def parse():
                     help="drift allowance (default 2 in 2D; 1 for laser3d, 0 for wake3d and quartic 3D)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, copy a 1 GiB float32 buffer (HBM counter calibration)")
+    ap.add_argument("--bc", choices=["absorb", "periodic"], default="absorb",
+                    help="x faces of the laser and wakefield cases: absorbing (the paper's laser cases, the "
+                         "default) or periodic")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the other workloads (3D laser, 2D QED foil, 3D QED at full HBM)")
     return ap.parse_args()
@@ -367,8 +370,11 @@ def sampled_step(sim, torch, L, nsample=2000, seed=21):
     qabs = sum(sn["qwv_abs"] for sn in snaps)
     L.pic_yee_step(sim.ctx, 2, sim.fields)
     torch.cuda.synchronize()
+    # the identity holds for a periodic box; absorbing faces drop the current
+    # deposited beyond them
+    periodic = cfg.bc_x == L.PIC_BC_PERIODIC
     return dict(F=F, snaps=snaps, species=[(sp.q, sp.m, sp.w0) for sp in sim.species],
-                sumJx_vs_sum_qwvx_rel=abs(jx - qwv) / max(qabs, 1e-300))
+                sumJx_vs_sum_qwvx_rel=abs(jx - qwv) / max(qabs, 1e-300) if periodic else None)
 
 
 def positions64(sim, p, idx):
@@ -389,7 +395,8 @@ def oracle_errors(cfg, sample, O):
     """The oracle's one-step push of the sample from the same state and
     fields: max relative momentum error and max position error (cells)."""
     import numpy as np
-    g = O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order, pusher=cfg.pusher)
+    g = O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order, pusher=cfg.pusher,
+               absorb_x=int(cfg.bc_x != 0))
     J = [np.zeros(sample["F"][0].shape) for _ in range(3)]
     du = dx = 0.0
     for (q, m, w0), sn in zip(sample["species"], sample["snaps"]):
@@ -518,6 +525,7 @@ def legs(args, torch, L, Simulation, log):
     log("leg: laser3d")
     wl = laser_plasma_3d(device="cuda", tile=(8, 8, 4), order=args.order)
     wl.cfg.pusher = L.PIC_PUSH_VAY if args.pusher == "vay" else L.PIC_PUSH_BORIS
+    wl.cfg.bc_x = L.PIC_BC_ABSORB if args.bc == "absorb" else L.PIC_BC_PERIODIC
     r3 = {"workload": wl.name, "tile": [8, 8, 4], "drift": 1}
     for prec, name, steps, warm in ((L.PIC_FP32_MIXED, "fp32", 16, 2), (L.PIC_FP64_PLAIN, "fp64_plain", 3, 1)):
         a.steps, a.warmup = steps, warm
@@ -600,7 +608,8 @@ def cpu_baseline(wl, O, target_s, log):
     import torch
     from paper_2104_00642_amd.workloads import to_fp64
     cfg = wl.cfg
-    g = O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order, pusher=cfg.pusher)
+    g = O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order, pusher=cfg.pusher,
+               absorb_x=int(cfg.bc_x != 0))
     F = [t.to("cpu", torch.float64).numpy().copy() for t in list(wl.E0) + list(wl.B0)]
     q, m, raw = wl.species[0]
     gen = torch.Generator().manual_seed(11)
@@ -623,11 +632,18 @@ def cpu_baseline(wl, O, target_s, log):
     t0 = time.perf_counter()
     O.push_parallel(g, sp, F, J)
     per = max(time.perf_counter() - t0 - fixed, 1e-3) / kp
-    k = int(min(1.5e8, max(1e6, target_s / per)))
-    sp = sample(k)
-    t0 = time.perf_counter()
-    threads = O.push_parallel(g, sp, F, J)
-    el = time.perf_counter() - t0
+    # the probe's first touch of fresh arrays makes it slower per particle
+    # than a long run: one resize from the timed run itself
+    for _ in range(2):
+        k = int(min(1.5e8, max(1e6, target_s / per)))
+        sp = sample(k)
+        t0 = time.perf_counter()
+        threads = O.push_parallel(g, sp, F, J)
+        el = time.perf_counter() - t0
+        if el >= 0.5 * target_s or k >= 1.5e8:
+            break
+        per = max(el - fixed, 1e-3) / k
+        del sp
     log(f"cpu baseline: {k} particle-steps in {el:.2f}s on {threads} threads (fixed cost {fixed:.2f}s per call)")
     return {"value": k / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{k} random particles of the workload, one oracle gather+push+deposit step each "
@@ -676,6 +692,7 @@ def main():
                                order=args.order)
         ppc = 16  # the plasma's 8 + 8 per cell (the beam adds 0.3%)
     wl.cfg.pusher = L.PIC_PUSH_VAY if args.pusher == "vay" else L.PIC_PUSH_BORIS
+    wl.cfg.bc_x = L.PIC_BC_ABSORB if args.bc == "absorb" else L.PIC_BC_PERIODIC
     out = {}
     samples = {}
     for prec in ([L.PIC_FP32_MIXED] if args.no_fp64 else [L.PIC_FP32_MIXED, L.PIC_FP64_PLAIN]):
@@ -720,7 +737,7 @@ def main():
                    "shape": {1: "linear", 2: "quadratic", 4: "quartic"}[args.order], "pusher": args.pusher,
                    "tile": r["tile"][:dim],
                    "sort_every": args.sort_every,
-                   "drift": args.drift, "parallelism": "single GPU"},
+                   "drift": args.drift, "x_faces": args.bc, "parallelism": "single GPU"},
         "gpd_only_particle_steps_per_s": r["n"] / (r["gpd_ms"] * 1e-3),
         "gpd_ms_avg": r["gpd_ms"],
         "timing_ms": {"step": r["step_ms_stats"], "gather_push_deposit": r["gpd_ms_stats"]},

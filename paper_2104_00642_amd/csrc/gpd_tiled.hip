@@ -88,8 +88,8 @@ struct TiledArgs {
     uint32_t *bin_rank;    // per entry of the straggler list and tail (capacity n)
     int part_off;          // first partial slot (doubles) of the launch
     int absorb_x;          // absorbing x faces: nothing is gathered from or deposited
-                           // beyond x nodes [0, n); gpd_absorb_kernel then zeroes the
-                           // weight of the particles that left
+                           // beyond x nodes [0, n), and a particle whose new position
+                           // leaves [0, (n-1) dx] gets weight 0
 };
 
 // Accessor of the LDS window: coordinates local to the window origin.  Fields
@@ -639,6 +639,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         uT[d] = a.u[d] + rebase;
     }
     const float *wT = a.w ? a.w + rebase : nullptr;
+    float *wW = a.w ? a.w + rebase : nullptr;  // absorption (weights are required with absorbing faces)
     float *chiT = a.chi ? a.chi + rebase : nullptr;
 
     // 1. stage the E/B window, zero the J window (window index decoded once
@@ -785,6 +786,9 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
             packed |= (WRAP ? wrap_index(cc[d] + dc[d], a.ng[d]) : cc[d] + dc[d])
                       << (d == 0 ? 0 : (d == 1 ? a.bx : a.bx + a.by));
         st(cellT, bo, packed);
+        // absorbing x faces: x nodes of the domain are [0, n-1], so a new
+        // cell outside [0, n-2] (before the wrap) is a position beyond a face
+        if (a.absorb_x && (unsigned)(cc[0] + dc[0]) >= (unsigned)(a.ng[0] - 1)) st(wW, bo, 0.0f);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) st(offT[d], bo, f[d]);
 #pragma unroll
@@ -828,16 +832,6 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         part[2 * t + 1] = sq * a.qdV;
         if (!LIST) a.strag_tile[t] = nstray;
     }
-}
-
-// Absorbing x faces: a particle whose new position left [0, (n-1) dx] sits in
-// x cell n-1 (moving out of cell n-2, or wrapped from cell 0: a step moves
-// less than a cell), the half cell beyond the far face; its weight becomes 0.
-// Run after the push, so the hot loop carries no per-particle test.
-__global__ void __launch_bounds__(256) gpd_absorb_kernel(const int32_t *cell, float *w, int64_t n, int mx,
-                                                         int last) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n && (cell[p] & mx) == last) w[p] = 0.0f;
 }
 
 // Clears the bin counters and the straggler count before the sorted pass.
@@ -1056,6 +1050,7 @@ __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
             a.off[d][p] = f[d];
         }
         a.cell[p] = packed;
+        if (a.absorb_x && (unsigned)(cc[0] + dc[0]) >= (unsigned)(a.ng[0] - 1)) a.w[p] = 0.0f;
 #pragma unroll
         for (int d = 0; d < 3; ++d) a.u[d][p] = u[d];
         if (a.chi) a.chi[p] = a.chi_scale * chi_of(u_old, u, EB);
@@ -1217,9 +1212,6 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
         case 34: launch_pusher<3, 4>(a, cfg.pusher, lds, s); break;
         default: return hipErrorInvalidValue;
     }
-    if (a.absorb_x)
-        gpd_absorb_kernel<<<(unsigned)((p->n + 255) / 256), 256, 0, s>>>(p->cell, a.w, p->n, (1 << a.bx) - 1,
-                                                                         a.ng[0] - 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !diag) return e;
     return launch_finalize(a.partials, (int64_t)nblocks, 2, diag, 0, 1.0, s);

@@ -93,12 +93,17 @@ def parse():
                     help="drift allowance (default 2 in 2D; 1 for laser3d, 0 for wake3d and quartic 3D)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, copy a 1 GiB float32 buffer (HBM counter calibration)")
-    ap.add_argument("--bc", choices=["absorb", "periodic"], default="absorb",
-                    help="x faces of the laser and wakefield cases: absorbing (the paper's laser cases, the "
-                         "default) or periodic")
+    ap.add_argument("--bc", choices=["absorb2", "absorb", "periodic"], default="absorb2",
+                    help="x faces of the laser and wakefield cases: absorbing with the second-order (the "
+                         "default) or first-order Mur rule for the fields, or periodic")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the other workloads (3D laser, 2D QED foil, 3D QED at full HBM)")
     return ap.parse_args()
+
+
+def bc_codes():
+    from paper_2104_00642_amd import _lib as L
+    return {"absorb2": L.PIC_BC_ABSORB2, "absorb": L.PIC_BC_ABSORB, "periodic": L.PIC_BC_PERIODIC}
 
 
 def stats_ms(v):
@@ -396,7 +401,7 @@ def oracle_errors(cfg, sample, O):
     fields: max relative momentum error and max position error (cells)."""
     import numpy as np
     g = O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order, pusher=cfg.pusher,
-               absorb_x=int(cfg.bc_x != 0))
+               absorb_x=int(cfg.bc_x))
     J = [np.zeros(sample["F"][0].shape) for _ in range(3)]
     du = dx = 0.0
     for (q, m, w0), sn in zip(sample["species"], sample["snaps"]):
@@ -525,7 +530,7 @@ def legs(args, torch, L, Simulation, log):
     log("leg: laser3d")
     wl = laser_plasma_3d(device="cuda", tile=(8, 8, 4), order=args.order)
     wl.cfg.pusher = L.PIC_PUSH_VAY if args.pusher == "vay" else L.PIC_PUSH_BORIS
-    wl.cfg.bc_x = L.PIC_BC_ABSORB if args.bc == "absorb" else L.PIC_BC_PERIODIC
+    wl.cfg.bc_x = bc_codes()[args.bc]
     r3 = {"workload": wl.name, "tile": [8, 8, 4], "drift": 1}
     for prec, name, steps, warm in ((L.PIC_FP32_MIXED, "fp32", 16, 2), (L.PIC_FP64_PLAIN, "fp64_plain", 3, 1)):
         a.steps, a.warmup = steps, warm
@@ -609,7 +614,7 @@ def cpu_baseline(wl, O, target_s, log):
     from paper_2104_00642_amd.workloads import to_fp64
     cfg = wl.cfg
     g = O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order, pusher=cfg.pusher,
-               absorb_x=int(cfg.bc_x != 0))
+               absorb_x=int(cfg.bc_x))
     F = [t.to("cpu", torch.float64).numpy().copy() for t in list(wl.E0) + list(wl.B0)]
     q, m, raw = wl.species[0]
     gen = torch.Generator().manual_seed(11)
@@ -692,7 +697,7 @@ def main():
                                order=args.order)
         ppc = 16  # the plasma's 8 + 8 per cell (the beam adds 0.3%)
     wl.cfg.pusher = L.PIC_PUSH_VAY if args.pusher == "vay" else L.PIC_PUSH_BORIS
-    wl.cfg.bc_x = L.PIC_BC_ABSORB if args.bc == "absorb" else L.PIC_BC_PERIODIC
+    wl.cfg.bc_x = bc_codes()[args.bc]
     out = {}
     samples = {}
     for prec in ([L.PIC_FP32_MIXED] if args.no_fp64 else [L.PIC_FP32_MIXED, L.PIC_FP64_PLAIN]):

@@ -74,17 +74,24 @@ typedef enum {
 } pic_status;
 
 enum { PIC_FP32_MIXED = 0, PIC_FP64_PLAIN = 1 };
-/* Boundaries, per axis.  PIC_BC_ABSORB is built for x (bc[0]): the domain is
- * x in [0, (n[0]-1) d[0]] (the absorbing faces of the paper's 1D case,
+/* Boundaries, per axis.  Absorbing faces are built for x (bc[0]): the domain
+ * is x in [0, (n[0]-1) d[0]] (the absorbing faces of the paper's 1D case,
  * Sec. III; their scheme is not printed).
- *   Fields: E_y, E_z on the two faces follow the first-order Mur rule over
- *   each half step, at x = 0 acting on E - E_inc so that a pulse set by
- *   pic_set_laser enters; E_x, B_y, B_z half a cell beyond the far face stay 0.
+ *   Fields: E_y, E_z on the two faces follow Mur's rule over each half step
+ *   (G. Mur, IEEE Trans. EMC 23, 377 (1981)), at x = 0 acting on E - E_inc so
+ *   that a pulse set by pic_set_laser enters; E_x, B_y, B_z half a cell
+ *   beyond the far face stay 0.  PIC_BC_ABSORB: first order, a plane wave at
+ *   angle theta from the normal comes back with amplitude
+ *   (1 - cos theta)/(1 + cos theta).  PIC_BC_ABSORB2: second order (the
+ *   transverse second differences of Engquist and Majda's condition), the
+ *   square of that; it keeps the face values of the previous E half update in
+ *   the context, so its first E half update after pic_init runs the
+ *   first-order rule, and a context must not be switched between field sets.
  *   Particles: nothing is gathered from or deposited to x nodes beyond
  *   [0, n[0]), and a particle whose new position leaves the domain is
  *   absorbed: its weight is set to 0 (per-particle weights are required; it
  *   stays in the arrays, wrapped in x, until the caller drops it). */
-enum { PIC_BC_PERIODIC = 0, PIC_BC_ABSORB = 1 };
+enum { PIC_BC_PERIODIC = 0, PIC_BC_ABSORB = 1, PIC_BC_ABSORB2 = 2 };
 /* Momentum update: Boris (Sec. II.C, Eqs. 13-16) or Vay, which Sec. II.C
  * names for fields whose electric and magnetic forces nearly cancel; Vay
  * solves u^{n+1} - u^n = q_m dt (E + (v^n + v^{n+1})/2 x B) in closed form
@@ -111,7 +118,7 @@ typedef struct {
     int64_t n[3];           /* cells per axis; n[2] = 1 when dim = 2                  */
     double d[3];            /* cell sizes (c/w_r)                                     */
     double dt;              /* step (1/w_r); PIC_E_CFL unless dt*sqrt(sum 1/d^2) <= 1  */
-    int32_t bc[3];          /* PIC_BC_PERIODIC; bc[0] may be PIC_BC_ABSORB (fields)     */
+    int32_t bc[3];          /* PIC_BC_PERIODIC; bc[0] may be PIC_BC_ABSORB(2)           */
     int32_t tile[3];        /* FP32 path tile in cells (must divide n); 0 = default   */
     uint64_t seed;          /* key of the counter-based generator (QED)               */
     double hbar_omega_mc2;  /* hbar w_r / (m_e c^2) for chi (2.4263e-6 at 1 um);
@@ -362,7 +369,7 @@ pic_status pic_qed_table_lookup(void *ctx, int32_t proc, int32_t what, const flo
                                 int64_t n, float *out, void *stream);
 
 /*
- * Pulse injected through the x = 0 face (requires bc[0] = PIC_BC_ABSORB), in
+ * Pulse injected through the x = 0 face (requires absorbing x faces), in
  * laser units (w_r = w_L: wavelength 2 pi, critical density 1):
  *   E_y = a0 exp(-r^2/waist^2) S((t - t0 - x)/duration) sin(x - t),
  *   E_z = the same with sin(x - t + pi/2) when circular, else 0,

@@ -54,7 +54,7 @@ class Grid:
     dt: float
     order: int = 2
     pusher: int = 0  # 0 Boris, 1 Vay
-    absorb_x: int = 0  # 1: absorbing x faces (fields)
+    absorb_x: int = 0  # absorbing x faces: 1 first-order, 2 second-order Mur rule for the fields
     laser: tuple = (0.0, 0.0, 0.0, 0.0)  # a0, waist, duration, t0 of the pulse injected at x = 0
     laser_circular: int = 0
 
@@ -103,7 +103,7 @@ def _declare(L):
     L.orc_deposit.argtypes = [_GP, C.c_double, _D, _D, C.c_double, _PP]
     L.orc_push.argtypes = [_GP, C.c_double, C.c_double, C.c_int64, _PP, _PP, _D, C.c_double,
                            _PP, _PP, _D]
-    L.orc_half_e.argtypes = [_GP, _PP, _PP, _PP, C.c_double]
+    L.orc_half_e.argtypes = [_GP, _PP, _PP, _PP, C.c_double, _D, C.POINTER(C.c_int32)]
     L.orc_half_b.argtypes = [_GP, _PP, _PP]
     L.orc_field_energy.argtypes = [_GP, _PP]
     L.orc_field_energy.restype = C.c_double
@@ -182,9 +182,26 @@ def deposit(grid: Grid, qw: float, xh, xe, vz: float, J):
     lib().orc_deposit(C.byref(grid.c()), qw, _dp(xh), _dp(xe), vz, _pp(J))
 
 
-def half_e(grid: Grid, E, B, J, t: float = 0.0):
-    """E half step; t is the time of E on entry (used by the injected pulse)."""
-    lib().orc_half_e(C.byref(grid.c()), _pp(E), _pp(B), _pp(J), float(t))
+class MurHistory:
+    """Face values of E_y, E_z (x nodes 0, 1, n-2, n-1) on entry to the last
+    E half update: the earlier time level of the second-order Mur rule."""
+
+    def __init__(self, grid: "Grid"):
+        n = list(grid.n) + [1] * (3 - len(grid.n))
+        self.values = np.zeros(8 * n[1] * n[2])
+        self.valid = C.c_int32(0)
+
+
+def half_e(grid: Grid, E, B, J, t: float = 0.0, mur: "MurHistory" = None):
+    """E half step; t is the time of E on entry (used by the injected pulse).
+    With second-order absorbing faces (absorb_x = 2) `mur` carries the face
+    history from call to call (without it, or on its first use, the
+    first-order rule runs)."""
+    if mur is None:
+        lib().orc_half_e(C.byref(grid.c()), _pp(E), _pp(B), _pp(J), float(t), None, None)
+    else:
+        lib().orc_half_e(C.byref(grid.c()), _pp(E), _pp(B), _pp(J), float(t), _dp(mur.values),
+                         C.byref(mur.valid))
 
 
 def half_b(grid: Grid, E, B):
@@ -266,6 +283,7 @@ class State:
     J: list
     species: list = field(default_factory=list)
     t: float = 0.0
+    mur: "MurHistory" = None  # second-order absorbing faces: made by the first step
 
     @staticmethod
     def zeros(grid: Grid):
@@ -317,7 +335,9 @@ def step(st: State, diag=None):
     B -= dt/2 curl E; E += dt/2 (curl B - J^{n+1}).  J^n is the current left
     in st.J by the previous step (zero at start)."""
     g = st.grid
-    half_e(g, st.E, st.B, st.J, st.t)
+    if g.absorb_x == 2 and st.mur is None:
+        st.mur = MurHistory(g)
+    half_e(g, st.E, st.B, st.J, st.t, st.mur)
     half_b(g, st.E, st.B)
     for a in range(3):
         st.J[a][...] = 0.0
@@ -325,7 +345,7 @@ def step(st: State, diag=None):
     for sp in st.species:
         push(g, sp, F, st.J, diag)
     half_b(g, st.E, st.B)
-    half_e(g, st.E, st.B, st.J, st.t + 0.5 * g.dt)
+    half_e(g, st.E, st.B, st.J, st.t + 0.5 * g.dt, st.mur)
     st.t += g.dt
 
 

@@ -38,7 +38,7 @@ typedef struct {
     double d[3];     /* cell sizes dx, dy, dz                            */
     double dt;       /* time step                                        */
     int32_t pusher;  /* 0 Boris (Sec. II.C), 1 Vay                       */
-    int32_t absorb_x;  /* 1: absorbing faces at x = 0 and x = (n-1) dx  */
+    int32_t absorb_x;  /* absorbing faces at x = 0 and x = (n-1) dx: 1 first-, 2 second-order Mur */
     double laser[4];   /* a0, waist, duration, t0 of the pulse injected
                           through x = 0 (a0 = 0: none)                   */
     int32_t laser_circular;
@@ -395,16 +395,29 @@ static double orc_incident(const orc_grid *g, int comp, double x, double y, doub
  * half_e(J^n); half_b; [particles]; half_b; half_e(J^{n+1}).
  *
  * Absorbing x faces (absorb_x): the domain is x in [0, (n-1) dx].  E_y and
- * E_z on the faces x = 0 and x = (n-1) dx follow the first-order Mur rule,
- * the one-way wave equation E_t = -/+ E_x centred between the face node and
- * its neighbour over the half step h = dt/2:
- *   E_0^new = E_1^old + k (E_1^new - E_0^old),   k = (h - dx) / (h + dx),
- * and the mirror at the far face; at x = 0 it acts on E - E_inc, so the
- * injected pulse enters while outgoing waves leave.  E_x, B_y, B_z half a
- * cell beyond the far face lie outside and stay 0.
+ * E_z on the faces x = 0 and x = (n-1) dx follow Mur's rule over the half
+ * step h = dt/2 (G. Mur, IEEE Trans. EMC 23, 377 (1981)); at x = 0 it acts
+ * on E - E_inc, so the injected pulse enters while outgoing waves leave.
+ * With node 0 on the face, node 1 inside, levels m-1, m, m+1 a half step
+ * apart and k = (h - dx)/(h + dx):
+ *   absorb_x = 1, first order, from the one-way wave equation E_t = E_x
+ *   centred between nodes 0 and 1:
+ *     E_0^{m+1} = E_1^m + k (E_1^{m+1} - E_0^m);
+ *   absorb_x = 2, second order, from E_xt - E_tt + (1/2)(E_yy + E_zz) = 0
+ *   (Engquist-Majda) centred the same way:
+ *     E_0^{m+1} = -E_1^{m-1} + k (E_1^{m+1} + E_0^{m-1})
+ *                 + 2 dx/(h + dx) (E_0^m + E_1^m)
+ *                 + h^2 dx / (2 (h + dx)) (D E_0^m + D E_1^m),
+ *   D the periodic second difference over y (and z) on the face planes.
+ *   Level m-1 comes from `mur` (the face values on entry to the previous
+ *   half update, kept by the caller between calls); while *mur_valid is 0
+ *   (the first call) the first-order rule runs instead.  Each call leaves its
+ *   entry values in `mur` and sets *mur_valid.
+ * The far face is the mirror, nodes n-1 and n-2.  E_x, B_y, B_z half a cell
+ * beyond the far face lie outside and stay 0.
  */
 void orc_half_e(const orc_grid *g, double *const *E, const double *const *B,
-                const double *const *J, double t) {
+                const double *const *J, double t, double *mur, int32_t *mur_valid) {
     const double h = 0.5 * g->dt;
     const double ix = 1.0 / g->d[0], iy = 1.0 / g->d[1];
     const double iz = g->dim == 3 ? 1.0 / g->d[2] : 0.0;
@@ -444,23 +457,70 @@ void orc_half_e(const orc_grid *g, double *const *E, const double *const *B,
                 }
             }
     if (ab) {
-        const double km = (h - g->d[0]) / (h + g->d[0]);
-        for (int64_t k = 0; k < g->n[2]; ++k)
-            for (int64_t j = 0; j < g->n[1]; ++j)
+        const double dx = g->d[0];
+        const double km = (h - dx) / (h + dx);
+        const int second = ab == 2 && mur && mur_valid && *mur_valid;
+        const int64_t ny = g->n[1], nz = g->n[2];
+        /* scattered entry values s[f][cmp][q] (face nodes 0, 1, n-2, n-1): E - E_inc at x = 0, 1 */
+        double *sc = (double *)malloc(sizeof(double) * 8 * (size_t)nyz);
+        for (int f = 0; f < 4; ++f)
+            for (int cmp = 0; cmp < 2; ++cmp)
+                for (int64_t k = 0; k < nz; ++k)
+                    for (int64_t j = 0; j < ny; ++j) {
+                        const int comp = 1 + cmp;
+                        const double y = (j + (comp == 1 ? 0.5 : 0.0)) * g->d[1];
+                        const double z = g->dim == 3 ? (k + (comp == 2 ? 0.5 : 0.0)) * g->d[2] : 0.0;
+                        const int64_t q = j + ny * k;
+                        double v = old[(f * 2 + cmp) * nyz + q];
+                        if (f < 2) v -= orc_incident(g, comp, f * dx, y, z, t);
+                        sc[(f * 2 + cmp) * nyz + q] = v;
+                    }
+        for (int64_t k = 0; k < nz; ++k)
+            for (int64_t j = 0; j < ny; ++j)
                 for (int cmp = 0; cmp < 2; ++cmp) {
                     const int comp = 1 + cmp;
-                    const int64_t q = j + g->n[1] * k;
+                    const int64_t q = j + ny * k;
                     /* stagger of the component: E_y at y + dy/2, E_z at z + dz/2 */
                     const double y = (j + (comp == 1 ? 0.5 : 0.0)) * g->d[1];
                     const double z = g->dim == 3 ? (k + (comp == 2 ? 0.5 : 0.0)) * g->d[2] : 0.0;
-                    const double x1 = g->d[0];
-                    double s0o = old[(0 * 2 + cmp) * nyz + q] - orc_incident(g, comp, 0.0, y, z, t);
-                    double s1o = old[(1 * 2 + cmp) * nyz + q] - orc_incident(g, comp, x1, y, z, t);
-                    double s1n = E[comp][idx3(g, 1, j, k)] - orc_incident(g, comp, x1, y, z, t + h);
-                    E[comp][idx3(g, 0, j, k)] = orc_incident(g, comp, 0.0, y, z, t + h) + s1o + km * (s1n - s0o);
-                    double e2o = old[(2 * 2 + cmp) * nyz + q], e3o = old[(3 * 2 + cmp) * nyz + q];
-                    E[comp][idx3(g, nx - 1, j, k)] = e2o + km * (E[comp][idx3(g, nx - 2, j, k)] - e3o);
+                    /* face f0 (on the face) and f1 (inside): x = 0 uses nodes 0, 1; the far face n-1, n-2 */
+                    for (int side = 0; side < 2; ++side) {
+                        const int f0 = side == 0 ? 0 : 3, f1 = side == 0 ? 1 : 2;
+                        const int64_t i0 = side == 0 ? 0 : nx - 1, i1 = side == 0 ? 1 : nx - 2;
+                        const double inc_new0 = side == 0 ? orc_incident(g, comp, 0.0, y, z, t + h) : 0.0;
+                        const double inc_new1 = side == 0 ? orc_incident(g, comp, dx, y, z, t + h) : 0.0;
+                        const double u0 = sc[(f0 * 2 + cmp) * nyz + q], u1 = sc[(f1 * 2 + cmp) * nyz + q];
+                        const double u1n = E[comp][idx3(g, i1, j, k)] - inc_new1;
+                        double u0n;
+                        if (!second) {
+                            u0n = u1 + km * (u1n - u0);
+                        } else {
+                            const double inc_old0 = side == 0 ? orc_incident(g, comp, 0.0, y, z, t - h) : 0.0;
+                            const double inc_old1 = side == 0 ? orc_incident(g, comp, dx, y, z, t - h) : 0.0;
+                            const double u0m = mur[(f0 * 2 + cmp) * nyz + q] - inc_old0;
+                            const double u1m = mur[(f1 * 2 + cmp) * nyz + q] - inc_old1;
+                            /* second differences along y (and z) of the entry values, both planes */
+                            double lap = 0.0;
+                            for (int f = 0; f < 2; ++f) {
+                                const double *pl = sc + ((f == 0 ? f0 : f1) * 2 + cmp) * nyz;
+                                const int64_t jp = (j + 1) % ny, jm = (j + ny - 1) % ny;
+                                lap += (pl[jp + ny * k] - 2.0 * pl[q] + pl[jm + ny * k]) / (g->d[1] * g->d[1]);
+                                if (g->dim == 3) {
+                                    const int64_t kp = (k + 1) % nz, kmi = (k + nz - 1) % nz;
+                                    lap += (pl[j + ny * kp] - 2.0 * pl[q] + pl[j + ny * kmi]) / (g->d[2] * g->d[2]);
+                                }
+                            }
+                            u0n = -u1m + km * (u1n + u0m) + 2.0 * dx / (h + dx) * (u0 + u1) +
+                                  h * h * dx / (2.0 * (h + dx)) * lap;
+                        }
+                        E[comp][idx3(g, i0, j, k)] = inc_new0 + u0n;
+                    }
                 }
+        if (ab == 2 && mur) {
+            memcpy(mur, old, sizeof(double) * 8 * (size_t)nyz);
+            if (mur_valid) *mur_valid = 1;
+        }
+        free(sc);
         free(old);
     }
 }

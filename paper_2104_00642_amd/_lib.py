@@ -28,6 +28,7 @@ PIC_F_NONFINITE, PIC_F_OFFSET, PIC_F_STRAGGLER, PIC_F_CAPACITY, PIC_F_QED_SATURA
 PIC_QED_TABLE, PIC_QED_MLP, PIC_QED_METHOD2 = 0, 1, 2
 PIC_PUSH_BORIS, PIC_PUSH_VAY = 0, 1
 PIC_BC_ABSORB = 1
+PIC_BC_ABSORB2 = 2
 PIC_MLP_NPARAM = 4610
 PIC_MLP_BYTES = 18440
 PIC_MLP_STATE_FLOATS = 4 * PIC_MLP_NPARAM + 1
@@ -173,7 +174,7 @@ class Config:
     seed: int = 0
     hbar_omega_mc2: float = 0.0
     pusher: int = PIC_PUSH_BORIS
-    bc_x: int = PIC_BC_PERIODIC  # or PIC_BC_ABSORB (fields)
+    bc_x: int = PIC_BC_PERIODIC  # or PIC_BC_ABSORB / PIC_BC_ABSORB2 (first- / second-order field rule)
 
     def c(self) -> pic_config:
         cfg = pic_config()

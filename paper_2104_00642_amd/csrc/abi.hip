@@ -161,7 +161,7 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
                 return fail(nullptr, PIC_E_ARG, "cells per axis must be in [8, 2^20]");
             if (!finite_pos(cfg->d[a])) return fail(nullptr, PIC_E_ARG, "cell sizes must be > 0");
             s += 1.0 / (cfg->d[a] * cfg->d[a]);
-            if (cfg->bc[a] != PIC_BC_PERIODIC && !(a == 0 && cfg->bc[a] == PIC_BC_ABSORB))
+            if (cfg->bc[a] != PIC_BC_PERIODIC && !(a == 0 && absorbing_x(*cfg)))
                 return fail(nullptr, PIC_E_UNSUPPORTED, "boundaries: periodic, or absorbing along x");
         } else if (cfg->n[a] != 1) {
             return fail(nullptr, PIC_E_ARG, "n[2] must be 1 in 2D");
@@ -242,8 +242,10 @@ extern "C" pic_status pic_init(const pic_config *cfg, void **out) {
         delete c;
         return st;
     }
-    if (e == hipSuccess && cfg->bc[0] == PIC_BC_ABSORB)
+    if (e == hipSuccess && absorbing_x(*cfg))
         e = hipMalloc(&c->mur_old, sizeof(double) * 8 * (size_t)cfg->n[1] * (size_t)cfg->n[2]);
+    if (e == hipSuccess && cfg->bc[0] == PIC_BC_ABSORB2)
+        e = hipMalloc(&c->mur_hist, sizeof(double) * 8 * (size_t)cfg->n[1] * (size_t)cfg->n[2]);
     if (e != hipSuccess) {
         pic_status st = hip_fail(nullptr, e, "pic_init");
         pic_destroy(c);
@@ -300,6 +302,7 @@ extern "C" void pic_destroy(void *ctx) {
     hipFree(c->qed.dev);
     hipFree(c->mlp_scratch);
     hipFree(c->mur_old);
+    hipFree(c->mur_hist);
     hipFree(c->gauss_part);
     for (void *p : c->retired) hipFree(p);
     delete c;
@@ -317,7 +320,7 @@ extern "C" pic_status pic_set_laser(void *ctx, const pic_laser *laser, double t)
     Ctx *c = (Ctx *)ctx;
     if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
     if (!laser || !isfinite(t)) return fail(c, PIC_E_ARG, "null laser or non-finite time");
-    if (c->cfg.bc[0] != PIC_BC_ABSORB) return fail(c, PIC_E_ARG, "injection needs bc[0] = PIC_BC_ABSORB");
+    if (!absorbing_x(c->cfg)) return fail(c, PIC_E_ARG, "injection needs absorbing x faces");
     if (!isfinite(laser->a0) || !isfinite(laser->t0) ||
         (laser->a0 != 0.0 && !(laser->waist > 0.0 && laser->duration > 0.0)))
         return fail(c, PIC_E_ARG, "laser: finite a0 and t0, positive waist and duration");
@@ -361,7 +364,7 @@ pic_status pic::validate_push_args(Ctx *c, const pic_species *sp, const pic_part
     if (p->n == 0) return PIC_OK;  // nothing to push; the arrays may be NULL
     for (int a = 0; a < 3; ++a)
         if (!p->u[a]) return fail(c, PIC_E_ARG, "momentum array is NULL");
-    if (c->cfg.bc[0] == PIC_BC_ABSORB && !p->w)
+    if (absorbing_x(c->cfg) && !p->w)
         return fail(c, PIC_E_ARG, "absorbing x faces need per-particle weights (absorbed particles get w = 0)");
     if (c->cfg.precision == PIC_FP32_MIXED) {
         if (!p->cell || !p->tile_start) return fail(c, PIC_E_ARG, "cell or tile_start is NULL");

@@ -305,7 +305,7 @@ hipError_t launch_gpd_plain(Ctx *c, const pic_species *sp, const pic_particles *
         a.jfac[d] = sp->q * cfg.d[d] / cfg.dt;
     }
     a.w = (double *)p->w;
-    a.absorb_x = cfg.bc[0] == PIC_BC_ABSORB;
+    a.absorb_x = absorbing_x(cfg);
     a.w0 = sp->w0;
     a.chi = cfg.hbar_omega_mc2 > 0.0 ? p->chi : nullptr;
     a.chi_scale = cfg.hbar_omega_mc2;

@@ -50,8 +50,12 @@ struct Ctx {
     float *mlp_scratch = nullptr;
     size_t mlp_scratch_cap = 0;  // floats
     // absorbing x faces: face values of E_y, E_z saved by the E half step
-    // (8 x n1 x n2 reals), the injected pulse and the field clock
+    // (8 x n1 x n2 reals), for the second-order rule those of the previous
+    // half step and whether they are there yet, the injected pulse and the
+    // field clock
     void *mur_old = nullptr;
+    void *mur_hist = nullptr;
+    int mur_valid = 0;
     pic_laser laser{};
     double time = 0.0;
     // block maxima of the Gauss residual (GAUSS_PART doubles)
@@ -63,6 +67,11 @@ struct Ctx {
     std::vector<void *> retired;
     std::string err;
 };
+
+// absorbing x faces (either order of the field rule)
+inline bool absorbing_x(const pic_config &cfg) {
+    return cfg.bc[0] == PIC_BC_ABSORB || cfg.bc[0] == PIC_BC_ABSORB2;
+}
 
 // error helpers
 pic_status fail(Ctx *c, pic_status s, const std::string &msg);

@@ -393,7 +393,7 @@ hipError_t launch_qed(Ctx *c, const pic_qed_args *qa, hipStream_t s) {
     a.seed = cfg.seed;
     a.step = qa->step;
     a.method2 = qa->mode == PIC_QED_METHOD2;
-    a.absorb_x = cfg.bc[0] == PIC_BC_ABSORB;
+    a.absorb_x = absorbing_x(cfg);
     a.status = c->status;
     // photons first (their pairs are created from this step's photons only),
     // then the leptons that existed at the start of the step

@@ -4,12 +4,20 @@
 // Bandwidth-bound stencil: one thread per cell, x-fastest so that every
 // wavefront reads and writes contiguous 256-byte rows; the -1/+1 neighbours
 // along y/z come from rows the neighbouring wavefronts already pulled into L2.
-// Periodic in every axis, or along x absorbing (PIC_BC_ABSORB): the domain is
-// x in [0, (n-1) dx]; E_y, E_z on its two faces follow the first-order Mur
-// rule E_0^new = E_1^old + k (E_1^new - E_0^old), k = (h - dx)/(h + dx) over
-// each half step h, applied at x = 0 to E - E_inc of the injected pulse; the
-// E kernel saves the old face values and a second kernel applies the rule.
-// E_x, B_y, B_z half a cell beyond the far face stay 0.
+// Periodic in every axis, or along x absorbing: the domain is x in
+// [0, (n-1) dx]; E_y, E_z on its two faces follow Mur's rule over each half
+// step h (G. Mur, IEEE Trans. EMC 23, 377 (1981)), applied at x = 0 to
+// E - E_inc of the injected pulse.  With node 0 on the face, node 1 inside,
+// k = (h - dx)/(h + dx) and levels m-1, m, m+1 a half step apart:
+//   first order (PIC_BC_ABSORB):  E_0^{m+1} = E_1^m + k (E_1^{m+1} - E_0^m)
+//   second order (PIC_BC_ABSORB2, Engquist-Majda E_xt - E_tt + (E_yy+E_zz)/2 = 0):
+//     E_0^{m+1} = -E_1^{m-1} + k (E_1^{m+1} + E_0^{m-1}) + 2dx/(h+dx) (E_0^m + E_1^m)
+//                 + h^2 dx/(2(h+dx)) (D E_0^m + D E_1^m),  D the periodic
+//     second difference over y (and z) on the face planes.
+// The E kernel saves the face values on entry (level m); the second-order
+// rule also keeps the previous call's (level m-1) in the context, and its
+// first call after pic_init runs the first-order rule.  E_x, B_y, B_z half a
+// cell beyond the far face stay 0.
 #include "device_common.h"
 #include "pic_internal.h"
 
@@ -25,6 +33,7 @@ struct YeeArgs {
     R inv_d[3];   // 1/d (0 for z in 2D)
     int absorb;   // absorbing x faces
     R *old;       // [x node 0, 1, n-2, n-1][E_y, E_z][j + n1 k]: face values before the E update
+    R *hist;      // the same on entry to the previous E update (second-order rule)
 };
 
 // the pulse injected through x = 0 (pic_laser), evaluated in FP64
@@ -89,29 +98,74 @@ __global__ void __launch_bounds__(256) yee_e_kernel(YeeArgs<R> a) {
     a.E[2][c] += a.h * (cz - a.J[2][c]);
 }
 
-// the Mur rule on the two x faces after an E half step from time t; one
-// thread per (j, k) line
+// Mur's rule on the two x faces after an E half step from time t; one
+// thread per (j, k) line.  `second`: the second-order rule (a.hist holds the
+// face values of the previous call); the second-order runs then copy this
+// call's entry values into a.hist (each thread its own line, while the
+// neighbours' lines are read from a.old only).
 template <typename R>
-__global__ void __launch_bounds__(256) yee_mur_kernel(YeeArgs<R> a, LaserArgs L, double t, double km) {
+__global__ void __launch_bounds__(256) yee_mur_kernel(YeeArgs<R> a, LaserArgs L, double t, double km, int second,
+                                                      int keep) {
     const int64_t nyz = (int64_t)a.n[1] * a.n[2];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nyz) return;
-    const int j = (int)(q % a.n[1]), k = (int)(q / a.n[1]);
+    const int n1 = a.n[1], n2 = a.n[2];
+    const int j = (int)(q % n1), k = (int)(q / n1);
     const int n0 = a.n[0];
     const int64_t row = (int64_t)n0 * q;
     const double h = (double)a.h, dx = L.d[0];
+    // neighbours along y and z on the face planes (periodic)
+    const int64_t qyp = (j + 1 == n1 ? 0 : j + 1) + (int64_t)n1 * k, qym = (j == 0 ? n1 - 1 : j - 1) + (int64_t)n1 * k;
+    const int64_t qzp = j + (int64_t)n1 * (k + 1 == n2 ? 0 : k + 1), qzm = j + (int64_t)n1 * (k == 0 ? n2 - 1 : k - 1);
+    const double iy2 = 1.0 / (L.d[1] * L.d[1]), iz2 = L.dim == 3 ? 1.0 / (L.d[2] * L.d[2]) : 0.0;
+    const double c2 = h * h * dx / (2.0 * (h + dx)), c1 = 2.0 * dx / (h + dx);
 #pragma unroll
     for (int cmp = 0; cmp < 2; ++cmp) {
         const int comp = 1 + cmp;
         R *E = a.E[comp];
-        const double y = (j + (comp == 1 ? 0.5 : 0.0)) * L.d[1];
-        const double z = L.dim == 3 ? (k + (comp == 2 ? 0.5 : 0.0)) * L.d[2] : 0.0;
-        const double s0o = (double)a.old[(0 + cmp) * nyz + q] - incident(L, comp, 0.0, y, z, t);
-        const double s1o = (double)a.old[(2 + cmp) * nyz + q] - incident(L, comp, dx, y, z, t);
-        const double s1n = (double)E[row + 1] - incident(L, comp, dx, y, z, t + h);
-        E[row] = (R)(incident(L, comp, 0.0, y, z, t + h) + s1o + km * (s1n - s0o));
-        const double e2o = (double)a.old[(4 + cmp) * nyz + q], e3o = (double)a.old[(6 + cmp) * nyz + q];
-        E[row + n0 - 1] = (R)(e2o + km * ((double)E[row + n0 - 2] - e3o));
+        const double sy = comp == 1 ? 0.5 : 0.0, sz = comp == 2 ? 0.5 : 0.0;
+        const double y = (j + sy) * L.d[1];
+        const double z = L.dim == 3 ? (k + sz) * L.d[2] : 0.0;
+        // positions of the periodic neighbours (the pulse is evaluated where each value sits)
+        const double yp = ((j + 1 == n1 ? 0 : j + 1) + sy) * L.d[1], ym = ((j == 0 ? n1 - 1 : j - 1) + sy) * L.d[1];
+        const double zp = L.dim == 3 ? ((k + 1 == n2 ? 0 : k + 1) + sz) * L.d[2] : 0.0;
+        const double zm = L.dim == 3 ? ((k == 0 ? n2 - 1 : k - 1) + sz) * L.d[2] : 0.0;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            // face node f0 and its neighbour f1 (entries of a.old / a.hist); x = 0 carries the pulse
+            const int f0 = side == 0 ? 0 : 3, f1 = side == 0 ? 1 : 2;
+            const int64_t i0 = side == 0 ? 0 : n0 - 1, i1 = side == 0 ? 1 : n0 - 2;
+            const R *o0 = a.old + (2 * f0 + cmp) * nyz, *o1 = a.old + (2 * f1 + cmp) * nyz;
+            auto inc = [&](double xx, double yy, double zz, double tt) {
+                return side == 0 ? incident(L, comp, xx, yy, zz, tt) : 0.0;
+            };
+            const double u0 = (double)o0[q] - inc(0.0, y, z, t), u1 = (double)o1[q] - inc(dx, y, z, t);
+            const double u1n = (double)E[row + i1] - inc(dx, y, z, t + h);
+            double u0n;
+            if (!second) {
+                u0n = u1 + km * (u1n - u0);
+            } else {
+                const R *p0 = a.hist + (2 * f0 + cmp) * nyz, *p1 = a.hist + (2 * f1 + cmp) * nyz;
+                const double u0m = (double)p0[q] - inc(0.0, y, z, t - h);
+                const double u1m = (double)p1[q] - inc(dx, y, z, t - h);
+                double lap = 0.0;
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    const R *o = f == 0 ? o0 : o1;
+                    const double xx = f == 0 ? 0.0 : dx, uc = f == 0 ? u0 : u1;
+                    lap += ((double)o[qyp] - inc(xx, yp, z, t) + (double)o[qym] - inc(xx, ym, z, t) - 2.0 * uc) * iy2;
+                    if (L.dim == 3)
+                        lap += ((double)o[qzp] - inc(xx, y, zp, t) + (double)o[qzm] - inc(xx, y, zm, t) - 2.0 * uc) *
+                               iz2;
+                }
+                u0n = -u1m + km * (u1n + u0m) + c1 * (u0 + u1) + c2 * lap;
+            }
+            E[row + i0] = (R)(inc(0.0, y, z, t + h) + u0n);
+        }
+    }
+    if (keep) {
+#pragma unroll
+        for (int f = 0; f < 8; ++f) a.hist[f * nyz + q] = a.old[f * nyz + q];
     }
 }
 
@@ -190,8 +244,9 @@ static hipError_t yee_typed(Ctx *c, int half, const pic_fields *f, double *diag,
         a.inv_d[d] = d < c->dim ? (R)(1.0 / cfg.d[d]) : R(0);
     }
     a.h = (R)(0.5 * cfg.dt);
-    a.absorb = cfg.bc[0] == PIC_BC_ABSORB;
+    a.absorb = absorbing_x(cfg);
     a.old = (R *)c->mur_old;
+    a.hist = (R *)c->mur_hist;
     LaserArgs las{};
     las.a0 = c->laser.a0;
     las.waist = c->laser.waist;
@@ -211,8 +266,12 @@ static hipError_t yee_typed(Ctx *c, int half, const pic_fields *f, double *diag,
     auto e_step = [&]() {
         if (c->dim == 3) yee_e_kernel<R, 3><<<grid, block, 0, s>>>(a);
         else yee_e_kernel<R, 2><<<grid, block, 0, s>>>(a);
-        if (a.absorb)
-            yee_mur_kernel<R><<<(unsigned)((nyz + 255) / 256), 256, 0, s>>>(a, las, t_e, km);
+        if (a.absorb) {
+            const int keep = cfg.bc[0] == PIC_BC_ABSORB2;
+            yee_mur_kernel<R><<<(unsigned)((nyz + 255) / 256), 256, 0, s>>>(a, las, t_e, km,
+                                                                              keep && c->mur_valid, keep);
+            c->mur_valid = keep;
+        }
     };
     auto b_step = [&]() {
         if (c->dim == 3) yee_b_kernel<R, 3><<<grid, block, 0, s>>>(a);

@@ -203,7 +203,8 @@ def laser_plasma_2d(seed=644, scale=1, device="cuda", ppc=32, order=2, t_kev=1.0
     wavelength, linearly polarized Gaussian pulse a0 = 2 (waist 5 lambda,
     10-cycle sin^2 envelope) moving into an underdense electron plasma of
     density 0.01 n_c behind a 2-lambda linear ramp, 32 particles per cell,
-    quadratic weights, dt = 0.95 of the Courant limit.  The box is periodic;
+    quadratic weights, dt = 0.95 of the Courant limit.  Periodic faces unless
+    the caller sets cfg.bc_x (the benchmark absorbs at the x faces);
     the ramp spans [12, 14] lambda and the pulse starts at x_pulse (default
     [12, 22] lambda: already inside the plasma, the state in which a
     1000-step run spends almost all of its steps; 1 lambda puts it in the

@@ -33,7 +33,7 @@ def random_fields(cfg: L.Config, seed: int, amp: float = 0.4):
 
 def oracle_grid(cfg: L.Config, laser=(0.0, 0.0, 0.0, 0.0), circular: bool = False) -> O.Grid:
     return O.Grid(cfg.dim, tuple(cfg.n[: cfg.dim]), tuple(cfg.d[: cfg.dim]), cfg.dt, cfg.order,
-                  pusher=cfg.pusher, absorb_x=int(cfg.bc_x == L.PIC_BC_ABSORB), laser=tuple(laser),
+                  pusher=cfg.pusher, absorb_x=int(cfg.bc_x), laser=tuple(laser),
                   laser_circular=int(circular))
 
 

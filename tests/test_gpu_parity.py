@@ -493,15 +493,17 @@ def test_yee_half_steps_match_oracle(dim, precision):
     assert np64(diag)[2] == pytest.approx(U, rel=max(tol, 1e-12) * 10)
 
 
+@pytest.mark.parametrize("bc", [L.PIC_BC_ABSORB, L.PIC_BC_ABSORB2])
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
-def test_absorbing_faces_and_injection_match_oracle(dim, precision):
-    """Yee half steps with absorbing x faces (Mur) and a pulse entering
-    through x = 0 (circular in 3D) against the oracle, from random fields
-    and currents, over three whole steps of the library's field clock."""
-    print(f"absorbing yee dim={dim} prec={precision}", flush=True)
+def test_absorbing_faces_and_injection_match_oracle(dim, precision, bc):
+    """Yee half steps with absorbing x faces (first- or second-order Mur) and
+    a pulse entering through x = 0 (circular in 3D) against the oracle, from
+    random fields and currents, over three whole steps of the library's field
+    clock (the second-order rule takes over from the second half update)."""
+    print(f"absorbing yee dim={dim} prec={precision} bc={bc}", flush=True)
     cfg = make_cfg(dim, 2, precision)
-    cfg.bc_x = L.PIC_BC_ABSORB
+    cfg.bc_x = bc
     laser = (0.7, 1.5, 4.0, -1.0)
     g = oracle_grid(cfg, laser, circular=dim == 3)
     E, B = random_fields(cfg, seed=15)
@@ -519,15 +521,16 @@ def test_absorbing_faces_and_injection_match_oracle(dim, precision):
     Bo = [b.numpy().copy() for b in B]
     Jo = [j.numpy().copy() for j in J]
     tol = 1e-13 if precision == L.PIC_FP64_PLAIN else 2e-6
+    mur = O.MurHistory(g)
     for step in range(3):
         for half in (1, 2):
             L.pic_yee_step(ctx, half, f)
             if half == 1:
-                O.half_e(g, Eo, Bo, Jo, t)
+                O.half_e(g, Eo, Bo, Jo, t, mur)
                 O.half_b(g, Eo, Bo)
             else:
                 O.half_b(g, Eo, Bo)
-                O.half_e(g, Eo, Bo, Jo, t + 0.5 * cfg.dt)
+                O.half_e(g, Eo, Bo, Jo, t + 0.5 * cfg.dt, mur)
                 t += cfg.dt
         torch.cuda.synchronize()
         for a in range(3):
@@ -544,16 +547,17 @@ def test_injection_needs_absorbing_faces():
         L.pic_set_laser(ctx, 1.0, 2.0, 10.0, 0.0)
 
 
+@pytest.mark.parametrize("bc", [L.PIC_BC_ABSORB, L.PIC_BC_ABSORB2])
 @pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
-def test_absorbing_run_with_injection_matches_oracle(precision):
+def test_absorbing_run_with_injection_matches_oracle(precision, bc):
     """Ten whole steps of a warm plasma slab (away from both faces) with
     absorbing x faces and a pulse entering through x = 0, against the
     oracle's steps."""
-    print(f"absorbing run prec={precision}", flush=True)
+    print(f"absorbing run prec={precision} bc={bc}", flush=True)
     from paper_2104_00642_amd.sim import Simulation
     from paper_2104_00642_amd.workloads import Workload
     cfg = make_cfg(2, 2, precision)
-    cfg.bc_x = L.PIC_BC_ABSORB
+    cfg.bc_x = bc
     laser = (0.5, 2.0, 6.0, 0.0)
     cells = [torch.randint(14, 34, (3000,), generator=torch.Generator().manual_seed(3)),
              torch.randint(0, cfg.n[1], (3000,), generator=torch.Generator().manual_seed(4))]
@@ -579,17 +583,18 @@ def test_absorbing_run_with_injection_matches_oracle(precision):
     assert sim.check()[0] == L.PIC_OK
 
 
+@pytest.mark.parametrize("bc", [L.PIC_BC_ABSORB, L.PIC_BC_ABSORB2])
 @pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
-def test_particles_leave_through_absorbing_faces(precision):
+def test_particles_leave_through_absorbing_faces(precision, bc):
     """Two warm slabs drifting out through the x faces (u_x = +-0.6) for ten
     steps with absorbing faces: the same particles are absorbed (weight 0)
     as in the oracle, and the fields match it, so nothing was gathered from
     or deposited across the periodic seam."""
-    print(f"absorbing particles prec={precision}", flush=True)
+    print(f"absorbing particles prec={precision} bc={bc}", flush=True)
     from paper_2104_00642_amd.sim import Simulation
     from paper_2104_00642_amd.workloads import Workload, concat
     cfg = make_cfg(2, 2, precision)
-    cfg.bc_x = L.PIC_BC_ABSORB
+    cfg.bc_x = bc
     parts = []
     for seed, (lo, hi), ux in ((21, (38, 47), 0.6), (22, (0, 6), -0.6)):
         g1 = torch.Generator().manual_seed(seed)

@@ -78,8 +78,8 @@ def energy_history(sim, steps, every=50):
 @pytest.mark.parametrize("order", [2, 4])
 def test_energy_drift_1000_steps_matches_oracle(order):
     """1000-step relative energy drift D = (U_1000 - U_0)/U_0 of the FP32 and
-    FP64 GPU paths against the oracle's: within 1% of the oracle's drift, or
-    within twice the seed-to-seed spread of D when that is larger."""
+    FP64 GPU paths against the oracle's: within 1% of the oracle's drift.
+    The seed-to-seed spread of D is printed beside it, for scale."""
     steps = 1000
     wl = heating_workload(7, order=order)
     st = oracle_state(wl, from_fp32=True)
@@ -105,12 +105,12 @@ def test_energy_drift_1000_steps_matches_oracle(order):
         h = energy_history(sim, steps)
         spread.append((h[-1] - u0) / u0)
     sigma = float(np.std(spread))
-    tol = max(0.01 * abs(D_orc), 2 * sigma)
+    tol = 0.01 * abs(D_orc)
     rel32 = abs(drifts[L.PIC_FP32_MIXED] - D_orc) / abs(D_orc)
     print(f"order {order} drift: oracle {D_orc:.3e}, GPU FP64 {drifts[L.PIC_FP64_PLAIN]:.3e}, GPU FP32 "
-          f"{drifts[L.PIC_FP32_MIXED]:.3e} ({rel32:.2%} of the oracle's); seed spread sigma {sigma:.2e}; "
-          f"tolerance {tol:.2e} ({'1% rule' if tol == 0.01 * abs(D_orc) else '2 sigma rule'})")
-    assert abs(drifts[L.PIC_FP64_PLAIN] - D_orc) <= 0.01 * abs(D_orc) + 1e-12
+          f"{drifts[L.PIC_FP32_MIXED]:.3e} ({rel32:.2%} of the oracle's); tolerance {tol:.2e}; "
+          f"seed-to-seed spread sigma {sigma:.2e}")
+    assert abs(drifts[L.PIC_FP64_PLAIN] - D_orc) <= tol + 1e-12
     assert abs(drifts[L.PIC_FP32_MIXED] - D_orc) <= tol
 
 

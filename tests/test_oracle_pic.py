@@ -570,6 +570,106 @@ def test_absorbing_faces_let_a_pulse_leave():
     assert left[1] < 0.01
 
 
+def mur_reflection(theta_deg, absorb, pol="z", dim=2, period=64, dt=0.6, x0=180.0, nx=360):
+    """Reflection coefficient of the x = 0 face for a plane wave packet
+    (wave vector at theta from the -x normal, one period of the transverse
+    wavenumber across the periodic box, or lambda = 40 cells at normal
+    incidence; Gaussian envelope of 2.5 lambda along x).  The reflected wave
+    is the difference between the run in the box and the same run in a box
+    that extends far beyond x = 0, taken once the packet has turned back
+    (energy ratio, square-rooted).  pol: the component tangential to the face
+    (z: E_z, y: E_y).  In 3D the plane of incidence is x-z, E along y, two
+    cells along y."""
+    th = math.radians(theta_deg)
+    kt = 0.0 if theta_deg == 0 else 2 * math.pi / period
+    k = 2 * math.pi / 40.0 if theta_deg == 0 else kt / math.sin(th)
+    kx = k * math.cos(th)
+    lw = 2.5 * 2 * math.pi / k
+    n = (-math.cos(th), math.sin(th))  # direction of travel: (x, transverse)
+    nt = period if dim == 2 else 2
+
+    def fields(nxg, shift):
+        shape = (1, nt, nxg) if dim == 2 else (period, nt, nxg)
+        E = [np.zeros(shape) for _ in range(3)]
+        B = [np.zeros(shape) for _ in range(3)]
+        ii = np.arange(nxg)[None, None, :].astype(float)
+        tt = (np.arange(nt)[None, :, None] if dim == 2 else np.arange(period)[:, None, None]).astype(float)
+
+        def wave(sx, st):
+            x = ii + sx + shift
+            return np.exp(-((x - x0) / lw) ** 2) * np.cos(-kx * x + kt * (tt + st))
+        if dim == 3:  # E_y, transverse axis z: B = n x E
+            E[1][...] = wave(0, 0)
+            B[0][...] = -n[1] * wave(0, 0.5)
+            B[2][...] = n[0] * wave(0.5, 0)
+        elif pol == "z":  # E_z, transverse axis y
+            E[2][...] = wave(0, 0)
+            B[0][...] = n[1] * wave(0, 0.5)
+            B[1][...] = -n[0] * wave(0.5, 0)
+        else:  # E in the x-y plane, perpendicular to n
+            E[0][...] = n[1] * wave(0.5, 0)
+            E[1][...] = -n[0] * wave(0, 0.5)
+            B[2][...] = -wave(0.5, 0.5)
+        return E, B
+
+    steps = int((x0 + 130.0) / math.cos(th) / dt)
+    runs = []
+    far = nx + 200
+    for nxg, shift in ((nx, 0.0), (2 * nx + 200, -float(far))):
+        cells = (nxg, nt) if dim == 2 else (nxg, nt, period)
+        g = O.Grid(dim, cells, (1.0,) * dim, dt, 1, absorb_x=absorb)
+        E, B = fields(nxg, shift)
+        J = [np.zeros_like(E[0]) for _ in range(3)]
+        if shift == 0.0:
+            e_in = sum((f ** 2).sum() for f in E + B)
+        mur = O.MurHistory(g)
+        t = 0.0
+        for _ in range(steps):
+            O.half_e(g, E, B, J, t, mur)
+            O.half_b(g, E, B)
+            O.half_b(g, E, B)
+            O.half_e(g, E, B, J, t + 0.5 * dt, mur)
+            t += dt
+        runs.append(E + B)
+    diff = sum(((a - b[..., far:far + nx]) ** 2).sum() for a, b in zip(*runs))
+    return math.sqrt(diff / e_in)
+
+
+def mur_r1(theta_deg):
+    """Reflection coefficient of the first-order one-way wave equation for a
+    plane wave at theta: (1 - cos)/(1 + cos); the second-order
+    (Engquist-Majda) condition gives its square."""
+    c = math.cos(math.radians(theta_deg))
+    return (1 - c) / (1 + c)
+
+
+@pytest.mark.parametrize("theta", [0, 45, 60])
+def test_first_order_absorber_reflects_as_its_one_way_equation(theta):
+    """First-order Mur faces reflect a plane wave at theta by (1-cos)/(1+cos)
+    up to the grid's dispersion at 40 cells per wavelength (a few 1e-3)."""
+    r = mur_reflection(theta, 1)
+    print(f"first order, theta {theta}: R {r:.4e} (closed form {mur_r1(theta):.4e})")
+    assert abs(r - mur_r1(theta)) <= 0.05 * mur_r1(theta) + 5e-3
+
+
+@pytest.mark.parametrize("theta,pol,dim", [(0, "z", 2), (30, "z", 2), (45, "z", 2), (60, "z", 2), (45, "y", 2),
+                                           (60, "y", 2), (45, "y", 3)])
+def test_second_order_absorber_reflects_the_square(theta, pol, dim):
+    """Second-order Mur faces (the transverse second differences included)
+    reflect a plane wave at theta by ((1-cos)/(1+cos))^2, up to the same
+    dispersion floor, for E tangential in (z) and perpendicular to (y) the
+    plane of incidence, and in 3D with the plane of incidence x-z (the z
+    differences).  Without the transverse term the rule reflects like the
+    first-order one; with its sign flipped, more."""
+    r = mur_reflection(theta, 2, pol=pol, dim=dim)
+    r2 = mur_r1(theta) ** 2
+    print(f"second order, theta {theta}, E_{pol}, {dim}D: R {r:.4e} (closed form {r2:.4e}, first order "
+          f"{mur_r1(theta):.4e})")
+    assert abs(r - r2) <= 0.12 * r2 + 5e-3
+    if theta >= 45:
+        assert r < 0.7 * mur_r1(theta)
+
+
 def test_injected_pulse_energy_speed_and_amplitude():
     """A plane pulse (a0 = 1, sin^2 field envelope of 6 periods) injected
     through x = 0 carries a0^2/2 * 3/8 * tau * L_y of field energy, moves at

@@ -412,6 +412,32 @@ pic_status pic_deposit_rho(void *ctx, const pic_species *sp, const pic_particles
 pic_status pic_gauss_residual(void *ctx, const pic_fields *fields, const double *rho, double *residual,
                               double *diag, void *stream);
 
+/*
+ * Self-fields of a relativistic bi-Gaussian bunch (Sec. III(c): Poisson's
+ * equation in the bunch's rest frame, then the Lorentz transformation to the
+ * laboratory frame).  The bunch of particles of charge `charge` has the lab
+ * density charge-carrier density n_b exp(-sum_a (x_a - center_a)^2 /
+ * (2 sigma_a^2)) and moves along +x with Lorentz factor gamma.  In its rest
+ * frame it is gamma sigma_x long; its field there is the free-space solution
+ * of lap phi' = -rho' (div E = rho, the units of Eq. 8), and in the lab
+ *   E_x = E'_x,  E_perp = gamma E'_perp,  B = beta x^ x E,
+ * evaluated at x' = gamma (x - center_x) on every node at each component's
+ * Yee position.  In a 2D box the bunch is uniform along z (sigma[2] and
+ * center[2] unused; E_z and B_y stay as they are).  The fields are ADDED to
+ * fields->E and fields->B (J untouched), in the context's precision, the
+ * arithmetic in FP64.  Free space: no periodic images and no faces; the box
+ * should hold the bunch well inside it.  Errors: PIC_E_ARG (NULL arguments,
+ * gamma < 1, sigmas not > 0, non-finite values).
+ */
+typedef struct {
+    double charge;      /* charge of the bunch's particles (units of e, with sign) */
+    double density;     /* peak lab density n_b of those particles (units of n_r)  */
+    double center[3];   /* centre (absolute position)                             */
+    double sigma[3];    /* lab rms sizes                                          */
+    double gamma;       /* Lorentz factor of the motion along +x (>= 1)           */
+} pic_beam;
+pic_status pic_beam_fields(void *ctx, const pic_beam *beam, const pic_fields *fields, void *stream);
+
 /* Synchronize `stream`, return the device status word in *flags (nullable)
  * and the number of straggler particles since the last check in
  * *stragglers (nullable), then clear both.  Returns PIC_E_CAPACITY if

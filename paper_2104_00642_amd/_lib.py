@@ -36,7 +36,7 @@ PIC_MLP_STATE_FLOATS = 4 * PIC_MLP_NPARAM + 1
 EXPORTED = ["pic_init", "pic_destroy", "pic_last_error", "pic_get_layout", "pic_gather_push_deposit",
             "pic_yee_step", "pic_sort", "pic_check", "pic_qed_step", "pic_mlp_forward", "pic_mlp_grad",
             "pic_mlp_train", "pic_qed_training_data", "pic_qed_table_lookup", "pic_set_laser", "pic_reserve",
-            "pic_deposit_rho", "pic_gauss_residual", "pic_gather_push_deposit_noalloc"]
+            "pic_deposit_rho", "pic_gauss_residual", "pic_beam_fields", "pic_gather_push_deposit_noalloc"]
 
 
 class PicError(RuntimeError):
@@ -56,6 +56,11 @@ class pic_config(C.Structure):
 class pic_laser(C.Structure):
     _fields_ = [("a0", C.c_double), ("waist", C.c_double), ("duration", C.c_double), ("t0", C.c_double),
                 ("circular", C.c_int32)]
+
+
+class pic_beam(C.Structure):
+    _fields_ = [("charge", C.c_double), ("density", C.c_double), ("center", C.c_double * 3),
+                ("sigma", C.c_double * 3), ("gamma", C.c_double)]
 
 
 class pic_species(C.Structure):
@@ -139,6 +144,8 @@ def lib():
         L.pic_gauss_residual.argtypes = [C.c_void_p, C.POINTER(pic_fields), C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_void_p]
         L.pic_gauss_residual.restype = C.c_int
+        L.pic_beam_fields.argtypes = [C.c_void_p, C.POINTER(pic_beam), C.POINTER(pic_fields), C.c_void_p]
+        L.pic_beam_fields.restype = C.c_int
         _lib = L
     return _lib
 
@@ -431,3 +438,31 @@ def pic_gauss_residual(ctx: Context, f: Fields, rho: torch.Tensor, residual: Opt
     fc = f.c()
     _check(lib().pic_gauss_residual(C.c_void_p(ctx.handle), C.byref(fc), _ptr(rho), _ptr(residual), _ptr(diag),
                                     _stream(stream)), C.c_void_p(ctx.handle))
+
+
+@dataclass
+class Beam:
+    """A bi-Gaussian bunch moving along +x: particle charge, peak lab
+    density, centre, lab rms sizes and Lorentz factor (pic_beam)."""
+    charge: float
+    density: float
+    center: tuple
+    sigma: tuple
+    gamma: float
+
+    def c(self) -> pic_beam:
+        b = pic_beam()
+        b.charge = float(self.charge)
+        b.density = float(self.density)
+        for a in range(3):
+            b.center[a] = float(self.center[a]) if a < len(self.center) else 0.0
+            b.sigma[a] = float(self.sigma[a]) if a < len(self.sigma) else 1.0
+        b.gamma = float(self.gamma)
+        return b
+
+
+def pic_beam_fields(ctx: Context, beam: Beam, f: Fields, stream=None):
+    bc = beam.c()
+    fc = f.c()
+    _check(lib().pic_beam_fields(C.c_void_p(ctx.handle), C.byref(bc), C.byref(fc), _stream(stream)),
+           C.c_void_p(ctx.handle))

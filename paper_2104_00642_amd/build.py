@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpic.so")
 SOURCES = ["abi.hip", "gpd_plain.hip", "gpd_tiled.hip", "yee.hip", "sort.hip", "qed_tables.hip", "qed.hip",
-           "mlp.hip", "diag.hip",
+           "mlp.hip", "diag.hip", "beam.hip",
            "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

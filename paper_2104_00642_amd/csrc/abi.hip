@@ -449,6 +449,24 @@ extern "C" pic_status pic_gauss_residual(void *ctx, const pic_fields *fields, co
     return PIC_OK;
 }
 
+extern "C" pic_status pic_beam_fields(void *ctx, const pic_beam *beam, const pic_fields *fields, void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (!beam || !fields) return fail(c, PIC_E_ARG, "beam or fields is NULL");
+    // written: E_x, E_y, B_z, and in 3D E_z, B_y
+    if (!fields->E[0] || !fields->E[1] || !fields->B[2] || (c->dim == 3 && (!fields->E[2] || !fields->B[1])))
+        return fail(c, PIC_E_ARG, "an E or B plane is NULL");
+    if (!(beam->gamma >= 1.0) || !isfinite(beam->gamma) || !isfinite(beam->charge) || !isfinite(beam->density))
+        return fail(c, PIC_E_ARG, "beam: gamma >= 1, finite charge and density");
+    for (int a = 0; a < c->dim; ++a)
+        if (!finite_pos(beam->sigma[a]) || !isfinite(beam->center[a]))
+            return fail(c, PIC_E_ARG, "beam: sigmas > 0 and a finite centre");
+    hipSetDevice(c->device);
+    hipError_t e = launch_beam_fields(c, beam, fields, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pic_beam_fields");
+    return PIC_OK;
+}
+
 extern "C" pic_status pic_sort(void *ctx, const pic_particles *src, const pic_particles *dst,
                                void *stream) {
     Ctx *c = (Ctx *)ctx;

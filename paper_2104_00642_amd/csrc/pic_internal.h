@@ -73,6 +73,8 @@ inline bool absorbing_x(const pic_config &cfg) {
     return cfg.bc[0] == PIC_BC_ABSORB || cfg.bc[0] == PIC_BC_ABSORB2;
 }
 
+hipError_t launch_beam_fields(Ctx *c, const pic_beam *beam, const pic_fields *f, hipStream_t s);
+
 // error helpers
 pic_status fail(Ctx *c, pic_status s, const std::string &msg);
 pic_status ensure_partials(Ctx *c, size_t n);

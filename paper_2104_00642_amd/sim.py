@@ -65,7 +65,10 @@ class Simulation:
                 parts.append(to_fp32(raw, bits, with_chi=with_chi))
             else:
                 parts.append(to_fp64(raw, cfg, from_fp32=from_fp32, with_chi=with_chi))
-        return Simulation(cfg, sps, parts, fields, sort_every=sort_every, device=device)
+        sim = Simulation(cfg, sps, parts, fields, sort_every=sort_every, device=device)
+        for b in wl.beams:  # self-fields of relativistic bunches (Sec. III(c))
+            L.pic_beam_fields(sim.ctx, b, sim.fields)
+        return sim
 
     def sort(self):
         for k, p in enumerate(self.particles):

@@ -12,12 +12,12 @@ with w_r = w_p the plasma density is 1.
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 from typing import Callable, Optional
 
 import torch
 
-from ._lib import PIC_FP32_MIXED, PIC_FP64_PLAIN, Config, Fields, Particles
+from ._lib import PIC_FP32_MIXED, PIC_FP64_PLAIN, Beam, Config, Fields, Particles
 
 LAMBDA = 2.0 * math.pi  # laser wavelength in c / w_L
 
@@ -136,6 +136,7 @@ class Workload:
     E0: Optional[list] = None   # initial E planes (float64) or None = zero
     B0: Optional[list] = None
     steps: int = 0
+    beams: list = field(default_factory=list)  # Beam bunches whose self-fields are added at start
 
 
 def langmuir_2d(seed=643, n=(64, 64), ppc=16, device="cpu", order=1, precision=PIC_FP64_PLAIN) -> Workload:
@@ -270,12 +271,11 @@ def beam_wakefield_3d(seed=648, scale=1, device="cuda", ppc=8, beam_ppc=4, order
     each, and a 1-GeV drive electron beam (gamma 1957) with a bi-Gaussian
     density of peak nb = 4 n_p and k_p sigma_x = k_p sigma_r = 0.5, sampled by
     4 particles per cell within 4 sigma of its centre (x = x_beam lambda_p,
-    on the axis).  The beam's self-fields are those of the ultrarelativistic
-    limit of the rest-frame Poisson solution boosted to the lab: with the
-    line charge Lambda(x) = q nb exp(-(x-x_b)^2/(2 sigma^2)) 2 pi sigma^2 (div E
-    = rho in these units), E_r = Lambda (1 - exp(-r^2/(2 sigma^2))) / (2 pi r),
-    E_x = 0 (order 1/gamma^2), B = beta x^ x E.  Periodic box; `scale`
-    divides the cell counts."""
+    on the axis).  The beam's self-fields (the rest-frame Poisson solution
+    boosted to the lab, Sec. III(c)) are not in E0/B0: the workload lists the
+    bunch in `beams` and the simulation adds its fields with pic_beam_fields.
+    Periodic faces unless the caller sets cfg.bc_x; `scale` divides the cell
+    counts."""
     lam_p = 2.0 * math.pi
     n = (512 // scale, 192 // scale, 192 // scale)
     d = (4 * lam_p / 512, 2 * lam_p / 192, 2 * lam_p / 192)
@@ -308,32 +308,10 @@ def beam_wakefield_3d(seed=648, scale=1, device="cuda", ppc=8, beam_ppc=4, order
          torch.zeros(N, device=device, dtype=torch.float64)]
     beam = RawParticles([bx.to(torch.int64), by.to(torch.int64), bz.to(torch.int64)], off, u,
                         (dens / beam_ppc).to(torch.float64))
-    # self-fields at each component's Yee location
-    beta = ub / gamma_b
-    shape = (n[2], n[1], n[0])
-    k_i = torch.arange(n[2], device=device, dtype=torch.float64).view(-1, 1, 1)
-    j_i = torch.arange(n[1], device=device, dtype=torch.float64).view(1, -1, 1)
-    i_i = torch.arange(n[0], device=device, dtype=torch.float64).view(1, 1, -1)
-
-    def e_perp(sx, sy, sz):
-        x = (i_i + sx) * d[0]
-        y = (j_i + sy) * d[1] - yc
-        z = (k_i + sz) * d[2] - zc
-        r2_ = y ** 2 + z ** 2
-        lam_x = -1.0 * nb * torch.exp(-((x - xb) ** 2) / (2 * sigma ** 2)) * 2 * math.pi * sigma ** 2
-        er_over_r = lam_x * (1 - torch.exp(-r2_ / (2 * sigma ** 2))) / (2 * math.pi * torch.clamp(r2_, min=1e-30))
-        return (er_over_r * y).expand(shape), (er_over_r * z).expand(shape)
-
-    zero = lambda: torch.zeros(shape, device=device, dtype=torch.float64)  # noqa: E731
-    Ey, _ = e_perp(0, 0.5, 0)
-    _, Ez = e_perp(0, 0, 0.5)
-    _, Ez_at_by = e_perp(0.5, 0, 0.5)
-    Ey_at_bz, _ = e_perp(0.5, 0.5, 0)
-    E = [zero(), Ey.contiguous(), Ez.contiguous()]
-    B = [zero(), (-beta * Ez_at_by).contiguous(), (beta * Ey_at_bz).contiguous()]
+    bunch = Beam(charge=-1.0, density=nb, center=(xb, yc, zc), sigma=(sigma, sigma, sigma), gamma=gamma_b)
     shape_name = {1: "linear", 2: "quadratic", 4: "quartic"}[order]
     return Workload(f"beam_wakefield_3d_{n[0]}x{n[1]}x{n[2]}_ppc{ppc}x2+{beam_ppc}_{shape_name}", cfg,
-                    [(-1.0, 1.0, el), (1.0, 1836.0, ion), (-1.0, 1.0, beam)], E, B, steps=0)
+                    [(-1.0, 1.0, el), (1.0, 1836.0, ion), (-1.0, 1.0, beam)], steps=0, beams=[bunch])
 
 
 QED_HBAR_OMEGA = 2.4263e-6  # hbar w_L / (m_e c^2) at lambda = 1 um

@@ -531,7 +531,15 @@ def legs(args, torch, L, Simulation, log):
     wl = laser_plasma_3d(device="cuda", tile=(8, 8, 4), order=args.order)
     wl.cfg.pusher = L.PIC_PUSH_VAY if args.pusher == "vay" else L.PIC_PUSH_BORIS
     wl.cfg.bc_x = bc_codes()[args.bc]
-    r3 = {"workload": wl.name, "tile": [8, 8, 4], "drift": 1}
+    # tile shape by timing: the shapes whose window fits the LDS that came out
+    # ahead in a sweep (8x8x4 with drift 1 and 8x8x8 with drift 0; 8x8x4 drift
+    # 0, 16x8x4 drift 0 and 4x4x4 drift 1 ran 5-70% slower)
+    from paper_2104_00642_amd.sim import autotune_tiles
+    log("leg: laser3d tile autotune")
+    best, tune = autotune_tiles(wl, [((8, 8, 4), 1), ((8, 8, 8), 0)], steps=8)
+    a.tile, a.drift = ",".join(str(t) for t in best[0]), best[1]
+    r3 = {"workload": wl.name, "tile": list(best[0]), "drift": best[1],
+          "tile_autotune_ms_per_step": tune}
     for prec, name, steps, warm in ((L.PIC_FP32_MIXED, "fp32", 16, 2), (L.PIC_FP64_PLAIN, "fp64_plain", 3, 1)):
         a.steps, a.warmup = steps, warm
         sim, n, secs, gpd_ms, status, extra = run_path(a, wl, prec, torch, L, Simulation)
@@ -552,6 +560,28 @@ def legs(args, torch, L, Simulation, log):
     r3["speedup_fp32_vs_fp64_plain"] = r3["fp32"]["particle_steps_per_s"] / r3["fp64_plain"]["particle_steps_per_s"]
     res["laser3d"] = r3
     del wl
+    torch.cuda.empty_cache()
+    # 512 x 192 x 192 beam-driven wakefield (8 + 8 per cell plasma, 4 per cell
+    # beam, bunch fields from the rest-frame solution), FP32
+    from paper_2104_00642_amd.workloads import beam_wakefield_3d
+    log("leg: wake3d")
+    a = argparse.Namespace(**vars(args))
+    a.tile, a.drift, a.sort_every, a.steps, a.warmup = "8,8,4", 0, 8, 16, 2
+    wl = beam_wakefield_3d(device="cuda", tile=(8, 8, 4), order=args.order)
+    wl.cfg.pusher = L.PIC_PUSH_VAY if args.pusher == "vay" else L.PIC_PUSH_BORIS
+    wl.cfg.bc_x = bc_codes()[args.bc]
+    sim, n, secs, gpd_ms, status, extra = run_path(a, wl, L.PIC_FP32_MIXED, torch, L, Simulation)
+    extra.pop("sample", None)
+    bpp = alg_bytes_per_particle(3, 4, 16)
+    gpd = extra["gpd_ms_stats"]["mean"]
+    res["wake3d"] = {"workload": wl.name, "tile": [8, 8, 4], "drift": 0, "particles": n, "steps": a.steps,
+                     "particle_steps_per_s": n * a.steps / secs, "ms_per_step": secs / a.steps * 1e3,
+                     "push_particle_steps_per_s": n / (gpd * 1e-3),
+                     "push_roofline_frac": n * bpp / (gpd * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "alg_bytes_per_particle": bpp, "push_ms": extra["gpd_ms_stats"],
+                     "step_ms": extra["step_ms_stats"], "sort_ms": extra.get("sort_ms"),
+                     "stragglers_per_step": extra["stragglers_per_step"]}
+    del sim, wl
     torch.cuda.empty_cache()
     # the surrogate, trained once on the library's tables
     ctx = L.pic_init(L.Config(dim=2, n=(64, 64), d=(0.1, 0.1), dt=0.05, hbar_omega_mc2=2.4263e-6))

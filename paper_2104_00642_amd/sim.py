@@ -126,3 +126,40 @@ class Simulation:
             shift += self.bits[a]
             out.append((c.to(torch.float64) + p.off[a].to(torch.float64)) * self.cfg.d[a])
         return out
+
+
+def autotune_tiles(wl: Workload, candidates, steps: int = 8, warmup: int = 1, device="cuda"):
+    """Tile shape and drift allowance of the FP32 push, chosen by timing.
+
+    For each (tile, drift) of `candidates` whose LDS window fits, builds the
+    workload's simulation, sorts once and times `steps` whole steps (the
+    sort at their start included, so shapes that shed more stragglers pay
+    for the sorts they need).  Returns ((tile, drift) of the fastest,
+    {label: ms per step or the reason it was skipped})."""
+    timings = {}
+    best, best_ms = None, float("inf")
+    for tile, drift in candidates:
+        label = "x".join(str(t) for t in tile) + f" drift {drift}"
+        try:
+            sim = Simulation.from_workload(wl, precision=L.PIC_FP32_MIXED, device=device, sort_every=steps,
+                                           tile=tuple(tile), drift=drift)
+        except L.PicError as e:  # window beyond the LDS, tile not dividing the grid, ...
+            timings[label] = str(e)
+            continue
+        for _ in range(warmup):
+            sim.step()
+        sim.sorted_at = -1  # the timed window starts with a sort
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            sim.step()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        timings[label] = ms
+        if ms < best_ms:
+            best, best_ms = (tuple(tile), drift), ms
+        del sim
+        torch.cuda.empty_cache()
+    return best, timings

@@ -974,27 +974,47 @@ __global__ void __launch_bounds__(256) gpd_bin_count_kernel(TiledArgs a) {
     }
 }
 
-// bin_start = exclusive scan of bin_count (one workgroup, in order)
+// bin_start = exclusive scan of bin_count (one workgroup, in order): chunks
+// of 1024 x 8 counts, each thread taking 8 consecutive ones (independent
+// loads, one memory latency per chunk), wavefront prefix sums by shuffles,
+// then the 16 wavefront totals
 __global__ void __launch_bounds__(1024) gpd_bin_scan_kernel(const uint32_t *count, int ntiles, int64_t *bstart) {
-    __shared__ int64_t part[1024];
-    const int per = (ntiles + 1023) / 1024;
-    const int lo = threadIdx.x * per, hi = min(lo + per, ntiles);
-    int64_t s = 0;
-    for (int i = lo; i < hi; ++i) s += count[i];
-    part[threadIdx.x] = s;
+    constexpr int PER = 8;
+    __shared__ int64_t wsum[16];
+    __shared__ int64_t carry_s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    for (int base = 0; base < ntiles; base += 1024 * PER) {
+        const int lo = base + (int)threadIdx.x * PER;
+        uint32_t v[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) v[k] = lo + k < ntiles ? count[lo + k] : 0u;
+        int64_t s = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) s += v[k];
+        // inclusive prefix of the thread totals within the wavefront
+        int64_t x = s;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
         __syncthreads();
-        part[threadIdx.x] += add;
+        int64_t before = carry_s;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        int64_t run = before + x - s;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (lo + k < ntiles) bstart[lo + k] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) carry_s = run;  // the last thread's running sum is the chunk's end
         __syncthreads();
     }
-    int64_t run = part[threadIdx.x] - s;
-    for (int i = lo; i < hi; ++i) {
-        bstart[i] = run;
-        run += count[i];
-    }
-    if (threadIdx.x == 1023) bstart[ntiles] = part[1023];
+    if (threadIdx.x == 0) bstart[ntiles] = carry_s;
 }
 
 template <int DIM>

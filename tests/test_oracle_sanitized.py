@@ -1,7 +1,8 @@
 """The oracle's C sources built with AddressSanitizer and
 UndefinedBehaviorSanitizer, exercised in a child process on the CPU: every
 entry point the tests use, on small 2D and 3D grids (every shape order,
-both pushers, absorbing faces with injection, the sort, rho and div, the QED
+both pushers, absorbing faces of both orders with injection, the sort, rho
+and div, the QED
 integrals and Philox).  Any out-of-bounds access, leak-free use after free
 or undefined behaviour aborts the child."""
 import os
@@ -21,7 +22,7 @@ rng = np.random.default_rng(3)
 for dim, n, d in ((2, (16, 12), (0.3, 0.25)), (3, (8, 6, 6), (0.3, 0.25, 0.2))):
     for order in (1, 2, 4):
         for pusher in (0, 1):
-            for absorb in (0, 1):
+            for absorb in (0, 1, 2):
                 g = O.Grid(dim, n, d, 0.1, order, pusher=pusher, absorb_x=absorb,
                            laser=(1.0, 1.0, 3.0, 0.0) if absorb else (0.0, 0.0, 0.0, 0.0))
                 st = O.State.zeros(g)

@@ -88,9 +88,10 @@ def parse():
     ap.add_argument("--workload", choices=["laser2d", "laser3d", "wake3d"], default="laser2d",
                     help="laser2d: 4096x2048 2D3V (the metric's workload); laser3d: 512x256x256 3D3V; "
                          "wake3d: 512x192x192 3D3V beam-driven wakefield")
-    ap.add_argument("--tile", type=str, default=None, help="tile in cells (default 16,16 / 8,8,4)")
+    ap.add_argument("--tile", type=str, default=None,
+                    help="tile in cells (default 16,16; 8,8,8 for laser3d, 8,8,4 for wake3d and quartic 3D)")
     ap.add_argument("--drift", type=int, default=None,
-                    help="drift allowance (default 2 in 2D; 1 for laser3d, 0 for wake3d and quartic 3D)")
+                    help="drift allowance (default 2 in 2D, 0 in 3D; 1 for laser3d with an 8,8,4 tile)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, copy a 1 GiB float32 buffer (HBM counter calibration)")
     ap.add_argument("--bc", choices=["absorb2", "absorb", "periodic"], default="absorb2",
@@ -532,11 +533,11 @@ def legs(args, torch, L, Simulation, log):
     wl.cfg.pusher = L.PIC_PUSH_VAY if args.pusher == "vay" else L.PIC_PUSH_BORIS
     wl.cfg.bc_x = bc_codes()[args.bc]
     # tile shape by timing: the shapes whose window fits the LDS that came out
-    # ahead in a sweep (8x8x4 with drift 1 and 8x8x8 with drift 0; 8x8x4 drift
+    # ahead in a sweep (8x8x8 with drift 0 and 8x8x4 with drift 1; 8x8x4 drift
     # 0, 16x8x4 drift 0 and 4x4x4 drift 1 ran 5-70% slower)
     from paper_2104_00642_amd.sim import autotune_tiles
     log("leg: laser3d tile autotune")
-    best, tune = autotune_tiles(wl, [((8, 8, 4), 1), ((8, 8, 8), 0)], steps=8)
+    best, tune = autotune_tiles(wl, [((8, 8, 8), 0), ((8, 8, 4), 1)], steps=8)
     a.tile, a.drift = ",".join(str(t) for t in best[0]), best[1]
     r3 = {"workload": wl.name, "tile": list(best[0]), "drift": best[1],
           "tile_autotune_ms_per_step": tune}
@@ -570,11 +571,14 @@ def legs(args, torch, L, Simulation, log):
     wl = beam_wakefield_3d(device="cuda", tile=(8, 8, 4), order=args.order)
     wl.cfg.pusher = L.PIC_PUSH_VAY if args.pusher == "vay" else L.PIC_PUSH_BORIS
     wl.cfg.bc_x = bc_codes()[args.bc]
+    best_w, tune_w = autotune_tiles(wl, [((8, 8, 4), 0), ((8, 8, 8), 0)], steps=8)
+    a.tile, a.drift = ",".join(str(t) for t in best_w[0]), best_w[1]
     sim, n, secs, gpd_ms, status, extra = run_path(a, wl, L.PIC_FP32_MIXED, torch, L, Simulation)
     extra.pop("sample", None)
     bpp = alg_bytes_per_particle(3, 4, 16)
     gpd = extra["gpd_ms_stats"]["mean"]
-    res["wake3d"] = {"workload": wl.name, "tile": [8, 8, 4], "drift": 0, "particles": n, "steps": a.steps,
+    res["wake3d"] = {"workload": wl.name, "tile": list(best_w[0]), "drift": best_w[1],
+                     "tile_autotune_ms_per_step": tune_w, "particles": n, "steps": a.steps,
                      "particle_steps_per_s": n * a.steps / secs, "ms_per_step": secs / a.steps * 1e3,
                      "push_particle_steps_per_s": n / (gpd * 1e-3),
                      "push_roofline_frac": n * bpp / (gpd * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -703,12 +707,13 @@ def main():
     log("generating workload")
     dim = 2 if args.workload == "laser2d" else 3
     if args.tile is None:
-        args.tile = "16,16" if dim == 2 else "8,8,4"
+        # 3D laser: 8x8x8 with drift 0 (13^3 window, compiled) timed fastest;
+        # the wakefield's cold plasma keeps 8x8x4 with drift 0 (two
+        # workgroups per CU)
+        args.tile = "16,16" if dim == 2 else ("8,8,8" if args.workload == "laser3d" and args.order == 2 else "8,8,4")
     if args.drift is None:
-        # 3D: the cold wakefield plasma barely leaves its tiles between sorts,
-        # so the smaller window of drift 0 (two workgroups per CU) pays; the
-        # a0 = 5 laser case needs drift 1
-        args.drift = 2 if dim == 2 else (0 if args.order == 4 or args.workload == "wake3d" else 1)
+        args.drift = 2 if dim == 2 else (1 if args.workload == "laser3d" and args.tile == "8,8,4" and args.order == 2
+                                         else 0)
     if args.sort_every is None:
         args.sort_every = 24 if dim == 2 else 8
     if args.steps is None:

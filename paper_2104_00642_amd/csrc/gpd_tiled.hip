@@ -1097,6 +1097,8 @@ __global__ void __launch_bounds__(256) gpd_global_kernel(TiledArgs a) {
 constexpr int W2X = 16 + 2 * 2 + 5, W2X4 = 16 + 2 * 2 + 7, W3X = 8 + 2 * 1 + 5, W3Z = 4 + 2 * 1 + 5;
 constexpr int W2S = 16 + 2 * 1 + 5;
 constexpr int W3X0 = 8 + 5, W3Z0 = 4 + 5;
+// 8 x 8 x 8 tiles with drift 0 (quadratic): 13 x 13 x 13
+constexpr int W3C0 = 8 + 5;
 
 // One push of a species:
 //   prep (zero bin counters) -> sorted pass (stragglers listed) -> bin count
@@ -1142,6 +1144,10 @@ static void launch_tiled(const TiledArgs &a, size_t lds, hipStream_t s) {
             return;
         }
         if constexpr (ORDER == 2) {
+            if (a.win[0] == W3C0 && a.win[1] == W3C0 && a.win[2] == W3C0) {
+                launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, W3C0, W3C0, W3C0>(a, lds, s);
+                return;
+            }
             if (a.win[0] == W3X0 && a.win[1] == W3X0 && a.win[2] == W3Z0) {
                 launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, W3X0, W3X0, W3Z0>(a, lds, s);
                 return;
@@ -1267,6 +1273,7 @@ hipError_t set_tiled_lds_limit(size_t bytes) {
     if (e == hipSuccess) e = set_lds<3, 1, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(bytes);
     if (e == hipSuccess) e = set_lds<3, 2, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(bytes);
     if (e == hipSuccess) e = set_lds<3, 2, PIC_TILED_THREADS_3D, W3X0, W3X0, W3Z0>(bytes);
+    if (e == hipSuccess) e = set_lds<3, 2, PIC_TILED_THREADS_3D, W3C0, W3C0, W3C0>(bytes);
     return e;
 }
 

@@ -142,20 +142,20 @@ def test_sort_then_fp32_push_matches_oracle(dim, order, pusher):
     assert np64(diag)[:2] == pytest.approx(diag_o, rel=1e-5)
 
 
-@pytest.mark.parametrize("dim,order,drift", [(2, 1, 2), (2, 2, 2), (2, 4, 2), (2, 1, 1), (2, 2, 1), (3, 2, 1),
-                                             (3, 2, 0), (3, 4, 0)])
-def test_default_tiles_fp32_push_matches_oracle(dim, order, drift):
+@pytest.mark.parametrize("dim,order,drift,tz", [(2, 1, 2, 0), (2, 2, 2, 0), (2, 4, 2, 0), (2, 1, 1, 0), (2, 2, 1, 0),
+                                                (3, 2, 1, 4), (3, 2, 0, 4), (3, 4, 0, 4), (3, 2, 0, 8)])
+def test_default_tiles_fp32_push_matches_oracle(dim, order, drift, tz):
     """The default tiles (16x16 with drift 2 in 2D; 8x8x4 with drift 1 or 0
-    in 3D) run the kernels compiled for their window shape; sort and push
-    against the oracle."""
-    print(f"default tiles dim={dim} order={order} drift={drift}", flush=True)
+    and 8x8x8 with drift 0 in 3D) run the kernels compiled for their window
+    shape; sort and push against the oracle."""
+    print(f"default tiles dim={dim} order={order} drift={drift} tile z {tz}", flush=True)
     if dim == 2:
         cfg = L.Config(dim=2, n=(48, 32), d=(0.3, 0.25), dt=courant_dt((0.3, 0.25), 0.9), order=order,
                        precision=L.PIC_FP32_MIXED, tile=(16, 16), drift=drift)
     else:
         d = (0.3, 0.25, 0.2)
-        cfg = L.Config(dim=3, n=(16, 16, 12), d=d, dt=courant_dt(d, 0.9), order=order,
-                       precision=L.PIC_FP32_MIXED, tile=(8, 8, 4), drift=drift)
+        cfg = L.Config(dim=3, n=(16, 16, 12 if tz == 4 else 16), d=d, dt=courant_dt(d, 0.9), order=order,
+                       precision=L.PIC_FP32_MIXED, tile=(8, 8, tz), drift=drift)
     raw = random_raw(cfg, 4001, seed=60 + 10 * dim + order)
     E, B = random_fields(cfg, seed=70 + dim + order)
     E = [e.to(torch.float32).to(torch.float64) for e in E]

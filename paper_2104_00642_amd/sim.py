@@ -162,4 +162,6 @@ def autotune_tiles(wl: Workload, candidates, steps: int = 8, warmup: int = 1, de
             best, best_ms = (tuple(tile), drift), ms
         del sim
         torch.cuda.empty_cache()
+    if best is None:
+        raise L.PicError(L.PIC_E_UNSUPPORTED, f"no candidate tile fits: {timings}")
     return best, timings

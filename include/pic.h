@@ -141,7 +141,8 @@ typedef struct {
     void *w;                /* nullable; float* or double*                             */
     float *chi;             /* nullable; chi at step n+1/2 written by the push (FP32)  */
     int64_t *tile_start;    /* FP32 path: ntiles+1 offsets of the tile-sorted order,
-                               written by pic_sort and read by the push               */
+                               written by pic_sort (dst) and read by the push and by
+                               the next pic_sort of these arrays (src, as a hint)     */
     /* QED (pic_qed_step; NULL/0 otherwise) */
     double *tau;            /* optical depth accumulated since the last event         */
     float *tau_thr;         /* threshold -ln r of the next event                      */
@@ -257,6 +258,14 @@ pic_status pic_yee_step(void *ctx, int32_t half, const pic_fields *fields, doubl
  * unchanged).  dst arrays must hold src->n elements and may not alias src.
  * Every non-NULL src array (cell, off, u, w, chi, tau, tau_thr, id) is
  * permuted into the matching dst array.  Bit-exact and deterministic.
+ * src->tile_start (nullable, ntiles+1 entries, not dst->tile_start) is read
+ * as a hint: the tile offsets of src's own order, as the sort that produced
+ * src wrote them.  Particles still inside the segment of their tile keep
+ * their relative order without being sorted again, so only the particles
+ * that changed tiles since (and those appended after tile_start[ntiles])
+ * pass through the key sort.  Any hint gives the same result: one that is
+ * not non-decreasing within [0, src->n] is ignored on the device, and a
+ * stale one only costs time.
  */
 pic_status pic_sort(void *ctx, const pic_particles *src, const pic_particles *dst, void *stream);
 

@@ -79,6 +79,10 @@ pic_status ensure_sort_scratch(Ctx *c, int64_t n) {
     const int64_t items = 256 * 16;
     const int64_t nblocks = (n + items - 1) / items;
     const size_t hist_need = (size_t)(256 * nblocks + (256 * nblocks + items - 1) / items + 16);
+    if (!c->inc && hipMalloc(&c->inc, inc_scratch_words(c->ntiles) * 4) != hipSuccess) {
+        c->inc = nullptr;
+        return fail(c, PIC_E_NOMEM, "cannot allocate sort scratch");
+    }
     if ((size_t)n <= c->sort_cap && hist_need <= c->hist_cap) return PIC_OK;
     for (int b = 0; b < 2; ++b) {
         retire(c, c->keys[b]);
@@ -299,6 +303,7 @@ extern "C" void pic_destroy(void *ctx) {
     }
     hipFree(c->hist);
     hipFree(c->final_perm);
+    hipFree(c->inc);
     hipFree(c->qed.dev);
     hipFree(c->mlp_scratch);
     hipFree(c->mur_old);

@@ -45,6 +45,9 @@ struct Ctx {
     uint32_t *final_perm = nullptr;
     size_t sort_cap = 0;         // elements
     size_t hist_cap = 0;         // entries
+    // re-binning from the source's tile offsets: hint check, stayer and
+    // mover counts per tile (inc_scratch_words(ntiles) words)
+    uint32_t *inc = nullptr;
     // QED tables (built at init when hbar_omega_mc2 > 0) and network outputs
     QedTables qed;
     float *mlp_scratch = nullptr;
@@ -124,6 +127,7 @@ hipError_t launch_gauss(Ctx *c, const pic_fields *f, const double *rho, double *
                         hipStream_t s);
 constexpr int GAUSS_PART = 1024;
 size_t sort_lds_bytes(int cells_per_tile);
+size_t inc_scratch_words(int64_t ntiles);
 hipError_t launch_finalize(const double *partials, int64_t nblocks, int nval, double *diag,
                            int diag_offset, double scale, hipStream_t s);
 

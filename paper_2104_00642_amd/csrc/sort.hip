@@ -14,6 +14,8 @@
 //      the r-th particles of every populated cell, cells ascending, gathering
 //      every particle array straight into the destination.
 // All integer work: the permutation is deterministic and bit-exact.
+#include <algorithm>
+
 #include "device_common.h"
 #include "pic_internal.h"
 
@@ -57,11 +59,7 @@ __device__ __forceinline__ void decode_cell(int32_t c, const SortGeom &g, int &i
 // above y that are not a z inside the grid: any in 2D, a negative cell) gets
 // the key ntiles: such particles follow the last tile in source order, where
 // the push flags them and leaves them unchanged.
-__global__ void __launch_bounds__(256) sort_keys_kernel(const int32_t *cell, int64_t n, SortGeom g,
-                                                        uint32_t *keys) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int32_t c = cell[p];
+__device__ __forceinline__ uint32_t tile_key(int32_t c, const SortGeom &g) {
     int ix, iy, iz;
     decode_cell(c, g, ix, iy, iz);
     const uint32_t above = (uint32_t)(c >> (g.bx + g.by));
@@ -69,22 +67,26 @@ __global__ void __launch_bounds__(256) sort_keys_kernel(const int32_t *cell, int
                     (unsigned)iy < (unsigned)(g.tile[1] * g.ntile_axis[1]) &&
                     above < (uint32_t)(g.dim == 3 ? g.tile[2] * g.ntile_axis[2] : 1);
     const int tx = ix / g.tile[0], ty = iy / g.tile[1], tz = g.dim == 3 ? (int)above / g.tile[2] : 0;
-    keys[p] = ok ? (uint32_t)(tx + g.ntile_axis[0] * (ty + g.ntile_axis[1] * tz))
-                 : (uint32_t)(g.ntile_axis[0] * g.ntile_axis[1] * g.ntile_axis[2]);
+    return ok ? (uint32_t)(tx + g.ntile_axis[0] * (ty + g.ntile_axis[1] * tz))
+              : (uint32_t)(g.ntile_axis[0] * g.ntile_axis[1] * g.ntile_axis[2]);
 }
 
-__global__ void __launch_bounds__(SORT_THREADS) radix_hist_kernel(const uint32_t *keys, int64_t n,
-                                                                  int shift, uint32_t *hist,
-                                                                  int64_t nblocks) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t start = (int64_t)blockIdx.x * SORT_ITEMS;
+__global__ void __launch_bounds__(256) sort_keys_kernel(const int32_t *cell, int64_t n, SortGeom g,
+                                                        uint32_t *keys) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    keys[p] = tile_key(cell[p], g);
+}
+
+// Digit histogram of keys [lo, hi) into the LDS counters h (one call per
+// block; lo and hi are uniform over the block).
+__device__ __forceinline__ void radix_hist_range(const uint32_t *keys, int64_t lo, int64_t hi, int shift,
+                                                 uint32_t *h) {
     const int lane = threadIdx.x & 63;
-    for (int r = 0; r < SORT_ROUNDS; ++r) {
-        const int64_t i = start + r * SORT_THREADS + threadIdx.x;
-        const uint32_t d = i < n ? (keys[i] >> shift) & 255u : 0u;
-        bool pending = i < n;
+    for (int64_t b0 = lo; b0 < hi; b0 += SORT_THREADS) {
+        const int64_t i = b0 + threadIdx.x;
+        const uint32_t d = i < hi ? (keys[i] >> shift) & 255u : 0u;
+        bool pending = i < hi;
         // The keys arrive nearly sorted (particles rarely change tiles between
         // sorts), so a wavefront holds few distinct digits, and LDS atomics on
         // one address serialize: lanes with equal digits add once per group.
@@ -100,8 +102,37 @@ __global__ void __launch_bounds__(SORT_THREADS) radix_hist_kernel(const uint32_t
         }
         if (pending) atomicAdd(&h[d], 1u);
     }
+}
+
+// Share of block b of a grid over a count held on the device: consecutive
+// ranges, a multiple of SORT_THREADS long.
+__device__ __forceinline__ void device_share(const uint32_t *count, int64_t &lo, int64_t &hi) {
+    const int64_t n = *count;
+    int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    per = (per + SORT_THREADS - 1) / SORT_THREADS * SORT_THREADS;
+    lo = min((int64_t)blockIdx.x * per, n);
+    hi = min(lo + per, n);
+}
+
+// KIN_DEV = false: block b takes keys [b SORT_ITEMS, (b+1) SORT_ITEMS) of n;
+// true: its share of the count *count.  hist is digit-major: hist[d G + b].
+template <bool KIN_DEV>
+__global__ void __launch_bounds__(SORT_THREADS) radix_hist_kernel(const uint32_t *keys, int64_t n,
+                                                                  const uint32_t *count, int shift,
+                                                                  uint32_t *hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    int64_t lo, hi;
+    if (KIN_DEV) {
+        device_share(count, lo, hi);
+    } else {
+        lo = (int64_t)blockIdx.x * SORT_ITEMS;
+        hi = min(lo + SORT_ITEMS, n);
+    }
+    radix_hist_range(keys, lo, hi, shift, h);
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
 // ---- device-wide exclusive scan of uint32 (chunks of SORT_ITEMS) --------
@@ -180,19 +211,26 @@ static hipError_t exclusive_scan(Ctx *c, uint32_t *a, int64_t n, uint32_t *sums,
 
 // ---- stable scatter ------------------------------------------------------
 
+template <bool KIN_DEV>
 __global__ void __launch_bounds__(SORT_THREADS) radix_scatter_kernel(
-    const uint32_t *kin, const uint32_t *vin, int64_t n, int shift, const uint32_t *offs,
-    int64_t nblocks, uint32_t *kout, uint32_t *vout) {
+    const uint32_t *kin, const uint32_t *vin, int64_t n, const uint32_t *count, int shift,
+    const uint32_t *offs, uint32_t *kout, uint32_t *vout) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[SORT_THREADS / 64][256];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
-    base[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+    base[t] = offs[(int64_t)t * gridDim.x + blockIdx.x];
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const int64_t start = (int64_t)blockIdx.x * SORT_ITEMS;
-    for (int r = 0; r < SORT_ROUNDS; ++r) {
-        const int64_t i = start + r * SORT_THREADS + t;
-        const bool valid = i < n;
+    int64_t lo, hi;
+    if (KIN_DEV) {
+        device_share(count, lo, hi);
+    } else {
+        lo = (int64_t)blockIdx.x * SORT_ITEMS;
+        hi = min(lo + SORT_ITEMS, n);
+    }
+    for (int64_t b0 = lo; b0 < hi; b0 += SORT_THREADS) {
+        const int64_t i = b0 + t;
+        const bool valid = i < hi;
         const uint32_t key = valid ? kin[i] : 0u;
         const uint32_t d = (key >> shift) & 255u;
 #pragma unroll
@@ -273,7 +311,7 @@ __global__ void __launch_bounds__(256) tail_copy_kernel(const uint32_t *vals, co
 // phases A and D issue the loads of SORT_AHEAD rounds before using them
 constexpr int SORT_AHEAD = 4;
 // entries per thread that phase D keeps in registers for a one-stage tile
-constexpr int PERM_REG = 8;
+constexpr int PERM_REG = 16;
 
 // Layers of phase C handled per pass: R layers x (cells/64) group counters
 // stay within 16 KB of LDS.
@@ -576,7 +614,313 @@ __global__ void __launch_bounds__(ORDER_THREADS, 8) tile_order_kernel(const uint
     }
 }
 
+// ---- re-binning from the source's own tile offsets ----------------------
+//
+// Between sorts few particles change tiles.  When src->tile_start holds a
+// partition of the source into tile segments (the offsets written by the
+// sort that produced the source), a particle of segment t whose key is t
+// "stays"; every other particle (another key, off the grid, outside every
+// segment) "moves".  In the sorted order tile t holds, by ascending source
+// index, the movers into t from before segment t, the stayers of t, then the
+// movers into t from after it.  So the positions follow from the stayer
+// counts and the movers sorted by (key, source index): one stable radix sort
+// of the movers instead of one of every key, with the same result.  A hint
+// that is not a partition (decreasing, negative, beyond n) makes every
+// particle a mover: the result is still the same.
+
+// blocks that take the particles before the first segment, and those after
+// the last one
+constexpr int INC_LOOSE = 256;
+
+struct IncRange {
+    int64_t lo, hi;
+    int64_t seg;  // tile of the segment, -1 outside the segments
+};
+
+// Work unit u: INC_LOOSE shares of [0, h[0]), the ntiles segments, INC_LOOSE
+// shares of [h[ntiles], n).  Without a valid hint the first run is [0, n).
+__device__ __forceinline__ IncRange inc_range(int64_t u, const int64_t *h, int64_t ntiles, int64_t n, bool ok) {
+    IncRange r;
+    if (u >= INC_LOOSE && u < INC_LOOSE + ntiles) {
+        const int64_t t = u - INC_LOOSE;
+        r.lo = ok ? h[t] : 0;
+        r.hi = ok ? h[t + 1] : 0;
+        r.seg = t;
+        return r;
+    }
+    const bool head = u < INC_LOOSE;
+    const int64_t a = head ? 0 : (ok ? h[ntiles] : n);
+    const int64_t b = head ? (ok ? h[0] : n) : n;
+    const int64_t k = head ? u : u - INC_LOOSE - ntiles;
+    int64_t per = (b - a + INC_LOOSE - 1) / INC_LOOSE;
+    per = (per + SORT_THREADS - 1) / SORT_THREADS * SORT_THREADS;
+    r.lo = min(a + k * per, b);
+    r.hi = min(r.lo + per, b);
+    r.seg = -1;
+    return r;
+}
+
+// rank of a flagged thread among the flagged threads of the block (thread
+// order) and their number; wt: SORT_THREADS/64 words of LDS
+__device__ __forceinline__ uint32_t block_flag_rank(bool f, uint32_t *wt, uint32_t &total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t b = __ballot(f);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    if (lane == 0) wt[wave] = (uint32_t)__popcll(b);
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < SORT_THREADS / 64; ++w) {
+        const uint32_t c = wt[w];
+        before += w < wave ? c : 0u;
+        total += c;
+    }
+    __syncthreads();
+    return before + (uint32_t)__popcll(b & lt);
+}
+
+// rounds of SORT_THREADS particles whose cells are loaded together
+constexpr int INC_AHEAD = 8;
+
+// flag = 1 when h is non-decreasing with h[0] >= 0 and h[ntiles] <= n
+__global__ void __launch_bounds__(1024) inc_check_kernel(const int64_t *h, int64_t ntiles, int64_t n,
+                                                         uint32_t *flag) {
+    int bad = 0;
+    for (int64_t i = threadIdx.x; i < ntiles; i += blockDim.x) bad |= h[i] > h[i + 1];
+    if (threadIdx.x == 0) bad |= h[0] < 0 || h[ntiles] > n;
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) *flag = bad ? 0u : 1u;
+}
+
+// Per unit: stayers (into stay[t]) and movers, the movers' keys and sources
+// written in source order at the start of the unit's own range of tk / ti.
+__global__ void __launch_bounds__(SORT_THREADS) inc_count_kernel(const int32_t *cell, SortGeom g, const int64_t *h,
+                                                                 int64_t ntiles, int64_t n, const uint32_t *flag,
+                                                                 uint32_t *stay, uint32_t *mcount, uint32_t *tk,
+                                                                 uint32_t *ti) {
+    __shared__ uint32_t wt[SORT_THREADS / 64];
+    const IncRange r = inc_range(blockIdx.x, h, ntiles, n, *flag != 0u);
+    uint32_t carry = 0, nstay = 0;
+    for (int64_t b0 = r.lo; b0 < r.hi; b0 += INC_AHEAD * SORT_THREADS) {
+        int32_t ce[INC_AHEAD];
+#pragma unroll
+        for (int q = 0; q < INC_AHEAD; ++q) {
+            const int64_t p = b0 + q * SORT_THREADS + threadIdx.x;
+            ce[q] = p < r.hi ? cell[p] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < INC_AHEAD; ++q) {
+            const int64_t p0 = b0 + q * SORT_THREADS;
+            if (p0 >= r.hi) break;  // uniform over the block
+            const int64_t p = p0 + threadIdx.x;
+            const bool valid = p < r.hi;
+            const uint32_t key = tile_key(ce[q], g);
+            const bool mv = valid && (int64_t)key != r.seg;
+            uint32_t tot;
+            const uint32_t rk = block_flag_rank(mv, wt, tot);
+            if (mv) {
+                tk[r.lo + carry + rk] = key;
+                ti[r.lo + carry + rk] = (uint32_t)p;
+            }
+            carry += tot;
+            nstay += (uint32_t)min((int64_t)SORT_THREADS, r.hi - p0) - tot;
+        }
+    }
+    if (threadIdx.x == 0) {
+        mcount[blockIdx.x] = carry;
+        if (r.seg >= 0) stay[r.seg] = nstay;
+        if (blockIdx.x == 0) mcount[gridDim.x] = 0u;  // the scan's last entry: the mover total
+    }
+}
+
+// movers of each unit to their place in the list (moff: exclusive scan of
+// the units' counts)
+__global__ void __launch_bounds__(SORT_THREADS) inc_compact_kernel(const int64_t *h, int64_t ntiles, int64_t n,
+                                                                   const uint32_t *flag, const uint32_t *moff,
+                                                                   const uint32_t *tk, const uint32_t *ti,
+                                                                   uint32_t *lk, uint32_t *li) {
+    const IncRange r = inc_range(blockIdx.x, h, ntiles, n, *flag != 0u);
+    const uint32_t o = moff[blockIdx.x], m = moff[blockIdx.x + 1] - o;
+    for (uint32_t j = threadIdx.x; j < m; j += SORT_THREADS) {
+        lk[o + j] = tk[r.lo + j];
+        li[o + j] = ti[r.lo + j];
+    }
+}
+
+// mstart[t] = first sorted mover with key >= t, t in [0, ntiles + 1]
+__global__ void __launch_bounds__(256) inc_bounds_kernel(const uint32_t *mk, const uint32_t *count, int64_t ntiles,
+                                                         uint32_t *mstart) {
+    const int64_t m = *count;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t tprev = i == 0 ? -1 : min((int64_t)mk[i - 1], ntiles);
+        const int64_t tcur = i == m ? ntiles + 1 : min((int64_t)mk[i], ntiles);
+        for (int64_t t = tprev + 1; t <= tcur; ++t) mstart[t] = (uint32_t)i;
+    }
+}
+
+// tile_start of the result: exclusive scan of stayers + movers per tile (one
+// workgroup, chunks of 1024 x 8 tiles, in order)
+__global__ void __launch_bounds__(1024) inc_tiles_kernel(const uint32_t *stay, const uint32_t *mstart,
+                                                         int64_t ntiles, int64_t *ts) {
+    constexpr int PER = 8;
+    __shared__ int64_t wsum[16];
+    __shared__ int64_t carry_s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < ntiles; base += 1024 * PER) {
+        const int64_t lo = base + (int64_t)threadIdx.x * PER;
+        int64_t v[PER];
+        int64_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t t = lo + k;
+            v[k] = t < ntiles ? (int64_t)stay[t] + (int64_t)(mstart[t + 1] - mstart[t]) : 0;
+            sum += v[k];
+        }
+        int64_t x = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        int64_t before = carry_s, total = carry_s;
+        for (int w = 0; w < 16; ++w) {
+            before += w < wave ? wsum[w] : 0;
+            total += wsum[w];
+        }
+        int64_t run = before + x - sum;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (lo + k < ntiles) ts[lo + k] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ts[ntiles] = carry_s;
+}
+
+// Stayers of segment t to ts[t] + (movers into t from before the segment) +
+// their rank among the segment's stayers.  mi: sorted movers' sources.
+__global__ void __launch_bounds__(SORT_THREADS) inc_stayers_kernel(const int32_t *cell, SortGeom g, const int64_t *h,
+                                                                   int64_t ntiles, const uint32_t *flag,
+                                                                   const uint32_t *stay, const uint32_t *mstart,
+                                                                   const uint32_t *mi, const int64_t *ts,
+                                                                   uint32_t *vals) {
+    __shared__ uint32_t wt[SORT_THREADS / 64];
+    __shared__ int64_t out_s;
+    const int64_t t = blockIdx.x;
+    if (*flag == 0u || stay[t] == 0u) return;
+    const int64_t lo = h[t], hi = h[t + 1];
+    if (threadIdx.x == 0) {
+        // movers into t are sorted by source: those before the segment first
+        uint32_t a = mstart[t], b = mstart[t + 1];
+        while (a < b) {
+            const uint32_t mid = a + (b - a) / 2;
+            if ((int64_t)mi[mid] < lo) a = mid + 1;
+            else b = mid;
+        }
+        out_s = ts[t] + (int64_t)(a - mstart[t]);
+    }
+    __syncthreads();
+    const int64_t out = out_s;
+    uint32_t carry = 0;
+    for (int64_t b0 = lo; b0 < hi; b0 += INC_AHEAD * SORT_THREADS) {
+        int32_t ce[INC_AHEAD];
+#pragma unroll
+        for (int q = 0; q < INC_AHEAD; ++q) {
+            const int64_t p = b0 + q * SORT_THREADS + threadIdx.x;
+            ce[q] = p < hi ? cell[p] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < INC_AHEAD; ++q) {
+            const int64_t p0 = b0 + q * SORT_THREADS;
+            if (p0 >= hi) break;  // uniform over the block
+            const int64_t p = p0 + threadIdx.x;
+            const bool st = p < hi && (int64_t)tile_key(ce[q], g) == t;
+            uint32_t tot;
+            const uint32_t rk = block_flag_rank(st, wt, tot);
+            if (st) vals[out + carry + rk] = (uint32_t)p;
+            carry += tot;
+        }
+    }
+}
+
+// Movers to ts[t] + their rank among the movers into t, after the stayers
+// when they come from after the segment.
+__global__ void __launch_bounds__(256) inc_movers_kernel(const uint32_t *mk, const uint32_t *mi, const uint32_t *count,
+                                                         const uint32_t *mstart, const int64_t *ts,
+                                                         const uint32_t *stay, const int64_t *h, int64_t ntiles,
+                                                         const uint32_t *flag, uint32_t *vals) {
+    const int64_t m = *count;
+    const bool ok = *flag != 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = min((int64_t)mk[i], ntiles);
+        const uint32_t src = mi[i];
+        int64_t pos = ts[t] + (i - (int64_t)mstart[t]);
+        if (ok && t < ntiles && (int64_t)src >= h[t]) pos += stay[t];
+        vals[pos] = src;
+    }
+}
+
 pic_status ensure_sort_scratch(Ctx *c, int64_t n);
+
+// words of Ctx::inc for a grid of ntiles tiles
+size_t inc_scratch_words(int64_t ntiles) {
+    const int64_t units = 2 * INC_LOOSE + ntiles;
+    return (size_t)(16 + ntiles + (units + 1) + ((units + 1 + SORT_ITEMS - 1) / SORT_ITEMS + 16) + (ntiles + 2) + 16);
+}
+
+// Source order (vals[cur]) and dst->tile_start from the source's tile offsets
+// (see inc_range): stayer counts, the movers listed in source order and
+// sorted by key, then both placed.
+static hipError_t rebin_from_hint(Ctx *c, const pic_particles *src, const pic_particles *dst, const SortGeom &g,
+                                  hipStream_t s, int &cur) {
+    const int64_t n = src->n, nt = c->ntiles;
+    const int64_t units = 2 * INC_LOOSE + nt;
+    uint32_t *flag = c->inc;
+    uint32_t *stay = c->inc + 16;                                  // nt
+    uint32_t *mcount = stay + nt;                                  // units + 1, then their exclusive scan
+    uint32_t *msums = mcount + units + 1;
+    uint32_t *mstart = msums + (units + 1 + SORT_ITEMS - 1) / SORT_ITEMS + 16;  // nt + 2
+    const int64_t *h = src->tile_start;
+    inc_check_kernel<<<1, 1024, 0, s>>>(h, nt, n, flag);
+    inc_count_kernel<<<(unsigned)units, SORT_THREADS, 0, s>>>(src->cell, g, h, nt, n, flag, stay, mcount,
+                                                              c->keys[0], c->vals[0]);
+    hipError_t e = exclusive_scan(c, mcount, units + 1, msums, s);
+    if (e != hipSuccess) return e;
+    inc_compact_kernel<<<(unsigned)units, SORT_THREADS, 0, s>>>(h, nt, n, flag, mcount, c->keys[0], c->vals[0],
+                                                                c->keys[1], c->vals[1]);
+    const uint32_t *m_dev = mcount + units;  // number of movers
+    int bits = 0;
+    while ((1ll << bits) <= nt) ++bits;
+    const int passes = bits == 0 ? 1 : (bits + 7) / 8;
+    const int64_t G = std::min<int64_t>((n + SORT_ITEMS - 1) / SORT_ITEMS, 4096);
+    int in = 1;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = 8 * pass;
+        radix_hist_kernel<true><<<(unsigned)G, SORT_THREADS, 0, s>>>(c->keys[in], 0, m_dev, shift, c->hist);
+        e = exclusive_scan(c, c->hist, 256 * G, c->hist + 256 * G, s);
+        if (e != hipSuccess) return e;
+        radix_scatter_kernel<true><<<(unsigned)G, SORT_THREADS, 0, s>>>(c->keys[in], c->vals[in], 0, m_dev, shift,
+                                                                        c->hist, c->keys[in ^ 1], c->vals[in ^ 1]);
+        in ^= 1;
+    }
+    const unsigned gb = (unsigned)std::min<int64_t>((n + 1 + 255) / 256, 2048);
+    inc_bounds_kernel<<<gb, 256, 0, s>>>(c->keys[in], m_dev, nt, mstart);
+    inc_tiles_kernel<<<1, 1024, 0, s>>>(stay, mstart, nt, dst->tile_start);
+    inc_stayers_kernel<<<(unsigned)nt, SORT_THREADS, 0, s>>>(src->cell, g, h, nt, flag, stay, mstart, c->vals[in],
+                                                             dst->tile_start, c->vals[in ^ 1]);
+    inc_movers_kernel<<<gb, 256, 0, s>>>(c->keys[in], c->vals[in], m_dev, mstart, dst->tile_start, stay, h, nt, flag,
+                                        c->vals[in ^ 1]);
+    cur = in ^ 1;
+    return hipGetLastError();
+}
 
 hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *dst, hipStream_t s) {
     const int64_t n = src->n;
@@ -609,26 +953,31 @@ hipError_t launch_sort(Ctx *c, const pic_particles *src, const pic_particles *ds
         tile_bounds_kernel<<<1, 256, 0, s>>>(c->keys[0], 0, c->ntiles, dst->tile_start);
         return hipGetLastError();
     }
-    sort_keys_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src->cell, n, g, c->keys[0]);
-    // keys run up to ntiles (the off-grid key)
-    int bits = 0;
-    while ((1ll << bits) <= c->ntiles) ++bits;
-    const int passes = bits == 0 ? 1 : (bits + 7) / 8;
-    const int64_t nblocks = (n + SORT_ITEMS - 1) / SORT_ITEMS;
     int cur = 0;
-    for (int pass = 0; pass < passes; ++pass) {
-        const int shift = 8 * pass;
-        radix_hist_kernel<<<(unsigned)nblocks, SORT_THREADS, 0, s>>>(c->keys[cur], n, shift, c->hist,
-                                                                     nblocks);
-        hipError_t e = exclusive_scan(c, c->hist, 256 * nblocks, c->hist + 256 * nblocks, s);
+    if (src->tile_start && src->tile_start != dst->tile_start) {
+        hipError_t e = rebin_from_hint(c, src, dst, g, s, cur);
         if (e != hipSuccess) return e;
-        radix_scatter_kernel<<<(unsigned)nblocks, SORT_THREADS, 0, s>>>(
-            c->keys[cur], pass == 0 ? nullptr : c->vals[cur], n, shift, c->hist, nblocks,
-            c->keys[cur ^ 1], c->vals[cur ^ 1]);
-        cur ^= 1;
+    } else {
+        sort_keys_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src->cell, n, g, c->keys[0]);
+        // keys run up to ntiles (the off-grid key)
+        int bits = 0;
+        while ((1ll << bits) <= c->ntiles) ++bits;
+        const int passes = bits == 0 ? 1 : (bits + 7) / 8;
+        const int64_t nblocks = (n + SORT_ITEMS - 1) / SORT_ITEMS;
+        for (int pass = 0; pass < passes; ++pass) {
+            const int shift = 8 * pass;
+            radix_hist_kernel<false><<<(unsigned)nblocks, SORT_THREADS, 0, s>>>(c->keys[cur], n, nullptr, shift,
+                                                                                c->hist);
+            hipError_t e = exclusive_scan(c, c->hist, 256 * nblocks, c->hist + 256 * nblocks, s);
+            if (e != hipSuccess) return e;
+            radix_scatter_kernel<false><<<(unsigned)nblocks, SORT_THREADS, 0, s>>>(
+                c->keys[cur], pass == 0 ? nullptr : c->vals[cur], n, nullptr, shift, c->hist, c->keys[cur ^ 1],
+                c->vals[cur ^ 1]);
+            cur ^= 1;
+        }
+        tile_bounds_kernel<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(c->keys[cur], n, c->ntiles,
+                                                                           dst->tile_start);
     }
-    tile_bounds_kernel<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(c->keys[cur], n, c->ntiles,
-                                                                       dst->tile_start);
     PermArgs pa{};
     pa.cell_in = src->cell;
     int nc = 0;

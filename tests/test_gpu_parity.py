@@ -705,6 +705,76 @@ def test_sort_3d_and_2d_many_particles(dim):
     assert np.array_equal(dst.w.cpu().numpy(), p.w.cpu().numpy()[perm])
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sort_from_tile_offsets_hint(dim):
+    """pic_sort with src->tile_start from the sort that produced src: after
+    a sort, 12% of the particles change cells (some to other tiles, some off
+    the grid) and 701 are appended; the result equals the oracle's order
+    bit for bit whether the hint is that sort's offsets, absent, not
+    non-decreasing, shifted so that particles precede the first segment, or
+    the destination's own offsets."""
+    print(f"sort with tile-offset hint dim={dim}", flush=True)
+    cfg = make_cfg(dim, 2, L.PIC_FP32_MIXED)
+    n0, nx = 60013, 701
+    raw = random_raw(cfg, n0, seed=17 + dim)
+    ctx = L.pic_init(cfg)
+    bits, tile, ntiles = L.pic_get_layout(ctx)
+    p = to_fp32(raw, bits, with_chi=True)
+    p.chi = torch.arange(n0, dtype=torch.float32)
+    src = L.Particles(n0, [t.to(DEV) for t in p.u], cell=p.cell.to(DEV), off=[t.to(DEV) for t in p.off],
+                      w=p.w.to(DEV), chi=p.chi.to(DEV))
+    first = src.empty_like()
+    first.tile_start = torch.empty(ntiles + 1, dtype=torch.int64, device=DEV)
+    L.pic_sort(ctx, src, first)  # no hint: every key sorted
+    torch.cuda.synchronize()
+    perm0, start0 = O.sort(oracle_grid(cfg), tile[:dim], [c.numpy() for c in raw.cell])
+    assert np.array_equal(first.tile_start.cpu().numpy(), start0)
+    # move some particles, send some off the grid, append others
+    rng = np.random.default_rng(5 + dim)
+    cells = [c.numpy()[perm0].astype(np.int64) for c in raw.cell]
+    moved = rng.random(n0) < 0.12
+    for a in range(dim):
+        step = rng.integers(-3, 4, n0)
+        cells[a] = np.where(moved, (cells[a] + step) % cfg.n[a], cells[a])
+    extra = random_raw(cfg, nx, seed=71 + dim)
+    cells = [np.concatenate([c, e.numpy()]) for c, e in zip(cells, extra.cell)]
+    n = n0 + nx
+    packed = to_fp32(type(raw)([torch.from_numpy(c) for c in cells], [torch.zeros(n, dtype=torch.float64)] * dim,
+                               [torch.zeros(n, dtype=torch.float64)] * 3, torch.ones(n, dtype=torch.float64)),
+                     bits).cell.numpy().astype(np.int64)
+    off_grid = rng.choice(n, 97, replace=False)
+    packed[off_grid] = -5
+    cells[0][off_grid] = -1
+    off = [torch.cat([first.off[a].cpu(), torch.rand(nx, dtype=torch.float32)]) for a in range(dim)]
+    u = [torch.cat([first.u[a].cpu(), torch.randn(nx, dtype=torch.float32)]) for a in range(3)]
+    w = torch.cat([first.w.cpu(), torch.ones(nx, dtype=torch.float32)])
+    chi = torch.arange(n, dtype=torch.float32)
+    perm, start = O.sort(oracle_grid(cfg), tile[:dim],
+                         [c.astype(np.int32) for c in cells] + ([] if dim == 3 else [np.zeros(n, np.int32)]))
+    h_good = first.tile_start.clone()
+    h_bad = h_good.clone()
+    h_bad[ntiles // 2] = h_bad[ntiles // 2 + 1] + 1
+    h_shift = torch.clamp(h_good + 1000, max=n0)
+    for label, hint in (("offsets of the last sort", h_good), ("none", None), ("decreasing", h_bad),
+                        ("shifted", h_shift), ("destination's own", "dst")):
+        s2 = L.Particles(n, [t.to(DEV) for t in u], cell=torch.from_numpy(packed.astype(np.int32)).to(DEV),
+                         off=[t.to(DEV) for t in off], w=w.to(DEV), chi=chi.to(DEV))
+        dst = s2.empty_like()
+        dst.tile_start = torch.full((ntiles + 1,), -7, dtype=torch.int64, device=DEV)
+        s2.tile_start = dst.tile_start if hint == "dst" else (None if hint is None else hint.clone())
+        L.pic_sort(ctx, s2, dst)
+        torch.cuda.synchronize()
+        print(f"  hint {label}", flush=True)
+        assert np.array_equal(dst.tile_start.cpu().numpy(), start)
+        assert np.array_equal(dst.chi.cpu().numpy().astype(np.int64), perm)
+        assert np.array_equal(dst.cell.cpu().numpy(), packed.astype(np.int32)[perm])
+        for a in range(dim):
+            assert np.array_equal(dst.off[a].cpu().numpy(), off[a].numpy()[perm])
+        for a in range(3):
+            assert np.array_equal(dst.u[a].cpu().numpy(), u[a].numpy()[perm])
+        assert np.array_equal(dst.w.cpu().numpy(), w.numpy()[perm])
+
+
 @pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])
 def test_multistep_run_matches_oracle(precision):
     """20 whole steps (Yee halves, push, deposit, sorts) of a warm plasma in

@@ -11,6 +11,7 @@ in the library's kernels.
 """
 from __future__ import annotations
 
+import dataclasses
 from typing import List, Optional
 
 import torch
@@ -73,7 +74,11 @@ class Simulation:
     def sort(self):
         for k, p in enumerate(self.particles):
             dst = self.spare[k]
-            L.pic_sort(self.ctx, p, dst)
+            # the arrays' tile offsets from their last sort let pic_sort move
+            # only the particles that changed tiles; before the first sort
+            # there are none to give
+            src = p if self.sorted_at >= 0 else dataclasses.replace(p, tile_start=None)
+            L.pic_sort(self.ctx, src, dst)
             self.particles[k], self.spare[k] = dst, p
         self.sorted_at = self.step_index
 
@@ -148,7 +153,7 @@ def autotune_tiles(wl: Workload, candidates, steps: int = 8, warmup: int = 1, de
             continue
         for _ in range(warmup):
             sim.step()
-        sim.sorted_at = -1  # the timed window starts with a sort
+        sim.sorted_at = sim.step_index - sim.sort_every  # the timed window starts with a sort
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()

@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(256) tail_copy_kernel(const uint32_t *vals, co
 // phases A and D issue the loads of SORT_AHEAD rounds before using them
 constexpr int SORT_AHEAD = 4;
 // entries per thread that phase D keeps in registers for a one-stage tile
-constexpr int PERM_REG = 16;
+constexpr int PERM_REG = 12;
 
 // Layers of phase C handled per pass: R layers x (cells/64) group counters
 // stay within 16 KB of LDS.
@@ -377,6 +377,46 @@ __device__ __forceinline__ uint32_t order_exscan(uint32_t v, uint32_t *wt, uint3
     return r;
 }
 
+// Per-entry scratch of tile_order_kernel: the cell key and in-cell rank of
+// every entry of the tile (the rank later replaced by the final position),
+// and the final position of every cell-order slot.  In global memory
+// (indexed like the sorted arrays), or, for a tile of at most
+// order_lds_entries(seg) entries, as 16-bit words in LDS indexed from the
+// tile's first entry: the ranks after the fixed arrays, then the cell keys
+// and slot positions, whose space later stages the columns.
+template <bool LDS>
+struct OrderScratch;
+template <>
+struct OrderScratch<false> {
+    uint32_t *lcell, *lrank, *posmap;
+    int64_t ts;
+    __device__ __forceinline__ uint32_t cell(int64_t i) const { return lcell[i]; }
+    __device__ __forceinline__ void set_cell(int64_t i, uint32_t v) const { lcell[i] = v; }
+    __device__ __forceinline__ uint32_t rank(int64_t i) const { return lrank[i]; }
+    __device__ __forceinline__ void set_rank(int64_t i, uint32_t v) const { lrank[i] = v; }
+    __device__ __forceinline__ uint32_t pos(uint32_t slot) const { return posmap[ts + slot]; }
+    __device__ __forceinline__ void set_pos(uint32_t slot, uint32_t v) const { posmap[ts + slot] = v; }
+};
+template <>
+struct OrderScratch<true> {
+    uint16_t *lk, *lr, *pm;
+    int64_t ts;
+    __device__ __forceinline__ uint32_t cell(int64_t i) const { return lk[i - ts]; }
+    __device__ __forceinline__ void set_cell(int64_t i, uint32_t v) const { lk[i - ts] = (uint16_t)v; }
+    __device__ __forceinline__ uint32_t rank(int64_t i) const { return lr[i - ts]; }
+    __device__ __forceinline__ void set_rank(int64_t i, uint32_t v) const { lr[i - ts] = (uint16_t)v; }
+    __device__ __forceinline__ uint32_t pos(uint32_t slot) const { return pm[slot]; }
+    __device__ __forceinline__ void set_pos(uint32_t slot, uint32_t v) const { pm[slot] = (uint16_t)v; }
+};
+
+// entries of a tile whose scratch fits the LDS stage of `seg` words: 16-bit
+// ranks (half a word each) plus 16-bit keys and slot positions (a word per
+// entry, later the staged column); a multiple of 64, below 2^16
+__host__ __device__ inline int order_lds_entries(int seg) {
+    const int e = (2 * seg / 3) & ~63;
+    return e < 65536 ? e : 65472;
+}
+
 // One workgroup of ORDER_THREADS per tile.
 //   A. each of the first RW wavefronts ranks the particles of its contiguous
 //      share of the tile within their cells (8 ballots match equal cells; the
@@ -393,10 +433,10 @@ __device__ __forceinline__ uint32_t order_exscan(uint32_t v, uint32_t *wt, uint3
 //      a tile's sources ascend and the reads are nearly sequential), placed
 //      at their final position in LDS, written out contiguously.
 // Loads of SORT_AHEAD rounds are issued before they are used.
-__global__ void __launch_bounds__(ORDER_THREADS, 8) tile_order_kernel(const uint32_t *vals, const int64_t *tile_start,
-                                                                   SortGeom g, int lbits, int seg, uint32_t *lcell,
-                                                                   uint32_t *lrank, uint32_t *posmap, PermArgs pa) {
-    extern __shared__ uint32_t sm[];
+template <bool LDS>
+__device__ __forceinline__ void order_tile(const uint32_t *vals, int64_t ts, int64_t te, const SortGeom &g, int lbits,
+                                           int seg, uint32_t *lcell, uint32_t *lrank, uint32_t *posmap,
+                                           const PermArgs &pa, uint32_t *sm, uint32_t &maxc_s) {
     const int ct = g.ct;
     const int ng = (ct + 63) >> 6;
     const int R = sort_layer_chunk(ct);
@@ -408,10 +448,19 @@ __global__ void __launch_bounds__(ORDER_THREADS, 8) tile_order_kernel(const uint
     uint32_t *lb = gc + R * ng;       // R: first position of each layer of the pass
     uint32_t *wt = lb + 256;          // ORDER_WAVES + 1: scan of wave totals
     uint32_t *stage = wt + 64;        // seg: a staged column
-    __shared__ uint32_t maxc_s;
-    const int t = blockIdx.x;
-    const int64_t ts = tile_start[t], te = tile_start[t + 1];
-    if (ts == te) return;
+    OrderScratch<LDS> sc;
+    if constexpr (LDS) {
+        const int ne = order_lds_entries(seg);
+        sc.lr = (uint16_t *)stage;
+        sc.lk = (uint16_t *)(stage + ne / 2);
+        sc.pm = sc.lk + ne;
+        stage += ne / 2;  // the keys' and slot positions' space, once they are used
+    } else {
+        sc.lcell = lcell;
+        sc.lrank = lrank;
+        sc.posmap = posmap;
+    }
+    sc.ts = ts;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t n_t = te - ts;
@@ -458,8 +507,8 @@ __global__ void __launch_bounds__(ORDER_THREADS, 8) tile_order_kernel(const uint
                 if (valid && rank == 0) wc[l] = prev + (uint32_t)__popcll(peers);
                 __builtin_amdgcn_wave_barrier();
                 if (valid) {
-                    lcell[i] = l;
-                    lrank[i] = prev + rank;
+                    sc.set_cell(i, l);
+                    sc.set_rank(i, prev + rank);
                 }
             }
         }
@@ -530,7 +579,7 @@ __global__ void __launch_bounds__(ORDER_THREADS, 8) tile_order_kernel(const uint
             for (uint32_t r = 0; r < rr; ++r) {
                 const bool has = c > r0 + r;
                 const uint64_t b = __ballot(has);
-                if (has) posmap[ts + cst[l] + r0 + r] = lb[r] + gc[r * ng + gi] + (uint32_t)__popcll(b & lt_mask);
+                if (has) sc.set_pos(cst[l] + r0 + r, lb[r] + gc[r * ng + gi] + (uint32_t)__popcll(b & lt_mask));
             }
         }
         __syncthreads();
@@ -544,16 +593,16 @@ __global__ void __launch_bounds__(ORDER_THREADS, 8) tile_order_kernel(const uint
             for (int q = 0; q < SORT_AHEAD; ++q) {
                 const int64_t i = i0 + q * 64;
                 if (i < c1) {
-                    const uint32_t l = lcell[i];
-                    slot[q] = cst[l] + wcnt[wave * ct + l] + lrank[i];
+                    const uint32_t l = sc.cell(i);
+                    slot[q] = cst[l] + wcnt[wave * ct + l] + sc.rank(i);
                 }
             }
 #pragma unroll
             for (int q = 0; q < SORT_AHEAD; ++q)
-                if (i0 + q * 64 < c1) pos[q] = posmap[ts + slot[q]];
+                if (i0 + q * 64 < c1) pos[q] = sc.pos(slot[q]);
 #pragma unroll
             for (int q = 0; q < SORT_AHEAD; ++q)
-                if (i0 + q * 64 < c1) lrank[i0 + q * 64] = pos[q];
+                if (i0 + q * 64 < c1) sc.set_rank(i0 + q * 64, pos[q]);
         }
     }
     __syncthreads();
@@ -566,7 +615,7 @@ __global__ void __launch_bounds__(ORDER_THREADS, 8) tile_order_kernel(const uint
 #pragma unroll
         for (int u = 0; u < PERM_REG; ++u) {
             const int64_t i = ts + threadIdx.x + (int64_t)u * ORDER_THREADS;
-            pos[u] = i < te ? lrank[i] : 0xFFFFFFFFu;
+            pos[u] = i < te ? sc.rank(i) : 0xFFFFFFFFu;
             v[u] = i < te ? vals[i] : 0u;
         }
         for (int col = 0; col < pa.ncol; ++col) {
@@ -596,7 +645,7 @@ __global__ void __launch_bounds__(ORDER_THREADS, 8) tile_order_kernel(const uint
 #pragma unroll
                 for (int u = 0; u < SORT_AHEAD; ++u) {
                     const int64_t i = i0 + u * ORDER_THREADS;
-                    pos[u] = i < te ? lrank[i] - (uint32_t)s0 : 0xFFFFFFFFu;
+                    pos[u] = i < te ? sc.rank(i) - (uint32_t)s0 : 0xFFFFFFFFu;
                     v[u] = i < te ? vals[i] : 0u;
                 }
 #pragma unroll
@@ -612,6 +661,20 @@ __global__ void __launch_bounds__(ORDER_THREADS, 8) tile_order_kernel(const uint
             __syncthreads();
         }
     }
+}
+
+__global__ void __launch_bounds__(ORDER_THREADS, 8) tile_order_kernel(const uint32_t *vals, const int64_t *tile_start,
+                                                                   SortGeom g, int lbits, int seg, uint32_t *lcell,
+                                                                   uint32_t *lrank, uint32_t *posmap, PermArgs pa) {
+    extern __shared__ uint32_t sm[];
+    __shared__ uint32_t maxc_s;
+    const int t = blockIdx.x;
+    const int64_t ts = tile_start[t], te = tile_start[t + 1];
+    if (ts == te) return;
+    if (te - ts <= order_lds_entries(seg))
+        order_tile<true>(vals, ts, te, g, lbits, seg, lcell, lrank, posmap, pa, sm, maxc_s);
+    else
+        order_tile<false>(vals, ts, te, g, lbits, seg, lcell, lrank, posmap, pa, sm, maxc_s);
 }
 
 // ---- re-binning from the source's own tile offsets ----------------------

@@ -212,6 +212,28 @@ pic_status pic_gather_push_deposit(void *ctx, const pic_species *sp, const pic_p
                                    const pic_fields *fields, double *diag, void *stream);
 
 /*
+ * Gather + push + deposit of several species (Secs. II.C-E, Sec. II.F: every
+ * species of a step moves in the same fields and adds to the same J):
+ * sp[k] and p[k] describe species k, nsp in [1, PIC_MAX_SPECIES], and each
+ * species must be listed once.  The result is that of one
+ * pic_gather_push_deposit per species in the order given, with one
+ * difference: on the FP32 path the species share each tile's pass (its
+ * field window is staged once and their currents meet in one fixed-point
+ * window), so J is rounded to FP32 once per tile instead of once per tile
+ * and species, and its last bits can differ.  Particle updates and flags
+ * are the same bit for bit; diag receives the sums over the species.  The
+ * FP64 plain path pushes the species one after another.  The call's scratch
+ * (the per-species lists of pic_gather_push_deposit, for all species at
+ * once) is grown on demand by the call itself, not by pic_reserve.  Errors
+ * as pic_gather_push_deposit, and PIC_E_ARG for nsp out of range or a
+ * species listed twice.
+ */
+#define PIC_MAX_SPECIES 4
+pic_status pic_gather_push_deposit_multi(void *ctx, int32_t nsp, const pic_species *sp,
+                                         const pic_particles *const *p, const pic_fields *fields,
+                                         double *diag, void *stream);
+
+/*
  * For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): pic_gather_push_deposit
  * with the same arguments, results and errors, but every scratch buffer of

@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 from dataclasses import dataclass, field
-from typing import Optional
+from typing import List, Optional
 
 import torch
 
@@ -29,6 +29,7 @@ PIC_QED_TABLE, PIC_QED_MLP, PIC_QED_METHOD2 = 0, 1, 2
 PIC_PUSH_BORIS, PIC_PUSH_VAY = 0, 1
 PIC_BC_ABSORB = 1
 PIC_BC_ABSORB2 = 2
+PIC_MAX_SPECIES = 4
 PIC_MLP_NPARAM = 4610
 PIC_MLP_BYTES = 18440
 PIC_MLP_STATE_FLOATS = 4 * PIC_MLP_NPARAM + 1
@@ -36,7 +37,8 @@ PIC_MLP_STATE_FLOATS = 4 * PIC_MLP_NPARAM + 1
 EXPORTED = ["pic_init", "pic_destroy", "pic_last_error", "pic_get_layout", "pic_gather_push_deposit",
             "pic_yee_step", "pic_sort", "pic_check", "pic_qed_step", "pic_mlp_forward", "pic_mlp_grad",
             "pic_mlp_train", "pic_qed_training_data", "pic_qed_table_lookup", "pic_set_laser", "pic_reserve",
-            "pic_deposit_rho", "pic_gauss_residual", "pic_beam_fields", "pic_gather_push_deposit_noalloc"]
+            "pic_deposit_rho", "pic_gauss_residual", "pic_beam_fields", "pic_gather_push_deposit_noalloc",
+            "pic_gather_push_deposit_multi"]
 
 
 class PicError(RuntimeError):
@@ -136,6 +138,10 @@ def lib():
                                                       C.POINTER(pic_particles), C.POINTER(pic_fields), C.c_void_p,
                                                       C.c_void_p]
         L.pic_gather_push_deposit_noalloc.restype = C.c_int
+        L.pic_gather_push_deposit_multi.argtypes = [C.c_void_p, C.c_int32, C.POINTER(pic_species),
+                                                    C.POINTER(C.POINTER(pic_particles)), C.POINTER(pic_fields),
+                                                    C.c_void_p, C.c_void_p]
+        L.pic_gather_push_deposit_multi.restype = C.c_int
         L.pic_reserve.argtypes = [C.c_void_p, C.c_int64]
         L.pic_reserve.restype = C.c_int
         L.pic_deposit_rho.argtypes = [C.c_void_p, C.POINTER(pic_species), C.POINTER(pic_particles), C.c_int32,
@@ -337,6 +343,20 @@ def pic_gather_push_deposit(ctx: Context, sp: Species, p: Particles, f: Fields,
     sc, pc, fc = sp.c(), p.c(), f.c()
     st = lib().pic_gather_push_deposit(C.c_void_p(ctx.handle), C.byref(sc), C.byref(pc), C.byref(fc),
                                        _ptr(diag), _stream(stream))
+    _check(st, C.c_void_p(ctx.handle))
+
+
+def pic_gather_push_deposit_multi(ctx: Context, species: List[Species], parts: List[Particles], f: Fields,
+                                  diag: Optional[torch.Tensor] = None, stream=None):
+    """Several species in one call: species[k] with parts[k]."""
+    if len(species) != len(parts):
+        raise ValueError("one Particles per Species")
+    sa = (pic_species * max(1, len(species)))(*[sp.c() for sp in species])
+    pcs = [p.c() for p in parts]
+    pa = (C.POINTER(pic_particles) * max(1, len(pcs)))(*[C.pointer(pc) for pc in pcs])
+    fc = f.c()
+    st = lib().pic_gather_push_deposit_multi(C.c_void_p(ctx.handle), len(species), sa, pa, C.byref(fc),
+                                             _ptr(diag), _stream(stream))
     _check(st, C.c_void_p(ctx.handle))
 
 

@@ -304,6 +304,7 @@ extern "C" void pic_destroy(void *ctx) {
     hipFree(c->hist);
     hipFree(c->final_perm);
     hipFree(c->inc);
+    hipFree(c->multi_scratch);
     hipFree(c->qed.dev);
     hipFree(c->mlp_scratch);
     hipFree(c->mur_old);
@@ -394,6 +395,62 @@ extern "C" pic_status pic_gather_push_deposit(void *ctx, const pic_species *sp, 
     hipError_t e = c->cfg.precision == PIC_FP32_MIXED ? launch_gpd_tiled(c, sp, p, fields, diag, s)
                                                       : launch_gpd_plain(c, sp, p, fields, diag, s);
     if (e != hipSuccess) return hip_fail(c, e, "pic_gather_push_deposit");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_gather_push_deposit_multi(void *ctx, int32_t nsp, const pic_species *sp,
+                                                    const pic_particles *const *p, const pic_fields *fields,
+                                                    double *diag, void *stream) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return fail(nullptr, PIC_E_ARG, "context is NULL");
+    if (nsp < 1 || nsp > PIC_MAX_SPECIES) return fail(c, PIC_E_ARG, "nsp must be in [1, PIC_MAX_SPECIES]");
+    if (!sp || !p) return fail(c, PIC_E_ARG, "species or particles is NULL");
+    int64_t total = 0;
+    for (int k = 0; k < nsp; ++k) {
+        pic_status st = validate_push_args(c, &sp[k], p[k], fields);
+        if (st != PIC_OK) return st;
+        total += p[k]->n;
+        for (int j = 0; j < k; ++j)
+            if (p[j]->n > 0 && p[k]->n > 0 && p[j]->cell == p[k]->cell && p[j]->u[0] == p[k]->u[0])
+                return fail(c, PIC_E_ARG, "a species is listed twice");
+    }
+    if (total == 0) return PIC_OK;
+    hipSetDevice(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (c->cfg.precision != PIC_FP32_MIXED) {
+        // the plain FP64 path has no tiles to share: one species after another
+        for (int k = 0; k < nsp && e == hipSuccess; ++k)
+            if (p[k]->n > 0) e = launch_gpd_plain(c, &sp[k], p[k], fields, diag, s);
+    } else {
+        // species with particles only (an empty one may have no arrays at all)
+        pic_species spk[PIC_MAX_SPECIES];
+        const pic_particles *pk[PIC_MAX_SPECIES];
+        int m = 0;
+        for (int k = 0; k < nsp; ++k)
+            if (p[k]->n > 0) {
+                spk[m] = sp[k];
+                pk[m++] = p[k];
+            }
+        PushScratch ps[PIC_MAX_SPECIES];
+        size_t need = 0;
+        for (int k = 0; k < m; ++k) need += carve_push_scratch(c, pk[k]->n, nullptr, ps[k]);
+        if (need > c->multi_cap) {
+            retire(c, c->multi_scratch);
+            c->multi_scratch = nullptr;
+            c->multi_cap = 0;
+            const size_t cap = need + need / 8 + 4096;
+            if (hipMalloc(&c->multi_scratch, cap) != hipSuccess) {
+                c->multi_scratch = nullptr;
+                return fail(c, PIC_E_NOMEM, "cannot allocate the several-species push scratch");
+            }
+            c->multi_cap = cap;
+        }
+        size_t off = 0;
+        for (int k = 0; k < m; ++k) off += carve_push_scratch(c, pk[k]->n, c->multi_scratch + off, ps[k]);
+        e = launch_gpd_tiled_multi(c, m, spk, pk, fields, diag, s, ps);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "pic_gather_push_deposit_multi");
     return PIC_OK;
 }
 

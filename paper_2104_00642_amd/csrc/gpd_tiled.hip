@@ -584,63 +584,74 @@ struct POff<true> {
     typedef uint64_t type;
 };
 
+// Species pushed in one pass over the tiles: each tile stages its field
+// window once, and the species' currents share its fixed-point window (the
+// scale bounds every species' contributions).  Grid, fields and window come
+// from sp[0]; particles, charge, mass and scratch from each sp[k].
+template <int NSP>
+struct TiledSet {
+    TiledArgs sp[NSP];
+    int nsp;
+};
+
 // LIST = false: the tile's particles are [tile_start[t], tile_start[t+1]) of
 // the sorted arrays.  LIST = true: they are bin_list[bin_start[t] ..
 // bin_start[t+1]) (the stragglers and appended particles binned by the tile
 // that holds them now).
-template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ, bool LIST, bool SPLIT = false>
-__global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
+template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ, bool LIST, bool SPLIT = false, int NSP = 1>
+__global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledSet<NSP> S) {
     typedef typename POff<LIST>::type off_t;
+    const TiledArgs &a0 = S.sp[0];
+    const int nsp = NSP == 1 ? 1 : S.nsp;
     const int b = blockIdx.x;
-    const int t = (b & 7) * a.chunk + (b >> 3);  // XCD-contiguous tile runs
-    if (t >= a.ntiles) return;
-    const int64_t *start = LIST ? a.bin_start : a.tile_start;
-    const int64_t pbeg = min(start[t], a.n), pend = min(start[t + 1], a.n);
+    const int t = (b & 7) * a0.chunk + (b >> 3);  // XCD-contiguous tile runs
+    if (t >= a0.ntiles) return;
+    // particles of a species in this tile: [beg, end) of its sorted or binned order
+    auto range = [&](const TiledArgs &a, int64_t &beg, int64_t &end) {
+        const int64_t *start = LIST ? a.bin_start : a.tile_start;
+        beg = min(start[t], a.n);
+        end = min(start[t + 1], a.n);
+    };
     __shared__ double red_k[NT / 64], red_q[NT / 64];
     __shared__ float wmax_s[NT / 64];
     __shared__ uint32_t nstray;
-    double *part = a.partials + a.part_off;
-    if (pbeg >= pend) {
+    bool any = false;
+    for (int k = 0; k < nsp; ++k) {
+        int64_t pb, pe;
+        range(S.sp[k], pb, pe);
+        any |= pb < pe;
+    }
+    if (!any) {
         if (threadIdx.x == 0) {
-            part[2 * t] = 0.0;
-            part[2 * t + 1] = 0.0;
-            if (!LIST) a.strag_tile[t] = 0u;
+            for (int k = 0; k < nsp; ++k) {
+                const TiledArgs &a = S.sp[k];
+                double *part = a.partials + a.part_off;
+                part[2 * t] = 0.0;
+                part[2 * t + 1] = 0.0;
+                if (!LIST) a.strag_tile[t] = 0u;
+            }
         }
         return;
     }
     if (threadIdx.x == 0) nstray = 0u;
-    const int tx = t % a.ntile_axis[0];
-    const int ty = (t / a.ntile_axis[0]) % a.ntile_axis[1];
-    const int tz = DIM == 3 ? t / (a.ntile_axis[0] * a.ntile_axis[1]) : 0;
+    const int tx = t % a0.ntile_axis[0];
+    const int ty = (t / a0.ntile_axis[0]) % a0.ntile_axis[1];
+    const int tz = DIM == 3 ? t / (a0.ntile_axis[0] * a0.ntile_axis[1]) : 0;
     // stencil reach around a particle's cell c: [c - RLO, c + RHI]
     constexpr int RLO = ORDER == 4 ? 3 : 2, RHI = ORDER == 4 ? 4 : 3;
-    const int g = a.drift + RLO;
-    const int org[3] = {tx * a.tile[0] - g, ty * a.tile[1] - g, DIM == 3 ? tz * a.tile[2] - g : 0};
+    const int g = a0.drift + RLO;
+    const int org[3] = {tx * a0.tile[0] - g, ty * a0.tile[1] - g, DIM == 3 ? tz * a0.tile[2] - g : 0};
     typedef typename std::conditional<SPLIT, LdsSplit2<WX, WY>, LdsAcc<WX, WY, WZ, DIM == 2>>::type Lds;
-    Lds lds = make_lds<Lds>(a);
+    Lds lds = make_lds<Lds>(a0);
     const int wn = lds.wn();
     const int wx = lds.wx(), wxy = lds.wxy();
     unsigned long long *jwin = (unsigned long long *)(pic_smem + lds.jbase());
-    const uint32_t np = (uint32_t)(pend - pbeg);
     // element offsets: sorted pass, bases moved to the tile's first particle
     // and one 32-bit offset per particle; binned pass, offsets of the listed
     // particles against the array bases
-    const int64_t rebase = LIST ? 0 : pbeg;
-    const int32_t *plist = a.bin_list + pbeg;
-    auto poff = [&](uint32_t i) -> off_t {
+    auto poff_of = [&](const int32_t *plist, uint32_t i) -> off_t {
         return LIST ? (off_t)4 * (off_t)(uint32_t)plist[i] : (off_t)(4u * i);
     };
-    auto pidx = [&](uint32_t i) -> int64_t { return LIST ? (int64_t)plist[i] : pbeg + i; };
-    int32_t *cellT = a.cell + rebase;
-    float *offT[3], *uT[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        offT[d] = a.off[d] + rebase;
-        uT[d] = a.u[d] + rebase;
-    }
-    const float *wT = a.w ? a.w + rebase : nullptr;
-    float *wW = a.w ? a.w + rebase : nullptr;  // absorption (weights are required with absorbing faces)
-    float *chiT = a.chi ? a.chi + rebase : nullptr;
 
     // 1. stage the E/B window, zero the J window (window index decoded once
     //    per cell), bound the weights of the tile.  With the window shape
@@ -652,11 +663,11 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         const int r2 = r - k * wxy;
         const int j = r2 / wx;
         const int i = r2 - j * wx;
-        const int gi = wrap_index(org[0] + i, a.ng[0]);
-        const int gj = wrap_index(org[1] + j, a.ng[1]);
-        const int gk = DIM == 3 ? wrap_index(org[2] + k, a.ng[2]) : 0;
-        gidx = (int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk);
-        beyond = a.absorb_x && (unsigned)(org[0] + i) >= (unsigned)a.ng[0];
+        const int gi = wrap_index(org[0] + i, a0.ng[0]);
+        const int gj = wrap_index(org[1] + j, a0.ng[1]);
+        const int gk = DIM == 3 ? wrap_index(org[2] + k, a0.ng[2]) : 0;
+        gidx = (int64_t)gi + (int64_t)a0.ng[0] * ((int64_t)gj + (int64_t)a0.ng[1] * gk);
+        beyond = a0.absorb_x && (unsigned)(org[0] + i) >= (unsigned)a0.ng[0];
     };
     constexpr int SITER = WX > 0 ? (WX * WY * WZ + NT - 1) / NT : 0;
     if constexpr (SITER > 0 && SITER <= 4) {
@@ -669,7 +680,7 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
                 bool beyond;
                 cell_src(r, gidx, beyond);
 #pragma unroll
-                for (int c = 0; c < 6; ++c) v[s][c] = beyond ? 0.0f : a.F[c][gidx];
+                for (int c = 0; c < 6; ++c) v[s][c] = beyond ? 0.0f : a0.F[c][gidx];
             }
         }
 #pragma unroll
@@ -686,20 +697,32 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
             bool beyond;
             cell_src(r, gidx, beyond);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) pic_smem[lds.slot(c, r)] = beyond ? 0.0f : a.F[c][gidx];
+            for (int c = 0; c < 6; ++c) pic_smem[lds.slot(c, r)] = beyond ? 0.0f : a0.F[c][gidx];
         }
     }
     for (int r = threadIdx.x; r < lds.jcount(); r += NT) jwin[r] = 0ull;
-    float wm = fabsf(a.w0);
-    if (wT) {
-        // four loads in flight per round
-        wm = 0.0f;
+    // bound of |q| |w| over the tile's particles of every species (the
+    // per-particle weights read with four loads in flight per round)
+    float wm = 0.0f;
+    for (int k = 0; k < nsp; ++k) {
+        const TiledArgs &a = S.sp[k];
+        int64_t pbeg, pend;
+        range(a, pbeg, pend);
+        if (pbeg >= pend) continue;
+        const float aq = fabsf(a.q);
+        if (!a.w) {
+            wm = fmaxf(wm, aq * fabsf(a.w0));
+            continue;
+        }
+        const uint32_t np = (uint32_t)(pend - pbeg);
+        const float *wT = a.w + (LIST ? 0 : pbeg);
+        const int32_t *plist = a.bin_list + pbeg;
         for (uint32_t i = threadIdx.x; i < np; i += 4 * NT) {
             float x[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) x[q] = i + q * NT < np ? fabsf(ld(wT, poff(i + q * NT))) : 0.0f;
+            for (int q = 0; q < 4; ++q) x[q] = i + q * NT < np ? fabsf(ld(wT, poff_of(plist, i + q * NT))) : 0.0f;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) wm = fmaxf(wm, x[q]);
+            for (int q = 0; q < 4; ++q) wm = fmaxf(wm, aq * x[q]);
         }
     }
 #pragma unroll
@@ -707,24 +730,49 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
     if ((threadIdx.x & 63) == 0) wmax_s[threadIdx.x >> 6] = wm;
     __syncthreads();
     {
-        float wmax = 0.0f;
+        float qwmax = 0.0f;
 #pragma unroll
-        for (int k = 0; k < NT / 64; ++k) wmax = fmaxf(wmax, wmax_s[k]);
-        // S = 2^(30 - ceil(log2 B)), B = |q| w_max max(1, d/dt): |contribution| * S <= 2^30
-        const float B = fabsf(a.q) * wmax * a.jmax;
+        for (int k = 0; k < NT / 64; ++k) qwmax = fmaxf(qwmax, wmax_s[k]);
+        // S = 2^(30 - ceil(log2 B)), B = max |q| w max(1, d/dt): |contribution| * S <= 2^30
+        const float B = qwmax * a0.jmax;
         int ex = 0;
         frexpf(B > 0.0f ? B : 1.0f, &ex);  // B < 2^ex
         lds.scale = ldexpf(1.0f, 30 - ex);
     }
 
-    // 2. particles of the tile, next particle prefetched while one is pushed
-    const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
+    // 2. particles of the tile, species after species, next particle
+    //    prefetched while one is pushed
+    const int mx = (1 << a0.bx) - 1, my = (1 << a0.by) - 1;
     const int hi[3] = {wx - RHI - 1, (DIM >= 2 ? wxy / wx : 1) - RHI - 1, (DIM == 3 ? wn / wxy : 1) - RHI - 1};
-    double kin = 0.0, chg = 0.0;
     // WRAP: the window crosses the periodic seam (or an absorbing face) along
     // some axis.  Otherwise a cell's window coordinate is its offset from the
     // origin, and a pushed particle (it stays within the window's reach)
     // cannot leave [0, n): neither needs the unwrap.
+    bool wraps = false;
+    const int wext[3] = {wx, DIM >= 2 ? wxy / wx : 1, DIM == 3 ? wn / wxy : 1};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) wraps |= org[d] < 0 || org[d] + wext[d] > a0.ng[d];
+    for (int k = 0; k < nsp; ++k) {
+    const TiledArgs &a = S.sp[k];
+    int64_t pbeg, pend;
+    range(a, pbeg, pend);
+    double kin = 0.0, chg = 0.0;
+    if (pbeg < pend) {
+    const uint32_t np = (uint32_t)(pend - pbeg);
+    const int64_t rebase = LIST ? 0 : pbeg;
+    const int32_t *plist = a.bin_list + pbeg;
+    auto poff = [&](uint32_t i) -> off_t { return poff_of(plist, i); };
+    auto pidx = [&](uint32_t i) -> int64_t { return LIST ? (int64_t)plist[i] : pbeg + i; };
+    int32_t *cellT = a.cell + rebase;
+    float *offT[3], *uT[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        offT[d] = a.off[d] + rebase;
+        uT[d] = a.u[d] + rebase;
+    }
+    const float *wT = a.w ? a.w + rebase : nullptr;
+    float *wW = a.w ? a.w + rebase : nullptr;  // absorption (weights are required with absorbing faces)
+    float *chiT = a.chi ? a.chi + rebase : nullptr;
     auto particles = [&](auto wrap_c) {
     constexpr bool WRAP = decltype(wrap_c)::value;
     uint32_t i = threadIdx.x;
@@ -763,7 +811,9 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         bool inside = DIM == 3 || (cell >> (a.bx + a.by)) == 0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            const int l = WRAP ? wrap_index(cc[d] - org[d], a.ng[d]) : cc[d] - org[d];
+            // no periodic image across an absorbing face: a particle on the
+            // far side of the domain is not in this window
+            const int l = WRAP && !(d == 0 && a.absorb_x) ? wrap_index(cc[d] - org[d], a.ng[d]) : cc[d] - org[d];
             lc[d] = l;
             inside &= (unsigned)(l - RLO) <= (unsigned)(hi[d] - RLO) && (unsigned)cc[d] < (unsigned)a.ng[d];
             inside &= __float_as_uint(f[d]) < 0x3f800000u;
@@ -798,12 +848,22 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         chg += (double)w;
     }
     };
-    bool wraps = false;
-    const int wext[3] = {wx, DIM >= 2 ? wxy / wx : 1, DIM == 3 ? wn / wxy : 1};
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) wraps |= org[d] < 0 || org[d] + wext[d] > a.ng[d];
     if (wraps) particles(std::integral_constant<bool, true>{});
     else particles(std::integral_constant<bool, false>{});
+    }
+    // fixed-order FP64 reduction of the species' diagnostics (its barrier
+    // also ends the species' LDS atomics and straggler count)
+    const double sk = block_sum<NT>(kin, red_k);
+    const double sq = block_sum<NT>(chg, red_q);
+    if (threadIdx.x == 0) {
+        double *part = a.partials + a.part_off;
+        part[2 * t] = sk * a.mdV;
+        part[2 * t + 1] = sq * a.qdV;
+        if (!LIST) a.strag_tile[t] = nstray;
+        nstray = 0u;
+    }
+    if (NSP > 1) __syncthreads();  // red_k, red_q and nstray are reused by the next species
+    }
     __syncthreads();
 
     // 3. flush the J window into global J (periodic wrap), skip exact zeros
@@ -813,24 +873,16 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledArgs a) {
         const int r2 = r - k * wxy;
         const int j = r2 / wx;
         const int ii = r2 - j * wx;
-        const int gi = wrap_index(org[0] + ii, a.ng[0]);
-        const int gj = wrap_index(org[1] + j, a.ng[1]);
-        const int gk = DIM == 3 ? wrap_index(org[2] + k, a.ng[2]) : 0;
-        const int64_t gidx = (int64_t)gi + (int64_t)a.ng[0] * ((int64_t)gj + (int64_t)a.ng[1] * gk);
-        if (a.absorb_x && (unsigned)(org[0] + ii) >= (unsigned)a.ng[0]) continue;  // beyond a face
+        const int gi = wrap_index(org[0] + ii, a0.ng[0]);
+        const int gj = wrap_index(org[1] + j, a0.ng[1]);
+        const int gk = DIM == 3 ? wrap_index(org[2] + k, a0.ng[2]) : 0;
+        const int64_t gidx = (int64_t)gi + (int64_t)a0.ng[0] * ((int64_t)gj + (int64_t)a0.ng[1] * gk);
+        if (a0.absorb_x && (unsigned)(org[0] + ii) >= (unsigned)a0.ng[0]) continue;  // beyond a face
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const long long q = (long long)jwin[lds.jslot(c, r)];
-            if (q != 0) atomicAdd(&a.J[c][gidx], (float)((double)q * inv_scale));
+            if (q != 0) atomicAdd(&a0.J[c][gidx], (float)((double)q * inv_scale));
         }
-    }
-    // 4. fixed-order FP64 reduction of the diagnostics
-    const double sk = block_sum<NT>(kin, red_k);
-    const double sq = block_sum<NT>(chg, red_q);
-    if (threadIdx.x == 0) {
-        part[2 * t] = sk * a.mdV;
-        part[2 * t + 1] = sq * a.qdV;
-        if (!LIST) a.strag_tile[t] = nstray;
     }
 }
 
@@ -1100,73 +1152,102 @@ constexpr int W3X0 = 8 + 5, W3Z0 = 4 + 5;
 // 8 x 8 x 8 tiles with drift 0 (quadratic): 13 x 13 x 13
 constexpr int W3C0 = 8 + 5;
 
-// One push of a species:
+// One push of NSP species (one when NSP = 1, S.nsp of them otherwise):
 //   prep (zero bin counters) -> sorted pass (stragglers listed) -> bin count
 //   -> bin scan -> bin scatter -> reset of the list -> binned pass -> global
-//   pass over whatever the binned pass listed.
-// Partials: [sorted pass: 2 ntiles][binned pass: 2 ntiles][global: 2 x 256].
-template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ, bool SPLIT = false>
-static void launch_passes(TiledArgs a, size_t lds, hipStream_t s) {
-    const dim3 tiles((unsigned)(8 * a.chunk)), block(NT), gb(GLOBAL_BLOCKS), b256(256);
-    gpd_prep_kernel<<<(unsigned)((a.ntiles + 255) / 256), 256, 0, s>>>(a.bin_count, a.ntiles, a.strag_count);
-    a.part_off = 0;
-    gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, false, SPLIT><<<tiles, block, lds, s>>>(a);
-    const dim3 bins((unsigned)(a.ntiles + TAIL_BLOCKS));
-    gpd_bin_count_kernel<DIM><<<bins, b256, 0, s>>>(a);
-    gpd_bin_scan_kernel<<<1, 1024, 0, s>>>(a.bin_count, a.ntiles, a.bin_start);
-    gpd_bin_scatter_kernel<DIM><<<bins, b256, 0, s>>>(a);
-    gpd_reset_kernel<<<1, 1, 0, s>>>(a.strag_count);
-    a.part_off = 2 * a.ntiles;
-    gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, true, SPLIT><<<tiles, block, lds, s>>>(a);
-    a.part_off = 4 * a.ntiles;
-    gpd_global_kernel<DIM, ORDER, PUSH><<<gb, b256, 0, s>>>(a);
+//   pass over whatever the binned pass listed.  The two tile passes take
+//   every species at once; the binning and global kernels go species by
+//   species.  Partials per species: [sorted pass: 2 ntiles][binned pass:
+//   2 ntiles][global: 2 x 256].
+template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ, bool SPLIT = false, int NSP = 1>
+static void launch_passes(TiledSet<NSP> S, size_t lds, hipStream_t s) {
+    const int nsp = NSP == 1 ? 1 : S.nsp;
+    const int ntiles = S.sp[0].ntiles;
+    const dim3 tiles((unsigned)(8 * S.sp[0].chunk)), block(NT), gb(GLOBAL_BLOCKS), b256(256);
+    for (int k = 0; k < nsp; ++k) {
+        TiledArgs &a = S.sp[k];
+        gpd_prep_kernel<<<(unsigned)((ntiles + 255) / 256), 256, 0, s>>>(a.bin_count, ntiles, a.strag_count);
+        a.part_off = 0;
+    }
+    gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, false, SPLIT, NSP><<<tiles, block, lds, s>>>(S);
+    const dim3 bins((unsigned)(ntiles + TAIL_BLOCKS));
+    for (int k = 0; k < nsp; ++k) {
+        TiledArgs &a = S.sp[k];
+        gpd_bin_count_kernel<DIM><<<bins, b256, 0, s>>>(a);
+        gpd_bin_scan_kernel<<<1, 1024, 0, s>>>(a.bin_count, ntiles, a.bin_start);
+        gpd_bin_scatter_kernel<DIM><<<bins, b256, 0, s>>>(a);
+        gpd_reset_kernel<<<1, 1, 0, s>>>(a.strag_count);
+        a.part_off = 2 * ntiles;
+    }
+    gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, true, SPLIT, NSP><<<tiles, block, lds, s>>>(S);
+    for (int k = 0; k < nsp; ++k) {
+        TiledArgs &a = S.sp[k];
+        a.part_off = 4 * ntiles;
+        gpd_global_kernel<DIM, ORDER, PUSH><<<gb, b256, 0, s>>>(a);
+    }
 }
 
-template <int DIM, int ORDER, int PUSH>
-static void launch_tiled(const TiledArgs &a, size_t lds, hipStream_t s) {
+template <int DIM, int ORDER, int PUSH, int NSP>
+static void launch_tiled(const TiledSet<NSP> &S, size_t lds, hipStream_t s) {
+    const TiledArgs &a = S.sp[0];
     if constexpr (DIM == 2) {
         if constexpr (ORDER != 4) {
             // 16 x 16 tiles with drift 1: the x-parity window layout
             if (a.win[0] == W2S && a.win[1] == W2S) {
-                launch_passes<2, ORDER, PUSH, PIC_TILED_THREADS_2D, W2S, W2S, 1, true>(a, LdsSplit2<W2S, W2S>::bytes(),
-                                                                                     s);
+                launch_passes<2, ORDER, PUSH, PIC_TILED_THREADS_2D, W2S, W2S, 1, true, NSP>(
+                    S, LdsSplit2<W2S, W2S>::bytes(), s);
                 return;
             }
         }
         constexpr int WX = ORDER == 4 ? W2X4 : W2X;
         if (a.win[0] == WX && a.win[1] == WX)
-            launch_passes<2, ORDER, PUSH, PIC_TILED_THREADS_2D, WX, WX, 1>(a, lds, s);
+            launch_passes<2, ORDER, PUSH, PIC_TILED_THREADS_2D, WX, WX, 1, false, NSP>(S, lds, s);
         else
-            launch_passes<2, ORDER, PUSH, PIC_TILED_THREADS_2D, 0, 0, 0>(a, lds, s);
+            launch_passes<2, ORDER, PUSH, PIC_TILED_THREADS_2D, 0, 0, 0, false, NSP>(S, lds, s);
     } else {
         if (a.win[0] == W3X && a.win[1] == W3X && a.win[2] == W3Z) {
-            launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, W3X, W3X, W3Z>(a, lds, s);
+            launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, W3X, W3X, W3Z, false, NSP>(S, lds, s);
             return;
         }
         if constexpr (ORDER == 2) {
             if (a.win[0] == W3C0 && a.win[1] == W3C0 && a.win[2] == W3C0) {
-                launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, W3C0, W3C0, W3C0>(a, lds, s);
+                launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, W3C0, W3C0, W3C0, false, NSP>(S, lds, s);
                 return;
             }
             if (a.win[0] == W3X0 && a.win[1] == W3X0 && a.win[2] == W3Z0) {
-                launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, W3X0, W3X0, W3Z0>(a, lds, s);
+                launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, W3X0, W3X0, W3Z0, false, NSP>(S, lds, s);
                 return;
             }
         }
-        launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, 0, 0, 0>(a, lds, s);
+        launch_passes<3, ORDER, PUSH, PIC_TILED_THREADS_3D, 0, 0, 0, false, NSP>(S, lds, s);
     }
 }
 
-template <int DIM, int ORDER>
-static void launch_pusher(const TiledArgs &a, int pusher, size_t lds, hipStream_t s) {
-    if (pusher == PIC_PUSH_VAY) launch_tiled<DIM, ORDER, PIC_PUSH_VAY>(a, lds, s);
-    else launch_tiled<DIM, ORDER, PIC_PUSH_BORIS>(a, lds, s);
+template <int DIM, int ORDER, int NSP>
+static void launch_pusher(const TiledSet<NSP> &S, int pusher, size_t lds, hipStream_t s) {
+    if (pusher == PIC_PUSH_VAY) launch_tiled<DIM, ORDER, PIC_PUSH_VAY, NSP>(S, lds, s);
+    else launch_tiled<DIM, ORDER, PIC_PUSH_BORIS, NSP>(S, lds, s);
+}
+
+template <int NSP>
+static hipError_t launch_set(Ctx *c, const TiledSet<NSP> &S, size_t lds, hipStream_t s) {
+    switch (c->dim * 10 + c->cfg.order) {
+        case 21: launch_pusher<2, 1, NSP>(S, c->cfg.pusher, lds, s); break;
+        case 22: launch_pusher<2, 2, NSP>(S, c->cfg.pusher, lds, s); break;
+        case 31: launch_pusher<3, 1, NSP>(S, c->cfg.pusher, lds, s); break;
+        case 32: launch_pusher<3, 2, NSP>(S, c->cfg.pusher, lds, s); break;
+        case 24: launch_pusher<2, 4, NSP>(S, c->cfg.pusher, lds, s); break;
+        case 34: launch_pusher<3, 4, NSP>(S, c->cfg.pusher, lds, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 size_t push_partials_tiled(int64_t ntiles) { return 2 * (2 * (size_t)ntiles + GLOBAL_BLOCKS); }
 
-hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *p,
-                            const pic_fields *f, double *diag, hipStream_t s, const PushScratch *ps) {
+// Arguments of one species' push; scratch from ps, or the context's own
+static TiledArgs tiled_args(Ctx *c, const pic_species *sp, const pic_particles *p, const pic_fields *f,
+                            const PushScratch &ps) {
     const pic_config &cfg = c->cfg;
     TiledArgs a{};
     a.cell = p->cell;
@@ -1206,7 +1287,19 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
     a.qdV = sp->q * dV;
     a.status = c->status;
     a.stragglers = (unsigned long long *)(c->status + 2);
-    a.strag_count = c->status + 4;
+    a.strag_count = ps.strag_count ? ps.strag_count : c->status + 4;
+    a.partials = ps.partials;
+    a.strag_list = ps.strag_list;
+    a.strag_tile = ps.strag_tile;
+    a.bin_list = ps.bin_list;
+    a.bin_rank = ps.bin_rank;
+    a.bin_start = ps.bin_start;
+    a.bin_count = ps.bin_count;
+    return a;
+}
+
+hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *p,
+                            const pic_fields *f, double *diag, hipStream_t s, const PushScratch *ps) {
     const size_t nblocks = 2 * (size_t)c->ntiles + GLOBAL_BLOCKS;
     PushScratch own;
     if (!ps) {
@@ -1221,35 +1314,42 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
         own.bin_count = c->bin_count;
         ps = &own;
     }
-    a.partials = ps->partials;
-    a.strag_list = ps->strag_list;
-    a.strag_tile = ps->strag_tile;
-    a.bin_list = ps->bin_list;
-    a.bin_rank = ps->bin_rank;
-    a.bin_start = ps->bin_start;
-    a.bin_count = ps->bin_count;
-    const size_t lds = c->lds_bytes;
-    switch (c->dim * 10 + cfg.order) {
-        case 21: launch_pusher<2, 1>(a, cfg.pusher, lds, s); break;
-        case 22: launch_pusher<2, 2>(a, cfg.pusher, lds, s); break;
-        case 31: launch_pusher<3, 1>(a, cfg.pusher, lds, s); break;
-        case 32: launch_pusher<3, 2>(a, cfg.pusher, lds, s); break;
-        case 24: launch_pusher<2, 4>(a, cfg.pusher, lds, s); break;
-        case 34: launch_pusher<3, 4>(a, cfg.pusher, lds, s); break;
-        default: return hipErrorInvalidValue;
-    }
-    hipError_t e = hipGetLastError();
+    TiledSet<1> S;
+    S.sp[0] = tiled_args(c, sp, p, f, *ps);
+    S.nsp = 1;
+    hipError_t e = launch_set<1>(c, S, c->lds_bytes, s);
     if (e != hipSuccess || !diag) return e;
-    return launch_finalize(a.partials, (int64_t)nblocks, 2, diag, 0, 1.0, s);
+    return launch_finalize(S.sp[0].partials, (int64_t)nblocks, 2, diag, 0, 1.0, s);
+}
+
+hipError_t launch_gpd_tiled_multi(Ctx *c, int nsp, const pic_species *sp, const pic_particles *const *p,
+                                  const pic_fields *f, double *diag, hipStream_t s, const PushScratch *ps) {
+    if (nsp < 1 || nsp > PIC_MAX_SPECIES) return hipErrorInvalidValue;
+    const size_t nblocks = 2 * (size_t)c->ntiles + GLOBAL_BLOCKS;
+    TiledSet<PIC_MAX_SPECIES> S{};
+    for (int k = 0; k < nsp; ++k) S.sp[k] = tiled_args(c, &sp[k], p[k], f, ps[k]);
+    S.nsp = nsp;
+    hipError_t e = launch_set<PIC_MAX_SPECIES>(c, S, c->lds_bytes, s);
+    for (int k = 0; k < nsp && e == hipSuccess && diag; ++k)
+        e = launch_finalize(S.sp[k].partials, (int64_t)nblocks, 2, diag, 0, 1.0, s);
+    return e;
+}
+
+template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ, int NSP>
+static hipError_t set_lds_n(size_t bytes) {
+    hipError_t e =
+        hipFuncSetAttribute((const void *)gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, false, false, NSP>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, true, false, NSP>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 template <int DIM, int ORDER, int PUSH, int NT, int WX, int WY, int WZ>
 static hipError_t set_lds_p(size_t bytes) {
-    hipError_t e = hipFuncSetAttribute((const void *)gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipError_t e = set_lds_n<DIM, ORDER, PUSH, NT, WX, WY, WZ, 1>(bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, true>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return set_lds_n<DIM, ORDER, PUSH, NT, WX, WY, WZ, PIC_MAX_SPECIES>(bytes);
 }
 
 template <int DIM, int ORDER, int NT, int WX, int WY, int WZ>

@@ -45,7 +45,7 @@ hipError_t noalloc_scratch_init(void **ptr) {
 
 // Carves the push's buffers from `base`; returns the bytes they take.  With
 // base = nullptr only counts.
-static size_t carve(Ctx *c, int64_t n, unsigned char *base, PushScratch &ps) {
+size_t carve_push_scratch(Ctx *c, int64_t n, unsigned char *base, PushScratch &ps) {
     size_t off = 0;
     auto take = [&](size_t bytes) -> unsigned char * {
         unsigned char *p = base ? base + off : nullptr;
@@ -64,6 +64,7 @@ static size_t carve(Ctx *c, int64_t n, unsigned char *base, PushScratch &ps) {
     ps.strag_list = (int32_t *)take(sizeof(int32_t) * (size_t)n);
     ps.bin_list = (int32_t *)take(sizeof(int32_t) * (size_t)n);
     ps.bin_rank = (uint32_t *)take(sizeof(uint32_t) * (size_t)n);
+    ps.strag_count = (uint32_t *)take(sizeof(uint32_t));
     return off;
 }
 
@@ -79,11 +80,11 @@ extern "C" pic_status pic_gather_push_deposit_noalloc(void *ctx, const pic_speci
     if (st != PIC_OK || p->n == 0) return st;
     if (!c->noalloc_scratch) return fail(c, PIC_E_HIP, "no-allocation scratch has no device address");
     PushScratch ps;
-    const size_t need = carve(c, p->n, nullptr, ps);
+    const size_t need = carve_push_scratch(c, p->n, nullptr, ps);
     if (need > NOALLOC_BYTES)
         return fail(c, PIC_E_ARG, "push needs " + std::to_string(need) + " bytes of scratch, more than the " +
                                       std::to_string(NOALLOC_BYTES) + " of the no-allocation entry point");
-    carve(c, p->n, (unsigned char *)c->noalloc_scratch, ps);
+    carve_push_scratch(c, p->n, (unsigned char *)c->noalloc_scratch, ps);
     hipSetDevice(c->device);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = c->cfg.precision == PIC_FP32_MIXED ? launch_gpd_tiled(c, sp, p, fields, diag, s, &ps)

@@ -66,6 +66,10 @@ struct Ctx {
     // device address of the library's static no-allocation scratch on this
     // context's device
     void *noalloc_scratch = nullptr;
+    // scratch of the several-species push (every species' lists and
+    // counters, carved like the no-allocation scratch)
+    unsigned char *multi_scratch = nullptr;
+    size_t multi_cap = 0;        // bytes
     // scratch outgrown by an enqueueing call, freed by pic_reserve / pic_destroy
     std::vector<void *> retired;
     std::string err;
@@ -96,6 +100,7 @@ struct PushScratch {
     uint32_t *bin_count = nullptr;   // ntiles
     uint32_t *strag_tile = nullptr;  // ntiles
     int64_t *bin_start = nullptr;    // ntiles + 1
+    uint32_t *strag_count = nullptr; // length of the binned pass's own list (NULL: the context's)
 };
 // doubles of FP64 partials one push writes (FP32 tiled path, FP64 plain path)
 size_t push_partials_tiled(int64_t ntiles);
@@ -107,6 +112,12 @@ hipError_t launch_gpd_plain(Ctx *c, const pic_species *sp, const pic_particles *
                             const pic_fields *f, double *diag, hipStream_t s, const PushScratch *ps = nullptr);
 hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *p,
                             const pic_fields *f, double *diag, hipStream_t s, const PushScratch *ps = nullptr);
+// several species in one pass over the tiles; ps[k]: scratch of species k
+hipError_t launch_gpd_tiled_multi(Ctx *c, int nsp, const pic_species *sp, const pic_particles *const *p,
+                                  const pic_fields *f, double *diag, hipStream_t s, const PushScratch *ps);
+// carves one push's scratch (FP32 tiled or FP64 plain path, n particles)
+// from base; returns the bytes it takes (base = nullptr: only counts)
+size_t carve_push_scratch(Ctx *c, int64_t n, unsigned char *base, PushScratch &ps);
 pic_status validate_push_args(Ctx *c, const pic_species *sp, const pic_particles *p, const pic_fields *fields);
 hipError_t noalloc_scratch_init(void **ptr);
 hipError_t launch_yee(Ctx *c, int half, const pic_fields *f, double *diag, hipStream_t s);

@@ -102,8 +102,12 @@ class Simulation:
             j.zero_()
         if events is not None:
             events[0].record()
-        for sp, p in zip(self.species, self.particles):
-            L.pic_gather_push_deposit(self.ctx, sp, p, self.fields, diag)
+        if self.fp32 and 1 < len(self.species) <= L.PIC_MAX_SPECIES:
+            # one pass over the tiles for every species
+            L.pic_gather_push_deposit_multi(self.ctx, self.species, self.particles, self.fields, diag)
+        else:
+            for sp, p in zip(self.species, self.particles):
+                L.pic_gather_push_deposit(self.ctx, sp, p, self.fields, diag)
         if events is not None:
             events[1].record()
         L.pic_yee_step(self.ctx, 2, self.fields, diag)

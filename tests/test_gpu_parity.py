@@ -9,7 +9,7 @@ import torch
 
 import oracle as O
 from paper_2104_00642_amd import _lib as L
-from paper_2104_00642_amd.workloads import concat, courant_dt, to_fp32, to_fp64
+from paper_2104_00642_amd.workloads import RawParticles, concat, courant_dt, to_fp32, to_fp64
 
 from _helpers import (DEV, np64, oracle_grid, oracle_species, periodic_dx, random_fields, random_raw,
                       rel_l2)
@@ -773,6 +773,176 @@ def test_sort_from_tile_offsets_hint(dim):
         for a in range(3):
             assert np.array_equal(dst.u[a].cpu().numpy(), u[a].numpy()[perm])
         assert np.array_equal(dst.w.cpu().numpy(), w.numpy()[perm])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_absorbing_window_has_no_periodic_image_in_x(dim):
+    """Particles listed in a tile at the high-x face whose cells are now at
+    the low-x face (moved there since the sort): the tile's window reaches
+    past the face, where a periodic image would put them, but with absorbing
+    faces they are stragglers and take their true position.  Momenta,
+    positions and J against the oracle."""
+    print(f"absorbing window image dim={dim}", flush=True)
+    cfg = make_cfg(dim, 2, L.PIC_FP32_MIXED)
+    cfg.bc_x = L.PIC_BC_ABSORB2
+    E, B = random_fields(cfg, seed=90 + dim, amp=0.3)
+    E = [e.to(torch.float32).to(torch.float64) for e in E]
+    B = [b.to(torch.float32).to(torch.float64) for b in B]
+    ctx = L.pic_init(cfg)
+    bits, tile, ntiles = L.pic_get_layout(ctx)
+    n = 3001
+    gen = torch.Generator().manual_seed(91 + dim)
+    cells = [torch.randint(0, cfg.n[0] - 1 if a == 0 else cfg.n[a], (n,), generator=gen) for a in range(dim)]
+    raw = random_raw(cfg, n, seed=92 + dim, uth=0.3, cells=cells)
+    p = to_fp32(raw, bits)
+    src = L.Particles(n, [t.to(DEV) for t in p.u], cell=p.cell.to(DEV), off=[t.to(DEV) for t in p.off],
+                      w=p.w.to(DEV))
+    dst = src.empty_like()
+    dst.tile_start = torch.empty(ntiles + 1, dtype=torch.int64, device=DEV)
+    L.pic_sort(ctx, src, dst)
+    perm, _ = O.sort(oracle_grid(cfg), tile[:dim], [c.numpy() for c in raw.cell])
+    rs = raw.subset(torch.from_numpy(perm))
+    # particles of the last tile column to the first two cells in x
+    last = rs.cell[0] >= cfg.n[0] - tile[0]
+    far = last & (torch.arange(n) % 3 == 0)
+    cx = torch.where(far, rs.cell[0] % 2, rs.cell[0])
+    rs = RawParticles([cx] + list(rs.cell[1:]), rs.off, rs.u, rs.w)
+    dst.cell.copy_(to_fp32(rs, bits).cell.to(DEV))
+    f = L.Fields([t.to(DEV, torch.float32) for t in E], [t.to(DEV, torch.float32) for t in B],
+                 [torch.zeros(cfg.plane_shape, dtype=torch.float32, device=DEV) for _ in range(3)])
+    L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), dst, f)
+    st, flags, nstray = L.pic_check(ctx)
+    so = oracle_species(cfg, rs, -1.0, 1.0, True)
+    J_o = [np.zeros(cfg.plane_shape) for _ in range(3)]
+    F = [a.numpy().copy() for a in E] + [a.numpy().copy() for a in B]
+    O.push(oracle_grid(cfg), so, F, J_o, np.zeros(2))
+    print(f"  {int(far.sum())} moved, {nstray} stragglers", flush=True)
+    assert st == L.PIC_OK and nstray >= int(far.sum()) > 20
+    for a in range(3):
+        assert np.abs(np64(dst.u[a]) - so.u[a]).max() < 2e-6 * max(1.0, np.abs(so.u[a]).max())
+        assert rel_l2(np64(f.J[a]), J_o[a]) < 1e-5
+    assert np.array_equal(np64(dst.w) == 0, so.w == 0)
+
+
+def _clone(p):
+    c = lambda t: None if t is None else t.clone()  # noqa: E731
+    return L.Particles(p.n, [c(t) for t in p.u], cell=c(p.cell), off=[c(t) for t in p.off],
+                       x=[c(t) for t in p.x], w=c(p.w), chi=c(p.chi), tile_start=c(p.tile_start))
+
+
+SPECIES3 = [(-1.0, 1.0, 4001, 0.8), (1.0, 1836.0, 3001, 0.02), (1.0, 1.0, 2003, 0.5)]
+
+
+@pytest.mark.parametrize("dim,bc", [(2, L.PIC_BC_PERIODIC), (2, L.PIC_BC_ABSORB2), (3, L.PIC_BC_PERIODIC),
+                                    (3, L.PIC_BC_ABSORB)])
+def test_species_in_one_pass_match_one_by_one(dim, bc):
+    """pic_gather_push_deposit_multi with electrons (with chi), protons and
+    positrons of different counts and weights, 3% of each moved out of their
+    tiles after the sort (stragglers of every species), against one
+    pic_gather_push_deposit per species: particles, chi, flags and straggler
+    counts bit for bit, J within the FP32 rounding of the per-species flushes,
+    diag to 1e-12; and J against the oracle's deposit of all three species at
+    the FP32 bar."""
+    print(f"species in one pass dim={dim} bc={bc}", flush=True)
+    cfg = make_cfg(dim, 2, L.PIC_FP32_MIXED)
+    cfg.bc_x = bc
+    E, B = random_fields(cfg, seed=70 + dim)
+    E = [e.to(torch.float32).to(torch.float64) for e in E]
+    B = [b.to(torch.float32).to(torch.float64) for b in B]
+    ctx = L.pic_init(cfg)
+    bits, tile, ntiles = L.pic_get_layout(ctx)
+    rng = np.random.default_rng(dim + 10 * bc)
+    seq, one, raws = [], [], []
+    # with absorbing faces the domain is x in [0, (n-1) dx]: no particle
+    # starts in the last cell
+    nx = cfg.n[0] - (0 if bc == L.PIC_BC_PERIODIC else 1)
+    for k, (q, m, n, uth) in enumerate(SPECIES3):
+        gen = torch.Generator().manual_seed(500 + 10 * dim + k)
+        cells = [torch.randint(0, nx if a == 0 else cfg.n[a], (n,), generator=gen) for a in range(dim)]
+        raw = random_raw(cfg, n, seed=300 + 10 * dim + k, uth=uth, cells=cells)
+        p = to_fp32(raw, bits, with_chi=k == 0)
+        src = L.Particles(n, [t.to(DEV) for t in p.u], cell=p.cell.to(DEV), off=[t.to(DEV) for t in p.off],
+                          w=p.w.to(DEV), chi=None if p.chi is None else p.chi.to(DEV))
+        dst = src.empty_like()
+        dst.tile_start = torch.empty(ntiles + 1, dtype=torch.int64, device=DEV)
+        L.pic_sort(ctx, src, dst)
+        perm, _ = O.sort(oracle_grid(cfg), tile[:dim], [c.numpy() for c in raw.cell])
+        rs = raw.subset(torch.from_numpy(perm))
+        moved = torch.from_numpy(rng.random(n) < 0.03)
+        cx = torch.where(moved, (rs.cell[0] + tile[0]) % nx, rs.cell[0])
+        rs = RawParticles([cx] + list(rs.cell[1:]), rs.off, rs.u, rs.w)
+        dst.cell.copy_(to_fp32(rs, bits).cell.to(DEV))
+        raws.append(rs)
+        seq.append(dst)
+        one.append(_clone(dst))
+    sps = [L.Species(q, m, 1.0) for q, m, _, _ in SPECIES3]
+    zero = lambda: [torch.zeros(cfg.plane_shape, dtype=torch.float32, device=DEV) for _ in range(3)]  # noqa: E731
+    f_seq = L.Fields([t.to(DEV, torch.float32) for t in E], [t.to(DEV, torch.float32) for t in B], zero())
+    f_one = L.Fields([t.to(DEV, torch.float32) for t in E], [t.to(DEV, torch.float32) for t in B], zero())
+    d_seq = torch.zeros(4, dtype=torch.float64, device=DEV)
+    d_one = torch.zeros(4, dtype=torch.float64, device=DEV)
+    for sp, p in zip(sps, seq):
+        L.pic_gather_push_deposit(ctx, sp, p, f_seq, d_seq)
+    chk_seq = L.pic_check(ctx)
+    L.pic_gather_push_deposit_multi(ctx, sps, one, f_one, d_one)
+    chk_one = L.pic_check(ctx)
+    torch.cuda.synchronize()
+    print(f"  check {chk_one}", flush=True)
+    assert chk_seq == chk_one and chk_one[0] == L.PIC_OK and chk_one[2] > 0
+    for a, b in zip(seq, one):
+        for t0, t1 in zip([a.cell, *a.off, *a.u, a.w], [b.cell, *b.off, *b.u, b.w]):
+            assert torch.equal(t0, t1)
+        if a.chi is not None:
+            assert torch.equal(a.chi, b.chi)
+    if bc != L.PIC_BC_PERIODIC:
+        assert any(int((p.w == 0).sum().item()) > 0 for p in one)  # some particles left through a face
+    J_o = [np.zeros(cfg.plane_shape) for _ in range(3)]
+    diag_o = np.zeros(2)
+    g = oracle_grid(cfg)
+    F = [a.numpy().copy() for a in E] + [a.numpy().copy() for a in B]
+    for (q, m, _, _), rs in zip(SPECIES3, raws):
+        O.push(g, oracle_species(cfg, rs, q, m, True), F, J_o, diag_o)
+    for a in range(3):
+        js, jo = np64(f_seq.J[a]), np64(f_one.J[a])
+        scale = np.abs(js).max()
+        print(f"  J[{a}] one pass vs one by one: max {np.abs(jo - js).max() / scale:.2e} of max, "
+              f"rel L2 {rel_l2(jo, js):.2e}; vs oracle {rel_l2(jo, J_o[a]):.2e}")
+        assert np.abs(jo - js).max() <= 4e-7 * scale
+        assert rel_l2(jo, J_o[a]) < 1e-5
+    assert np64(d_one)[:2] == pytest.approx(np64(d_seq)[:2], rel=1e-12)
+    assert np64(d_one)[:2] == pytest.approx(diag_o, rel=1e-5)
+
+
+def test_species_in_one_pass_fp64_and_errors():
+    """The plain FP64 path pushes the species one after another: particles
+    bit for bit as with one call each, J to the rounding of its FP64 global
+    atomics, whose order varies from run to run; nsp outside
+    [1, PIC_MAX_SPECIES] and a species listed twice are rejected before
+    anything runs."""
+    cfg = make_cfg(2, 2, L.PIC_FP64_PLAIN)
+    E, B = random_fields(cfg, seed=5)
+    ctx = L.pic_init(cfg)
+    sps = [L.Species(q, m, 1.0) for q, m, _, _ in SPECIES3[:2]]
+    parts = []
+    for k, (q, m, n, uth) in enumerate(SPECIES3[:2]):
+        p = to_fp64(random_raw(cfg, n, seed=40 + k, uth=uth), cfg)
+        parts.append(L.Particles(p.n, [t.to(DEV) for t in p.u], x=[t.to(DEV) for t in p.x], w=p.w.to(DEV)))
+    twin = [_clone(p) for p in parts]
+    zero = lambda: [torch.zeros(cfg.plane_shape, dtype=torch.float64, device=DEV) for _ in range(3)]  # noqa: E731
+    f1 = L.Fields([t.to(DEV) for t in E], [t.to(DEV) for t in B], zero())
+    f2 = L.Fields([t.to(DEV) for t in E], [t.to(DEV) for t in B], zero())
+    for sp, p in zip(sps, parts):
+        L.pic_gather_push_deposit(ctx, sp, p, f1)
+    L.pic_gather_push_deposit_multi(ctx, sps, twin, f2)
+    torch.cuda.synchronize()
+    for a in range(3):
+        assert rel_l2(np64(f2.J[a]), np64(f1.J[a])) < 1e-14
+    for p0, p1 in zip(parts, twin):
+        for t0, t1 in zip([*p0.x, *p0.u], [*p1.x, *p1.u]):
+            assert torch.equal(t0, t1)
+    for bad_sp, bad_p in (([], []), (sps * 3, twin * 3), (sps[:1] * 2, [twin[0], twin[0]])):
+        with pytest.raises(L.PicError):
+            L.pic_gather_push_deposit_multi(ctx, bad_sp, bad_p, f2)
 
 
 @pytest.mark.parametrize("precision", [L.PIC_FP64_PLAIN, L.PIC_FP32_MIXED])

@@ -833,9 +833,11 @@ def _clone(p):
 SPECIES3 = [(-1.0, 1.0, 4001, 0.8), (1.0, 1836.0, 3001, 0.02), (1.0, 1.0, 2003, 0.5)]
 
 
-@pytest.mark.parametrize("dim,bc", [(2, L.PIC_BC_PERIODIC), (2, L.PIC_BC_ABSORB2), (3, L.PIC_BC_PERIODIC),
-                                    (3, L.PIC_BC_ABSORB)])
-def test_species_in_one_pass_match_one_by_one(dim, bc):
+@pytest.mark.parametrize("dim,bc,order,pusher", [
+    (2, L.PIC_BC_PERIODIC, 2, L.PIC_PUSH_BORIS), (2, L.PIC_BC_ABSORB2, 2, L.PIC_PUSH_BORIS),
+    (3, L.PIC_BC_PERIODIC, 2, L.PIC_PUSH_BORIS), (3, L.PIC_BC_ABSORB, 2, L.PIC_PUSH_BORIS),
+    (2, L.PIC_BC_PERIODIC, 4, L.PIC_PUSH_VAY), (3, L.PIC_BC_PERIODIC, 1, L.PIC_PUSH_VAY)])
+def test_species_in_one_pass_match_one_by_one(dim, bc, order, pusher):
     """pic_gather_push_deposit_multi with electrons (with chi), protons and
     positrons of different counts and weights, 3% of each moved out of their
     tiles after the sort (stragglers of every species), against one
@@ -843,15 +845,15 @@ def test_species_in_one_pass_match_one_by_one(dim, bc):
     counts bit for bit, J within the FP32 rounding of the per-species flushes,
     diag to 1e-12; and J against the oracle's deposit of all three species at
     the FP32 bar."""
-    print(f"species in one pass dim={dim} bc={bc}", flush=True)
-    cfg = make_cfg(dim, 2, L.PIC_FP32_MIXED)
+    print(f"species in one pass dim={dim} bc={bc} order={order} pusher={pusher}", flush=True)
+    cfg = make_cfg(dim, order, L.PIC_FP32_MIXED, pusher=pusher)
     cfg.bc_x = bc
     E, B = random_fields(cfg, seed=70 + dim)
     E = [e.to(torch.float32).to(torch.float64) for e in E]
     B = [b.to(torch.float32).to(torch.float64) for b in B]
     ctx = L.pic_init(cfg)
     bits, tile, ntiles = L.pic_get_layout(ctx)
-    rng = np.random.default_rng(dim + 10 * bc)
+    rng = np.random.default_rng(dim + 10 * bc + 100 * order)
     seq, one, raws = [], [], []
     # with absorbing faces the domain is x in [0, (n-1) dx]: no particle
     # starts in the last cell
@@ -911,6 +913,34 @@ def test_species_in_one_pass_match_one_by_one(dim, bc):
         assert rel_l2(jo, J_o[a]) < 1e-5
     assert np64(d_one)[:2] == pytest.approx(np64(d_seq)[:2], rel=1e-12)
     assert np64(d_one)[:2] == pytest.approx(diag_o, rel=1e-5)
+
+
+def test_species_in_one_pass_skips_empty_species():
+    """An empty species (n = 0, no arrays) in the list is skipped: the
+    result is that of the other species alone."""
+    cfg = make_cfg(2, 2, L.PIC_FP32_MIXED)
+    E, B = random_fields(cfg, seed=6)
+    ctx = L.pic_init(cfg)
+    bits, tile, ntiles = L.pic_get_layout(ctx)
+    raw = random_raw(cfg, 2001, seed=61)
+    p = to_fp32(raw, bits)
+    src = L.Particles(raw.n, [t.to(DEV) for t in p.u], cell=p.cell.to(DEV), off=[t.to(DEV) for t in p.off],
+                      w=p.w.to(DEV))
+    a = src.empty_like()
+    a.tile_start = torch.empty(ntiles + 1, dtype=torch.int64, device=DEV)
+    L.pic_sort(ctx, src, a)
+    b = _clone(a)
+    zero = lambda: [torch.zeros(cfg.plane_shape, dtype=torch.float32, device=DEV) for _ in range(3)]  # noqa: E731
+    fa = L.Fields([t.to(DEV, torch.float32) for t in E], [t.to(DEV, torch.float32) for t in B], zero())
+    fb = L.Fields([t.to(DEV, torch.float32) for t in E], [t.to(DEV, torch.float32) for t in B], zero())
+    el = L.Species(-1.0, 1.0, 1.0)
+    L.pic_gather_push_deposit(ctx, el, a, fa)
+    L.pic_gather_push_deposit_multi(ctx, [L.Species(1.0, 1836.0, 1.0), el], [L.Particles(0, [None] * 3), b], fb)
+    torch.cuda.synchronize()
+    for t0, t1 in zip([a.cell, *a.off, *a.u], [b.cell, *b.off, *b.u]):
+        assert torch.equal(t0, t1)
+    for c in range(3):
+        assert rel_l2(np64(fb.J[c]), np64(fa.J[c])) < 1e-6
 
 
 def test_species_in_one_pass_fp64_and_errors():

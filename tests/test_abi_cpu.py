@@ -61,4 +61,5 @@ def test_null_arguments(piclib):
     assert piclib.pic_deposit_rho(None, None, None, 1, None, None) == L.PIC_E_ARG
     assert piclib.pic_gauss_residual(None, None, None, None, None, None) == L.PIC_E_ARG
     assert piclib.pic_beam_fields(None, None, None, None) == L.PIC_E_ARG
+    assert piclib.pic_gather_push_deposit_multi(None, 2, None, None, None, None, None) == L.PIC_E_ARG
     piclib.pic_destroy(None)

@@ -202,6 +202,58 @@ def test_laser_3d_full_size():
         assert du < U_TOL and dx < X_TOL and jrel < J_TOL
 
 
+def test_laser_3d_full_size_species_in_one_pass():
+    """The same case in the benchmark's timed launch: tile 8 x 8 x 8 with
+    drift 0 (its choice by timing) and both species in one pass over the
+    tiles (pic_gather_push_deposit_multi, as Simulation.step pushes them):
+    sampled particles of each species against the oracle, the charge-
+    conserving sum over both species, and the element-wise current on two
+    32^3 windows (one across the periodic y and z seams)."""
+    print("full size: 3D laser-plasma 512x256x256, 8+8 ppc, FP32, species in one pass", flush=True)
+    wl = W.laser_plasma_3d(device=DEV, tile=(8, 8, 8))
+    sim = Simulation.from_workload(wl, precision=L.PIC_FP32_MIXED, device=DEV, sort_every=1 << 30,
+                                   tile=(8, 8, 8), drift=0)
+    sim.sort()
+    torch.cuda.synchronize()
+    for p in sim.particles:
+        check_sorted(p, sim.bits, sim.tile, sim.ntiles, sim.cfg)
+    L.pic_yee_step(sim.ctx, 1, sim.fields)
+    for j in sim.fields.J:
+        j.zero_()
+    torch.cuda.synchronize()
+    F = host_fields(sim.fields)
+    windows = [((60, 112, 112), (32, 32, 32)), ((60, 240, 240), (32, 32, 32))]
+    snaps = [window_snapshot(sim, lo, size) for lo, size in windows]
+    samples = []
+    for k, (sp, p) in enumerate(zip(sim.species, sim.particles)):
+        gen = torch.Generator().manual_seed(17 + k)
+        idx = torch.randint(0, p.n, (2000,), generator=gen).to(DEV)
+        samples.append(dict(idx=idx, x0=positions_fp32(p, sim.bits, sim.cfg, idx), u0=[np64(t[idx]) for t in p.u],
+                            w0=np64(p.w[idx])))
+    L.pic_gather_push_deposit_multi(sim.ctx, sim.species, sim.particles, sim.fields)
+    torch.cuda.synchronize()
+    st, flags, nstray = sim.check()
+    assert st == L.PIC_OK, flags
+    jx = float(sim.fields.J[0].double().sum().item())
+    qwv_sum, qwv_abs = 0.0, 0.0
+    for k, (sp, p, snap) in enumerate(zip(sim.species, sim.particles, samples)):
+        idx = snap["idx"]
+        snap.update(x1=positions_fp32(p, sim.bits, sim.cfg, idx), u1=[np64(t[idx]) for t in p.u])
+        osp, _, _ = oracle_sample(sim.cfg, sp, snap, F)
+        du, dx = push_errors(sim.cfg, snap, osp)
+        print(f"  species {k}: {p.n} particles, sample 2000: du {du:.2e}, dx {dx:.2e} cells", flush=True)
+        assert du < U_TOL and dx < X_TOL
+        u = [t[: p.n].double() for t in p.u]
+        qwv = sp.q * p.w[: p.n].double() * u[0] / torch.sqrt(1 + u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+        qwv_sum += float(qwv.sum().item())
+        qwv_abs += float(qwv.abs().sum().item())
+        del u, qwv
+    jrel = abs(jx - qwv_sum) / qwv_abs
+    print(f"  {nstray} stragglers; sum J_x vs sum q w v_x over both species {jrel:.2e}", flush=True)
+    assert jrel < J_TOL
+    check_windows(sim, windows, snaps, F)
+
+
 # the trained surrogate's rate error over its chi range (its training test
 # bounds the maximum at 1e-3); outside the range the tables answer
 NET_RATE_REL = 1e-3

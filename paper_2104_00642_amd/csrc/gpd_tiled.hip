@@ -960,18 +960,16 @@ __device__ __forceinline__ int neighbour_slot(const TiledArgs &a, int st, int dt
 // farther destinations (and the tail) reserve one by one.  A particle with an
 // offset outside [0,1) or a cell off the grid is flagged PIC_F_OFFSET and left
 // unchanged (never pushed).
+// (The straggler flag and count are left to the bin scan, which reads every
+// tile's count anyway: one atomic per block on one shared address serialized
+// the blocks once most tiles had stragglers.)
 template <int DIM>
 __global__ void __launch_bounds__(256) gpd_bin_count_kernel(TiledArgs a) {
     __shared__ uint32_t lcnt[BIN_SLOTS], gbase[BIN_SLOTS];
-    __shared__ uint32_t nfound;
     for (int k = threadIdx.x; k < BIN_SLOTS; k += blockDim.x) lcnt[k] = 0u;
-    if (threadIdx.x == 0) nfound = 0u;
     __syncthreads();
     const BinItems it = bin_items(a);
-    if (!it.tail && threadIdx.x == 0 && a.strag_tile[blockIdx.x] > 0u) {
-        atomicOr(a.status, PIC_F_STRAGGLER);
-        atomicAdd(a.stragglers, (unsigned long long)a.strag_tile[blockIdx.x]);
-    }
+    int found = 0;
     const int st = blockIdx.x;
     const int mx = (1 << a.bx) - 1, my = (1 << a.by) - 1;
     for (int64_t k = it.lo; k < it.hi; k += it.stride) {
@@ -999,10 +997,9 @@ __global__ void __launch_bounds__(256) gpd_bin_count_kernel(TiledArgs a) {
         // otherwise the final rank straight from the global counter
         a.bin_rank[k] = slot >= 0 ? (0x80000000u | atomicAdd(&lcnt[slot], 1u))
                                   : atomicAdd(&a.bin_count[dt], 1u);
-        if (!it.tail) atomicAdd(&nfound, 1u);
+        found = 1;
     }
-    __syncthreads();
-    if (it.tail || nfound == 0u) return;
+    if (!__syncthreads_or(found) || it.tail) return;
     // reserve each neighbour's share, then turn local ranks into final ones
     const int sc[3] = {st % a.ntile_axis[0], (st / a.ntile_axis[0]) % a.ntile_axis[1],
                        st / (a.ntile_axis[0] * a.ntile_axis[1])};
@@ -1029,19 +1026,30 @@ __global__ void __launch_bounds__(256) gpd_bin_count_kernel(TiledArgs a) {
 // bin_start = exclusive scan of bin_count (one workgroup, in order): chunks
 // of 1024 x 8 counts, each thread taking 8 consecutive ones (independent
 // loads, one memory latency per chunk), wavefront prefix sums by shuffles,
-// then the 16 wavefront totals
-__global__ void __launch_bounds__(1024) gpd_bin_scan_kernel(const uint32_t *count, int ntiles, int64_t *bstart) {
+// then the 16 wavefront totals.  It also sums the sorted pass's straggler
+// counts per tile (strag_tile) and, when there are any, raises
+// PIC_F_STRAGGLER and adds them to the run's count: one atomic per call.
+__global__ void __launch_bounds__(1024) gpd_bin_scan_kernel(const uint32_t *count, const uint32_t *strag_tile,
+                                                            int ntiles, int64_t *bstart, uint32_t *status,
+                                                            unsigned long long *stragglers) {
     constexpr int PER = 8;
     __shared__ int64_t wsum[16];
     __shared__ int64_t carry_s;
+    __shared__ unsigned long long nsum[16];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
+    unsigned long long ns = 0;
     for (int base = 0; base < ntiles; base += 1024 * PER) {
         const int lo = base + (int)threadIdx.x * PER;
-        uint32_t v[PER];
+        uint32_t v[PER], g[PER];
 #pragma unroll
-        for (int k = 0; k < PER; ++k) v[k] = lo + k < ntiles ? count[lo + k] : 0u;
+        for (int k = 0; k < PER; ++k) {
+            v[k] = lo + k < ntiles ? count[lo + k] : 0u;
+            g[k] = lo + k < ntiles ? strag_tile[lo + k] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) ns += g[k];
         int64_t s = 0;
 #pragma unroll
         for (int k = 0; k < PER; ++k) s += v[k];
@@ -1066,7 +1074,19 @@ __global__ void __launch_bounds__(1024) gpd_bin_scan_kernel(const uint32_t *coun
         if (threadIdx.x == 1023) carry_s = run;  // the last thread's running sum is the chunk's end
         __syncthreads();
     }
-    if (threadIdx.x == 0) bstart[ntiles] = carry_s;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ns += __shfl_xor(ns, o);
+    if (lane == 0) nsum[wave] = ns;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bstart[ntiles] = carry_s;
+        unsigned long long tot = 0;
+        for (int w = 0; w < 16; ++w) tot += nsum[w];
+        if (tot > 0) {
+            atomicOr(status, PIC_F_STRAGGLER);
+            atomicAdd(stragglers, tot);
+        }
+    }
 }
 
 template <int DIM>
@@ -1174,7 +1194,8 @@ static void launch_passes(TiledSet<NSP> S, size_t lds, hipStream_t s) {
     for (int k = 0; k < nsp; ++k) {
         TiledArgs &a = S.sp[k];
         gpd_bin_count_kernel<DIM><<<bins, b256, 0, s>>>(a);
-        gpd_bin_scan_kernel<<<1, 1024, 0, s>>>(a.bin_count, ntiles, a.bin_start);
+        gpd_bin_scan_kernel<<<1, 1024, 0, s>>>(a.bin_count, a.strag_tile, ntiles, a.bin_start, a.status,
+                                               a.stragglers);
         gpd_bin_scatter_kernel<DIM><<<bins, b256, 0, s>>>(a);
         gpd_reset_kernel<<<1, 1, 0, s>>>(a.strag_count);
         a.part_off = 2 * ntiles;

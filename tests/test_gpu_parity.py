@@ -222,7 +222,19 @@ def stragglers_case(cfg, seed=None):
     sp_o, J_o, _ = run_oracle_push(cfg, raw_sorted, E, B, -1.0, 1.0, from_fp32=True)
     L.pic_gather_push_deposit(ctx, L.Species(-1.0, 1.0, 1.0), p, f)
     st, flags, nstray = L.pic_check(ctx)
-    assert flags & L.PIC_F_STRAGGLER and nstray > 0 and st == L.PIC_OK
+    # the count is exact: particles whose cell lies outside their sorted
+    # tile widened by the drift allowance on each side (periodic)
+    _, tile, _ = L.pic_get_layout(ctx)
+    nta = [cfg.n[a] // tile[a] for a in range(dim)]
+    rem = np.repeat(np.arange(len(start) - 1), np.diff(start))
+    outside = np.zeros(raw.n, dtype=bool)
+    for a in range(dim):
+        lo = (rem % nta[a]) * tile[a] - cfg.drift
+        rem = rem // nta[a]
+        outside |= np.mod(raw_sorted.cell[a].numpy() - lo, cfg.n[a]) >= tile[a] + 2 * cfg.drift
+    print(f"  {len(idx)} moved, {nstray} stragglers (expected {int(outside.sum())})", flush=True)
+    assert flags & L.PIC_F_STRAGGLER and st == L.PIC_OK
+    assert nstray == int(outside.sum()) > 0
     for a in range(3):
         ug = np64(p.u[a])
         assert np.max(np.abs(ug - sp_o.u[a]) / (1.0 + np.abs(sp_o.u[a]))) < 2e-6

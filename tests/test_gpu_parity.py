@@ -143,11 +143,14 @@ def test_sort_then_fp32_push_matches_oracle(dim, order, pusher):
 
 
 @pytest.mark.parametrize("dim,order,drift,tz", [(2, 1, 2, 0), (2, 2, 2, 0), (2, 4, 2, 0), (2, 1, 1, 0), (2, 2, 1, 0),
-                                                (3, 2, 1, 4), (3, 2, 0, 4), (3, 4, 0, 4), (3, 2, 0, 8)])
+                                                (3, 2, 1, 4), (3, 2, 0, 4), (3, 4, 0, 4), (3, 2, 0, 8),
+                                                (3, 2, 1, 8)])
 def test_default_tiles_fp32_push_matches_oracle(dim, order, drift, tz):
     """The default tiles (16x16 with drift 2 in 2D; 8x8x4 with drift 1 or 0
     and 8x8x8 with drift 0 in 3D) run the kernels compiled for their window
-    shape; sort and push against the oracle."""
+    shape; sort and push against the oracle.  8x8x8 with drift 1 is the
+    largest window that fits the LDS (15^3 cells, 162000 bytes; run-time
+    window shape)."""
     print(f"default tiles dim={dim} order={order} drift={drift} tile z {tz}", flush=True)
     if dim == 2:
         cfg = L.Config(dim=2, n=(48, 32), d=(0.3, 0.25), dt=courant_dt((0.3, 0.25), 0.9), order=order,

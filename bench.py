@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--sort-every", type=int, default=None,
                     help="steps between sorts (default 24 in 2D, 8 in 3D, where fast particles leave their "
                          "tiles sooner)")
+    ap.add_argument("--ion-sort-factor", type=int, default=1,
+                    help="species of mass >= 100 m_e (the ions) are sorted every F * sort_every steps")
     ap.add_argument("--scale", type=int, default=1, help="divide the grid (tests only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
@@ -282,7 +284,8 @@ def qed_measure(torch, L, n=1 << 24, reps=5):
 def run_path(args, wl, precision, torch, L, Simulation):
     sim = Simulation.from_workload(wl, precision=precision, device="cuda",
                                    sort_every=args.sort_every,
-                                   tile=tuple(int(v) for v in args.tile.split(",")), drift=args.drift)
+                                   tile=tuple(int(v) for v in args.tile.split(",")), drift=args.drift,
+                                   heavy_sort_factor=args.ion_sort_factor)
     n = sum(p.n for p in sim.particles)
     for _ in range(args.warmup):
         sim.step()
@@ -346,8 +349,9 @@ def sampled_step(sim, torch, L, nsample=2000, seed=21):
     (for the oracle check of the CPU leg); also the global current check
     sum J_x = sum q w v_x of the push (charge conservation, no oracle)."""
     import numpy as np
-    if sim.fp32 and sim.step_index - sim.sorted_at >= sim.sort_every:
-        sim.sort()
+    due = sim.sort_due()
+    if due:
+        sim.sort(due)
     L.pic_yee_step(sim.ctx, 1, sim.fields)
     for j in sim.fields.J:
         j.zero_()
@@ -737,7 +741,7 @@ def main():
     if args.sort_every is None:
         args.sort_every = 24 if dim == 2 else 8
     if args.steps is None:
-        args.steps = 2 * args.sort_every
+        args.steps = 2 * args.sort_every * (max(1, args.ion_sort_factor) if dim == 3 else 1)
     if dim == 2:
         wl = laser_plasma_2d(scale=args.scale, device="cuda", order=args.order)
         ppc = 32

@@ -4,7 +4,8 @@
     J = 0
     pic_gather_push_deposit(species ...)  particles n -> n+1, J^{n+1}
     pic_yee_step(half=2)                  -> E^{n+1}, B^{n+1}
-    pic_sort every `sort_every` steps (FP32 layout)
+    pic_sort of each species every `sort_every` steps (FP32 layout; a slow
+    species, such as the ions, may take a longer interval of its own)
 
 Orchestration only (Sec. II.F of the paper gives the order); every step runs
 in the library's kernels.
@@ -22,13 +23,19 @@ from .workloads import RawParticles, Workload, fields_for, to_fp32, to_fp64
 
 class Simulation:
     def __init__(self, cfg: L.Config, species: List[L.Species], particles: List[L.Particles],
-                 fields: L.Fields, sort_every: int = 8, device="cuda"):
+                 fields: L.Fields, sort_every: int = 8, device="cuda",
+                 sort_every_species: Optional[List[int]] = None):
         self.cfg = cfg
         self.ctx = L.pic_init(cfg)
         self.species = species
         self.particles = particles
         self.fields = fields
         self.sort_every = max(1, int(sort_every))
+        # steps between the sorts of each species (default: sort_every for all)
+        self.sort_every_species = ([max(1, int(v)) for v in sort_every_species] if sort_every_species
+                                   else [self.sort_every] * len(particles))
+        if len(self.sort_every_species) != len(particles):
+            raise ValueError("sort_every_species needs one interval per species")
         self.device = device
         self.fp32 = cfg.precision == L.PIC_FP32_MIXED
         self.bits, self.tile, self.ntiles = L.pic_get_layout(self.ctx)
@@ -42,11 +49,13 @@ class Simulation:
         # scratch for the largest species up front: no call grows it later
         L.pic_reserve(self.ctx, max([p.capacity or p.n for p in particles] + [0]))
         self.step_index = 0
-        self.sorted_at = -1
+        self.sorted_at = [-1] * len(particles)  # step of each species' last sort (-1: never)
 
     @staticmethod
     def from_workload(wl: Workload, precision=L.PIC_FP32_MIXED, device="cuda", sort_every=8,
-                      from_fp32=False, with_chi=False, drift=2, tile=None):
+                      from_fp32=False, with_chi=False, drift=2, tile=None, heavy_sort_factor=1):
+        """heavy_sort_factor: species of mass >= 100 m_e (the ions) are sorted
+        every heavy_sort_factor * sort_every steps."""
         cfg = L.Config(**{**wl.cfg.__dict__})
         cfg.precision = precision
         cfg.drift = drift
@@ -66,21 +75,35 @@ class Simulation:
                 parts.append(to_fp32(raw, bits, with_chi=with_chi))
             else:
                 parts.append(to_fp64(raw, cfg, from_fp32=from_fp32, with_chi=with_chi))
-        sim = Simulation(cfg, sps, parts, fields, sort_every=sort_every, device=device)
+        every = [sort_every * (max(1, int(heavy_sort_factor)) if m >= 100.0 else 1) for _, m, _ in wl.species]
+        sim = Simulation(cfg, sps, parts, fields, sort_every=sort_every, device=device, sort_every_species=every)
         for b in wl.beams:  # self-fields of relativistic bunches (Sec. III(c))
             L.pic_beam_fields(sim.ctx, b, sim.fields)
         return sim
 
-    def sort(self):
-        for k, p in enumerate(self.particles):
-            dst = self.spare[k]
+    def sort(self, which=None):
+        """Sort the species `which` (indices; default every species)."""
+        for k in range(len(self.particles)) if which is None else which:
+            p, dst = self.particles[k], self.spare[k]
             # the arrays' tile offsets from their last sort let pic_sort move
             # only the particles that changed tiles; before the first sort
             # there are none to give
-            src = p if self.sorted_at >= 0 else dataclasses.replace(p, tile_start=None)
+            src = p if self.sorted_at[k] >= 0 else dataclasses.replace(p, tile_start=None)
             L.pic_sort(self.ctx, src, dst)
             self.particles[k], self.spare[k] = dst, p
-        self.sorted_at = self.step_index
+            self.sorted_at[k] = self.step_index
+
+    def sort_due(self):
+        """Indices of the species whose sort interval has run out (FP32)."""
+        if not self.fp32:
+            return []
+        return [k for k, at in enumerate(self.sorted_at)
+                if at < 0 or self.step_index - at >= self.sort_every_species[k]]
+
+    def restart_sort_cycles(self):
+        """Make the next step sort every species (a timed window that starts
+        with whole sort cycles)."""
+        self.sorted_at = [self.step_index - e for e in self.sort_every_species]
 
     def step(self, with_diag: bool = False, events=None, gauss=None):
         """One step; `events` = (start, end) torch events recorded on the
@@ -88,8 +111,9 @@ class Simulation:
         (rho, residual) FP64 planes that receive the charge density at the
         half step and div E - rho after the first half field update (the
         residual's maximum goes to diag[3] when with_diag)."""
-        if self.fp32 and (self.sorted_at < 0 or self.step_index - self.sorted_at >= self.sort_every):
-            self.sort()
+        due = self.sort_due()
+        if due:
+            self.sort(due)
         diag = self.diag if with_diag else None
         L.pic_yee_step(self.ctx, 1, self.fields)
         if gauss is not None:
@@ -157,7 +181,7 @@ def autotune_tiles(wl: Workload, candidates, steps: int = 8, warmup: int = 1, de
             continue
         for _ in range(warmup):
             sim.step()
-        sim.sorted_at = sim.step_index - sim.sort_every  # the timed window starts with a sort
+        sim.restart_sort_cycles()  # the timed window starts with a sort
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()

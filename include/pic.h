@@ -162,7 +162,11 @@ typedef struct {
 /* Create a context for one grid and step (validates the configuration and
  * allocates the context's scratch).  Errors: PIC_E_ARG, PIC_E_CFL,
  * PIC_E_UNSUPPORTED, PIC_E_NOMEM, PIC_E_HIP; *out is NULL on error and
- * pic_last_error(NULL) holds the message. */
+ * pic_last_error(NULL) holds the message.  FP32 path: the tile window,
+ * tile + 2 drift + 5 cells per axis (tile + 2 drift + 7 with quartic
+ * weights), takes 48 B per cell of LDS and must fit 159 KB (the 160 KB of
+ * one workgroup less the push kernel's own 1 KB) and the grid, else
+ * PIC_E_UNSUPPORTED. */
 pic_status pic_init(const pic_config *cfg, void **out);
 void pic_destroy(void *ctx);
 const char *pic_last_error(const void *ctx);

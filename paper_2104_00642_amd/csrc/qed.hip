@@ -69,11 +69,13 @@ constexpr int QED_PHOTON_THREADS = 512;
 // every thread of the group calls this (uniform control flow) with want =
 // whether it appends one particle; ranks come from a ballot per wavefront,
 // one LDS atomic per wavefront and one global atomic per workgroup, so the
-// shared counter is not serialized per particle.  Slots at or beyond `cap`
-// are dropped: the counter is brought back to cap and PIC_F_CAPACITY set.
-// Returns the slot, or -1.
-__device__ int64_t group_reserve(bool want, unsigned long long *counter, int64_t cap, uint32_t *status) {
-    __shared__ unsigned s_cnt;
+// shared counter is not serialized per particle.  The group's appends are
+// slots base + rank (rank < count, in wavefront then lane order); slots at
+// or beyond `cap` are dropped: the counter is brought back to cap and
+// PIC_F_CAPACITY set.  base and count are the same in every thread.
+__device__ void group_slots(bool want, unsigned long long *counter, int64_t cap, uint32_t *status,
+                            unsigned long long &base, unsigned &count, unsigned &rank) {
+    __shared__ unsigned s_cnt, s_total;
     __shared__ unsigned long long s_base;
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
@@ -86,20 +88,31 @@ __device__ int64_t group_reserve(bool want, unsigned long long *counter, int64_t
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned cnt = s_cnt;
-        unsigned long long base = 0;
+        unsigned long long b = 0;
         if (cnt) {
-            base = atomicAdd(counter, (unsigned long long)cnt);
-            const unsigned long long end = base + cnt, c = (unsigned long long)cap;
+            b = atomicAdd(counter, (unsigned long long)cnt);
+            const unsigned long long end = b + cnt, c = (unsigned long long)cap;
             if (end > c) {
-                atomicAdd(counter, 0ull - (end - (base > c ? base : c)));
+                atomicAdd(counter, 0ull - (end - (b > c ? b : c)));
                 atomicOr(status, PIC_F_CAPACITY);
             }
         }
-        s_base = base;
+        s_base = b;
+        s_total = cnt;  // s_cnt is cleared by the next call before its first barrier
     }
     __syncthreads();
+    base = s_base;
+    count = s_total;
+    rank = wbase + (unsigned)__popcll(mask & ((1ull << lane) - 1));
+}
+
+// The slot of the calling thread's append, or -1 (none, or beyond cap).
+__device__ int64_t group_reserve(bool want, unsigned long long *counter, int64_t cap, uint32_t *status) {
+    unsigned long long base;
+    unsigned count, rank;
+    group_slots(want, counter, cap, status, base, count, rank);
     if (!want) return -1;
-    const int64_t slot = (int64_t)(s_base + wbase + __popcll(mask & ((1ull << lane) - 1)));
+    const int64_t slot = (int64_t)(base + rank);
     return slot < cap ? slot : -1;
 }
 
@@ -121,48 +134,61 @@ __device__ void qed_write(const QedArgs &a, int s, int64_t idx, int32_t cell, co
 
 // one thread per lepton of species s (0 electrons, 1 positrons); the photon
 // of an event has energy fraction uf along u and the lepton recoils
-// collinearly
+// collinearly.  Every per-lepton input is loaded in one round (one memory
+// latency instead of a chain of them: weight, then momentum and chi, then
+// the optical depth).
 __global__ void __launch_bounds__(QED_THREADS) qed_lepton_kernel(QedArgs a, int s) {
     const QedSpecies &L = a.sp[s];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool fire = false;
-    float u[3] = {0.0f, 0.0f, 0.0f}, pu2 = 0.0f, gam = 1.0f, uf = 0.0f, w = 0.0f;
+    const bool in = p < L.n;
+    float w = 0.0f, chi = 0.0f, thr = 0.0f, net_F = 0.0f, net_uf = 0.0f;
+    float u[3] = {0.0f, 0.0f, 0.0f};
+    double tau = 0.0;
     uint64_t id = 0;
-    if (p < L.n) {
+    if (in) {
         w = L.w ? L.w[p] : 1.0f;
-        if (w != 0.0f) {
-            u[0] = L.u[0][p];
-            u[1] = L.u[1][p];
-            u[2] = L.u[2][p];
-            const float chi = L.chi[p];
-            pu2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-            gam = sqrtf(1.0f + pu2);
-            if (a.method2) {
-                if (chi > 0.0f) {
-                    id = L.id[p];
-                    double r1, r2;
-                    qed_uniforms(a.seed, id, a.step, 0u, r1, r2);
-                    const float F = qed_rate_F(a.tab, QED_COMPTON, chi);
-                    const double acc = a.rate_scale * (double)F / (double)gam * (double)a.dt *
-                                       (double)qed_density(a.tab, QED_COMPTON, chi, (float)r1);
-                    if (acc > 1.0) atomicOr(a.status, PIC_F_QED_SATURATED);
-                    fire = acc > r2;
-                    uf = (float)(r1 * r1 * r1);
-                }
-            } else {
-                const float F = a.mlp_out ? a.mlp_out[2 * p] : qed_rate_F(a.tab, QED_COMPTON, chi);
-                double tau = L.tau[p] + a.rate_scale * (double)F / (double)gam * (double)a.dt;
-                if (tau >= (double)L.tau_thr[p] && chi > 0.0f) {
-                    id = L.id[p];
-                    double ru, rt;
-                    qed_uniforms(a.seed, id, a.step, 0u, ru, rt);
-                    uf = a.mlp_out ? a.mlp_out[2 * p + 1] : qed_inverse(a.tab, QED_COMPTON, chi, (float)ru);
-                    fire = true;
-                    tau = 0.0;
-                    L.tau_thr[p] = (float)(-log(rt));
-                }
-                L.tau[p] = tau;
+        u[0] = L.u[0][p];
+        u[1] = L.u[1][p];
+        u[2] = L.u[2][p];
+        chi = L.chi[p];
+        id = L.id[p];
+        if (!a.method2) {
+            tau = L.tau[p];
+            thr = L.tau_thr[p];
+        }
+        if (a.mlp_out) {
+            net_F = a.mlp_out[2 * p];
+            net_uf = a.mlp_out[2 * p + 1];
+        }
+    }
+    bool fire = false;
+    float pu2 = 0.0f, gam = 1.0f, uf = 0.0f;
+    if (in && w != 0.0f) {
+        pu2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        gam = sqrtf(1.0f + pu2);
+        if (a.method2) {
+            if (chi > 0.0f) {
+                double r1, r2;
+                qed_uniforms(a.seed, id, a.step, 0u, r1, r2);
+                const float F = qed_rate_F(a.tab, QED_COMPTON, chi);
+                const double acc = a.rate_scale * (double)F / (double)gam * (double)a.dt *
+                                   (double)qed_density(a.tab, QED_COMPTON, chi, (float)r1);
+                if (acc > 1.0) atomicOr(a.status, PIC_F_QED_SATURATED);
+                fire = acc > r2;
+                uf = (float)(r1 * r1 * r1);
             }
+        } else {
+            const float F = a.mlp_out ? net_F : qed_rate_F(a.tab, QED_COMPTON, chi);
+            tau += a.rate_scale * (double)F / (double)gam * (double)a.dt;
+            if (tau >= (double)thr && chi > 0.0f) {
+                double ru, rt;
+                qed_uniforms(a.seed, id, a.step, 0u, ru, rt);
+                uf = a.mlp_out ? net_uf : qed_inverse(a.tab, QED_COMPTON, chi, (float)ru);
+                fire = true;
+                tau = 0.0;
+                L.tau_thr[p] = (float)(-log(rt));
+            }
+            L.tau[p] = tau;
         }
     }
     const float pm = sqrtf(pu2);
@@ -174,10 +200,32 @@ __global__ void __launch_bounds__(QED_THREADS) qed_lepton_kernel(QedArgs a, int 
         for (int c = 0; c < 3; ++c) L.u[c][p] = u[c] * f;
     }
     if (a.has[2]) {  // uniform over the grid
-        const int64_t slot = group_reserve(fire && eps >= a.emin, a.sp[2].n_dev, a.sp[2].capacity, a.status);
-        if (slot >= 0) {
-            const float off[3] = {L.off[0][p], L.off[1][p], a.dim == 3 ? L.off[2][p] : 0.0f};
-            qed_write(a, 2, slot, L.cell[p], off, k, w, qed_child_id(a.seed, id, a.step, 1u));
+        // A few percent of the leptons emit, so most wavefronts hold one or
+        // two: the emitters leave their photon in LDS at their rank among
+        // the group's appends, and the first `count` threads write the
+        // photons (the same slots, by few full wavefronts instead of many
+        // nearly empty ones)
+        __shared__ uint32_t e_src[QED_THREADS];
+        __shared__ float e_k[3][QED_THREADS], e_w[QED_THREADS];
+        __shared__ uint64_t e_id[QED_THREADS];
+        const bool emit = fire && eps >= a.emin;
+        unsigned long long base;
+        unsigned count, rank;
+        group_slots(emit, a.sp[2].n_dev, a.sp[2].capacity, a.status, base, count, rank);
+        if (emit) {
+            e_src[rank] = threadIdx.x;
+            for (int c = 0; c < 3; ++c) e_k[c][rank] = k[c];
+            e_w[rank] = w;
+            e_id[rank] = id;
+        }
+        __syncthreads();
+        const int64_t slot = (int64_t)(base + threadIdx.x);
+        if (threadIdx.x < count && slot < a.sp[2].capacity) {
+            const int64_t q = (int64_t)blockIdx.x * blockDim.x + e_src[threadIdx.x];
+            const float off[3] = {L.off[0][q], L.off[1][q], a.dim == 3 ? L.off[2][q] : 0.0f};
+            const float kq[3] = {e_k[0][threadIdx.x], e_k[1][threadIdx.x], e_k[2][threadIdx.x]};
+            qed_write(a, 2, slot, L.cell[q], off, kq, e_w[threadIdx.x],
+                      qed_child_id(a.seed, e_id[threadIdx.x], a.step, 1u));
         }
     }
 }
@@ -321,15 +369,42 @@ __global__ void __launch_bounds__(QED_PHOTON_THREADS) qed_photon_kernel(QedArgs 
     const float xs = fminf(fmaxf(x, 0.0f), 1.0f);
     const float ep = xs * eps, em = (1.0f - xs) * eps;
     const float np_ = sqrtf(fmaxf(ep * ep - 1.0f, 0.0f)) / eps, nm = sqrtf(fmaxf(em * em - 1.0f, 0.0f)) / eps;
-    if (a.has[1]) {  // uniform over the grid
-        const int64_t slot = group_reserve(decay, a.sp[1].n_dev, a.sp[1].capacity, a.status);
-        const float up[3] = {np_ * k[0], np_ * k[1], np_ * k[2]};
-        if (slot >= 0) qed_write(a, 1, slot, packed, f, up, w, qed_child_id(a.seed, id, a.step, 2u));
-    }
-    if (a.has[0]) {
-        const int64_t slot = group_reserve(decay, a.sp[0].n_dev, a.sp[0].capacity, a.status);
-        const float um[3] = {nm * k[0], nm * k[1], nm * k[2]};
-        if (slot >= 0) qed_write(a, 0, slot, packed, f, um, w, qed_child_id(a.seed, id, a.step, 3u));
+    if (a.has[0] || a.has[1]) {  // uniform over the grid
+        // as in the lepton kernel: the decaying photons leave their pair in
+        // LDS at their rank among the group's decays (the same in both
+        // reservations), and the first `count` threads write the positrons
+        // and electrons
+        __shared__ int32_t d_cell[QED_PHOTON_THREADS];
+        __shared__ float d_f[3][QED_PHOTON_THREADS], d_k[3][QED_PHOTON_THREADS];
+        __shared__ float d_n[2][QED_PHOTON_THREADS], d_w[QED_PHOTON_THREADS];
+        __shared__ uint64_t d_id[QED_PHOTON_THREADS];
+        unsigned long long base[2] = {0ull, 0ull};
+        unsigned count = 0, rank = 0;
+        if (a.has[1]) group_slots(decay, a.sp[1].n_dev, a.sp[1].capacity, a.status, base[1], count, rank);
+        if (a.has[0]) group_slots(decay, a.sp[0].n_dev, a.sp[0].capacity, a.status, base[0], count, rank);
+        if (decay) {
+            d_cell[rank] = packed;
+            for (int c = 0; c < 3; ++c) {
+                d_f[c][rank] = f[c];
+                d_k[c][rank] = k[c];
+            }
+            d_n[0][rank] = nm;   // electron
+            d_n[1][rank] = np_;  // positron
+            d_w[rank] = w;
+            d_id[rank] = id;
+        }
+        __syncthreads();
+        const unsigned t = threadIdx.x;
+        if (t < count) {
+            const float ft[3] = {d_f[0][t], d_f[1][t], d_f[2][t]};
+            for (int s2 = 1; s2 >= 0; --s2) {  // positron (tag 2), electron (tag 3)
+                const int64_t slot = (int64_t)(base[s2] + t);
+                if (!a.has[s2] || slot >= a.sp[s2].capacity) continue;
+                const float n = d_n[s2][t];
+                const float us[3] = {n * d_k[0][t], n * d_k[1][t], n * d_k[2][t]};
+                qed_write(a, s2, slot, d_cell[t], ft, us, d_w[t], qed_child_id(a.seed, d_id[t], a.step, 3u - s2));
+            }
+        }
     }
 }
 

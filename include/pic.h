@@ -245,7 +245,7 @@ pic_status pic_gather_push_deposit_multi(void *ctx, int32_t nsp, const pic_speci
  * from a static device array of PIC_NOALLOC_SCRATCH_BYTES that each GPU the
  * library runs on holds until the process ends; the call allocates nothing
  * and frees nothing.  Scratch per push (each part rounded up to 256 bytes):
- * FP32 path 12 B per particle, 48 B per tile, 4 KB and a counter; FP64 path 16 B per
+ * FP32 path 12 B per particle, 52 B per tile, 4 KB and a counter; FP64 path 16 B per
  * 256 particles.  A push needing more returns PIC_E_ARG before anything is
  * enqueued (with 4096 tiles the FP32 path takes up to about 5.5e6
  * particles).  Every call on one GPU shares its array

@@ -55,6 +55,7 @@ pic_status ensure_partials(Ctx *c, size_t n) {
 pic_status ensure_strag_list(Ctx *c, int64_t n) {
     if (!c->bin_count) {
         if (hipMalloc(&c->bin_count, sizeof(uint32_t) * (size_t)c->ntiles) != hipSuccess ||
+            hipMalloc(&c->bin_wmax, sizeof(uint32_t) * (size_t)c->ntiles) != hipSuccess ||
             hipMalloc(&c->strag_tile, sizeof(uint32_t) * (size_t)c->ntiles) != hipSuccess ||
             hipMalloc(&c->bin_start, sizeof(int64_t) * ((size_t)c->ntiles + 1)) != hipSuccess)
             return fail(c, PIC_E_NOMEM, "cannot allocate the tile bins");
@@ -296,6 +297,7 @@ extern "C" void pic_destroy(void *ctx) {
     hipFree(c->bin_list);
     hipFree(c->bin_rank);
     hipFree(c->bin_count);
+    hipFree(c->bin_wmax);
     hipFree(c->strag_tile);
     hipFree(c->bin_start);
     for (int b = 0; b < 2; ++b) {

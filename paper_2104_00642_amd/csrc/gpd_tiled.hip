@@ -84,6 +84,7 @@ struct TiledArgs {
     // bin_start[t+1]); bin_count/bin_rank build it
     int32_t *bin_list;
     int64_t *bin_start;    // ntiles + 1
+    uint32_t *bin_wmax;    // ntiles: max |q| w over each tile's bin, as float bits (binning)
     uint32_t *bin_count;   // ntiles
     uint32_t *bin_rank;    // per entry of the straggler list and tail (capacity n)
     int part_off;          // first partial slot (doubles) of the launch
@@ -701,28 +702,32 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledSet<NSP> S) {
         }
     }
     for (int r = threadIdx.x; r < lds.jcount(); r += NT) jwin[r] = 0ull;
-    // bound of |q| |w| over the tile's particles of every species (the
-    // per-particle weights read with four loads in flight per round)
+    // bound of |q| |w| over the tile's particles of every species: the
+    // binning's per-bin bound in the binned pass, else the per-particle
+    // weights read with four loads in flight per round
     float wm = 0.0f;
-    for (int k = 0; k < nsp; ++k) {
-        const TiledArgs &a = S.sp[k];
-        int64_t pbeg, pend;
-        range(a, pbeg, pend);
-        if (pbeg >= pend) continue;
-        const float aq = fabsf(a.q);
-        if (!a.w) {
-            wm = fmaxf(wm, aq * fabsf(a.w0));
-            continue;
-        }
-        const uint32_t np = (uint32_t)(pend - pbeg);
-        const float *wT = a.w + (LIST ? 0 : pbeg);
-        const int32_t *plist = a.bin_list + pbeg;
-        for (uint32_t i = threadIdx.x; i < np; i += 4 * NT) {
-            float x[4];
+    if constexpr (LIST) {
+        for (int k = 0; k < nsp; ++k) wm = fmaxf(wm, __uint_as_float(S.sp[k].bin_wmax[t]));
+    } else {
+        for (int k = 0; k < nsp; ++k) {
+            const TiledArgs &a = S.sp[k];
+            int64_t pbeg, pend;
+            range(a, pbeg, pend);
+            if (pbeg >= pend) continue;
+            const float aq = fabsf(a.q);
+            if (!a.w) {
+                wm = fmaxf(wm, aq * fabsf(a.w0));
+                continue;
+            }
+            const uint32_t np = (uint32_t)(pend - pbeg);
+            const float *wT = a.w + pbeg;
+            for (uint32_t i = threadIdx.x; i < np; i += 4 * NT) {
+                float x[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) x[q] = i + q * NT < np ? fabsf(ld(wT, poff_of(plist, i + q * NT))) : 0.0f;
+                for (int q = 0; q < 4; ++q) x[q] = i + q * NT < np ? fabsf(ld(wT, 4u * (i + q * NT))) : 0.0f;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) wm = fmaxf(wm, aq * x[q]);
+                for (int q = 0; q < 4; ++q) wm = fmaxf(wm, aq * x[q]);
+            }
         }
     }
 #pragma unroll
@@ -886,10 +891,14 @@ __global__ void __launch_bounds__(NT) gpd_tiled_kernel(TiledSet<NSP> S) {
     }
 }
 
-// Clears the bin counters and the straggler count before the sorted pass.
-__global__ void gpd_prep_kernel(uint32_t *bin_count, int ntiles, uint32_t *strag_count) {
+// Clears the bin counters, the bins' weight bounds and the straggler count
+// before the sorted pass.
+__global__ void gpd_prep_kernel(uint32_t *bin_count, uint32_t *bin_wmax, int ntiles, uint32_t *strag_count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ntiles) bin_count[i] = 0u;
+    if (i < ntiles) {
+        bin_count[i] = 0u;
+        bin_wmax[i] = 0u;
+    }
     if (i == 0) *strag_count = 0u;
 }
 
@@ -963,11 +972,20 @@ __device__ __forceinline__ int neighbour_slot(const TiledArgs &a, int st, int dt
 // (The straggler flag and count are left to the bin scan, which reads every
 // tile's count anyway: one atomic per block on one shared address serialized
 // the blocks once most tiles had stragglers.)
+// It also bounds |q| w over each destination tile's bin (bin_wmax, the
+// float's bits: for values >= 0 the unsigned order is the float order; a NaN
+// weight is left out, as the tile kernel's fmaxf leaves it out), so that the
+// binned pass reads its fixed-point scale instead of a pass over its
+// particles' weights.
 template <int DIM>
 __global__ void __launch_bounds__(256) gpd_bin_count_kernel(TiledArgs a) {
-    __shared__ uint32_t lcnt[BIN_SLOTS], gbase[BIN_SLOTS];
-    for (int k = threadIdx.x; k < BIN_SLOTS; k += blockDim.x) lcnt[k] = 0u;
+    __shared__ uint32_t lcnt[BIN_SLOTS], gbase[BIN_SLOTS], lwmax[BIN_SLOTS];
+    for (int k = threadIdx.x; k < BIN_SLOTS; k += blockDim.x) {
+        lcnt[k] = 0u;
+        lwmax[k] = 0u;
+    }
     __syncthreads();
+    const float aq = fabsf(a.q);
     const BinItems it = bin_items(a);
     int found = 0;
     const int st = blockIdx.x;
@@ -993,10 +1011,17 @@ __global__ void __launch_bounds__(256) gpd_bin_count_kernel(TiledArgs a) {
         }
         const int dt = tile_of(a, DIM, cell);
         const int slot = it.tail ? -1 : neighbour_slot<DIM>(a, st, dt);
+        const float qw = aq * fabsf(a.w ? a.w[p] : a.w0);
+        const uint32_t qwb = qw == qw ? __float_as_uint(qw) : 0u;
         // neighbour: rank inside the block's share (top bit marks it);
         // otherwise the final rank straight from the global counter
-        a.bin_rank[k] = slot >= 0 ? (0x80000000u | atomicAdd(&lcnt[slot], 1u))
-                                  : atomicAdd(&a.bin_count[dt], 1u);
+        if (slot >= 0) {
+            a.bin_rank[k] = 0x80000000u | atomicAdd(&lcnt[slot], 1u);
+            atomicMax(&lwmax[slot], qwb);
+        } else {
+            a.bin_rank[k] = atomicAdd(&a.bin_count[dt], 1u);
+            atomicMax(&a.bin_wmax[dt], qwb);
+        }
         found = 1;
     }
     if (!__syncthreads_or(found) || it.tail) return;
@@ -1013,6 +1038,7 @@ __global__ void __launch_bounds__(256) gpd_bin_count_kernel(TiledArgs a) {
         }
         const int dt = dc[0] + a.ntile_axis[0] * (dc[1] + a.ntile_axis[1] * dc[2]);
         gbase[k] = atomicAdd(&a.bin_count[dt], lcnt[k]);
+        atomicMax(&a.bin_wmax[dt], lwmax[k]);
     }
     __syncthreads();
     for (int64_t k = it.lo; k < it.hi; k += it.stride) {
@@ -1186,7 +1212,8 @@ static void launch_passes(TiledSet<NSP> S, size_t lds, hipStream_t s) {
     const dim3 tiles((unsigned)(8 * S.sp[0].chunk)), block(NT), gb(GLOBAL_BLOCKS), b256(256);
     for (int k = 0; k < nsp; ++k) {
         TiledArgs &a = S.sp[k];
-        gpd_prep_kernel<<<(unsigned)((ntiles + 255) / 256), 256, 0, s>>>(a.bin_count, ntiles, a.strag_count);
+        gpd_prep_kernel<<<(unsigned)((ntiles + 255) / 256), 256, 0, s>>>(a.bin_count, a.bin_wmax, ntiles,
+                                                                         a.strag_count);
         a.part_off = 0;
     }
     gpd_tiled_kernel<DIM, ORDER, PUSH, NT, WX, WY, WZ, false, SPLIT, NSP><<<tiles, block, lds, s>>>(S);
@@ -1316,6 +1343,7 @@ static TiledArgs tiled_args(Ctx *c, const pic_species *sp, const pic_particles *
     a.bin_rank = ps.bin_rank;
     a.bin_start = ps.bin_start;
     a.bin_count = ps.bin_count;
+    a.bin_wmax = ps.bin_wmax;
     return a;
 }
 
@@ -1333,6 +1361,7 @@ hipError_t launch_gpd_tiled(Ctx *c, const pic_species *sp, const pic_particles *
         own.bin_rank = c->bin_rank;
         own.bin_start = c->bin_start;
         own.bin_count = c->bin_count;
+        own.bin_wmax = c->bin_wmax;
         ps = &own;
     }
     TiledSet<1> S;

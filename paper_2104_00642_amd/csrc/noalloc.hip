@@ -59,6 +59,7 @@ size_t carve_push_scratch(Ctx *c, int64_t n, unsigned char *base, PushScratch &p
     const size_t nt = (size_t)c->ntiles;
     ps.partials = (double *)take(sizeof(double) * push_partials_tiled(c->ntiles));
     ps.bin_count = (uint32_t *)take(sizeof(uint32_t) * nt);
+    ps.bin_wmax = (uint32_t *)take(sizeof(uint32_t) * nt);
     ps.strag_tile = (uint32_t *)take(sizeof(uint32_t) * nt);
     ps.bin_start = (int64_t *)take(sizeof(int64_t) * (nt + 1));
     ps.strag_list = (int32_t *)take(sizeof(int32_t) * (size_t)n);

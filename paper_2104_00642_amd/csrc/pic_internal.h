@@ -33,6 +33,7 @@ struct Ctx {
     uint32_t *bin_rank = nullptr;
     size_t strag_cap = 0;        // entries
     uint32_t *bin_count = nullptr;  // ntiles
+    uint32_t *bin_wmax = nullptr;   // ntiles: bound of |q| w of each tile's bin (float bits)
     uint32_t *strag_tile = nullptr; // ntiles
     int64_t *bin_start = nullptr;   // ntiles + 1
     // FP64 block partials of the diagnostics reductions
@@ -98,6 +99,7 @@ struct PushScratch {
     int32_t *bin_list = nullptr;
     uint32_t *bin_rank = nullptr;
     uint32_t *bin_count = nullptr;   // ntiles
+    uint32_t *bin_wmax = nullptr;    // ntiles
     uint32_t *strag_tile = nullptr;  // ntiles
     int64_t *bin_start = nullptr;    // ntiles + 1
     uint32_t *strag_count = nullptr; // length of the binned pass's own list (NULL: the context's)

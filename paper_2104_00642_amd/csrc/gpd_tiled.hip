@@ -1003,7 +1003,10 @@ __global__ void __launch_bounds__(256) gpd_bin_count_kernel(TiledArgs a) {
             fs += f;
             ok &= f >= 0.0f && f < 1.0f && (unsigned)cc[d] < (unsigned)a.ng[d];
         }
-        if (!isfinite(a.u[0][p] + a.u[1][p] + a.u[2][p]) || !isfinite(fs)) atomicOr(a.status, PIC_F_NONFINITE);
+        // (the sorted pass has checked the stragglers' momenta already; the
+        // particles appended after the last tile it never saw)
+        if ((it.tail && !isfinite(a.u[0][p] + a.u[1][p] + a.u[2][p])) || !isfinite(fs))
+            atomicOr(a.status, PIC_F_NONFINITE);
         if (!ok) {
             atomicOr(a.status, PIC_F_OFFSET);
             a.bin_rank[k] = BIN_SKIP;

@@ -312,6 +312,8 @@ __global__ void __launch_bounds__(256) tail_copy_kernel(const uint32_t *vals, co
 constexpr int SORT_AHEAD = 4;
 // entries per thread that phase D keeps in registers for a one-stage tile
 constexpr int PERM_REG = 12;
+// entries per thread of the two-columns-per-round path
+constexpr int PAIR_REG = 6;
 
 // Layers of phase C handled per pass: R layers x (cells/64) group counters
 // stay within 16 KB of LDS.
@@ -609,7 +611,48 @@ __device__ __forceinline__ void order_tile(const uint32_t *vals, int64_t ts, int
     //    columns through LDS.  A tile that fits one stage and PERM_REG
     //    entries per thread keeps its entries' final positions and sources
     //    in registers across the columns (read once, not once per column);
-    //    larger tiles go `seg` final positions at a time.
+    //    larger tiles go `seg` final positions at a time.  A tile of at most
+    //    PAIR_REG entries per thread (the 3D tiles) moves two columns per
+    //    round: the second stages in the per-wavefront counters' space, free
+    //    once the positions are known, so each round has twice the loads in
+    //    flight and the rounds of barriers and write-outs halve.
+    if (n_t <= (int64_t)seg && n_t <= (int64_t)PAIR_REG * ORDER_THREADS && n_t <= (int64_t)RW * ct) {
+        uint32_t *stage2 = wcnt;
+        uint32_t pos[PAIR_REG], v[PAIR_REG];
+#pragma unroll
+        for (int u = 0; u < PAIR_REG; ++u) {
+            const int64_t i = ts + threadIdx.x + (int64_t)u * ORDER_THREADS;
+            pos[u] = i < te ? sc.rank(i) : 0xFFFFFFFFu;
+            v[u] = i < te ? vals[i] : 0u;
+        }
+        for (int col = 0; col < pa.ncol; col += 2) {
+            const bool two = col + 1 < pa.ncol;
+            const uint32_t *src0 = pa.src[col], *src1 = pa.src[two ? col + 1 : col];
+            const int sd0 = pa.stride[col], sd1 = pa.stride[two ? col + 1 : col];
+            uint32_t x0[PAIR_REG], x1[PAIR_REG];
+#pragma unroll
+            for (int u = 0; u < PAIR_REG; ++u)
+                if (pos[u] != 0xFFFFFFFFu) {
+                    x0[u] = src0[(int64_t)v[u] * sd0];
+                    if (two) x1[u] = src1[(int64_t)v[u] * sd1];
+                }
+#pragma unroll
+            for (int u = 0; u < PAIR_REG; ++u)
+                if (pos[u] != 0xFFFFFFFFu) {
+                    stage[pos[u]] = x0[u];
+                    if (two) stage2[pos[u]] = x1[u];
+                }
+            __syncthreads();
+            uint32_t *d0 = pa.dst[col] + ts * sd0;
+            for (uint32_t j = threadIdx.x; j < (uint32_t)n_t; j += ORDER_THREADS) d0[(int64_t)j * sd0] = stage[j];
+            if (two) {
+                uint32_t *d1 = pa.dst[col + 1] + ts * sd1;
+                for (uint32_t j = threadIdx.x; j < (uint32_t)n_t; j += ORDER_THREADS) d1[(int64_t)j * sd1] = stage2[j];
+            }
+            __syncthreads();
+        }
+        return;
+    }
     if (n_t <= (int64_t)seg && n_t <= (int64_t)PERM_REG * ORDER_THREADS) {
         uint32_t pos[PERM_REG], v[PERM_REG];
 #pragma unroll

@@ -272,6 +272,54 @@ def test_creation_capacity_is_enforced():
     # every lepton still fired and recoiled (a tiny photon may not change u in FP32)
     assert np.all(el.tau.cpu().numpy()[:n] == 0.0)
     assert el.u[0].cpu().numpy()[:n].mean() < 2000.0
+    # the photons that fit are whole: each from its own lepton (id, cell),
+    # along that lepton's momentum, with the lepton's weight and a fresh
+    # optical depth
+    parent_of = {Q.child_id(SEED, k, 1, 1): k for k in range(1, n + 1)}
+    ids = [int(i) & 0xFFFFFFFFFFFFFFFF for i in ph.id.cpu().numpy()[:10]]
+    assert all(i in parent_of for i in ids) and len(set(ids)) == 10
+    cells = el.cell.cpu().numpy()
+    assert [int(c) for c in ph.cell.cpu().numpy()[:10]] == [int(cells[parent_of[i] - 1]) for i in ids]
+    assert np.all(ph.u[0].cpu().numpy()[:10] > 0.0)
+    assert np.all(ph.u[1].cpu().numpy()[:10] == 0.0) and np.all(ph.u[2].cpu().numpy()[:10] == 0.0)
+    assert np.all(ph.w.cpu().numpy()[:10] == 1.0) and np.all(ph.tau.cpu().numpy()[:10] == 0.0)
+    thr = ph.tau_thr.cpu().numpy()[:10]
+    assert np.all(np.isfinite(thr)) and np.all(thr > 0.0)
+
+
+def test_pair_capacity_is_enforced():
+    """Every photon decays; the positrons and electrons that fit their
+    (different) capacities are whole pair members of distinct photons."""
+    cfg = qed_cfg()
+    ctx = L.pic_init(cfg)
+    bits, _, _ = L.pic_get_layout(ctx)
+    n, eps, chi = 100, 1000.0, 4.9
+    ph = species(n, n, bits, np.full(n, eps, dtype=np.float32), None, np.zeros(n, dtype=np.float32))
+    el = species(0, 7, bits, [])
+    po = species(0, 12, bits, [])
+    run_qed(ctx, cfg, fields(cfg, chi / (HBAR_W * eps)), electrons=el, positrons=po, photons=ph)
+    st, flags, _ = L.pic_check(ctx)
+    assert st == L.PIC_E_CAPACITY and flags & L.PIC_F_CAPACITY
+    assert int(el.n_dev.item()) == 7 and int(po.n_dev.item()) == 12
+    assert np.all(ph.w.cpu().numpy()[:n] == 0.0)
+    cells = ph.cell.cpu().numpy()  # the photons' cells after their move
+    members = {}
+    for sp, m, tag in ((po, 12, 2), (el, 7, 3)):
+        parent_of = {Q.child_id(SEED, k, 1, tag): k for k in range(1, n + 1)}
+        ids = [int(i) & 0xFFFFFFFFFFFFFFFF for i in sp.id.cpu().numpy()[:m]]
+        assert all(i in parent_of for i in ids) and len(set(ids)) == m
+        parents = [parent_of[i] for i in ids]
+        assert [int(c) for c in sp.cell.cpu().numpy()[:m]] == [int(cells[k - 1]) for k in parents]
+        assert np.all(sp.u[0].cpu().numpy()[:m] >= 0.0)
+        assert np.all(sp.u[1].cpu().numpy()[:m] == 0.0) and np.all(sp.u[2].cpu().numpy()[:m] == 0.0)
+        assert np.all(sp.w.cpu().numpy()[:m] == 1.0)
+        ux = sp.u[0].cpu().numpy()[:m].astype(np.float64)
+        members[tag] = dict(zip(parents, np.sqrt(1.0 + ux ** 2)))
+    both = set(members[2]) & set(members[3])
+    for k in both:  # members of one photon share its energy
+        a, b = members[2][k], members[3][k]
+        if min(a, b) > 1.0 + 1e-3:
+            assert a + b == pytest.approx(eps, rel=1e-5)
 
 
 # ---------------------------------------------------------------- Method II
